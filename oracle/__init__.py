@@ -1,0 +1,135 @@
+"""CPU oracle for canonical k-mer counting — TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The product library never imports,
+links or calls it.
+
+Two independent implementations of the k-mer histogram (Section II) are here:
+
+* ``liboracle.so`` (``kc_oracle.cpp``): the serial sort-based counter of
+  Algorithm 1 ("Serial Algorithm": GetFirstKmer, rolling update, Sort,
+  Accumulate) extended with the 2k-bit mask, the rolling reverse complement
+  and the canonical form min(kmer, rc); plus an unordered_map cross-check and a
+  selected-keys counter for inputs too large to count in full.
+* ``brute.py``: pure-Python string brute force for tiny inputs.
+
+Neither shares code with the GPU path. Parity pins: see tests/test_oracle_*.py.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kc_oracle.cpp")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread",
+                               _SRC, "-o", tmp])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = ctypes.CDLL(_SO)
+            p, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+            L.oracle_valid_windows.restype = u64
+            L.oracle_valid_windows.argtypes = [p, p, u64, i32]
+            L.oracle_count_sort.restype = i32
+            L.oracle_count_sort.argtypes = [p, p, u64, i32, i32, p, p, p, u64, p]
+            L.oracle_count_map.restype = i32
+            L.oracle_count_map.argtypes = [p, p, u64, i32, p, p, p, u64, p]
+            L.oracle_count_selected.restype = i32
+            L.oracle_count_selected.argtypes = [p, p, u64, i32, i32, p, p, u64, p]
+            _lib = L
+    return _lib
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _prep(reads, offsets):
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    if reads.size == 0:
+        reads = np.zeros(1, dtype=np.uint8)
+    return reads, offsets
+
+
+def max_windows(offsets, k: int) -> int:
+    """Number of length-k windows (valid or not): sum over reads of max(0, len-k+1)."""
+    lens = np.diff(np.asarray(offsets, dtype=np.int64))
+    return int(np.maximum(lens - k + 1, 0).sum())
+
+
+def valid_windows(reads, offsets, k: int) -> int:
+    reads, offsets = _prep(reads, offsets)
+    return int(lib().oracle_valid_windows(_p(reads), _p(offsets), offsets.size - 1, k))
+
+
+def _result(lo, hi, cnt, n, k):
+    lo, cnt = lo[:n].copy(), cnt[:n].copy()
+    if k > 32:
+        return np.stack([lo, hi[:n].copy()], axis=1), cnt
+    return lo, cnt
+
+
+def count(reads, offsets, k: int, threads: int | None = None, method: str = "sort"):
+    """Sorted canonical (k-mer, count) pairs.
+
+    Returns (keys, counts): keys uint64[D] for k <= 32, uint64[D, 2] as (lo, hi)
+    for k > 32; counts uint32[D].
+    """
+    reads, offsets = _prep(reads, offsets)
+    n = offsets.size - 1
+    cap = max(1, max_windows(offsets, k))
+    lo = np.empty(cap, dtype=np.uint64)
+    hi = np.empty(cap, dtype=np.uint64)
+    cnt = np.empty(cap, dtype=np.uint32)
+    n_out = np.zeros(1, dtype=np.uint64)
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    if method == "sort":
+        rc = lib().oracle_count_sort(_p(reads), _p(offsets), n, k, threads, _p(lo), _p(hi),
+                                     _p(cnt), cap, _p(n_out))
+    elif method == "map":
+        rc = lib().oracle_count_map(_p(reads), _p(offsets), n, k, _p(lo), _p(hi), _p(cnt), cap,
+                                    _p(n_out))
+    else:
+        raise ValueError(method)
+    if rc != 0:
+        raise RuntimeError("oracle error %d" % rc)
+    return _result(lo, hi, cnt, int(n_out[0]), k)
+
+
+def count_selected(reads, offsets, k: int, keys, threads: int | None = None):
+    """Count only the given canonical keys (uint64[m] or uint64[m, 2]). Returns uint64[m]."""
+    reads, offsets = _prep(reads, offsets)
+    keys = np.asarray(keys, dtype=np.uint64)
+    if keys.ndim == 2:
+        lo, hi = np.ascontiguousarray(keys[:, 0]), np.ascontiguousarray(keys[:, 1])
+    else:
+        lo, hi = np.ascontiguousarray(keys), None
+    out = np.zeros(lo.shape[0], dtype=np.uint64)
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    rc = lib().oracle_count_selected(_p(reads), _p(offsets), offsets.size - 1, k, threads,
+                                     _p(lo), _p(hi), lo.shape[0], _p(out))
+    if rc != 0:
+        raise RuntimeError("oracle error %d" % rc)
+    return out

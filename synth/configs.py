@@ -1,0 +1,73 @@
+"""The five workload recipes (genome, reads, k, P) with a size fraction.
+
+``frac`` scales genome length and read count together (coverage kept), so that
+the same recipe yields a small case for fast tests and the full-size case.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import CONFIG_SEED_BASE, genome, reads
+
+CONFIGS = {
+    1: dict(name="c1_plain_k31_P1_100kbp_10x", backbone=100_000, families="none",
+            n_reads=6_667, read_len=150, err=0.005, n_rate=0.0, ks=(31,), P=1),
+    2: dict(name="c2_plain_k31_P64_5Mbp_repeats_30x", backbone=5_000_000, families="c2",
+            n_reads=1_000_000, read_len=150, err=0.01, n_rate=1e-4, ks=(31,), P=64),
+    3: dict(name="c3_plain_k31_k21_P256_200Mbp_zipf_30x", backbone=110_000_000, families="c3",
+            n_reads=40_000_000, read_len=150, err=0.005, n_rate=0.0, ks=(31, 21), P=256),
+}
+
+
+def family_layout(kind: str, seed: int, frac: float = 1.0):
+    """Repeat families as (length, copies, divergence) tuples."""
+    rng = np.random.Generator(np.random.PCG64(seed ^ 0xFA11))
+    if kind == "none":
+        return []
+    if kind == "c2":
+        # 5 families of length U[1, 6] kbp, each inserted 40 times at 2% divergence.
+        lens = rng.integers(1000, 6001, size=5)
+        copies = max(1, int(round(40 * frac)))
+        return [(int(l), copies, 0.02) for l in lens]
+    if kind == "c3":
+        # 50 families, length U[1, 6] kbp, Zipf(1.2) copy numbers capped at 1e4,
+        # scaled so the copies total 90 Mbp (45% of 200 Mbp); divergence U[2, 5]%.
+        lens = rng.integers(1000, 6001, size=50).astype(np.float64)
+        divs = rng.uniform(0.02, 0.05, size=50)
+        target = 90_000_000 * frac
+        ranks = np.arange(1, 51, dtype=np.float64)
+        cap = max(1.0, 1e4 * frac)
+
+        def total(A):
+            c = np.minimum(cap, np.round(A * ranks ** -1.2))
+            return float((c * lens).sum())
+
+        lo, hi = 0.0, 1e9
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if total(mid) < target:
+                lo = mid
+            else:
+                hi = mid
+        c = np.minimum(cap, np.round(hi * ranks ** -1.2)).astype(np.int64)
+        return [(int(l), int(cc), float(d)) for l, cc, d in zip(lens, c, divs) if cc > 0]
+    raise ValueError(kind)
+
+
+def make_config(idx: int, frac: float = 1.0, threads: int | None = None):
+    """Build config ``idx`` at size fraction ``frac``.
+
+    Returns dict(reads=uint8[], offsets=uint64[n+1], ks=tuple, P=int, name=str, genome_len=int).
+    """
+    c = CONFIGS[idx]
+    seed = CONFIG_SEED_BASE + idx
+    backbone = max(1000, int(round(c["backbone"] * frac)))
+    fams = family_layout(c["families"], seed, frac)
+    g = genome(seed, backbone, fams)
+    n_reads = max(1, int(round(c["n_reads"] * frac)))
+    r, off = reads(g, n_reads, c["read_len"], err_rate=c["err"], n_rate=c["n_rate"],
+                   seed=seed, threads=threads)
+    name = c["name"] if frac == 1.0 else "%s@%g" % (c["name"], frac)
+    return dict(reads=r, offsets=off, ks=c["ks"], P=c["P"], name=name, genome_len=int(g.shape[0]))
