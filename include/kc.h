@@ -1,0 +1,133 @@
+/*
+ * kc.h — canonical k-mer counting on one MI355X (gfx950): the C ABI.
+ *
+ * What is computed (the k-mer histogram of Section II, counted as in
+ * Algorithm 1 "Serial Algorithm" and Algorithm 3 "FA-BSP Algorithm"):
+ *   - read i is the byte range reads[offsets[i] .. offsets[i+1]);
+ *   - a window is k consecutive bytes of one read; it is valid iff every byte
+ *     is A/C/G/T (either case); windows touching any other byte ('N', IUPAC
+ *     codes, ...) are skipped;
+ *   - bases are coded A=0, C=1, G=2, T=3 with the first base most
+ *     significant (Encode / GetFirstKmer of Algorithm 1), masked to 2k bits;
+ *   - the counted key is the canonical k-mer min(kmer, reverse complement)
+ *     as an unsigned 2k-bit integer;
+ *   - the result is every distinct key with its number of valid windows,
+ *     sorted by key ascending ("ordered array of {k-mer, count}", Algorithm 1),
+ *     from count 1 up (Section VI counts from 1 to the maximum).
+ * The P owner partitions stand in for the paper's P processing elements
+ * (OwnerPE, Algorithms 2-4); the result does not depend on P.
+ *
+ * Conventions
+ *   - All array arguments of kc_count / kc_count_ex are DEVICE pointers
+ *     (memory from hipMalloc, or a torch CUDA tensor's data pointer) unless
+ *     named host_*. n_out is a host pointer.
+ *   - Keys: k <= 32 -> one uint64 per key (key in the low 2k bits);
+ *           33 <= k <= 64 -> two uint64 per key, low word first (lo, hi).
+ *   - The caller owns inputs and outputs. The library owns its scratch memory
+ *     (a per-host-thread, per-device arena kept between calls) and keeps no
+ *     caller pointer after a call returns.
+ *   - Calls are synchronous with respect to the host: when they return, the
+ *     outputs are complete. Work is issued on `stream` (NULL = the legacy
+ *     default stream).
+ *   - No C++ exception crosses this boundary. On error, the outputs are
+ *     unspecified except *n_out for KC_E_CAPACITY; kc_last_error() gives a
+ *     message (per host thread).
+ */
+#ifndef KC_H
+#define KC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define KC_OK 0
+#define KC_E_INVAL (-1)    /* bad argument: NULL pointer, k outside [1,64], P < 1,
+                              offsets decreasing */
+#define KC_E_NOMEM (-2)    /* device or host allocation failed */
+#define KC_E_CAPACITY (-3) /* output arrays too small; *n_out holds the size needed */
+#define KC_E_OVERFLOW (-4) /* a count exceeds UINT32_MAX */
+#define KC_E_DEVICE (-5)   /* HIP runtime error (message in kc_last_error) */
+#define KC_E_INTERNAL (-6) /* a device self-check failed (message in kc_last_error) */
+
+/* Tuning knobs. Zero in any field means "choose automatically".
+ * None of them changes the result, only how it is computed. */
+typedef struct kc_options {
+  int shard_bits;      /* log2 of the number of first-level key-range shards
+                          (owner buckets are unions of shards); 1..10 */
+  int leaf_target;     /* target valid windows per leaf partition when splitting */
+  int leaf_attempt;    /* partitions up to this many windows are counted directly */
+  int table_slots_log2;/* log2 of the LDS open-addressing table per leaf (10..13 for
+                          k<=32, 10..12 for k>32) */
+  int check;           /* 1 = run the device self-check of the output (sorted,
+                          canonical, in range, sum of counts == valid windows) */
+  int timing;          /* 1 = record per-stage times (kc_last_stats) */
+  int mode;            /* 0 = partitioned LDS counting (default);
+                          1 = one global open-addressing HBM table, then sort */
+  int reserved[5];
+} kc_options;
+
+/* Statistics of the last successful call on this host thread. */
+typedef struct kc_stats {
+  uint64_t n_bases;        /* bytes covered by the reads */
+  uint64_t valid_windows;  /* W: valid windows (= sum of the output counts) */
+  uint64_t distinct;       /* D: distinct canonical keys (= *n_out) */
+  uint64_t n_leaves;       /* leaf partitions counted */
+  uint64_t n_levels;       /* partitioning levels below the shard level */
+  uint64_t n_overflow;     /* leaf attempts that overflowed the table and were split */
+  uint64_t max_leaf_windows;
+  uint64_t max_owner_windows; /* windows in the largest of the P owner buckets */
+  uint64_t table_slots;    /* slots of the global table (mode 1), else 0 */
+  double   ms_total;       /* host wall time of the call */
+  double   ms_stage[8];    /* timing=1: pack, window-hist, owner-scatter, split, leaf-count,
+                              concat, check, global-table (ms, device events) */
+} kc_stats;
+
+/* Count canonical k-mers (plain form).
+ *   reads      device, ASCII bytes; read i = reads[offsets[i] .. offsets[i+1])
+ *   offsets    device, n_reads+1 non-decreasing byte offsets (offsets[0] may be > 0)
+ *   n_reads    number of reads (0 allowed)
+ *   k          1..64
+ *   P          number of owner partitions (>= 1)
+ *   out_keys   device, room for kc_max_outputs() keys (1 or 2 uint64 each, see above)
+ *   out_counts device, room for kc_max_outputs() counts
+ *   n_out      host; receives the number of distinct keys written
+ * Returns KC_OK or a negative status. */
+int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
+             uint64_t* out_keys, uint32_t* out_counts, uint64_t* n_out);
+
+/* As kc_count with an explicit output capacity (in keys), options (NULL =
+ * automatic) and a HIP stream (hipStream_t passed as void*, NULL = default).
+ * If more than out_capacity keys result, returns KC_E_CAPACITY with *n_out set. */
+int kc_count_ex(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
+                uint64_t* out_keys, uint32_t* out_counts, uint64_t out_capacity,
+                uint64_t* n_out, const kc_options* opt, void* stream);
+
+/* Upper bound on the number of output keys (= number of length-k windows,
+ * valid or not): sum over reads of max(0, len - k + 1). host_offsets is a
+ * HOST array of n_reads+1 offsets. Returns 0 for bad arguments. */
+uint64_t kc_max_outputs(const uint64_t* host_offsets, uint64_t n_reads, int k);
+
+/* Copy the statistics of this thread's last successful call. Returns KC_OK,
+ * or KC_E_INVAL if out is NULL. */
+int kc_last_stats(kc_stats* out);
+
+/* Release this thread's scratch arena (device memory is freed). */
+void kc_release_scratch(void);
+
+/* Static description of a status code. */
+const char* kc_strerror(int status);
+
+/* Message for the last error on this host thread ("" if none). */
+const char* kc_last_error(void);
+
+/* Library version string. */
+const char* kc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KC_H */

@@ -1,0 +1,155 @@
+"""ctypes binding of ``include/kc.h`` (argument marshalling only).
+
+Torch is used for device memory and the current stream; nothing is computed
+here. If ``libkc.so`` is missing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libkc.so")
+_lock = threading.Lock()
+_lib = None
+
+STATUS = {0: "KC_OK", -1: "KC_E_INVAL", -2: "KC_E_NOMEM", -3: "KC_E_CAPACITY",
+          -4: "KC_E_OVERFLOW", -5: "KC_E_DEVICE", -6: "KC_E_INTERNAL"}
+
+EXPORTED_SYMBOLS = ["kc_count", "kc_count_ex", "kc_max_outputs", "kc_last_stats",
+                    "kc_release_scratch", "kc_strerror", "kc_last_error", "kc_version"]
+
+
+class KcOptions(ctypes.Structure):
+    _fields_ = [("shard_bits", ctypes.c_int), ("leaf_target", ctypes.c_int),
+                ("leaf_attempt", ctypes.c_int), ("table_slots_log2", ctypes.c_int),
+                ("check", ctypes.c_int), ("timing", ctypes.c_int), ("mode", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
+
+
+class KcStats(ctypes.Structure):
+    _fields_ = [("n_bases", ctypes.c_uint64), ("valid_windows", ctypes.c_uint64),
+                ("distinct", ctypes.c_uint64), ("n_leaves", ctypes.c_uint64),
+                ("n_levels", ctypes.c_uint64), ("n_overflow", ctypes.c_uint64),
+                ("max_leaf_windows", ctypes.c_uint64), ("max_owner_windows", ctypes.c_uint64),
+                ("table_slots", ctypes.c_uint64), ("ms_total", ctypes.c_double),
+                ("ms_stage", ctypes.c_double * 8)]
+
+
+STAGES = ["pack", "window_hist", "owner_scatter", "split", "leaf_count", "concat", "check",
+          "global_table"]
+
+
+class KcError(RuntimeError):
+    def __init__(self, status: int, message: str, n_out: int = 0):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, message))
+        self.status = status
+        self.n_out = n_out
+
+
+def library_path() -> str:
+    return _SO
+
+
+def lib():
+    """Load libkc.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_SO):
+                raise ImportError("libkc.so not built: run __graft_entry__.build() "
+                                  "(or python -m paper_2505_04431_amd._build)")
+            L = ctypes.CDLL(_SO)
+            p, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+            L.kc_count.restype = i32
+            L.kc_count.argtypes = [p, p, u64, i32, i32, p, p, p]
+            L.kc_count_ex.restype = i32
+            L.kc_count_ex.argtypes = [p, p, u64, i32, i32, p, p, u64, p, p, p]
+            L.kc_max_outputs.restype = u64
+            L.kc_max_outputs.argtypes = [p, u64, i32]
+            L.kc_last_stats.restype = i32
+            L.kc_last_stats.argtypes = [p]
+            L.kc_release_scratch.restype = None
+            L.kc_release_scratch.argtypes = []
+            L.kc_strerror.restype = ctypes.c_char_p
+            L.kc_strerror.argtypes = [i32]
+            L.kc_last_error.restype = ctypes.c_char_p
+            L.kc_last_error.argtypes = []
+            L.kc_version.restype = ctypes.c_char_p
+            L.kc_version.argtypes = []
+            _lib = L
+    return _lib
+
+
+def options(**kw) -> KcOptions:
+    o = KcOptions()
+    for name, v in kw.items():
+        setattr(o, name, int(v))
+    return o
+
+
+def max_outputs(host_offsets, k: int) -> int:
+    off = np.ascontiguousarray(np.asarray(host_offsets), dtype=np.uint64)
+    return int(lib().kc_max_outputs(off.ctypes.data, off.size - 1, k))
+
+
+def last_stats() -> dict:
+    s = KcStats()
+    lib().kc_last_stats(ctypes.byref(s))
+    d = {name: getattr(s, name) for name, _ in KcStats._fields_ if name != "ms_stage"}
+    d["ms_stage"] = {n: s.ms_stage[i] for i, n in enumerate(STAGES)}
+    return d
+
+
+def _check_tensor(t, what, dtypes):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA (ROCm) tensor" % what)
+    if t.dtype not in dtypes:
+        raise TypeError("%s has dtype %s" % (what, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+
+
+def count_into(reads, offsets, k: int, P: int, out_keys, out_counts, capacity: int,
+               opts: KcOptions | None = None, stream=None) -> int:
+    """Call kc_count_ex on torch device tensors; returns the number of keys written."""
+    import torch
+    _check_tensor(reads, "reads", (torch.uint8,))
+    _check_tensor(offsets, "offsets", (torch.int64, torch.uint64))
+    _check_tensor(out_keys, "out_keys", (torch.int64, torch.uint64))
+    _check_tensor(out_counts, "out_counts", (torch.int32, torch.uint32))
+    if stream is None:
+        stream = torch.cuda.current_stream(reads.device).cuda_stream
+    n_out = ctypes.c_uint64(0)
+    with torch.cuda.device(reads.device):
+        st = lib().kc_count_ex(reads.data_ptr(), offsets.data_ptr(), offsets.numel() - 1, k, P,
+                               out_keys.data_ptr(), out_counts.data_ptr(), capacity,
+                               ctypes.byref(n_out),
+                               ctypes.byref(opts) if opts is not None else None, stream)
+    if st != 0:
+        raise KcError(st, lib().kc_last_error().decode(), int(n_out.value))
+    return int(n_out.value)
+
+
+def count(reads, offsets, k: int, P: int = 1, opts: KcOptions | None = None, stream=None,
+          capacity: int | None = None):
+    """Count canonical k-mers of device reads.
+
+    reads: uint8 CUDA tensor; offsets: int64 CUDA tensor of n_reads+1 offsets.
+    Returns (keys, counts): int64 tensors [D] (k <= 32) or [D, 2] as (lo, hi)
+    words (k > 32), and int32 counts [D] (bit patterns of uint64 / uint32).
+    """
+    import torch
+    if capacity is None:
+        capacity = max_outputs(offsets.cpu().numpy().view(np.uint64), k)
+    capacity = max(1, int(capacity))
+    words = 2 if k > 32 else 1
+    keys = torch.empty((capacity, words) if words == 2 else (capacity,), dtype=torch.int64,
+                       device=reads.device)
+    counts = torch.empty(capacity, dtype=torch.int32, device=reads.device)
+    n = count_into(reads, offsets, k, P, keys, counts, capacity, opts, stream)
+    return keys[:n], counts[:n]

@@ -1,0 +1,50 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+public header declares, and its host-only helpers behave."""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+import paper_2505_04431_amd as kc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "kc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    L = kc.lib()
+    syms = header_symbols()
+    assert "kc_count" in syms and "kc_count_ex" in syms
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(kc.EXPORTED_SYMBOLS) == syms
+
+
+def test_library_is_gfx950_build():
+    assert kc.lib().kc_version().decode().endswith("gfx950")
+    with open(kc.library_path(), "rb") as f:
+        blob = f.read()
+    assert b"gfx950" in blob
+
+
+def test_max_outputs_and_strerror():
+    offs = np.array([0, 5, 5, 7, 100], dtype=np.uint64)
+    assert kc.max_outputs(offs, 3) == 3 + 0 + 0 + 91
+    assert kc.max_outputs(offs, 1) == 100
+    assert kc.max_outputs(np.array([0, 5, 3], dtype=np.uint64), 2) == 0
+    L = kc.lib()
+    assert L.kc_strerror(0) == b"ok"
+    assert L.kc_strerror(-3) == b"output capacity too small"
+    assert L.kc_strerror(-99) == b"unknown status"
+
+
+def test_options_layout_matches_header():
+    # kc_options: 7 ints + 5 reserved; kc_stats: 9 uint64 + 9 doubles
+    assert ctypes.sizeof(kc.kc.KcOptions) == 12 * 4
+    assert ctypes.sizeof(kc.kc.KcStats) == 9 * 8 + 9 * 8

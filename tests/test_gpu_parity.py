@@ -1,0 +1,144 @@
+"""Parity of the HIP path (called through the C ABI) with the CPU oracle.
+
+Integer work: every comparison is bit-exact, element by element.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_same, gpu_count, to_device
+from helpers import keys_as_ints, revcomp_bytes, to_arrays
+from oracle import brute
+
+pytestmark = pytest.mark.gpu
+
+KS = [1, 2, 3, 4, 5, 8, 15, 16, 17, 21, 31, 32, 33, 55, 63, 64]
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")
+
+
+def _pairs(keys, cnt, k):
+    return list(zip(keys_as_ints(keys, k), [int(c) for c in cnt]))
+
+
+def test_hand_examples():
+    for e in json.load(open(GOLDEN))["examples"]:
+        r, o = to_arrays(e["reads"])
+        keys, cnt = gpu_count(r, o, e["k"], P=2, check=1)
+        assert _pairs(keys, cnt, e["k"]) == [(brute.encode(s), c) for s, c in e["expect"]], e["name"]
+
+
+@pytest.mark.parametrize("k", KS)
+def test_brute_force_ragged(k):
+    for seed in range(2):
+        text, offs = synth.ragged_reads(1000 * k + seed, 60, 0, 3 * k + 40, b"ACGTACGTACGTacgtNR")
+        want = brute.count_strings(brute.split_reads(text.tobytes(), offs), k)
+        keys, cnt = gpu_count(text, offs, k, P=3, check=1)
+        assert _pairs(keys, cnt, k) == want
+
+
+@pytest.mark.parametrize("k", [1, 2, 7, 16, 21, 31, 32, 33, 47, 55, 63, 64])
+def test_oracle_random_genome_reads(k):
+    # several thousand reads: many shards, several tiles per shard, ragged tail
+    g = synth.genome(500 + k, 40_000, [(800, 10, 0.02)])
+    r, o = synth.reads(g, 3001, 151, err_rate=0.01, n_rate=0.002, seed=k)
+    assert_same(gpu_count(r, o, k, P=5, check=1), oracle.count(r, o, k), "k=%d" % k)
+
+
+def test_config1_full_element_wise():
+    c = synth.make_config(1)
+    want = oracle.count(c["reads"], c["offsets"], 31)
+    assert_same(gpu_count(c["reads"], c["offsets"], 31, P=1, check=1), want, "config 1")
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 64, 256, 1024])
+def test_p_invariance(P):
+    c = synth.make_config(2, frac=0.05)
+    want = oracle.count(c["reads"], c["offsets"], 31)
+    assert_same(gpu_count(c["reads"], c["offsets"], 31, P=P), want, "P=%d" % P)
+
+
+@pytest.mark.parametrize("opts", [
+    dict(table_slots_log2=10),
+    dict(table_slots_log2=11, leaf_target=300),          # deep splits
+    dict(leaf_attempt=1 << 30),                           # overflow -> split path
+    dict(shard_bits=1),
+    dict(shard_bits=10, leaf_target=64, leaf_attempt=128),
+])
+def test_knob_invariance(opts):
+    c = synth.make_config(2, frac=0.02)
+    for k in (31, 55):
+        want = oracle.count(c["reads"], c["offsets"], k)
+        assert_same(gpu_count(c["reads"], c["offsets"], k, P=7, check=1, **opts), want,
+                    "k=%d %s" % (k, opts))
+
+
+def test_strand_flip_permutation_and_unaligned_base():
+    g = synth.genome(31, 30_000, [(500, 20, 0.01)])
+    r, o = synth.reads(g, 2000, 150, err_rate=0.005, n_rate=0.001, seed=3)
+    base = gpu_count(r, o, 31, P=4)
+    assert_same(gpu_count(revcomp_bytes(r, o), o, 31, P=4), base, "strand flip")
+    perm = np.random.Generator(np.random.PCG64(1)).permutation(o.size - 1)
+    chunks = [r[int(o[i]):int(o[i + 1])] for i in perm]
+    o2 = np.zeros_like(o)
+    np.cumsum([len(x) for x in chunks], out=o2[1:])
+    assert_same(gpu_count(np.concatenate(chunks), o2, 31, P=4), base, "permutation")
+    for pad in (1, 3, 13, 64, 77):
+        assert_same(gpu_count(r, o, 31, P=4, pad_front=pad), base, "pad %d" % pad)
+
+
+def test_empty_and_degenerate_inputs():
+    empty = (np.zeros(0, dtype=np.uint8), np.zeros(1, dtype=np.uint64))
+    k, c = gpu_count(*empty, 31)
+    assert k.size == 0 and c.size == 0
+    r, o = to_arrays(["", "ACG", "", "NNNNNNNNNNNNNNNNNNNNNNNNNNNNNNNNNNNNNN"])
+    k, c = gpu_count(r, o, 31)
+    assert k.size == 0
+    r, o = to_arrays(["A" * 5000, "T" * 3000])
+    k, c = gpu_count(r, o, 31, check=1)
+    assert k.tolist() == [0] and c.tolist() == [5000 - 30 + 3000 - 30]
+    r, o = to_arrays(["ACGT" * 2000])
+    for kk in (1, 2, 64):
+        assert_same(gpu_count(r, o, kk), oracle.count(r, o, kk), "periodic k=%d" % kk)
+
+
+def test_error_paths():
+    import torch
+    import paper_2505_04431_amd as kc
+    r, o = to_arrays(["ACGTACGT"])
+    rt, ot = to_device(r, o)
+    keys = torch.empty(8, dtype=torch.int64, device=rt.device)
+    cnt = torch.empty(8, dtype=torch.int32, device=rt.device)
+    for bad_k in (0, 65):
+        with pytest.raises(kc.KcError) as e:
+            kc.count_into(rt, ot, bad_k, 1, keys, cnt, 8)
+        assert e.value.status == -1
+    with pytest.raises(kc.KcError) as e:
+        kc.count_into(rt, ot, 3, 0, keys, cnt, 8)
+    assert e.value.status == -1
+    want = oracle.count(r, o, 2)
+    with pytest.raises(kc.KcError) as e:
+        kc.count_into(rt, ot, 2, 1, keys, cnt, len(want[0]) - 1)
+    assert e.value.status == -3 and e.value.n_out == len(want[0])
+    bad = torch.tensor([0, 5, 3], dtype=torch.int64, device=rt.device)
+    with pytest.raises(kc.KcError) as e:
+        kc.count_into(rt, bad, 2, 1, keys, cnt, 8)
+    assert e.value.status == -1
+
+
+def test_config2_full_element_wise():
+    """The benchmark workload (5 Mbp + repeats, 1M reads, k=31, P=64), full size."""
+    c = synth.make_config(2)
+    want = oracle.count(c["reads"], c["offsets"], 31)
+    got = gpu_count(c["reads"], c["offsets"], 31, P=64, check=1)
+    assert_same(got, want, "config 2")
+    assert int(got[1].sum(dtype=np.uint64)) == oracle.valid_windows(c["reads"], c["offsets"], 31)
+
+
+def test_k55_long_reads():
+    g = synth.genome(55, 200_000, [(3000, 5, 0.01)])
+    r, o = synth.reads(g, 300, 10_000, err_rate=0.01, seed=5)
+    assert_same(gpu_count(r, o, 55, P=8, check=1), oracle.count(r, o, 55), "k=55 long reads")
