@@ -13,20 +13,20 @@ struct SplitItem {
   uint32_t bin, pad;
 };
 
-// Per bin being split: its sub-bin counters start at hist_off; the sub-bin of
-// a key is (key >> shift) & ((1 << nbits) - 1).
+// Per bin being split: its sub-bin counters (and cursors, and leaf slots in the
+// device-planned path) start at hist_off; the sub-bin of a key is
+// (key >> shift) & ((1 << nbits) - 1). nbits == 0: the bin is not split.
 struct SplitBin {
   uint64_t hist_off;
   uint32_t shift, nbits;
 };
 
-// A leaf partition: records [begin, end) of buffer `buf` (0 = A, 1 = B);
-// its sorted (key, count) pairs go to the other buffer at [begin, begin + d)
-// and, at the end, to the output at out_off.
+// A leaf partition: records [begin, end) of buffer `buf` (0 = A, 1 = B) whose
+// keys share their top `bits` key bits. Its sorted (key, count) pairs are
+// written to the other buffer (and the pair-count array) at [begin, begin + d).
 struct Leaf {
   uint64_t begin, end;
-  uint64_t out_off;
-  uint32_t buf, pad;
+  uint32_t buf, bits;
 };
 
 // Device-side result flags of the output self-check.
@@ -35,12 +35,30 @@ struct CheckResult {
   unsigned int not_sorted, not_canonical, out_of_range, zero_count;
 };
 
-constexpr int kMaxShardBits = 10;  // first-level shards (owner buckets are unions of them)
-constexpr int kSplitMaxBits = 8;   // sub-bins per split step: up to 256
-constexpr int kSplitTile = 8192;   // records per split work item
-constexpr int kWinStarts = 8;      // window starts per thread in the window kernels
+// Per-call device state: counters written by the planning kernels and flags.
+struct DevState {
+  unsigned long long W;         // valid windows
+  unsigned long long n_items;   // split work items
+  unsigned long long n_leaves;  // leaf slots
+  unsigned long long D;         // distinct keys (sum of leaf counts)
+  unsigned long long n_large;   // leaves handled by the block-wide leaf kernel
+  unsigned int overflow;        // a leaf table overflowed (device-planned path cannot finish)
+  unsigned int count_overflow;  // a count exceeds 2^32-1
+  unsigned int pad[2];
+  CheckResult check;
+};
 
-// `wide` selects 128-bit keys (33 <= k <= 64) instead of 64-bit keys.
+constexpr int kMaxShardBits = 10;  // first-level shards (owner buckets are unions of them)
+constexpr int kSplitMaxBits = 10;  // sub-bins per split step: up to 1024
+constexpr int kWinStarts = 8;      // window starts per thread in the window kernels
+constexpr uint32_t kLeafOverflow = 0xFFFFFFFFu;
+
+int max_leaf_slots_log2(bool wide);
+int max_shard_bits();
+int split_tile(bool wide);  // records per split work item
+
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
+
 hipError_t launch_pack(const uint8_t* src, uint64_t n_bytes, const uint64_t* offsets,
                        uint64_t n_reads, uint64_t off0, uint64_t* packed, uint64_t* inv,
                        uint64_t* endm, uint64_t nchunks, hipStream_t s);
@@ -54,29 +72,59 @@ hipError_t launch_window_scatter(bool wide, const uint64_t* packed, const uint64
                                  const uint64_t* endm, uint64_t n_bytes, int k, int shard_bits,
                                  unsigned long long* cursor, void* out, hipStream_t s);
 
+// Device planning of the first split level. order[] lists shards
+// owner-major; sbegin[] receives each shard's record range start, cursor[] a
+// copy for the scatter; bins[] the split of each shard; items[] the tiles of
+// the split shards (item_off[] holds nb+1 prefix offsets of them); subhist[]
+// (max_leaves entries) is prepared: zeros for split shards, the shard size for
+// unsplit ones; st->n_items and st->n_leaves are set.
+hipError_t launch_plan_shards(const unsigned long long* hist, const int* order, int shard_bits,
+                              int keybits, uint64_t leaf_target, uint64_t leaf_attempt,
+                              int tile, unsigned long long* sbegin, unsigned long long* cursor,
+                              SplitBin* bins, SplitItem* items, unsigned long long* item_off,
+                              unsigned long long* subhist, uint64_t max_leaves,
+                              uint64_t max_items, DevState* st, hipStream_t s);
+
+// Device planning of the leaves (one block): leaf table in key order and the
+// sub-bin cursors of the split shards.
+hipError_t launch_plan_leaves(const unsigned long long* hist, const unsigned long long* sbegin,
+                              const SplitBin* bins, int shard_bits,
+                              const unsigned long long* subhist, Leaf* leaves,
+                              unsigned long long* cursor, hipStream_t s);
+
+// Split kernels loop over st->n_items items (persistent grid of at most max_items blocks).
 hipError_t launch_split_hist(bool wide, const void* src, const SplitItem* items,
-                             uint64_t n_items, const SplitBin* bins,
+                             const DevState* st, uint64_t max_items, const SplitBin* bins,
                              unsigned long long* subhist, hipStream_t s);
 
 hipError_t launch_split_scatter(bool wide, const void* src, void* dst, const SplitItem* items,
-                                uint64_t n_items, const SplitBin* bins,
+                                const DevState* st, uint64_t max_items, const SplitBin* bins,
                                 unsigned long long* cursor, hipStream_t s);
 
-// Count each leaf in an LDS open-addressing table; write sorted pairs next to it.
-// d_out[i] = distinct keys of leaf i, or 0xFFFFFFFF if its table overflowed.
-hipError_t launch_leaf_count(bool wide, void* bufA, void* bufB, uint32_t* tmp_cnt,
-                             const Leaf* leaves, uint64_t n_leaves, uint32_t* d_out,
-                             int slots_log2, unsigned int* count_overflow, hipStream_t s);
+// Count each of the st->n_leaves leaves in an LDS open-addressing table, sort
+// its distinct keys, write the pairs next to it. d_out[i] = distinct keys of
+// leaf i, or kLeafOverflow (and st->overflow = 1) if its table overflowed.
+// Leaves of at most small_leaf_max() records are handled by one-wave
+// workgroups with private tables; larger ones (listed in large_list, which
+// holds max_leaves entries) by 1024-thread workgroups.
+hipError_t launch_leaf_count(bool wide, int k, void* bufA, void* bufB, uint32_t* tmp_cnt,
+                             const Leaf* leaves, DevState* st, uint64_t max_leaves,
+                             uint32_t* d_out, int slots_log2, uint32_t* large_list,
+                             hipStream_t s);
+uint64_t small_leaf_max(bool wide);
+
+// Exclusive scan of leaf counts into output offsets; st->D = total. bsum
+// holds scan_blocks(max_leaves) values.
+hipError_t launch_plan_out(const uint32_t* d, DevState* st, unsigned long long* bsum,
+                           uint64_t max_leaves, unsigned long long* out_off, hipStream_t s);
+uint64_t scan_blocks(uint64_t max_leaves);
 
 hipError_t launch_concat(bool wide, const void* bufA, const void* bufB, const uint32_t* tmp_cnt,
-                         const Leaf* leaves, const uint32_t* d, uint64_t n_leaves,
+                         const Leaf* leaves, const uint32_t* d, const unsigned long long* out_off,
+                         const DevState* st, uint64_t max_leaves, uint64_t cap,
                          uint64_t* out_keys, uint32_t* out_counts, hipStream_t s);
 
 hipError_t launch_check(bool wide, const uint64_t* keys, const uint32_t* counts, uint64_t n,
                         int k, CheckResult* res, hipStream_t s);
-
-int max_leaf_slots_log2(bool wide);
-int max_shard_bits();
-int split_tile(bool wide);  // records per split work item
 
 }  // namespace kc

@@ -76,6 +76,9 @@ template <> struct Key<uint64_t> {
   __device__ static bool in_range(uint64_t x, int k) { return (x & ~mask64(k)) == 0; }
 };
 
+// LDS atomics take unsigned long long; same key semantics as uint64_t.
+template <> struct Key<unsigned long long> : Key<uint64_t> {};
+
 template <> struct Key<u128> {
   static constexpr bool kWide = true;
   __device__ static u128 empty() { return ~(u128)0; }
@@ -102,44 +105,69 @@ template <> struct Key<u128> {
   __device__ static bool in_range(u128 x, int k) { return (x & ~mask128(k)) == 0; }
 };
 
-// ---------------------------------------------------------------- block scan
+// ---------------------------------------------------------------- block scans
 
-// Exclusive scan of one value per thread; returns the prefix, sets *total.
-template <int TB>
-__device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* scratch, uint32_t* total) {
-  const int tid = threadIdx.x;
-  scratch[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < TB; off <<= 1) {
-    uint32_t add = tid >= off ? scratch[tid - off] : 0u;
-    __syncthreads();
-    scratch[tid] += add;
-    __syncthreads();
+// Exclusive scan of one value per thread (wave shuffles, then one wave over
+// the wave totals); returns the prefix and sets *total. wsum holds TB/64 values.
+template <int TB, typename T>
+__device__ __forceinline__ T block_exscan(T v, T* wsum, T* total) {
+  constexpr int NW = TB / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T y = __shfl_up(x, off);
+    if (lane >= off) x += y;
   }
-  uint32_t incl = scratch[tid];
-  uint32_t tot = scratch[TB - 1];
+  if (lane == 63) wsum[wid] = x;
   __syncthreads();
-  *total = tot;
-  return incl - v;
+  if (wid == 0) {
+    T w = lane < NW ? wsum[lane] : (T)0;
+#pragma unroll
+    for (int off = 1; off < NW; off <<= 1) {
+      const T y = __shfl_up(w, off);
+      if (lane >= off) w += y;
+    }
+    if (lane < NW) wsum[lane] = w;  // inclusive prefix of the wave totals
+  }
+  __syncthreads();
+  const T before = wid ? wsum[wid - 1] : (T)0;
+  *total = wsum[NW - 1];
+  __syncthreads();
+  return before + x - v;
 }
 
 // Exclusive scan of an LDS array a[0..n) into out[0..n); returns the total.
+// If maxv is not null it receives the largest a[i].
 template <int TB>
 __device__ __forceinline__ uint32_t block_exscan_array(const uint32_t* a, uint32_t* out, int n,
-                                                       uint32_t* scratch) {
+                                                       uint32_t* wsum, uint32_t* maxv = nullptr) {
   const int per = (n + TB - 1) / TB;
   const int b = threadIdx.x * per;
   const int e = min(n, b + per);
-  uint32_t s = 0;
-  for (int i = b; i < e; ++i) s += a[i];
+  uint32_t s = 0, m = 0;
+  for (int i = b; i < e; ++i) {
+    s += a[i];
+    m = max(m, a[i]);
+  }
+  if (maxv) {
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(maxv, m);
+  }
   uint32_t total;
-  uint32_t run = block_exscan<TB>(s, scratch, &total);
+  uint32_t run = block_exscan<TB, uint32_t>(s, wsum, &total);
   for (int i = b; i < e; ++i) {
     out[i] = run;
     run += a[i];
   }
   __syncthreads();
   return total;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
 // ---------------------------------------------------------------- pack
@@ -314,7 +342,7 @@ __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restric
   __shared__ uint32_t hist[NBMAX];
   __shared__ uint32_t loff[NBMAX];
   __shared__ unsigned long long gbase[NBMAX];
-  __shared__ uint32_t scratch[TB];
+  __shared__ uint32_t wsum[TB / 64];
   const int nb = 1 << shard_bits;
   const uint64_t n_tiles = (n_threads + TB - 1) / TB;
   for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
@@ -339,7 +367,7 @@ __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restric
       }
     }
     __syncthreads();
-    const uint32_t total = block_exscan_array<TB>(hist, loff, nb, scratch);
+    const uint32_t total = block_exscan_array<TB>(hist, loff, nb, wsum);
     for (int i = threadIdx.x; i < nb; i += TB)
       if (hist[i]) gbase[i] = atomicAdd(&cursor[i], (unsigned long long)hist[i]);
 #pragma unroll
@@ -359,78 +387,281 @@ __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restric
   }
 }
 
+// ---------------------------------------------------------------- planning (one block)
+
+constexpr int kPlanTB = 1024;
+
+__device__ __forceinline__ int ceil_log2_dev(uint64_t x) {
+  return x <= 1 ? 0 : 64 - __builtin_clzll(x - 1);
+}
+
+// Shard plan: owner-major record ranges, split decision per shard, split
+// work items, leaf slot offsets (leaf slots follow key order).
+__global__ void __launch_bounds__(kPlanTB) k_plan_shards(
+    const unsigned long long* __restrict__ hist, const int* __restrict__ order, int shard_bits,
+    int keybits, uint64_t leaf_target, uint64_t leaf_attempt, int tile,
+    unsigned long long* __restrict__ sbegin, unsigned long long* __restrict__ cursor,
+    SplitBin* __restrict__ bins, unsigned long long* __restrict__ item_off,
+    unsigned long long* __restrict__ subhist, DevState* __restrict__ st) {
+  __shared__ unsigned long long wsum[kPlanTB / 64];
+  const int nb = 1 << shard_bits;  // <= kPlanTB
+  const int t = threadIdx.x;
+  unsigned long long total;
+  // owner-major exclusive scan: the t-th shard in owner order
+  const int co = t < nb ? order[t] : 0;
+  const unsigned long long ho = t < nb ? hist[co] : 0ull;
+  const unsigned long long b0 = block_exscan<kPlanTB, unsigned long long>(ho, wsum, &total);
+  if (t < nb) {
+    sbegin[co] = b0;
+    cursor[co] = b0;
+  }
+  // split decision for shard t (key order)
+  const unsigned long long h = t < nb ? hist[t] : 0ull;
+  int nbits = 0;
+  const int remaining = keybits - shard_bits;
+  if (h > leaf_attempt && remaining > 0) {
+    nbits = ceil_log2_dev((h + leaf_target - 1) / leaf_target);
+    nbits = max(1, min(nbits, min(kSplitMaxBits, remaining)));
+  }
+  const unsigned long long L = h == 0 ? 0ull : (nbits ? (1ull << nbits) : 1ull);
+  const unsigned long long loff = block_exscan<kPlanTB, unsigned long long>(L, wsum, &total);
+  const unsigned long long n_leaves = total;
+  const unsigned long long ni = nbits ? (h + tile - 1) / tile : 0ull;
+  const unsigned long long ioff = block_exscan<kPlanTB, unsigned long long>(ni, wsum, &total);
+  const unsigned long long n_items = total;
+  if (t < nb) {
+    bins[t] = SplitBin{loff, (uint32_t)(keybits - shard_bits - nbits), (uint32_t)nbits};
+    item_off[t] = ioff;
+    if (!nbits && h) subhist[loff] = h;  // split shards' counters were cleared before
+  }
+  if (t == 0) {
+    item_off[nb] = n_items;
+    st->n_items = n_items;
+    st->n_leaves = n_leaves;
+  }
+}
+
+// Split work items: item i belongs to the shard c with item_off[c] <= i < item_off[c+1].
+__global__ void k_plan_items(const unsigned long long* __restrict__ hist,
+                             const unsigned long long* __restrict__ sbegin,
+                             const unsigned long long* __restrict__ item_off, int shard_bits,
+                             int tile, const DevState* __restrict__ st,
+                             SplitItem* __restrict__ items) {
+  const int nb = 1 << shard_bits;
+  const unsigned long long n = st->n_items;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    int lo = 0, hi = nb - 1;  // last c with item_off[c] <= i
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (item_off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const unsigned long long a = sbegin[lo] + (i - item_off[lo]) * (unsigned long long)tile;
+    items[i] = SplitItem{a, min(sbegin[lo] + hist[lo], a + (unsigned long long)tile), (uint32_t)lo, 0};
+  }
+}
+
+// Leaf table (key order) and sub-bin cursors: block c handles shard c.
+__global__ void __launch_bounds__(kPlanTB) k_plan_leaves(
+    const unsigned long long* __restrict__ hist, const unsigned long long* __restrict__ sbegin,
+    const SplitBin* __restrict__ bins, int shard_bits,
+    const unsigned long long* __restrict__ subhist, Leaf* __restrict__ leaves,
+    unsigned long long* __restrict__ cursor) {
+  __shared__ unsigned long long wsum[kPlanTB / 64];
+  const int c = blockIdx.x;
+  const unsigned long long h = hist[c];
+  if (!h) return;
+  const SplitBin b = bins[c];
+  if (b.nbits == 0) {
+    if (threadIdx.x == 0) leaves[b.hist_off] = Leaf{sbegin[c], sbegin[c] + h, 0u, (uint32_t)shard_bits};
+    return;
+  }
+  const uint32_t nsub = 1u << b.nbits;  // <= kPlanTB
+  const uint32_t j = threadIdx.x;
+  const unsigned long long n = j < nsub ? subhist[b.hist_off + j] : 0ull;
+  unsigned long long total;
+  const unsigned long long off = block_exscan<kPlanTB, unsigned long long>(n, wsum, &total);
+  if (j < nsub) {
+    const unsigned long long run = sbegin[c] + off;
+    leaves[b.hist_off + j] = Leaf{run, run + n, 1u, (uint32_t)(shard_bits + b.nbits)};
+    cursor[b.hist_off + j] = run;
+  }
+}
+
+// Leaves above the small-leaf size go to a list of their own (order irrelevant).
+__global__ void k_classify_leaves(const Leaf* __restrict__ leaves, DevState* __restrict__ st,
+                                  uint64_t small_max, uint32_t* __restrict__ large) {
+  const unsigned long long n = st->n_leaves;
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  for (unsigned long long i0 = (unsigned long long)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
+    const unsigned long long i = i0 + threadIdx.x;
+    const Leaf lf = i < n ? leaves[i] : Leaf{0, 0, 0, 0};
+    const bool big = lf.end - lf.begin > small_max;
+    const unsigned long long m = __ballot(big);
+    if (!m) continue;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(&st->n_large, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader);
+    if (big) large[base + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)i;
+  }
+}
+
+// Output offsets: exclusive scan of the leaf counts in leaf (= key) order, in
+// three steps (tile sums, scan of tile sums, tile scans). Overflowed leaves
+// count zero and raise st->overflow.
+constexpr int kScanTB = 256, kScanPer = 16, kScanTile = kScanTB * kScanPer;
+
+__global__ void __launch_bounds__(kScanTB) k_scan_reduce(const uint32_t* __restrict__ d,
+                                                         DevState* __restrict__ st,
+                                                         unsigned long long* __restrict__ bsum) {
+  __shared__ unsigned long long wsum[kScanTB / 64];
+  const unsigned long long n = st->n_leaves;
+  const unsigned long long base = (unsigned long long)blockIdx.x * kScanTile;
+  unsigned long long s = 0;
+  uint32_t ovf = 0;
+  for (int j = 0; j < kScanPer; ++j) {
+    const unsigned long long i = base + (unsigned long long)j * kScanTB + threadIdx.x;
+    if (i < n) {
+      const uint32_t x = d[i];
+      if (x == kLeafOverflow) ovf = 1;
+      else s += x;
+    }
+  }
+  if (ovf) atomicOr(&st->overflow, 1u);
+  unsigned long long total;
+  (void)block_exscan<kScanTB, unsigned long long>(s, wsum, &total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kPlanTB) k_scan_top(unsigned long long* __restrict__ bsum,
+                                                      uint32_t nblocks, DevState* __restrict__ st) {
+  __shared__ unsigned long long wsum[kPlanTB / 64];
+  const uint32_t per = (nblocks + kPlanTB - 1) / kPlanTB;
+  const uint32_t b = threadIdx.x * per, e = min(nblocks, b + per);
+  unsigned long long s = 0;
+  for (uint32_t i = b; i < e; ++i) s += bsum[i];
+  unsigned long long total;
+  unsigned long long run = block_exscan<kPlanTB, unsigned long long>(s, wsum, &total);
+  for (uint32_t i = b; i < e; ++i) {
+    const unsigned long long x = bsum[i];
+    bsum[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0) st->D = total;
+}
+
+__global__ void __launch_bounds__(kScanTB) k_scan_down(const uint32_t* __restrict__ d,
+                                                       const DevState* __restrict__ st,
+                                                       const unsigned long long* __restrict__ bsum,
+                                                       unsigned long long* __restrict__ out_off) {
+  __shared__ unsigned long long wsum[kScanTB / 64];
+  const unsigned long long n = st->n_leaves;
+  // thread t owns kScanPer consecutive leaves of the tile
+  const unsigned long long base = (unsigned long long)blockIdx.x * kScanTile +
+                                  (unsigned long long)threadIdx.x * kScanPer;
+  uint32_t v[kScanPer];
+  unsigned long long s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const unsigned long long i = base + j;
+    v[j] = i < n ? d[i] : 0u;
+    if (v[j] == kLeafOverflow) v[j] = 0;
+    s += v[j];
+  }
+  unsigned long long total;
+  unsigned long long run = bsum[blockIdx.x] + block_exscan<kScanTB, unsigned long long>(s, wsum, &total);
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const unsigned long long i = base + j;
+    if (i < n) out_off[i] = run;
+    run += v[j];
+  }
+}
+
 // ---------------------------------------------------------------- split (MSD step)
 
 template <typename K, int TB>
 __global__ void __launch_bounds__(TB) k_split_hist(const K* __restrict__ src,
                                                    const SplitItem* __restrict__ items,
+                                                   const DevState* __restrict__ st,
                                                    const SplitBin* __restrict__ bins,
                                                    unsigned long long* __restrict__ subhist) {
   __shared__ uint32_t h[1 << kSplitMaxBits];
-  const SplitItem it = items[blockIdx.x];
-  const SplitBin bn = bins[it.bin];
-  const int nsub = 1 << bn.nbits;
-  for (int i = threadIdx.x; i < nsub; i += TB) h[i] = 0;
-  __syncthreads();
-  for (uint64_t r = it.begin + threadIdx.x; r < it.end; r += TB)
-    atomicAdd(&h[Key<K>::bits(src[r], bn.shift, bn.nbits)], 1u);
-  __syncthreads();
-  for (int i = threadIdx.x; i < nsub; i += TB)
-    if (h[i]) atomicAdd(&subhist[bn.hist_off + i], (unsigned long long)h[i]);
+  const unsigned long long n_items = st->n_items;
+  for (unsigned long long w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const SplitItem it = items[w];
+    const SplitBin bn = bins[it.bin];
+    const int nsub = 1 << bn.nbits;
+    for (int i = threadIdx.x; i < nsub; i += TB) h[i] = 0;
+    __syncthreads();
+    for (uint64_t r = it.begin + threadIdx.x; r < it.end; r += TB)
+      atomicAdd(&h[Key<K>::bits(src[r], bn.shift, bn.nbits)], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nsub; i += TB)
+      if (h[i]) atomicAdd(&subhist[bn.hist_off + i], (unsigned long long)h[i]);
+    __syncthreads();
+  }
 }
 
 template <typename K, int TB, int R>
 __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
                                                       K* __restrict__ dst,
                                                       const SplitItem* __restrict__ items,
+                                                      const DevState* __restrict__ st,
                                                       const SplitBin* __restrict__ bins,
                                                       unsigned long long* __restrict__ cursor) {
   constexpr int NS = 1 << kSplitMaxBits;
   __shared__ K stage[TB * R];
-  __shared__ uint8_t ssub[TB * R];
+  __shared__ uint16_t ssub[TB * R];
   __shared__ uint32_t hist[NS];
   __shared__ uint32_t loff[NS];
   __shared__ unsigned long long gbase[NS];
-  __shared__ uint32_t scratch[TB];
-  const SplitItem it = items[blockIdx.x];
-  const SplitBin bn = bins[it.bin];
-  const int nsub = 1 << bn.nbits;
-  for (int i = threadIdx.x; i < nsub; i += TB) hist[i] = 0;
-  __syncthreads();
-  K key[R];
-  uint32_t sub[R], rank[R];
+  __shared__ uint32_t wsum[TB / 64];
+  const unsigned long long n_items = st->n_items;
+  for (unsigned long long w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const SplitItem it = items[w];
+    const SplitBin bn = bins[it.bin];
+    const int nsub = 1 << bn.nbits;
+    for (int i = threadIdx.x; i < nsub; i += TB) hist[i] = 0;
+    __syncthreads();
+    K key[R];
+    uint32_t sub[R], rank[R];
 #pragma unroll
-  for (int j = 0; j < R; ++j) {
-    const uint64_t r = it.begin + threadIdx.x + (uint64_t)j * TB;
-    if (r < it.end) {
-      key[j] = src[r];
-      sub[j] = Key<K>::bits(key[j], bn.shift, bn.nbits);
-      rank[j] = atomicAdd(&hist[sub[j]], 1u);
+    for (int j = 0; j < R; ++j) {
+      const uint64_t r = it.begin + threadIdx.x + (uint64_t)j * TB;
+      if (r < it.end) {
+        key[j] = src[r];
+        sub[j] = Key<K>::bits(key[j], bn.shift, bn.nbits);
+        rank[j] = atomicAdd(&hist[sub[j]], 1u);
+      }
     }
-  }
-  __syncthreads();
-  const uint32_t total = block_exscan_array<TB>(hist, loff, nsub, scratch);
-  for (int i = threadIdx.x; i < nsub; i += TB)
-    if (hist[i]) gbase[i] = atomicAdd(&cursor[bn.hist_off + i], (unsigned long long)hist[i]);
+    __syncthreads();
+    const uint32_t total = block_exscan_array<TB>(hist, loff, nsub, wsum);
+    for (int i = threadIdx.x; i < nsub; i += TB)
+      if (hist[i]) gbase[i] = atomicAdd(&cursor[bn.hist_off + i], (unsigned long long)hist[i]);
 #pragma unroll
-  for (int j = 0; j < R; ++j) {
-    const uint64_t r = it.begin + threadIdx.x + (uint64_t)j * TB;
-    if (r < it.end) {
-      const uint32_t p = loff[sub[j]] + rank[j];
-      stage[p] = key[j];
-      ssub[p] = (uint8_t)sub[j];
+    for (int j = 0; j < R; ++j) {
+      const uint64_t r = it.begin + threadIdx.x + (uint64_t)j * TB;
+      if (r < it.end) {
+        const uint32_t p = loff[sub[j]] + rank[j];
+        stage[p] = key[j];
+        ssub[p] = (uint16_t)sub[j];
+      }
     }
-  }
-  __syncthreads();
-  for (uint32_t j = threadIdx.x; j < total; j += TB) {
-    const uint32_t b = ssub[j];
-    dst[gbase[b] + (j - loff[b])] = stage[j];
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < total; j += TB) {
+      const uint32_t b = ssub[j];
+      dst[gbase[b] + (j - loff[b])] = stage[j];
+    }
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- leaf count
 
-// Bitonic sort of (keys, counts) in LDS, n a power of two.
+// Bitonic sort of (keys, counts) in LDS, n a power of two (fallback sort).
 template <typename K, typename C, int TB>
 __device__ __forceinline__ void bitonic_sort(K* keys, C* cnt, uint32_t n) {
   for (uint32_t size = 2; size <= n; size <<= 1) {
@@ -453,212 +684,326 @@ __device__ __forceinline__ void bitonic_sort(K* keys, C* cnt, uint32_t n) {
   }
 }
 
+// Workgroup-scope flag in LDS (a volatile LDS variable would be accessed with
+// flat instructions that also wait for all outstanding global memory operations).
+__device__ __forceinline__ uint32_t ovf_get(uint32_t* f) {
+  return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void ovf_set(uint32_t* f) {
+  __hip_atomic_store(f, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ uint32_t next_pow2(uint32_t x) {
   return x <= 2 ? 2u : 1u << (32 - __builtin_clz(x - 1));
 }
 
-// 64-bit keys: EMPTY (all ones) is never a canonical key for k <= 32, so a
-// slot is claimed by a 64-bit CAS of the key word itself.
+// Table slots for a leaf of n records: enough that n distinct keys stay below
+// 7/8 load, at least TB, at most CMAX.
 template <int TB, int CMAX>
-__global__ void __launch_bounds__(TB) k_leaf_count64(uint64_t* bufA, uint64_t* bufB,
+__device__ __forceinline__ uint32_t leaf_slots(uint64_t n, uint32_t cmax_rt) {
+  const uint64_t want = n + n / 7 + 1;
+  uint32_t c = want >= cmax_rt ? cmax_rt : next_pow2((uint32_t)want);
+  return c < (uint32_t)TB ? (uint32_t)TB : c;
+}
+
+// Epilogue shared by both key widths: the table (tk, tc) has been filled with
+// Cn slots. The distinct keys are grouped by a counting sort on the key bits
+// just below the leaf's common prefix; each key then finds its place inside
+// its group by counting the smaller keys of the group, and the pair is written
+// to dst/tmp_cnt at [begin, begin + d) in key order. Keys of one group share a
+// long prefix when sequencing errors sit near the k-mer's end (the erroneous
+// copies of one k-mer), so groups are not always tiny; a group larger than
+// kRankMax switches the leaf to a bitonic sort. Returns d.
+constexpr uint32_t kRankMax = 256;
+
+template <typename K, typename C, int TB, int PER>
+__device__ __forceinline__ uint32_t leaf_sort_write(K* tk, C* tc, uint32_t* aux, uint32_t* wsum,
+                                                    uint32_t* s_max, uint32_t Cn, int keybits,
+                                                    int prefix_bits, K* __restrict__ dst,
+                                                    uint32_t* __restrict__ tmp_cnt,
+                                                    uint64_t begin, bool (*occupied)(C)) {
+  K rk[PER];
+  C rc[PER];
+  uint32_t rank[PER], bk[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {  // slot j*TB + tid: consecutive lanes, consecutive slots
+    const uint32_t s = (uint32_t)j * TB + threadIdx.x;
+    rc[j] = 0;
+    if (s < Cn) {
+      rk[j] = tk[s];
+      rc[j] = tc[s];
+    }
+  }
+  int nbk_bits = 31 - __builtin_clz(Cn) - 1;  // Cn/2 groups
+  if (nbk_bits > keybits - prefix_bits) nbk_bits = keybits - prefix_bits;
+  const uint32_t nbk = 1u << nbk_bits;
+  const int shift = keybits - prefix_bits - nbk_bits;
+  for (uint32_t i = threadIdx.x; i < nbk; i += TB) aux[i] = 0;
+  if (threadIdx.x == 0) *s_max = 0;
+  __syncthreads();  // table copied to registers; group counters cleared
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    if (occupied(rc[j])) {
+      bk[j] = nbk_bits ? Key<K>::bits(rk[j], shift, nbk_bits) : 0u;
+      rank[j] = atomicAdd(&aux[bk[j]], 1u);
+    }
+  }
+  __syncthreads();
+  const uint32_t d = block_exscan_array<TB>(aux, aux + nbk, (int)nbk, wsum, s_max);
+  const uint32_t maxb = *s_max;
+  const uint32_t* boff = aux + nbk;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    if (occupied(rc[j])) {
+      const uint32_t p = boff[bk[j]] + rank[j];
+      tk[p] = rk[j];
+      tc[p] = rc[j];
+    }
+  }
+  __syncthreads();
+  if (maxb <= kRankMax) {
+    for (uint32_t i = threadIdx.x; i < d; i += TB) {
+      const K x = tk[i];
+      const uint32_t b = nbk_bits ? Key<K>::bits(x, shift, nbk_bits) : 0u;
+      const uint32_t a = boff[b], m = aux[b];
+      uint32_t r = 0;
+      for (uint32_t t = a; t < a + m; ++t) r += tk[t] < x;
+      dst[begin + a + r] = x;
+      tmp_cnt[begin + a + r] = (uint32_t)tc[i];
+    }
+    return d;
+  }
+  const uint32_t n2 = next_pow2(d);
+  for (uint32_t i = d + threadIdx.x; i < n2; i += TB) {
+    tk[i] = ~(K)0;
+    tc[i] = 0;
+  }
+  __syncthreads();
+  bitonic_sort<K, C, TB>(tk, tc, n2);
+  for (uint32_t i = threadIdx.x; i < d; i += TB) {
+    dst[begin + i] = tk[i];
+    tmp_cnt[begin + i] = (uint32_t)tc[i];
+  }
+  return d;
+}
+
+__device__ bool occ32(uint32_t c) { return c != 0; }
+__device__ bool occ64(unsigned long long c) { return c != 0; }
+
+// 64-bit keys: EMPTY (all ones) is never a canonical key for k <= 32, so a
+// slot is claimed by a 64-bit CAS of the key word itself; the count is then
+// added with an atomic add.
+template <int TB, int CMAX, int R>
+__global__ void __launch_bounds__(TB) k_leaf_count64(int k, uint64_t* bufA, uint64_t* bufB,
                                                      uint32_t* __restrict__ tmp_cnt,
                                                      const Leaf* __restrict__ leaves,
+                                                     DevState* __restrict__ st,
                                                      uint32_t* __restrict__ d_out,
-                                                     int slots_log2) {
+                                                     int slots_log2,
+                                                     const uint32_t* __restrict__ list,
+                                                     uint64_t small_max) {
   __shared__ unsigned long long tk[CMAX];
   __shared__ uint32_t tc[CMAX];
-  __shared__ uint32_t scratch[TB];
-  __shared__ uint32_t s_nd;
-  __shared__ volatile uint32_t s_ovf;
-  const uint32_t C = 1u << slots_log2;
-  const uint32_t cmask = C - 1;
-  const Leaf lf = leaves[blockIdx.x];
-  const uint64_t* src = lf.buf ? bufB : bufA;
-  uint64_t* dst = lf.buf ? bufA : bufB;
+  __shared__ uint32_t aux[CMAX];
+  __shared__ uint32_t wsum[TB / 64];
+  __shared__ uint32_t s_nd, s_max;
+  __shared__ uint32_t s_ovf;  // accessed only through ovf_get / ovf_set
   const unsigned long long EMPTY = ~0ull;
-  for (uint32_t i = threadIdx.x; i < C; i += TB) {
-    tk[i] = EMPTY;
-    tc[i] = 0;
-  }
-  if (threadIdx.x == 0) {
-    s_nd = 0;
-    s_ovf = 0;
-  }
-  __syncthreads();
-  const uint32_t limit = C - (C >> 3);
-  for (uint64_t r = lf.begin + threadIdx.x; r < lf.end; r += TB) {
-    if (s_ovf) break;
-    const unsigned long long key = src[r];
-    uint32_t pos = (uint32_t)fmix64(key) & cmask;
-    bool done = false;
-    for (uint32_t probe = 0; probe < C; ++probe) {
-      const unsigned long long prev = atomicCAS(&tk[pos], EMPTY, key);
-      if (prev == EMPTY) {
-        atomicAdd(&tc[pos], 1u);
-        if (atomicAdd(&s_nd, 1u) + 1 >= limit) s_ovf = 1;
-        done = true;
-        break;
-      }
-      if (prev == key) {
-        atomicAdd(&tc[pos], 1u);
-        done = true;
-        break;
-      }
-      pos = (pos + 1) & cmask;
+  const uint32_t cmax_rt = 1u << slots_log2;
+  // list != nullptr: the leaves listed there (large ones); else every leaf of
+  // at most small_max records.
+  const unsigned long long count = list ? st->n_large : st->n_leaves;
+  for (unsigned long long it = blockIdx.x; it < count; it += gridDim.x) {
+    const unsigned long long l = list ? (unsigned long long)list[it] : it;
+    const Leaf lf = leaves[l];
+    const uint64_t n = lf.end - lf.begin;
+    if (n == 0) {
+      if (threadIdx.x == 0) d_out[l] = 0;
+      continue;
     }
-    if (!done) s_ovf = 1;
-  }
-  __syncthreads();
-  if (s_ovf) {
-    if (threadIdx.x == 0) d_out[blockIdx.x] = 0xFFFFFFFFu;
-    return;
-  }
-  // compaction to the front of the table (in place, via registers)
-  constexpr int PER = CMAX / TB;
-  const uint32_t per = C / TB;
-  unsigned long long rk[PER];
-  uint32_t rc[PER];
-  uint32_t mine = 0;
+    if (!list && n > small_max) continue;
+    const uint64_t* src = lf.buf ? bufB : bufA;
+    uint64_t* dst = lf.buf ? bufA : bufB;
+    const uint32_t Cn = leaf_slots<TB, CMAX>(n, cmax_rt);
+    const uint32_t cmask = Cn - 1;
+    for (uint32_t i = threadIdx.x; i < Cn; i += TB) {
+      tk[i] = EMPTY;
+      tc[i] = 0;
+    }
+    if (threadIdx.x == 0) {
+      s_nd = 0;
+      __hip_atomic_store(&s_ovf, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    const uint32_t limit = Cn - (Cn >> 3);
+    const bool track = n >= limit;  // fewer records than the limit cannot overflow
+    // records are loaded R per thread before inserting, so that the loads of a
+    // batch are in flight together instead of one round trip per insert
+    for (uint64_t base = lf.begin; base < lf.end; base += (uint64_t)TB * R) {
+      if (ovf_get(&s_ovf)) break;
+      unsigned long long kb[R];
 #pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    if ((uint32_t)j < per) {
-      rk[j] = tk[threadIdx.x * per + j];
-      rc[j] = tc[threadIdx.x * per + j];
-      mine += rk[j] != EMPTY;
-    }
-  }
-  uint32_t d;
-  uint32_t base = block_exscan<TB>(mine, scratch, &d);
+      for (int j = 0; j < R; ++j) {
+        const uint64_t r = base + (uint64_t)j * TB + threadIdx.x;
+        kb[j] = r < lf.end ? src[r] : EMPTY;
+      }
 #pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    if ((uint32_t)j < per && rk[j] != EMPTY) {
-      tk[base] = rk[j];
-      tc[base] = rc[j];
-      ++base;
+      for (int j = 0; j < R; ++j) {
+        const unsigned long long key = kb[j];
+        if (key == EMPTY) continue;
+        uint32_t pos = (uint32_t)fmix64(key) & cmask;
+        bool done = false;
+        for (uint32_t probe = 0; probe < Cn; ++probe) {
+          unsigned long long cur = tk[pos];
+          if (cur == EMPTY) {
+            cur = atomicCAS(&tk[pos], EMPTY, key);
+            if (cur == EMPTY) {
+              atomicAdd(&tc[pos], 1u);
+              if (track && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
+              done = true;
+              break;
+            }
+          }
+          if (cur == key) {
+            atomicAdd(&tc[pos], 1u);
+            done = true;
+            break;
+          }
+          pos = (pos + 1) & cmask;
+        }
+        if (!done) ovf_set(&s_ovf);
+      }
     }
+    __syncthreads();
+    if (ovf_get(&s_ovf)) {
+      if (threadIdx.x == 0) {
+        d_out[l] = kLeafOverflow;
+        atomicOr(&st->overflow, 1u);
+      }
+      __syncthreads();
+      continue;
+    }
+    const uint32_t d = leaf_sort_write<unsigned long long, uint32_t, TB, CMAX / TB>(
+        tk, tc, aux, wsum, &s_max, Cn, 2 * k, (int)lf.bits, (unsigned long long*)dst, tmp_cnt,
+        lf.begin, occ32);
+    if (threadIdx.x == 0) d_out[l] = d;
+    __syncthreads();
   }
-  __syncthreads();
-  const uint32_t n = next_pow2(d);
-  for (uint32_t i = d + threadIdx.x; i < n; i += TB) {
-    tk[i] = EMPTY;
-    tc[i] = 0;
-  }
-  __syncthreads();
-  bitonic_sort<unsigned long long, uint32_t, TB>(tk, tc, n);
-  for (uint32_t i = threadIdx.x; i < d; i += TB) {
-    dst[lf.begin + i] = tk[i];
-    tmp_cnt[lf.begin + i] = tc[i];
-  }
-  if (threadIdx.x == 0) d_out[blockIdx.x] = d;
 }
 
 // 128-bit keys: no 128-bit CAS, so a slot is claimed through its count word:
 // 0 = empty, LOCK = being written; the claimer writes the key and then
 // publishes the count. Others seeing LOCK retry the same slot; the claimer
 // publishes in the same pass without waiting on anyone, so the retry ends.
-template <int TB, int CMAX>
-__global__ void __launch_bounds__(TB) k_leaf_count128(u128* bufA, u128* bufB,
+template <int TB, int CMAX, int R>
+__global__ void __launch_bounds__(TB) k_leaf_count128(int k, u128* bufA, u128* bufB,
                                                       uint32_t* __restrict__ tmp_cnt,
                                                       const Leaf* __restrict__ leaves,
+                                                      DevState* __restrict__ st,
                                                       uint32_t* __restrict__ d_out,
                                                       int slots_log2,
-                                                      unsigned int* __restrict__ count_overflow) {
+                                                      const uint32_t* __restrict__ list,
+                                                      uint64_t small_max) {
   __shared__ u128 tk[CMAX];
   __shared__ unsigned long long tc[CMAX];
-  __shared__ uint32_t scratch[TB];
-  __shared__ uint32_t s_nd;
-  __shared__ volatile uint32_t s_ovf;
-  const uint32_t C = 1u << slots_log2;
-  const uint32_t cmask = C - 1;
-  const Leaf lf = leaves[blockIdx.x];
-  const u128* src = lf.buf ? bufB : bufA;
-  u128* dst = lf.buf ? bufA : bufB;
+  __shared__ uint32_t aux[CMAX];
+  __shared__ uint32_t wsum[TB / 64];
+  __shared__ uint32_t s_nd, s_max, s_cov;
+  __shared__ uint32_t s_ovf;  // accessed only through ovf_get / ovf_set
   const unsigned long long LOCK = 1ull << 63;
-  for (uint32_t i = threadIdx.x; i < C; i += TB) tc[i] = 0;
-  if (threadIdx.x == 0) {
-    s_nd = 0;
-    s_ovf = 0;
-  }
-  __syncthreads();
-  const uint32_t limit = C - (C >> 3);
-  for (uint64_t r = lf.begin + threadIdx.x; r < lf.end; r += TB) {
-    if (s_ovf) break;
-    const u128 key = src[r];
-    uint32_t pos = (uint32_t)Key<u128>::hash(key) & cmask;
-    uint32_t probe = 0, spins = 0;
-    bool done = false;
-    while (probe < C) {
-      unsigned long long c =
-          __hip_atomic_load(&tc[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (c == 0) {
-        unsigned long long expect = 0;
-        if (__hip_atomic_compare_exchange_strong(&tc[pos], &expect, LOCK, __ATOMIC_ACQ_REL,
-                                                 __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-          tk[pos] = key;
-          __hip_atomic_store(&tc[pos], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-          if (atomicAdd(&s_nd, 1u) + 1 >= limit) s_ovf = 1;
+  const uint32_t cmax_rt = 1u << slots_log2;
+  // list != nullptr: the leaves listed there (large ones); else every leaf of
+  // at most small_max records.
+  const unsigned long long count = list ? st->n_large : st->n_leaves;
+  for (unsigned long long it = blockIdx.x; it < count; it += gridDim.x) {
+    const unsigned long long l = list ? (unsigned long long)list[it] : it;
+    const Leaf lf = leaves[l];
+    const uint64_t n = lf.end - lf.begin;
+    if (n == 0) {
+      if (threadIdx.x == 0) d_out[l] = 0;
+      continue;
+    }
+    if (!list && n > small_max) continue;
+    const u128* src = lf.buf ? bufB : bufA;
+    u128* dst = lf.buf ? bufA : bufB;
+    const uint32_t Cn = leaf_slots<TB, CMAX>(n, cmax_rt);
+    const uint32_t cmask = Cn - 1;
+    for (uint32_t i = threadIdx.x; i < Cn; i += TB) tc[i] = 0;
+    if (threadIdx.x == 0) {
+      s_nd = 0;
+      __hip_atomic_store(&s_ovf, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      s_cov = 0;
+    }
+    __syncthreads();
+    const uint32_t limit = Cn - (Cn >> 3);
+    const bool track = n >= limit;  // fewer records than the limit cannot overflow
+    for (uint64_t base = lf.begin; base < lf.end; base += (uint64_t)TB * R) {
+      if (ovf_get(&s_ovf)) break;
+      u128 kb[R];
+      bool kv[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const uint64_t r = base + (uint64_t)j * TB + threadIdx.x;
+        kv[j] = r < lf.end;
+        kb[j] = kv[j] ? src[r] : (u128)0;
+      }
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+      if (!kv[j]) continue;
+      const u128 key = kb[j];
+      uint32_t pos = (uint32_t)Key<u128>::hash(key) & cmask;
+      uint32_t probe = 0, spins = 0;
+      bool done = false;
+      while (probe < Cn) {
+        unsigned long long c =
+            __hip_atomic_load(&tc[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (c == 0) {
+          unsigned long long expect = 0;
+          if (__hip_atomic_compare_exchange_strong(&tc[pos], &expect, LOCK, __ATOMIC_ACQ_REL,
+                                                   __ATOMIC_ACQUIRE,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            tk[pos] = key;
+            __hip_atomic_store(&tc[pos], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (track && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
+            done = true;
+            break;
+          }
+          c = expect;
+        }
+        if (c == LOCK) {
+          if (++spins > (1u << 22)) break;  // cannot happen; guards against a hang
+          continue;
+        }
+        if (tk[pos] == key) {
+          __hip_atomic_fetch_add(&tc[pos], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           done = true;
           break;
         }
-        c = expect;
+        pos = (pos + 1) & cmask;
+        ++probe;
       }
-      if (c == LOCK) {
-        if (++spins > (1u << 22)) break;  // cannot happen; guards against a hang
-        continue;
+      if (!done) ovf_set(&s_ovf);
       }
-      if (tk[pos] == key) {
-        __hip_atomic_fetch_add(&tc[pos], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        done = true;
-        break;
+    }
+    __syncthreads();
+    if (ovf_get(&s_ovf)) {
+      if (threadIdx.x == 0) {
+        d_out[l] = kLeafOverflow;
+        atomicOr(&st->overflow, 1u);
       }
-      pos = (pos + 1) & cmask;
-      ++probe;
+      __syncthreads();
+      continue;
     }
-    if (!done) s_ovf = 1;
-  }
-  __syncthreads();
-  if (s_ovf) {
-    if (threadIdx.x == 0) d_out[blockIdx.x] = 0xFFFFFFFFu;
-    return;
-  }
-  constexpr int PER = CMAX / TB;
-  const uint32_t per = C / TB;
-  u128 rk[PER];
-  unsigned long long rc[PER];
-  uint32_t mine = 0;
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    if ((uint32_t)j < per) {
-      rc[j] = tc[threadIdx.x * per + j];
-      rk[j] = tk[threadIdx.x * per + j];
-      mine += rc[j] != 0;
+    for (uint32_t i = threadIdx.x; i < Cn; i += TB)
+      if (tc[i] > 0xFFFFFFFFull) s_cov = 1;
+    const uint32_t d = leaf_sort_write<u128, unsigned long long, TB, CMAX / TB>(
+        tk, tc, aux, wsum, &s_max, Cn, 2 * k, (int)lf.bits, dst, tmp_cnt, lf.begin, occ64);
+    if (threadIdx.x == 0) {
+      d_out[l] = d;
+      if (s_cov) atomicOr(&st->count_overflow, 1u);
     }
+    __syncthreads();
   }
-  uint32_t d;
-  uint32_t base = block_exscan<TB>(mine, scratch, &d);
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    if ((uint32_t)j < per && rc[j] != 0) {
-      tk[base] = rk[j];
-      tc[base] = rc[j];
-      ++base;
-    }
-  }
-  __syncthreads();
-  const uint32_t n = next_pow2(d);
-  for (uint32_t i = d + threadIdx.x; i < n; i += TB) {
-    tk[i] = ~(u128)0;
-    tc[i] = 0;
-  }
-  __syncthreads();
-  bitonic_sort<u128, unsigned long long, TB>(tk, tc, n);
-  for (uint32_t i = threadIdx.x; i < d; i += TB) {
-    dst[lf.begin + i] = tk[i];
-    const unsigned long long c = tc[i];
-    if (c > 0xFFFFFFFFull) atomicOr(count_overflow, 1u);
-    tmp_cnt[lf.begin + i] = (uint32_t)c;
-  }
-  if (threadIdx.x == 0) d_out[blockIdx.x] = d;
 }
 
 // ---------------------------------------------------------------- concat + check
@@ -669,21 +1014,33 @@ __global__ void __launch_bounds__(256) k_concat(const K* __restrict__ bufA,
                                                 const uint32_t* __restrict__ tmp_cnt,
                                                 const Leaf* __restrict__ leaves,
                                                 const uint32_t* __restrict__ d,
+                                                const unsigned long long* __restrict__ out_off,
+                                                const DevState* __restrict__ st, uint64_t cap,
                                                 uint64_t* __restrict__ out_keys,
                                                 uint32_t* __restrict__ out_counts) {
-  const Leaf lf = leaves[blockIdx.x];
-  const K* src = lf.buf ? bufA : bufB;  // sorted pairs sit in the other buffer
-  const uint32_t n = d[blockIdx.x];
-  for (uint32_t i = threadIdx.x; i < n; i += 256) {
-    const K key = src[lf.begin + i];
-    const uint64_t o = lf.out_off + i;
-    if (Key<K>::kWide) {
-      out_keys[2 * o] = (uint64_t)key;
-      out_keys[2 * o + 1] = (uint64_t)((u128)key >> 64);
-    } else {
-      out_keys[o] = (uint64_t)key;
+  // one wave per leaf, many leaves in flight per CU
+  const unsigned long long n_leaves = st->n_leaves;
+  const unsigned lane = threadIdx.x & 63;
+  const unsigned long long nw = (unsigned long long)gridDim.x * 4;
+  for (unsigned long long l = (unsigned long long)blockIdx.x * 4 + (threadIdx.x >> 6); l < n_leaves;
+       l += nw) {
+    const uint32_t n = d[l];
+    if (n == 0 || n == kLeafOverflow) continue;
+    const Leaf lf = leaves[l];
+    const K* src = lf.buf ? bufA : bufB;  // sorted pairs sit in the other buffer
+    const unsigned long long base = out_off[l];
+    for (uint32_t i = lane; i < n; i += 64) {
+      const uint64_t o = base + i;
+      if (o >= cap) break;
+      const K key = src[lf.begin + i];
+      if (Key<K>::kWide) {
+        out_keys[2 * o] = (uint64_t)key;
+        out_keys[2 * o + 1] = (uint64_t)((u128)key >> 64);
+      } else {
+        out_keys[o] = (uint64_t)key;
+      }
+      out_counts[o] = tmp_cnt[lf.begin + i];
     }
-    out_counts[o] = tmp_cnt[lf.begin + i];
   }
 }
 
@@ -733,6 +1090,10 @@ constexpr int kSplitR = 8;
 constexpr int kLeafTB = 1024;
 constexpr int kLeafCmax64 = 8192;
 constexpr int kLeafCmax128 = 4096;
+constexpr unsigned kPersistentGrid = 1024;  // blocks of the persistent kernels
+constexpr int kSmallCmax64 = 1024;  // one-wave leaf kernel: slots of its private table
+constexpr int kSmallCmax128 = 512;
+constexpr unsigned kSmallGrid = 256 * 20;
 
 inline unsigned grid_for(uint64_t n, unsigned tb, unsigned cap) {
   uint64_t g = (n + tb - 1) / tb;
@@ -740,10 +1101,22 @@ inline unsigned grid_for(uint64_t n, unsigned tb, unsigned cap) {
   return g ? (unsigned)g : 1u;
 }
 
+inline unsigned persistent(uint64_t max_n, unsigned cap) {
+  return (unsigned)(max_n == 0 ? 1 : (max_n < cap ? max_n : cap));
+}
+
 }  // namespace
 
 int max_leaf_slots_log2(bool wide) { return wide ? 12 : 13; }
 int max_shard_bits() { return kMaxShardBits; }
+int split_tile(bool wide) { return wide ? kSplitTB128 * kSplitR : kSplitTB64 * kSplitR; }
+
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v,
+                           hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_pack(const uint8_t* src, uint64_t n_bytes, const uint64_t* offsets,
                        uint64_t n_reads, uint64_t off0, uint64_t* packed, uint64_t* inv,
@@ -788,61 +1161,116 @@ hipError_t launch_window_scatter(bool wide, const uint64_t* packed, const uint64
   return hipGetLastError();
 }
 
-int split_tile(bool wide) { return wide ? kSplitTB128 * kSplitR : kSplitTB64 * kSplitR; }
+hipError_t launch_plan_shards(const unsigned long long* hist, const int* order, int shard_bits,
+                              int keybits, uint64_t leaf_target, uint64_t leaf_attempt,
+                              int tile, unsigned long long* sbegin, unsigned long long* cursor,
+                              SplitBin* bins, SplitItem* items, unsigned long long* item_off,
+                              unsigned long long* subhist, uint64_t max_leaves,
+                              uint64_t max_items, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(max_leaves, 256, 1024)), dim3(256), 0, s, subhist,
+                     max_leaves, 0ull);
+  hipLaunchKernelGGL(k_plan_shards, dim3(1), dim3(kPlanTB), 0, s, hist, order, shard_bits,
+                     keybits, leaf_target, leaf_attempt, tile, sbegin, cursor, bins, item_off,
+                     subhist, st);
+  hipLaunchKernelGGL(k_plan_items, dim3(grid_for(max_items, 256, 2048)), dim3(256), 0, s, hist,
+                     sbegin, item_off, shard_bits, tile, st, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_leaves(const unsigned long long* hist, const unsigned long long* sbegin,
+                              const SplitBin* bins, int shard_bits,
+                              const unsigned long long* subhist, Leaf* leaves,
+                              unsigned long long* cursor, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan_leaves, dim3(1u << shard_bits), dim3(kPlanTB), 0, s, hist, sbegin,
+                     bins, shard_bits, subhist, leaves, cursor);
+  return hipGetLastError();
+}
 
 hipError_t launch_split_hist(bool wide, const void* src, const SplitItem* items,
-                             uint64_t n_items, const SplitBin* bins,
+                             const DevState* st, uint64_t max_items, const SplitBin* bins,
                              unsigned long long* subhist, hipStream_t s) {
-  if (!n_items) return hipSuccess;
+  const unsigned grid = persistent(max_items, 4096);
   if (wide)
-    hipLaunchKernelGGL((k_split_hist<u128, 256>), dim3((unsigned)n_items), dim3(256), 0, s,
-                       (const u128*)src, items, bins, subhist);
+    hipLaunchKernelGGL((k_split_hist<u128, 256>), dim3(grid), dim3(256), 0, s, (const u128*)src,
+                       items, st, bins, subhist);
   else
-    hipLaunchKernelGGL((k_split_hist<uint64_t, 256>), dim3((unsigned)n_items), dim3(256), 0, s,
-                       (const uint64_t*)src, items, bins, subhist);
+    hipLaunchKernelGGL((k_split_hist<uint64_t, 256>), dim3(grid), dim3(256), 0, s,
+                       (const uint64_t*)src, items, st, bins, subhist);
   return hipGetLastError();
 }
 
 hipError_t launch_split_scatter(bool wide, const void* src, void* dst, const SplitItem* items,
-                                uint64_t n_items, const SplitBin* bins,
+                                const DevState* st, uint64_t max_items, const SplitBin* bins,
                                 unsigned long long* cursor, hipStream_t s) {
-  if (!n_items) return hipSuccess;
+  const unsigned grid = persistent(max_items, 2048);
   if (wide)
-    hipLaunchKernelGGL((k_split_scatter<u128, kSplitTB128, kSplitR>), dim3((unsigned)n_items),
-                       dim3(kSplitTB128), 0, s, (const u128*)src, (u128*)dst, items, bins, cursor);
-  else
-    hipLaunchKernelGGL((k_split_scatter<uint64_t, kSplitTB64, kSplitR>), dim3((unsigned)n_items),
-                       dim3(kSplitTB64), 0, s, (const uint64_t*)src, (uint64_t*)dst, items, bins,
+    hipLaunchKernelGGL((k_split_scatter<u128, kSplitTB128, kSplitR>), dim3(grid),
+                       dim3(kSplitTB128), 0, s, (const u128*)src, (u128*)dst, items, st, bins,
                        cursor);
+  else
+    hipLaunchKernelGGL((k_split_scatter<uint64_t, kSplitTB64, kSplitR>), dim3(grid),
+                       dim3(kSplitTB64), 0, s, (const uint64_t*)src, (uint64_t*)dst, items, st,
+                       bins, cursor);
   return hipGetLastError();
 }
 
-hipError_t launch_leaf_count(bool wide, void* bufA, void* bufB, uint32_t* tmp_cnt,
-                             const Leaf* leaves, uint64_t n_leaves, uint32_t* d_out,
-                             int slots_log2, unsigned int* count_overflow, hipStream_t s) {
-  if (!n_leaves) return hipSuccess;
-  if (wide)
-    hipLaunchKernelGGL((k_leaf_count128<kLeafTB, kLeafCmax128>), dim3((unsigned)n_leaves),
-                       dim3(kLeafTB), 0, s, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, d_out,
-                       slots_log2, count_overflow);
-  else
-    hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64>), dim3((unsigned)n_leaves),
-                       dim3(kLeafTB), 0, s, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves,
-                       d_out, slots_log2);
+uint64_t small_leaf_max(bool wide) {
+  // n + n/7 + 1 <= slots of the one-wave kernel
+  return wide ? 447 : 895;
+}
+
+hipError_t launch_leaf_count(bool wide, int k, void* bufA, void* bufB, uint32_t* tmp_cnt,
+                             const Leaf* leaves, DevState* st, uint64_t max_leaves,
+                             uint32_t* d_out, int slots_log2, uint32_t* large_list,
+                             hipStream_t s) {
+  const uint64_t small_max = small_leaf_max(wide);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &st->n_large, (uint64_t)1, 0ull);
+  hipLaunchKernelGGL(k_classify_leaves, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s,
+                     leaves, st, small_max, large_list);
+  const unsigned gsmall = persistent(max_leaves, kSmallGrid);
+  const unsigned glarge = persistent(max_leaves, kPersistentGrid);
+  if (wide) {
+    hipLaunchKernelGGL((k_leaf_count128<64, kSmallCmax128, 8>), dim3(gsmall), dim3(64), 0, s, k,
+                       (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
+                       __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max);
+    hipLaunchKernelGGL((k_leaf_count128<kLeafTB, kLeafCmax128, 4>), dim3(glarge), dim3(kLeafTB), 0,
+                       s, k, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out, slots_log2,
+                       (const uint32_t*)large_list, small_max);
+  } else {
+    hipLaunchKernelGGL((k_leaf_count64<64, kSmallCmax64, 8>), dim3(gsmall), dim3(64), 0, s, k,
+                       (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
+                       __builtin_ctz(kSmallCmax64), (const uint32_t*)nullptr, small_max);
+    hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4>), dim3(glarge), dim3(kLeafTB), 0,
+                       s, k, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
+                       slots_log2, (const uint32_t*)large_list, small_max);
+  }
+  return hipGetLastError();
+}
+
+uint64_t scan_blocks(uint64_t max_leaves) { return (max_leaves + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_plan_out(const uint32_t* d, DevState* st, unsigned long long* bsum,
+                           uint64_t max_leaves, unsigned long long* out_off, hipStream_t s) {
+  const uint64_t nb = scan_blocks(max_leaves);
+  if (nb > 65536u * kPlanTB) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanTB), 0, s, d, st, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kPlanTB), 0, s, bsum, (uint32_t)nb, st);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanTB), 0, s, d, st, bsum, out_off);
   return hipGetLastError();
 }
 
 hipError_t launch_concat(bool wide, const void* bufA, const void* bufB, const uint32_t* tmp_cnt,
-                         const Leaf* leaves, const uint32_t* d, uint64_t n_leaves,
+                         const Leaf* leaves, const uint32_t* d, const unsigned long long* out_off,
+                         const DevState* st, uint64_t max_leaves, uint64_t cap,
                          uint64_t* out_keys, uint32_t* out_counts, hipStream_t s) {
-  if (!n_leaves) return hipSuccess;
+  const unsigned grid = persistent((max_leaves + 3) / 4, 16384);
   if (wide)
-    hipLaunchKernelGGL(k_concat<u128>, dim3((unsigned)n_leaves), dim3(256), 0, s,
-                       (const u128*)bufA, (const u128*)bufB, tmp_cnt, leaves, d, out_keys,
+    hipLaunchKernelGGL(k_concat<u128>, dim3(grid), dim3(256), 0, s, (const u128*)bufA,
+                       (const u128*)bufB, tmp_cnt, leaves, d, out_off, st, cap, out_keys,
                        out_counts);
   else
-    hipLaunchKernelGGL(k_concat<uint64_t>, dim3((unsigned)n_leaves), dim3(256), 0, s,
-                       (const uint64_t*)bufA, (const uint64_t*)bufB, tmp_cnt, leaves, d, out_keys,
+    hipLaunchKernelGGL(k_concat<uint64_t>, dim3(grid), dim3(256), 0, s, (const uint64_t*)bufA,
+                       (const uint64_t*)bufB, tmp_cnt, leaves, d, out_off, st, cap, out_keys,
                        out_counts);
   return hipGetLastError();
 }

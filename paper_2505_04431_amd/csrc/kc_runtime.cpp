@@ -31,7 +31,10 @@ struct DevBuf {
 struct Ctx {
   int device = -1;
   DevBuf packed, inv, endm, bufA, bufB, tmpcnt;
-  DevBuf hist, wcount, cursor, items, bins, subhist, leaves, dcnt, flags, check;
+  DevBuf hist, sbegin, cursor, cursor2, order, items, bins, subhist, leaves, dcnt, outoff, state;
+  DevBuf large, bsum, itemoff;
+  std::vector<int> order_host;
+  int order_P = -1, order_sb = -1;
   void* host = nullptr;  // pinned staging for small device<->host copies
   size_t host_cap = 0;
   hipEvent_t ev[16] = {};
@@ -40,8 +43,9 @@ struct Ctx {
   ~Ctx() {
     int prev = -1;
     if (hipGetDevice(&prev) == hipSuccess && device >= 0) (void)hipSetDevice(device);
-    DevBuf* all[] = {&packed, &inv, &endm, &bufA, &bufB, &tmpcnt, &hist, &wcount,
-                     &cursor, &items, &bins, &subhist, &leaves, &dcnt, &flags, &check};
+    DevBuf* all[] = {&packed, &inv, &endm,   &bufA,  &bufB,    &tmpcnt, &hist,   &sbegin, &cursor,
+                     &cursor2, &order, &items, &bins, &subhist, &leaves, &dcnt, &outoff, &state,
+                     &large,   &bsum,  &itemoff};
     for (DevBuf* b : all)
       if (b->p) (void)hipFree(b->p);
     if (host) (void)hipHostFree(host);
@@ -143,7 +147,7 @@ struct LeafDone {
   u128 start;  // first key of its range
   uint64_t begin, end;
   uint32_t d;
-  int buf;
+  int buf, bits;
 };
 
 struct Timer {
@@ -178,9 +182,255 @@ struct Timer {
 enum { ST_PACK = 0, ST_HIST = 1, ST_SCATTER = 2, ST_SPLIT = 3, ST_LEAF = 4, ST_CONCAT = 5,
        ST_CHECK = 6, ST_NONE = -1 };
 
-__global__ void k_offsets_ok(const uint64_t* off, uint64_t n, unsigned int* bad) {
+__global__ void k_offsets_ok(const uint64_t* off, uint64_t n, unsigned int* bad) {  // sets *bad if decreasing
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n && off[i + 1] < off[i]) atomicOr(bad, 1u);
+}
+
+
+struct Call {
+  const uint8_t* reads;
+  const uint64_t* offsets;
+  uint64_t n_reads;
+  int k, P;
+  uint64_t* out_keys;
+  uint32_t* out_counts;
+  uint64_t cap;
+  kc_options o;
+  hipStream_t st;
+  // derived
+  uint64_t N = 0, off0 = 0;
+  bool wide = false;
+  int keybits = 0, sb = 0, nb = 0, slots_log2 = 0;
+  size_t ksz = 8;
+  uint64_t C = 0, T = 0, H = 0;
+};
+
+// Owner-major order of the shards: owner(s) = multiply-shift range reduction of
+// a 64-bit mix of the shard index onto [0, P). Cached per (P, shard bits).
+const std::vector<int>& owner_order(Ctx& c, const Call& q, kc_stats& S,
+                                    const std::vector<uint64_t>* hist) {
+  static thread_local std::vector<int> order;
+  static thread_local std::vector<uint64_t> owner;
+  order.resize(q.nb);
+  owner.resize(q.nb);
+  for (int i = 0; i < q.nb; ++i) {
+    order[i] = i;
+    owner[i] = (uint64_t)(((u128)host_mix((uint64_t)i * 0x9E3779B97F4A7C15ull + 0x51ED27ull) *
+                           (u128)(uint64_t)q.P) >> 64);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return owner[a] < owner[b]; });
+  if (hist) {
+    uint64_t cur = ~0ull, w = 0;
+    for (int i : order) {
+      if (owner[i] != cur) {
+        S.max_owner_windows = std::max(S.max_owner_windows, w);
+        w = 0;
+        cur = owner[i];
+      }
+      w += (*hist)[i];
+    }
+    S.max_owner_windows = std::max(S.max_owner_windows, w);
+  }
+  (void)c;
+  return order;
+}
+
+void upload_sync(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (!bytes) return;
+  hipchk(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+  hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+kc::DevState read_state(Ctx& c, hipStream_t st) {
+  kc::DevState* h = (kc::DevState*)host_stage(c, sizeof(kc::DevState));
+  hipchk(hipMemcpyAsync(h, c.state.p, sizeof(kc::DevState), hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync");
+  hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+  return *h;
+}
+
+// Host-driven partitioning with any number of split levels: used when a leaf
+// of the device-planned path overflowed its table. Starts from the packed
+// input and the shard histogram already on the device.
+void general_path(Ctx& c, Call& q, kc_stats& S, Timer& tm) {
+  const hipStream_t st = q.st;
+  std::vector<uint64_t> hist(q.nb);
+  {
+    uint64_t* hh = (uint64_t*)host_stage(c, (size_t)q.nb * 8);
+    hipchk(hipMemcpyAsync(hh, c.hist.p, (size_t)q.nb * 8, hipMemcpyDeviceToHost, st),
+           "hipMemcpyAsync");
+    hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+    std::memcpy(hist.data(), hh, (size_t)q.nb * 8);
+  }
+  const std::vector<int>& order = owner_order(c, q, S, &hist);
+  std::vector<uint64_t> sbegin(q.nb);
+  uint64_t run = 0;
+  for (int i : order) {
+    sbegin[i] = run;
+    run += hist[i];
+  }
+  const uint64_t W = run;
+  upload_sync(c.cursor.p, sbegin.data(), (size_t)q.nb * 8, st);
+  hipchk(kc::launch_window_scatter(q.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
+                                   (uint64_t*)c.endm.p, q.N, q.k, q.sb,
+                                   (unsigned long long*)c.cursor.p, c.bufA.p, st),
+         "owner scatter launch");
+  tm.mark(ST_SCATTER);
+
+  std::vector<Bin> cur;
+  for (int i = 0; i < q.nb; ++i)
+    if (hist[i]) cur.push_back(Bin{sbegin[i], sbegin[i] + hist[i], (u128)i, q.sb, 0});
+  std::vector<LeafDone> done;
+  void* bufs[2] = {c.bufA.p, c.bufB.p};
+  kc::DevState* dst_state = (kc::DevState*)c.state.p;
+  const uint64_t T = std::min<uint64_t>(q.T, q.C / 4);  // finer leaves than the fast path
+  const uint64_t H = q.C / 2;
+  int level = 0;
+  while (!cur.empty()) {
+    std::vector<Bin> attempt, split;
+    std::vector<bool> was_ovf;
+    for (const Bin& b : cur) {
+      const uint64_t n = b.end - b.begin;
+      if (b.bits >= q.keybits || n <= H) {
+        if (b.bits >= q.keybits && n > 0xFFFFFFFFull)
+          fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
+        attempt.push_back(b);
+      } else {
+        split.push_back(b);
+        was_ovf.push_back(false);
+      }
+    }
+    if (!attempt.empty()) {
+      const size_t na = attempt.size();
+      std::vector<kc::Leaf> lv(na);
+      for (size_t i = 0; i < na; ++i)
+        lv[i] = kc::Leaf{attempt[i].begin, attempt[i].end, (uint32_t)attempt[i].buf,
+                         (uint32_t)attempt[i].bits};
+      ensure(c.leaves, na * sizeof(kc::Leaf), "leaf table");
+      ensure(c.dcnt, na * 4, "leaf counts");
+      ensure(c.large, na * 4, "large-leaf list");
+      upload_sync(c.leaves.p, lv.data(), na * sizeof(kc::Leaf), st);
+      unsigned long long nl = na;
+      upload_sync(&dst_state->n_leaves, &nl, 8, st);
+      hipchk(kc::launch_leaf_count(q.wide, q.k, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                                   (kc::Leaf*)c.leaves.p, dst_state, na, (uint32_t*)c.dcnt.p,
+                                   q.slots_log2, (uint32_t*)c.large.p, st),
+             "leaf count launch");
+      tm.mark(ST_LEAF);
+      uint32_t* hd = (uint32_t*)host_stage(c, na * 4);
+      hipchk(hipMemcpyAsync(hd, c.dcnt.p, na * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+      hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+      for (size_t i = 0; i < na; ++i) {
+        const Bin& b = attempt[i];
+        if (hd[i] == kc::kLeafOverflow) {
+          if (b.bits >= q.keybits) fail(KC_E_INTERNAL, "single-key partition overflowed its table");
+          ++S.n_overflow;
+          split.push_back(b);
+          was_ovf.push_back(true);
+        } else {
+          done.push_back(LeafDone{b.prefix << (q.keybits - b.bits), b.begin, b.end, hd[i], b.buf,
+                                  b.bits});
+          S.max_leaf_windows = std::max(S.max_leaf_windows, b.end - b.begin);
+        }
+      }
+    }
+    if (split.empty()) break;
+    ++level;
+    const size_t ns = split.size();
+    std::vector<kc::SplitBin> sbins(ns);
+    std::vector<kc::SplitItem> items;
+    uint64_t hoff = 0;
+    const uint64_t tile = (uint64_t)kc::split_tile(q.wide);
+    for (size_t i = 0; i < ns; ++i) {
+      const Bin& b = split[i];
+      const uint64_t n = b.end - b.begin;
+      const int remaining = q.keybits - b.bits;
+      int nbits = ceil_log2((n + T - 1) / T);
+      if (was_ovf[i]) nbits = std::max(nbits, 2);
+      nbits = std::max(1, std::min(nbits, std::min(kc::kSplitMaxBits, remaining)));
+      sbins[i] = kc::SplitBin{hoff, (uint32_t)(q.keybits - b.bits - nbits), (uint32_t)nbits};
+      hoff += 1ull << nbits;
+      for (uint64_t a = b.begin; a < b.end; a += tile)
+        items.push_back(kc::SplitItem{a, std::min(b.end, a + tile), (uint32_t)i, 0});
+    }
+    ensure(c.bins, ns * sizeof(kc::SplitBin), "split bins");
+    ensure(c.items, items.size() * sizeof(kc::SplitItem), "split items");
+    ensure(c.subhist, hoff * 8, "sub-bin histogram");
+    ensure(c.cursor2, hoff * 8, "sub-bin cursors");
+    upload_sync(c.items.p, items.data(), items.size() * sizeof(kc::SplitItem), st);
+    upload_sync(c.bins.p, sbins.data(), ns * sizeof(kc::SplitBin), st);
+    unsigned long long ni = items.size();
+    upload_sync(&dst_state->n_items, &ni, 8, st);
+    hipchk(kc::launch_fill_u64((unsigned long long*)c.subhist.p, hoff, 0, st), "fill launch");
+    const int src = split[0].buf;
+    hipchk(kc::launch_split_hist(q.wide, bufs[src], (kc::SplitItem*)c.items.p, dst_state,
+                                 items.size(), (kc::SplitBin*)c.bins.p,
+                                 (unsigned long long*)c.subhist.p, st),
+           "split histogram launch");
+    uint64_t* hsub = (uint64_t*)host_stage(c, hoff * 8 + 64);
+    hipchk(hipMemcpyAsync(hsub, c.subhist.p, hoff * 8, hipMemcpyDeviceToHost, st),
+           "hipMemcpyAsync");
+    hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+    std::vector<Bin> next;
+    std::vector<uint64_t> hcur(hoff);
+    for (size_t i = 0; i < ns; ++i) {
+      const Bin& b = split[i];
+      const kc::SplitBin& sbn = sbins[i];
+      uint64_t r = b.begin;
+      for (uint64_t j = 0; j < (1ull << sbn.nbits); ++j) {
+        const uint64_t cnt = hsub[sbn.hist_off + j];
+        hcur[sbn.hist_off + j] = r;
+        if (cnt)
+          next.push_back(Bin{r, r + cnt, (b.prefix << sbn.nbits) | (u128)j,
+                             b.bits + (int)sbn.nbits, 1 - b.buf});
+        r += cnt;
+      }
+      if (r != b.end) fail(KC_E_INTERNAL, "split histogram does not match partition size");
+    }
+    upload_sync(c.cursor2.p, hcur.data(), hoff * 8, st);
+    hipchk(kc::launch_split_scatter(q.wide, bufs[src], bufs[1 - src], (kc::SplitItem*)c.items.p,
+                                    dst_state, items.size(), (kc::SplitBin*)c.bins.p,
+                                    (unsigned long long*)c.cursor2.p, st),
+           "split scatter launch");
+    tm.mark(ST_SPLIT);
+    hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+    cur.swap(next);
+  }
+  S.n_levels = level;
+  std::sort(done.begin(), done.end(),
+            [](const LeafDone& a, const LeafDone& b) { return a.start < b.start; });
+  const size_t nl = done.size();
+  std::vector<kc::Leaf> lv(nl);
+  std::vector<uint32_t> dv(nl);
+  uint64_t D = 0;
+  for (size_t i = 0; i < nl; ++i) {
+    lv[i] = kc::Leaf{done[i].begin, done[i].end, (uint32_t)done[i].buf, (uint32_t)done[i].bits};
+    dv[i] = done[i].d;
+    D += done[i].d;
+  }
+  (void)W;
+  S.n_leaves = nl;
+  ensure(c.leaves, nl * sizeof(kc::Leaf), "leaf table");
+  ensure(c.dcnt, nl * 4, "leaf counts");
+  ensure(c.outoff, nl * 8, "output offsets");
+  ensure(c.bsum, kc::scan_blocks(nl) * 8, "scan block sums");
+  upload_sync(c.leaves.p, lv.data(), nl * sizeof(kc::Leaf), st);
+  upload_sync(c.dcnt.p, dv.data(), nl * 4, st);
+  unsigned long long nlu = nl;
+  upload_sync(&dst_state->n_leaves, &nlu, 8, st);
+  unsigned int zero = 0;
+  upload_sync(&dst_state->overflow, &zero, 4, st);
+  hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dst_state, (unsigned long long*)c.bsum.p, nl,
+                             (unsigned long long*)c.outoff.p, st),
+         "plan_out launch");
+  hipchk(kc::launch_concat(q.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                           (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
+                           (unsigned long long*)c.outoff.p, dst_state, nl, q.cap, q.out_keys,
+                           q.out_counts, st),
+         "concat launch");
+  tm.mark(ST_CONCAT);
+  (void)D;
 }
 
 int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
@@ -194,313 +444,192 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   if (!offsets) fail(KC_E_INVAL, "offsets is NULL");
   if (n_reads && !reads) fail(KC_E_INVAL, "reads is NULL");
   if (cap && (!out_keys || !out_counts)) fail(KC_E_INVAL, "output pointer is NULL");
-  kc_options o;
-  std::memset(&o, 0, sizeof(o));
-  if (opt) o = *opt;
-  if (o.mode != 0) fail(KC_E_INVAL, "mode must be 0");
+  Call q{reads, offsets, n_reads, k, P, out_keys, out_counts, cap, {}, st};
+  std::memset(&q.o, 0, sizeof(q.o));
+  if (opt) q.o = *opt;
+  if (q.o.mode != 0) fail(KC_E_INVAL, "mode must be 0");
 
   Ctx& c = context();
   std::memset(&g_stats, 0, sizeof(g_stats));
   kc_stats S;
   std::memset(&S, 0, sizeof(S));
-  Timer tm(c, st, o.timing != 0);
+  Timer tm(c, st, q.o.timing != 0);
 
-  // ---- offsets: first/last, monotonicity
-  ensure(c.flags, 64, "flags");
-  uint64_t* h = (uint64_t*)host_stage(c, 64);
-  hipchk(hipMemsetAsync(c.flags.p, 0, 16, st), "hipMemsetAsync");
+  // ---- offsets: first/last, monotonicity (host sync 1 of 2)
+  ensure(c.state, sizeof(kc::DevState), "device state");
+  hipchk(kc::launch_fill_u64((unsigned long long*)c.state.p, sizeof(kc::DevState) / 8, 0, st),
+         "fill launch");
   if (n_reads) {
     const unsigned g = (unsigned)((n_reads + 255) / 256);
     hipLaunchKernelGGL(k_offsets_ok, dim3(g), dim3(256), 0, st, offsets, n_reads,
-                       (unsigned int*)c.flags.p);
+                       &((kc::DevState*)c.state.p)->overflow);
     hipchk(hipGetLastError(), "offsets check launch");
   }
+  uint64_t* h = (uint64_t*)host_stage(c, 64);
   hipchk(hipMemcpyAsync(h, offsets, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
   hipchk(hipMemcpyAsync(h + 1, offsets + n_reads, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-  hipchk(hipMemcpyAsync(h + 2, c.flags.p, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  hipchk(hipMemcpyAsync(h + 2, &((kc::DevState*)c.state.p)->overflow, 4, hipMemcpyDeviceToHost,
+                        st),
+         "hipMemcpyAsync");
   hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
   const uint64_t off0 = h[0], offn = h[1];
   if ((uint32_t)h[2] != 0 || offn < off0) fail(KC_E_INVAL, "offsets must be non-decreasing");
-  const uint64_t N = offn - off0;
-  S.n_bases = N;
-  if (N == 0) {
+  q.off0 = off0;
+  q.N = offn - off0;
+  S.n_bases = q.N;
+  if (q.N == 0) {
     g_stats = S;
     return KC_OK;
   }
+  q.wide = k > 32;
+  q.keybits = 2 * k;
+  q.ksz = q.wide ? 16 : 8;
+  const int max_slots = kc::max_leaf_slots_log2(q.wide);
+  q.slots_log2 = q.o.table_slots_log2 > 0
+                     ? std::min(std::max(q.o.table_slots_log2, 10), max_slots)
+                     : max_slots;
+  q.C = 1ull << q.slots_log2;
+  // default leaf size: about half of what the one-wave leaf kernel takes, so
+  // that nearly all leaves (after the split's size spread) stay in that kernel
+  q.T = q.o.leaf_target > 0 ? (uint64_t)q.o.leaf_target : (kc::small_leaf_max(q.wide) + 1) / 2;
+  q.H = q.o.leaf_attempt > 0 ? (uint64_t)q.o.leaf_attempt : (q.C * 7) / 8;
+  int sb = q.o.shard_bits;
+  if (sb <= 0) {
+    sb = std::max(8, ceil_log2((uint64_t)P));
+    sb = std::max(sb, ceil_log2(q.N / (q.T << kc::kSplitMaxBits) + 1));
+  }
+  sb = std::min(sb, kc::max_shard_bits());
+  sb = std::min(sb, q.keybits);
+  q.sb = sb;
+  q.nb = 1 << sb;
 
-  const bool wide = k > 32;
-  const int keybits = 2 * k;
-  const size_t ksz = wide ? 16 : 8;
-  const uint64_t nchunks = (N + 63) / 64 + 2;
+  const uint64_t nchunks = (q.N + 63) / 64 + 2;
   ensure(c.packed, nchunks * 16, "packed bases");
   ensure(c.inv, nchunks * 8, "invalid mask");
   ensure(c.endm, nchunks * 8, "end mask");
+  // record buffers sized by the byte count, an upper bound of the window count
+  ensure(c.bufA, q.N * q.ksz, "record buffer A");
+  ensure(c.bufB, q.N * q.ksz, "record buffer B");
+  ensure(c.tmpcnt, q.N * 4, "pair counts");
+  const uint64_t tile = (uint64_t)kc::split_tile(q.wide);
+  const uint64_t max_items = q.N / tile + (uint64_t)q.nb + 1;
+  const uint64_t max_leaves =
+      std::min<uint64_t>((uint64_t)q.nb << kc::kSplitMaxBits, 2 * q.N / q.T + 2 * (uint64_t)q.nb) +
+      1;
+  ensure(c.hist, (size_t)q.nb * 8, "shard histogram");
+  ensure(c.sbegin, (size_t)q.nb * 8, "shard begins");
+  ensure(c.cursor, (size_t)q.nb * 8, "shard cursors");
+  ensure(c.order, (size_t)q.nb * 4, "owner order");
+  ensure(c.bins, (size_t)q.nb * sizeof(kc::SplitBin), "split bins");
+  ensure(c.items, max_items * sizeof(kc::SplitItem), "split items");
+  ensure(c.itemoff, ((size_t)q.nb + 1) * 8, "split item offsets");
+  ensure(c.subhist, max_leaves * 8, "sub-bin histogram");
+  ensure(c.cursor2, max_leaves * 8, "sub-bin cursors");
+  ensure(c.leaves, max_leaves * sizeof(kc::Leaf), "leaf table");
+  ensure(c.dcnt, max_leaves * 4, "leaf counts");
+  ensure(c.outoff, max_leaves * 8, "output offsets");
+  ensure(c.large, max_leaves * 4, "large-leaf list");
+  ensure(c.bsum, kc::scan_blocks(max_leaves) * 8, "scan block sums");
+  if (c.order_P != P || c.order_sb != sb) {
+    const std::vector<int>& order = owner_order(c, q, S, nullptr);
+    c.order_host.assign(order.begin(), order.end());
+    upload_sync(c.order.p, c.order_host.data(), (size_t)q.nb * 4, st);
+    c.order_P = P;
+    c.order_sb = sb;
+  }
+  kc::DevState* dstate = (kc::DevState*)c.state.p;
+
   tm.mark(ST_NONE);
-  hipchk(kc::launch_pack(reads + off0, N, offsets, n_reads, off0, (uint64_t*)c.packed.p,
+  hipchk(kc::launch_pack(reads + off0, q.N, offsets, n_reads, off0, (uint64_t*)c.packed.p,
                          (uint64_t*)c.inv.p, (uint64_t*)c.endm.p, nchunks, st),
          "pack launch");
   tm.mark(ST_PACK);
-
-  // ---- first level: shard histogram
-  int sb = o.shard_bits;
-  if (sb <= 0) sb = std::max(8, ceil_log2((uint64_t)P));
-  sb = std::min(sb, kc::max_shard_bits());
-  sb = std::min(sb, keybits);
-  const int nb = 1 << sb;
-  ensure(c.hist, (size_t)nb * 8, "shard histogram");
-  ensure(c.wcount, 64, "window count");
-  hipchk(hipMemsetAsync(c.hist.p, 0, (size_t)nb * 8, st), "hipMemsetAsync");
-  hipchk(hipMemsetAsync(c.wcount.p, 0, 8, st), "hipMemsetAsync");
-  hipchk(kc::launch_window_hist(wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
-                                (uint64_t*)c.endm.p, N, k, sb, (unsigned long long*)c.hist.p,
-                                (unsigned long long*)c.wcount.p, st),
+  hipchk(kc::launch_fill_u64((unsigned long long*)c.hist.p, q.nb, 0, st), "fill launch");
+  hipchk(kc::launch_window_hist(q.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
+                                (uint64_t*)c.endm.p, q.N, k, sb, (unsigned long long*)c.hist.p,
+                                &dstate->W, st),
          "window histogram launch");
   tm.mark(ST_HIST);
-  uint64_t* hh = (uint64_t*)host_stage(c, (size_t)(nb + 1) * 8);
-  hipchk(hipMemcpyAsync(hh, c.hist.p, (size_t)nb * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-  hipchk(hipMemcpyAsync(hh + nb, c.wcount.p, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-  hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-  std::vector<uint64_t> hist(hh, hh + nb);
-  const uint64_t W = hh[nb];
-  S.valid_windows = W;
-  uint64_t hsum = 0;
-  for (uint64_t x : hist) hsum += x;
-  if (hsum != W) fail(KC_E_INTERNAL, "shard histogram does not sum to the valid window count");
-  if (W == 0) {
-    tm.collect(S);
-    g_stats = S;
-    return KC_OK;
-  }
-
-  // ---- owner-major layout of shards: each owner's shards form one contiguous range
-  std::vector<int> order(nb);
-  std::vector<uint64_t> owner(nb);
-  for (int i = 0; i < nb; ++i) {
-    order[i] = i;
-    owner[i] = (uint64_t)(((u128)host_mix((uint64_t)i * 0x9E3779B97F4A7C15ull + 0x51ED27ull) *
-                           (u128)(uint64_t)P) >> 64);
-  }
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return owner[a] < owner[b]; });
-  std::vector<uint64_t> sbegin(nb);
-  {
-    uint64_t run = 0, cur_owner = ~0ull, owner_w = 0;
-    for (int i : order) {
-      if (owner[i] != cur_owner) {
-        S.max_owner_windows = std::max(S.max_owner_windows, owner_w);
-        owner_w = 0;
-        cur_owner = owner[i];
-      }
-      sbegin[i] = run;
-      run += hist[i];
-      owner_w += hist[i];
-    }
-    S.max_owner_windows = std::max(S.max_owner_windows, owner_w);
-  }
-  ensure(c.bufA, W * ksz, "record buffer A");
-  ensure(c.bufB, W * ksz, "record buffer B");
-  ensure(c.tmpcnt, W * 4, "pair counts");
-  ensure(c.cursor, (size_t)nb * 8, "cursors");
-  // host-to-device copies read pageable vectors that outlive the copy; the
-  // pinned staging buffer is used only for device-to-host copies followed by a
-  // synchronize, so it is never overwritten while a copy is pending
-  hipchk(hipMemcpyAsync(c.cursor.p, sbegin.data(), (size_t)nb * 8, hipMemcpyHostToDevice, st),
-         "hipMemcpyAsync");
-  hipchk(kc::launch_window_scatter(wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
-                                   (uint64_t*)c.endm.p, N, k, sb, (unsigned long long*)c.cursor.p,
-                                   c.bufA.p, st),
+  // ---- device-planned partitioning: shard plan, scatter, one split level, leaves
+  hipchk(kc::launch_plan_shards((unsigned long long*)c.hist.p, (const int*)c.order.p, sb,
+                                q.keybits, q.T, q.H, (int)tile, (unsigned long long*)c.sbegin.p,
+                                (unsigned long long*)c.cursor.p, (kc::SplitBin*)c.bins.p,
+                                (kc::SplitItem*)c.items.p, (unsigned long long*)c.itemoff.p,
+                                (unsigned long long*)c.subhist.p, max_leaves, max_items, dstate,
+                                st),
+         "plan_shards launch");
+  hipchk(kc::launch_window_scatter(q.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
+                                   (uint64_t*)c.endm.p, q.N, k, sb,
+                                   (unsigned long long*)c.cursor.p, c.bufA.p, st),
          "owner scatter launch");
   tm.mark(ST_SCATTER);
-
-  std::vector<Bin> cur;
-  for (int i = 0; i < nb; ++i)
-    if (hist[i]) cur.push_back(Bin{sbegin[i], sbegin[i] + hist[i], (u128)i, sb, 0});
-
-  const int max_slots = kc::max_leaf_slots_log2(wide);
-  int slots_log2 = o.table_slots_log2 > 0 ? std::min(std::max(o.table_slots_log2, 10), max_slots)
-                                          : max_slots;
-  const uint64_t C = 1ull << slots_log2;
-  const uint64_t T = o.leaf_target > 0 ? (uint64_t)o.leaf_target : C / 2;
-  const uint64_t H = o.leaf_attempt > 0 ? (uint64_t)o.leaf_attempt : 2 * C;
-
-  std::vector<LeafDone> done;
-  void* bufs[2] = {c.bufA.p, c.bufB.p};
-  ensure(c.check, 64, "overflow flag");
-  hipchk(hipMemsetAsync(c.check.p, 0, 64, st), "hipMemsetAsync");
-  unsigned int* count_ovf = (unsigned int*)c.check.p;
-
-  int level = 0;
-  while (!cur.empty()) {
-    std::vector<Bin> attempt, split;
-    std::vector<bool> ovf_flag;
-    for (const Bin& b : cur) {
-      const uint64_t n = b.end - b.begin;
-      if (b.bits >= keybits || n <= H) {
-        if (b.bits >= keybits && n > 0xFFFFFFFFull)
-          fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
-        attempt.push_back(b);
-      } else {
-        split.push_back(b);
-      }
-    }
-    std::vector<bool> was_ovf(split.size(), false);
-    if (!attempt.empty()) {
-      const size_t na = attempt.size();
-      std::vector<kc::Leaf> lv(na);
-      for (size_t i = 0; i < na; ++i) lv[i] = kc::Leaf{attempt[i].begin, attempt[i].end, 0,
-                                                       (uint32_t)attempt[i].buf, 0};
-      ensure(c.leaves, na * sizeof(kc::Leaf), "leaf table");
-      ensure(c.dcnt, na * 4, "leaf counts");
-      hipchk(hipMemcpyAsync(c.leaves.p, lv.data(), na * sizeof(kc::Leaf), hipMemcpyHostToDevice,
-                            st),
-             "hipMemcpyAsync");
-      hipchk(kc::launch_leaf_count(wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
-                                   (kc::Leaf*)c.leaves.p, na, (uint32_t*)c.dcnt.p, slots_log2,
-                                   count_ovf, st),
-             "leaf count launch");
-      tm.mark(ST_LEAF);
-      uint32_t* hd = (uint32_t*)host_stage(c, na * 4);
-      hipchk(hipMemcpyAsync(hd, c.dcnt.p, na * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-      hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-      for (size_t i = 0; i < na; ++i) {
-        const Bin& b = attempt[i];
-        if (hd[i] == 0xFFFFFFFFu) {
-          if (b.bits >= keybits) fail(KC_E_INTERNAL, "single-key partition overflowed its table");
-          ++S.n_overflow;
-          split.push_back(b);
-          was_ovf.push_back(true);
-        } else {
-          const u128 start = b.prefix << (keybits - b.bits);
-          done.push_back(LeafDone{start, b.begin, b.end, hd[i], b.buf});
-          S.max_leaf_windows = std::max(S.max_leaf_windows, b.end - b.begin);
-        }
-      }
-    }
-    if (split.empty()) break;
-    ++level;
-    // ---- split step: histogram of the next key bits, then scatter into sub-bins
-    const size_t ns = split.size();
-    std::vector<kc::SplitBin> sbins(ns);
-    std::vector<kc::SplitItem> items;
-    uint64_t hoff = 0;
-    const uint64_t tile = (uint64_t)kc::split_tile(wide);
-    for (size_t i = 0; i < ns; ++i) {
-      const Bin& b = split[i];
-      const uint64_t n = b.end - b.begin;
-      const int remaining = keybits - b.bits;
-      int nbits = ceil_log2((n + T - 1) / T);
-      if (was_ovf[i]) nbits = std::max(nbits, 2);
-      nbits = std::max(1, std::min(nbits, std::min(kc::kSplitMaxBits, remaining)));
-      sbins[i] = kc::SplitBin{hoff, (uint32_t)(keybits - b.bits - nbits), (uint32_t)nbits};
-      hoff += 1ull << nbits;
-      for (uint64_t a = b.begin; a < b.end; a += tile)
-        items.push_back(kc::SplitItem{a, std::min(b.end, a + tile), (uint32_t)i, 0});
-    }
-    ensure(c.bins, ns * sizeof(kc::SplitBin), "split bins");
-    ensure(c.items, items.size() * sizeof(kc::SplitItem), "split items");
-    ensure(c.subhist, hoff * 8, "sub-bin histogram");
-    hipchk(hipMemcpyAsync(c.items.p, items.data(), items.size() * sizeof(kc::SplitItem),
-                          hipMemcpyHostToDevice, st),
-           "hipMemcpyAsync");
-    hipchk(hipMemcpyAsync(c.bins.p, sbins.data(), ns * sizeof(kc::SplitBin),
-                          hipMemcpyHostToDevice, st),
-           "hipMemcpyAsync");
-    hipchk(hipMemsetAsync(c.subhist.p, 0, hoff * 8, st), "hipMemsetAsync");
-    const int src = split[0].buf;
-    hipchk(kc::launch_split_hist(wide, bufs[src], (kc::SplitItem*)c.items.p, items.size(),
-                                 (kc::SplitBin*)c.bins.p, (unsigned long long*)c.subhist.p, st),
-           "split histogram launch");
-    uint64_t* hsub = (uint64_t*)host_stage(c, hoff * 8 + 64);
-    hipchk(hipMemcpyAsync(hsub, c.subhist.p, hoff * 8, hipMemcpyDeviceToHost, st),
-           "hipMemcpyAsync");
-    hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-    std::vector<Bin> next;
-    std::vector<uint64_t> hcur(hoff);
-    for (size_t i = 0; i < ns; ++i) {
-      const Bin& b = split[i];
-      const kc::SplitBin& sbn = sbins[i];
-      uint64_t run = b.begin;
-      for (uint64_t j = 0; j < (1ull << sbn.nbits); ++j) {
-        const uint64_t cnt = hsub[sbn.hist_off + j];
-        hcur[sbn.hist_off + j] = run;
-        if (cnt)
-          next.push_back(Bin{run, run + cnt, (b.prefix << sbn.nbits) | (u128)j,
-                             b.bits + (int)sbn.nbits, 1 - b.buf});
-        run += cnt;
-      }
-      if (run != b.end) fail(KC_E_INTERNAL, "split histogram does not match partition size");
-    }
-    ensure(c.cursor, hoff * 8, "cursors");
-    hipchk(hipMemcpyAsync(c.cursor.p, hcur.data(), hoff * 8, hipMemcpyHostToDevice, st),
-           "hipMemcpyAsync");
-    hipchk(kc::launch_split_scatter(wide, bufs[src], bufs[1 - src], (kc::SplitItem*)c.items.p,
-                                    items.size(), (kc::SplitBin*)c.bins.p,
-                                    (unsigned long long*)c.cursor.p, st),
-           "split scatter launch");
-    tm.mark(ST_SPLIT);
-    // the vectors read by the copies above go out of scope at the end of this pass
-    hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-    cur.swap(next);
-  }
-  S.n_levels = level;
-
-  // ---- order leaves by key range, output offsets, concat
-  std::sort(done.begin(), done.end(),
-            [](const LeafDone& a, const LeafDone& b) { return a.start < b.start; });
-  uint64_t D = 0;
-  const size_t nl = done.size();
-  std::vector<kc::Leaf> lv(nl);
-  std::vector<uint32_t> dv(nl);
-  for (size_t i = 0; i < nl; ++i) {
-    lv[i] = kc::Leaf{done[i].begin, done[i].end, D, (uint32_t)done[i].buf, 0};
-    dv[i] = done[i].d;
-    D += done[i].d;
-  }
-  S.distinct = D;
-  S.n_leaves = nl;
-  if (D > cap) {
-    *n_out = D;
-    fail(KC_E_CAPACITY, "output capacity " + std::to_string(cap) + " < " + std::to_string(D) +
-                            " distinct k-mers");
-  }
-  ensure(c.leaves, nl * sizeof(kc::Leaf), "leaf table");
-  ensure(c.dcnt, nl * 4, "leaf counts");
-  hipchk(hipMemcpyAsync(c.leaves.p, lv.data(), nl * sizeof(kc::Leaf), hipMemcpyHostToDevice, st),
-         "hipMemcpyAsync");
-  hipchk(hipMemcpyAsync(c.dcnt.p, dv.data(), nl * 4, hipMemcpyHostToDevice, st),
-         "hipMemcpyAsync");
-  hipchk(kc::launch_concat(wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
-                           (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p, nl, out_keys, out_counts,
-                           st),
+  hipchk(kc::launch_split_hist(q.wide, c.bufA.p, (kc::SplitItem*)c.items.p, dstate, max_items,
+                               (kc::SplitBin*)c.bins.p, (unsigned long long*)c.subhist.p, st),
+         "split histogram launch");
+  hipchk(kc::launch_plan_leaves((unsigned long long*)c.hist.p, (unsigned long long*)c.sbegin.p,
+                                (kc::SplitBin*)c.bins.p, sb, (unsigned long long*)c.subhist.p,
+                                (kc::Leaf*)c.leaves.p, (unsigned long long*)c.cursor2.p, st),
+         "plan_leaves launch");
+  hipchk(kc::launch_split_scatter(q.wide, c.bufA.p, c.bufB.p, (kc::SplitItem*)c.items.p, dstate,
+                                  max_items, (kc::SplitBin*)c.bins.p,
+                                  (unsigned long long*)c.cursor2.p, st),
+         "split scatter launch");
+  tm.mark(ST_SPLIT);
+  hipchk(kc::launch_leaf_count(q.wide, k, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                               (kc::Leaf*)c.leaves.p, dstate, max_leaves, (uint32_t*)c.dcnt.p,
+                               q.slots_log2, (uint32_t*)c.large.p, st),
+         "leaf count launch");
+  tm.mark(ST_LEAF);
+  hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dstate, (unsigned long long*)c.bsum.p, max_leaves,
+                             (unsigned long long*)c.outoff.p, st),
+         "plan_out launch");
+  hipchk(kc::launch_concat(q.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                           (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
+                           (unsigned long long*)c.outoff.p, dstate, max_leaves, cap, out_keys,
+                           out_counts, st),
          "concat launch");
   tm.mark(ST_CONCAT);
-  if (o.check) {
-    hipchk(hipMemsetAsync((char*)c.check.p + 16, 0, sizeof(kc::CheckResult), st),
-           "hipMemsetAsync");
-    hipchk(kc::launch_check(wide, out_keys, out_counts, D, k,
-                            (kc::CheckResult*)((char*)c.check.p + 16), st),
+  kc::DevState ds = read_state(c, st);  // host sync 2 of 2
+  S.n_levels = 1;
+  S.n_leaves = ds.n_leaves;
+  if (ds.overflow) {
+    // some leaf had more distinct keys than its table holds: redo the
+    // partitioning with host-planned recursive splits
+    ++S.n_overflow;
+    general_path(c, q, S, tm);
+    ds = read_state(c, st);
+    if (ds.overflow) fail(KC_E_INTERNAL, "leaf overflow in the recursive path");
+  }
+  S.valid_windows = ds.W;
+  S.distinct = ds.D;
+  if (ds.count_overflow) fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
+  if (ds.D > cap) {
+    *n_out = ds.D;
+    fail(KC_E_CAPACITY, "output capacity " + std::to_string(cap) + " < " + std::to_string(ds.D) +
+                            " distinct k-mers");
+  }
+  if (q.o.check) {
+    hipchk(kc::launch_fill_u64((unsigned long long*)&dstate->check, sizeof(kc::CheckResult) / 8,
+                               0, st),
+           "fill launch");
+    hipchk(kc::launch_check(q.wide, out_keys, out_counts, ds.D, k, &dstate->check, st),
            "check launch");
     tm.mark(ST_CHECK);
-  }
-  uint32_t* hf = (uint32_t*)host_stage(c, 64);
-  hipchk(hipMemcpyAsync(hf, c.check.p, 16 + sizeof(kc::CheckResult), hipMemcpyDeviceToHost, st),
-         "hipMemcpyAsync");
-  hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-  if (hf[0]) fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
-  if (o.check) {
-    kc::CheckResult r;
-    std::memcpy(&r, (char*)hf + 16, sizeof(r));
-    if (r.sum_counts != W || r.not_sorted || r.not_canonical || r.out_of_range || r.zero_count) {
+    const kc::DevState d2 = read_state(c, st);
+    const kc::CheckResult& r = d2.check;
+    if (r.sum_counts != ds.W || r.not_sorted || r.not_canonical || r.out_of_range ||
+        r.zero_count) {
       char msg[256];
       std::snprintf(msg, sizeof msg,
                     "device self-check failed: sum %llu (want %llu), unsorted %u, "
                     "non-canonical %u, out of range %u, zero counts %u",
-                    r.sum_counts, (unsigned long long)W, r.not_sorted, r.not_canonical,
+                    r.sum_counts, (unsigned long long)ds.W, r.not_sorted, r.not_canonical,
                     r.out_of_range, r.zero_count);
       fail(KC_E_INTERNAL, msg);
     }
   }
   tm.collect(S);
-  *n_out = D;
+  *n_out = ds.D;
   S.ms_total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host0).count();
   g_stats = S;

@@ -76,6 +76,22 @@ def test_knob_invariance(opts):
                     "k=%d %s" % (k, opts))
 
 
+def test_fast_path_and_recursive_fallback_agree():
+    """Default settings finish in the device-planned path; huge unsplit leaves
+    overflow their tables and take the host-planned recursive path."""
+    import paper_2505_04431_amd as kc
+    c = synth.make_config(2, frac=0.05)
+    want = oracle.count(c["reads"], c["offsets"], 31)
+    assert_same(gpu_count(c["reads"], c["offsets"], 31, P=64), want, "fast path")
+    st = kc.last_stats()
+    assert st["n_overflow"] == 0 and st["n_levels"] == 1
+    assert st["valid_windows"] == int(want[1].sum()) and st["distinct"] == len(want[1])
+    assert_same(gpu_count(c["reads"], c["offsets"], 31, P=64, leaf_attempt=1 << 30,
+                          shard_bits=4), want, "fallback path")
+    st = kc.last_stats()
+    assert st["n_overflow"] >= 1
+
+
 def test_strand_flip_permutation_and_unaligned_base():
     g = synth.genome(31, 30_000, [(500, 20, 0.01)])
     r, o = synth.reads(g, 2000, 150, err_rate=0.005, n_rate=0.001, seed=3)
