@@ -72,6 +72,16 @@ template <> struct Key<uint64_t> {
     uint64_t fwd = rev2(v) >> (64 - 2 * k);  // first base most significant
     return fwd < rc ? fwd : rc;
   }
+  __device__ static uint64_t mask(int k) { return mask64(k); }
+  __device__ static uint64_t window(uint64_t p0, uint64_t p1, int s, int k) {
+    return (s ? (p0 >> s) | (p1 << (64 - s)) : p0) & mask64(k);
+  }
+  __device__ static uint64_t fwd_of(uint64_t p0, uint64_t p1, uint64_t, int s, int k) {
+    return rev2(window(p0, p1, s, k)) >> (64 - 2 * k);
+  }
+  __device__ static uint64_t rc_of(uint64_t p0, uint64_t p1, uint64_t, int s, int k) {
+    return ~window(p0, p1, s, k) & mask64(k);
+  }
   __device__ static uint64_t revcomp(uint64_t x, int k) { return rev2(~x & mask64(k)) >> (64 - 2 * k); }
   __device__ static bool in_range(uint64_t x, int k) { return (x & ~mask64(k)) == 0; }
 };
@@ -96,6 +106,19 @@ template <> struct Key<u128> {
     u128 r = ((u128)rev2((uint64_t)v) << 64) | rev2((uint64_t)(v >> 64));
     u128 fwd = r >> (128 - 2 * k);
     return fwd < rc ? fwd : rc;
+  }
+  __device__ static u128 mask(int k) { return mask128(k); }
+  __device__ static u128 window(uint64_t p0, uint64_t p1, uint64_t p2, int s, int k) {
+    const uint64_t lo = s ? (p0 >> s) | (p1 << (64 - s)) : p0;
+    const uint64_t hi = s ? (p1 >> s) | (p2 << (64 - s)) : p1;
+    return (((u128)hi << 64) | lo) & mask128(k);
+  }
+  __device__ static u128 fwd_of(uint64_t p0, uint64_t p1, uint64_t p2, int s, int k) {
+    const u128 v = window(p0, p1, p2, s, k);
+    return (((u128)rev2((uint64_t)v) << 64) | rev2((uint64_t)(v >> 64))) >> (128 - 2 * k);
+  }
+  __device__ static u128 rc_of(uint64_t p0, uint64_t p1, uint64_t p2, int s, int k) {
+    return ~window(p0, p1, p2, s, k) & mask128(k);
   }
   __device__ static u128 revcomp(u128 x, int k) {
     u128 c = ~x & mask128(k);
@@ -286,6 +309,31 @@ __device__ __forceinline__ void load_window_words(const uint64_t* __restrict__ p
   p2 = Key<K>::kWide ? packed[w + 2] : 0;
 }
 
+// Canonical keys of the S windows starting at bytes g .. g+S-1 (g a multiple
+// of S, S dividing 32). The first is built directly from the packed words,
+// the others by rolling one base in: fwd = ((fwd << 2) | x) & mask and
+// rc = (rc >> 2) | ((3 - x) << 2(k-1)), x being the base at g+i+k-1.
+// Keys of invalid starts are computed too (the caller masks them).
+template <typename K, int S>
+__device__ __forceinline__ void canon_run(uint64_t p0, uint64_t p1, uint64_t p2, uint64_t g, int k,
+                                          K (&out)[S]) {
+  const int s0 = (int)(g & 31);
+  out[0] = Key<K>::canon(p0, p1, p2, 2 * s0, k);
+  K fwd = Key<K>::fwd_of(p0, p1, p2, 2 * s0, k);
+  K rc = Key<K>::rc_of(p0, p1, p2, 2 * s0, k);
+  const K mask = Key<K>::mask(k);
+  const int top = 2 * (k - 1);
+#pragma unroll
+  for (int i = 1; i < S; ++i) {
+    const int p = s0 + i + k - 1;  // position of the incoming base within words p0..p2
+    const uint64_t w = p < 32 ? p0 : (p < 64 ? p1 : p2);
+    const uint32_t x = (uint32_t)(w >> (2 * (p & 31))) & 3u;
+    fwd = ((fwd << 2) | (K)x) & mask;
+    rc = (rc >> 2) | ((K)(3u - x) << top);
+    out[i] = fwd < rc ? fwd : rc;
+  }
+}
+
 template <typename K>
 __device__ __forceinline__ uint32_t shard_of(K key, int k, int shard_bits) {
   return (uint32_t)(key >> (2 * k - shard_bits));
@@ -310,14 +358,12 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
     if (!vm) continue;
     uint64_t p0, p1, p2;
     load_window_words<K, S>(packed, g, p0, p1, p2);
-    const int s0 = 2 * (int)(g & 31);
-    while (vm) {
-      const int i = __builtin_ctz(vm);
-      vm &= vm - 1;
-      K key = Key<K>::canon(p0, p1, p2, s0 + 2 * i, k);
-      atomicAdd(&sh[shard_of(key, k, shard_bits)], 1u);
-      ++w;
-    }
+    K keys[S];
+    canon_run<K, S>(p0, p1, p2, g, k, keys);
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+      if (vm & (1u << i)) atomicAdd(&sh[shard_of(keys[i], k, shard_bits)], 1u);
+    w += __builtin_popcount(vm);
   }
   // per-wave sum of valid windows, one global atomic per wave
   for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
@@ -356,11 +402,10 @@ __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restric
     if (vm) {
       uint64_t p0, p1, p2;
       load_window_words<K, S>(packed, g, p0, p1, p2);
-      const int s0 = 2 * (int)(g & 31);
+      canon_run<K, S>(p0, p1, p2, g, k, key);
 #pragma unroll
       for (int i = 0; i < S; ++i) {
         if (vm & (1u << i)) {
-          key[i] = Key<K>::canon(p0, p1, p2, s0 + 2 * i, k);
           bin[i] = shard_of(key[i], k, shard_bits);
           rank[i] = atomicAdd(&hist[bin[i]], 1u);
         }
@@ -684,6 +729,13 @@ __device__ __forceinline__ void bitonic_sort(K* keys, C* cnt, uint32_t n) {
   }
 }
 
+// Table slot of a 64-bit key: multiply-shift (Knuth) of a 32-bit fold of the
+// key; collisions are resolved by linear probing, so only speed depends on it.
+__device__ __forceinline__ uint32_t slot_hash(uint64_t key, int bits) {
+  const uint32_t f = (uint32_t)key * 0x9E3779B1u + (uint32_t)(key >> 32) * 0x85EBCA77u;
+  return (f ^ (f >> 15)) * 0x2C1B3C6Du >> (32 - bits);
+}
+
 // Workgroup-scope flag in LDS (a volatile LDS variable would be accessed with
 // flat instructions that also wait for all outstanding global memory operations).
 __device__ __forceinline__ uint32_t ovf_get(uint32_t* f) {
@@ -743,10 +795,12 @@ __device__ __forceinline__ uint32_t leaf_sort_write(K* tk, C* tc, uint32_t* aux,
   __syncthreads();  // table copied to registers; group counters cleared
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    if (occupied(rc[j])) {
-      bk[j] = nbk_bits ? Key<K>::bits(rk[j], shift, nbk_bits) : 0u;
-      rank[j] = atomicAdd(&aux[bk[j]], 1u);
-    }
+    // every slot adds 0 or 1 (empty slots add 0 to a spread-out counter), so
+    // no branch per slot
+    const bool o = occupied(rc[j]);
+    const uint32_t s = (uint32_t)j * TB + threadIdx.x;
+    bk[j] = o ? (nbk_bits ? Key<K>::bits(rk[j], shift, nbk_bits) : 0u) : (s & (nbk - 1));
+    rank[j] = atomicAdd(&aux[bk[j]], o ? 1u : 0u);
   }
   __syncthreads();
   const uint32_t d = block_exscan_array<TB>(aux, aux + nbk, (int)nbk, wsum, s_max);
@@ -767,7 +821,11 @@ __device__ __forceinline__ uint32_t leaf_sort_write(K* tk, C* tc, uint32_t* aux,
       const uint32_t b = nbk_bits ? Key<K>::bits(x, shift, nbk_bits) : 0u;
       const uint32_t a = boff[b], m = aux[b];
       uint32_t r = 0;
-      for (uint32_t t = a; t < a + m; ++t) r += tk[t] < x;
+      uint32_t t = a;
+      for (; t + 4 <= a + m; t += 4)
+        r += (uint32_t)(tk[t] < x) + (uint32_t)(tk[t + 1] < x) + (uint32_t)(tk[t + 2] < x) +
+             (uint32_t)(tk[t + 3] < x);
+      for (; t < a + m; ++t) r += tk[t] < x;
       dst[begin + a + r] = x;
       tmp_cnt[begin + a + r] = (uint32_t)tc[i];
     }
@@ -824,8 +882,13 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int k, uint64_t* bufA, uint
     if (!list && n > small_max) continue;
     const uint64_t* src = lf.buf ? bufB : bufA;
     uint64_t* dst = lf.buf ? bufA : bufB;
-    const uint32_t Cn = leaf_slots<TB, CMAX>(n, cmax_rt);
+    // First try a table sized for half the records being distinct; if it
+    // fills up, count the leaf again with a table large enough for all.
+    const uint32_t Cfull = leaf_slots<TB, CMAX>(n, cmax_rt);
+    uint32_t Cn = leaf_slots<TB, CMAX>(n / 2, cmax_rt);
+    for (;;) {
     const uint32_t cmask = Cn - 1;
+    const int slot_bits = 31 - __builtin_clz(Cn);
     for (uint32_t i = threadIdx.x; i < Cn; i += TB) {
       tk[i] = EMPTY;
       tc[i] = 0;
@@ -838,7 +901,10 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int k, uint64_t* bufA, uint
     const uint32_t limit = Cn - (Cn >> 3);
     const bool track = n >= limit;  // fewer records than the limit cannot overflow
     // records are loaded R per thread before inserting, so that the loads of a
-    // batch are in flight together instead of one round trip per insert
+    // batch are in flight together instead of one round trip per insert. The
+    // probe loop has a single exit flag (always-CAS: a CAS on a slot holding
+    // another key just returns that key), which keeps divergent control flow,
+    // and its scalar bookkeeping, small.
     for (uint64_t base = lf.begin; base < lf.end; base += (uint64_t)TB * R) {
       if (ovf_get(&s_ovf)) break;
       unsigned long long kb[R];
@@ -850,31 +916,30 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int k, uint64_t* bufA, uint
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const unsigned long long key = kb[j];
-        if (key == EMPTY) continue;
-        uint32_t pos = (uint32_t)fmix64(key) & cmask;
-        bool done = false;
-        for (uint32_t probe = 0; probe < Cn; ++probe) {
-          unsigned long long cur = tk[pos];
-          if (cur == EMPTY) {
-            cur = atomicCAS(&tk[pos], EMPTY, key);
-            if (cur == EMPTY) {
-              atomicAdd(&tc[pos], 1u);
-              if (track && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
-              done = true;
-              break;
-            }
-          }
-          if (cur == key) {
+        uint32_t pos = slot_hash(key, slot_bits);
+        bool todo = key != EMPTY;
+        uint32_t probes = 0;
+        while (todo) {
+          const unsigned long long prev = atomicCAS(&tk[pos], EMPTY, key);
+          const bool hit = (prev == EMPTY) | (prev == key);
+          if (hit) {
             atomicAdd(&tc[pos], 1u);
-            done = true;
-            break;
+            if (track && prev == EMPTY && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
           }
           pos = (pos + 1) & cmask;
+          todo = !hit & (++probes < Cn);
+          if (!hit && probes >= Cn) ovf_set(&s_ovf);
         }
-        if (!done) ovf_set(&s_ovf);
       }
     }
     __syncthreads();
+    if (ovf_get(&s_ovf) && Cn < Cfull) {
+      Cn = Cfull;
+      __syncthreads();
+      continue;  // retry this leaf with the full table
+    }
+    break;
+    }
     if (ovf_get(&s_ovf)) {
       if (threadIdx.x == 0) {
         d_out[l] = kLeafOverflow;
@@ -926,7 +991,9 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int k, u128* bufA, u128* b
     if (!list && n > small_max) continue;
     const u128* src = lf.buf ? bufB : bufA;
     u128* dst = lf.buf ? bufA : bufB;
-    const uint32_t Cn = leaf_slots<TB, CMAX>(n, cmax_rt);
+    const uint32_t Cfull = leaf_slots<TB, CMAX>(n, cmax_rt);
+    uint32_t Cn = leaf_slots<TB, CMAX>(n / 2, cmax_rt);
+    for (;;) {
     const uint32_t cmask = Cn - 1;
     for (uint32_t i = threadIdx.x; i < Cn; i += TB) tc[i] = 0;
     if (threadIdx.x == 0) {
@@ -986,6 +1053,13 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int k, u128* bufA, u128* b
       }
     }
     __syncthreads();
+    if (ovf_get(&s_ovf) && Cn < Cfull) {
+      Cn = Cfull;
+      __syncthreads();
+      continue;  // retry this leaf with the full table
+    }
+    break;
+    }
     if (ovf_get(&s_ovf)) {
       if (threadIdx.x == 0) {
         d_out[l] = kLeafOverflow;
@@ -1087,9 +1161,9 @@ constexpr int kScatterTB128 = 512;
 constexpr int kSplitTB64 = 1024;
 constexpr int kSplitTB128 = 512;
 constexpr int kSplitR = 8;
-constexpr int kLeafTB = 1024;
-constexpr int kLeafCmax64 = 8192;
-constexpr int kLeafCmax128 = 4096;
+constexpr int kLeafTB = 512;
+constexpr int kLeafCmax64 = 4096;
+constexpr int kLeafCmax128 = 2048;
 constexpr unsigned kPersistentGrid = 1024;  // blocks of the persistent kernels
 constexpr int kSmallCmax64 = 1024;  // one-wave leaf kernel: slots of its private table
 constexpr int kSmallCmax128 = 512;
@@ -1107,7 +1181,7 @@ inline unsigned persistent(uint64_t max_n, unsigned cap) {
 
 }  // namespace
 
-int max_leaf_slots_log2(bool wide) { return wide ? 12 : 13; }
+int max_leaf_slots_log2(bool wide) { return wide ? 11 : 12; }
 int max_shard_bits() { return kMaxShardBits; }
 int split_tile(bool wide) { return wide ? kSplitTB128 * kSplitR : kSplitTB64 * kSplitR; }
 

@@ -491,7 +491,9 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   q.C = 1ull << q.slots_log2;
   // default leaf size: about half of what the one-wave leaf kernel takes, so
   // that nearly all leaves (after the split's size spread) stay in that kernel
-  q.T = q.o.leaf_target > 0 ? (uint64_t)q.o.leaf_target : (kc::small_leaf_max(q.wide) + 1) / 2;
+  // default leaf size: half of the largest table, so that the size spread of
+  // the split leaves nearly every leaf within one table
+  q.T = q.o.leaf_target > 0 ? (uint64_t)q.o.leaf_target : (q.C * 3) / 4;
   q.H = q.o.leaf_attempt > 0 ? (uint64_t)q.o.leaf_attempt : (q.C * 7) / 8;
   int sb = q.o.shard_bits;
   if (sb <= 0) {
