@@ -26,19 +26,27 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
 def stage_bytes(st: dict, k: int) -> dict:
-    """Algorithmic HBM bytes of each stage of one call (bytes model)."""
+    """Algorithmic HBM bytes of each stage of one call (the bytes model in the design doc).
+
+    N bases, W valid windows, D distinct keys, K key bytes (8 for k <= 32, else 16).
+    Records are written once by the owner scatter, read by the split histogram,
+    read and written by the split scatter, read by the leaf count, which writes
+    (key, count) pairs that the concat reads and writes to the output.
+    """
     N = st["n_bases"]
     W = st["valid_windows"]
     D = st["distinct"]
     K = 16 if k > 32 else 8
-    levels = st["n_levels"]
+    packed = N / 4 + N / 8 + N / 8          # 2-bit bases + invalid mask + read-end mask
     return {
-        "pack": N * 1.0 + N / 4 + N / 8 + N / 8,          # read ASCII, write 2-bit + two masks
-        "window_hist": N / 4 + N / 8 + N / 8,              # read packed bases + masks
-        "owner_scatter": N / 4 + N / 8 + N / 8 + K * W,    # read packed, write one record per window
-        "split": levels * 3 * K * W,                       # per level: read (hist), read + write (scatter)
-        "leaf_count": K * W + (K + 4) * D,                 # read records, write sorted pairs
-        "concat": 2 * (K + 4) * D,                         # read pairs, write output
+        "pack": N + packed,                  # read ASCII, write packed + masks
+        "window_hist": packed,               # read packed + masks
+        "owner_scatter": packed + K * W,     # read packed, write one record per window
+        "split_hist": K * W,                 # read records
+        "split_scatter": 2 * K * W,          # read + write records
+        "leaf_large": K * st["large_records"] + (K + 4) * st["large_distinct"],
+        "leaf_small": K * (W - st["large_records"]) + (K + 4) * (D - st["large_distinct"]),
+        "concat": 2 * (K + 4) * D,           # read pairs, write output
     }
 
 
@@ -101,7 +109,10 @@ def main() -> int:
     sb = stage_bytes(st, k)
     dom = max((n for n in avg if n in sb), key=lambda n: avg[n])
     achieved = sb[dom] / (avg[dom] / 1e3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+    kernel_names = {"leaf_large": "k_leaf_count64<512, 4096, 4>" if k <= 32 else
+                    "k_leaf_count128<512, 2048, 4>"}
+    roofline = {"bound": "hbm", "kernel": kernel_names.get(dom, dom), "stage": dom,
+                "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None,
                 "stage_ms": {n: round(v, 4) for n, v in avg.items()},

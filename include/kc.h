@@ -59,13 +59,12 @@ typedef struct kc_options {
                           (owner buckets are unions of shards); 1..10 */
   int leaf_target;     /* target valid windows per leaf partition when splitting */
   int leaf_attempt;    /* partitions up to this many windows are counted directly */
-  int table_slots_log2;/* log2 of the LDS open-addressing table per leaf (10..13 for
-                          k<=32, 10..12 for k>32) */
+  int table_slots_log2;/* log2 of the largest LDS open-addressing table per leaf
+                          (10..12 for k<=32, 10..11 for k>32) */
   int check;           /* 1 = run the device self-check of the output (sorted,
                           canonical, in range, sum of counts == valid windows) */
   int timing;          /* 1 = record per-stage times (kc_last_stats) */
-  int mode;            /* 0 = partitioned LDS counting (default);
-                          1 = one global open-addressing HBM table, then sort */
+  int mode;            /* must be 0 (partitioned counting in LDS tables) */
   int reserved[5];
 } kc_options;
 
@@ -79,10 +78,15 @@ typedef struct kc_stats {
   uint64_t n_overflow;     /* leaf attempts that overflowed the table and were split */
   uint64_t max_leaf_windows;
   uint64_t max_owner_windows; /* windows in the largest of the P owner buckets */
-  uint64_t table_slots;    /* slots of the global table (mode 1), else 0 */
-  double   ms_total;       /* host wall time of the call */
-  double   ms_stage[8];    /* timing=1: pack, window-hist, owner-scatter, split, leaf-count,
-                              concat, check, global-table (ms, device events) */
+  uint64_t table_slots;    /* reserved (0) */
+  uint64_t large_records;   /* records counted by the 512-thread leaf kernel */
+  uint64_t large_distinct;  /* distinct keys it wrote */
+  double   ms_total;        /* host wall time of the call */
+  double   ms_stage[12];    /* timing=1, device events on the call's stream (ms):
+                               0 pack, 1 window histogram, 2 owner scatter (with the shard
+                               plan), 3 split histogram, 4 split scatter (with the leaf plan),
+                               5 small-leaf count (with leaf classification), 6 large-leaf
+                               count, 7 output offsets, 8 concat, 9 self-check, 10-11 unused */
 } kc_stats;
 
 /* Count canonical k-mers (plain form).
@@ -104,6 +108,38 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
 int kc_count_ex(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
                 uint64_t* out_keys, uint32_t* out_counts, uint64_t out_capacity,
                 uint64_t* n_out, const kc_options* opt, void* stream);
+
+/* ---- Batched form: many independent read sets counted together.
+ * The sets are consecutive in one read stream: set s holds host_set_reads[s]
+ * reads and host_set_bytes[s] bytes, and has its own k (1..32). A set's
+ * result is exactly what kc_count gives for its reads alone. All sets are
+ * counted in one pass per distinct k with keys (set id << 2k) | k-mer, so the
+ * counts of different sets never mix; the passes and the final placement of
+ * each set's pairs are recorded once into a HIP graph and replayed.
+ *
+ * kc_batch_plan: host arrays of n_sets entries; P as in kc_count; opt may be
+ *   NULL. Allocates device memory for the batch; *plan receives the handle.
+ * kc_batch_run: reads/offsets are device arrays laid out as planned
+ *   (offsets has sum(host_set_reads)+1 entries); out_keys/out_counts device
+ *   arrays of out_capacity entries (one uint64 key each); host_out_set_offsets
+ *   a host array of n_sets+1 entries receiving where each set's pairs start.
+ *   Returns KC_E_INVAL if the inputs do not match the plan, KC_E_CAPACITY (with
+ *   *n_out set) if the outputs are too small. The graph is recorded on the
+ *   first run and recorded again when a pointer or the capacity changes.
+ *   Runs with one plan must not overlap; the plan keeps its scratch memory.
+ * kc_batch_max_outputs: an upper bound of the pairs of the batch.
+ * kc_batch_stats: totals of the last run (windows, distinct, leaves, times).
+ * kc_batch_free: releases the plan. */
+typedef struct kc_batch kc_batch;
+int kc_batch_plan(const uint64_t* host_set_reads, const uint64_t* host_set_bytes,
+                  const int* host_ks, uint32_t n_sets, int P, const kc_options* opt,
+                  kc_batch** plan);
+int kc_batch_run(kc_batch* plan, const uint8_t* reads, const uint64_t* offsets,
+                 uint64_t* out_keys, uint32_t* out_counts, uint64_t out_capacity,
+                 uint64_t* host_out_set_offsets, uint64_t* n_out, void* stream);
+uint64_t kc_batch_max_outputs(const kc_batch* plan);
+int kc_batch_stats(const kc_batch* plan, kc_stats* out);
+void kc_batch_free(kc_batch* plan);
 
 /* Upper bound on the number of output keys (= number of length-k windows,
  * valid or not): sum over reads of max(0, len - k + 1). host_offsets is a

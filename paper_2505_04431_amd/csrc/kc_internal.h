@@ -42,11 +42,23 @@ struct DevState {
   unsigned long long n_leaves;  // leaf slots
   unsigned long long D;         // distinct keys (sum of leaf counts)
   unsigned long long n_large;   // leaves handled by the block-wide leaf kernel
+  unsigned long long large_records, large_distinct;  // work of the block-wide leaf kernel
   unsigned int overflow;        // a leaf table overflowed (device-planned path cannot finish)
   unsigned int count_overflow;  // a count exceeds 2^32-1
   unsigned int pad[2];
   CheckResult check;
 };
+
+// Read sets of a batch, for the window kernels: set_byte_off[s] is the first
+// byte of set s relative to the packed stream (n_sets + 1 entries), and
+// set_local[s] its id within the k-class being counted (kNoSet if the set
+// belongs to another class).
+struct BatchSets {
+  const unsigned long long* set_byte_off;
+  const uint32_t* set_local;
+  uint32_t n_sets;
+};
+constexpr uint32_t kNoSet = 0xFFFFFFFFu;
 
 constexpr int kMaxShardBits = 10;  // first-level shards (owner buckets are unions of them)
 constexpr int kSplitMaxBits = 10;  // sub-bins per split step: up to 1024
@@ -63,13 +75,17 @@ hipError_t launch_pack(const uint8_t* src, uint64_t n_bytes, const uint64_t* off
                        uint64_t n_reads, uint64_t off0, uint64_t* packed, uint64_t* inv,
                        uint64_t* endm, uint64_t nchunks, hipStream_t s);
 
+// Window kernels over the bytes [byte_begin, byte_end) of the packed stream.
+// keybits = 2k (plain) or 2k + set id bits (batch: batch != nullptr).
 hipError_t launch_window_hist(bool wide, const uint64_t* packed, const uint64_t* inv,
-                              const uint64_t* endm, uint64_t n_bytes, int k, int shard_bits,
+                              const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end, int k,
+                              int keybits, int shard_bits, const BatchSets* batch,
                               unsigned long long* hist, unsigned long long* wcount,
                               hipStream_t s);
 
 hipError_t launch_window_scatter(bool wide, const uint64_t* packed, const uint64_t* inv,
-                                 const uint64_t* endm, uint64_t n_bytes, int k, int shard_bits,
+                                 const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end,
+                                 int k, int keybits, int shard_bits, const BatchSets* batch,
                                  unsigned long long* cursor, void* out, hipStream_t s);
 
 // Device planning of the first split level. order[] lists shards
@@ -107,9 +123,12 @@ hipError_t launch_split_scatter(bool wide, const void* src, void* dst, const Spl
 // Leaves of at most small_leaf_max() records are handled by one-wave
 // workgroups with private tables; larger ones (listed in large_list, which
 // holds max_leaves entries) by 1024-thread workgroups.
-hipError_t launch_leaf_count(bool wide, int k, void* bufA, void* bufB, uint32_t* tmp_cnt,
+hipError_t launch_leaf_small(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
-                             uint32_t* d_out, int slots_log2, uint32_t* large_list,
+                             uint32_t* d_out, uint32_t* large_list, hipStream_t s);
+hipError_t launch_leaf_large(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
+                             const Leaf* leaves, DevState* st, uint64_t max_leaves,
+                             uint32_t* d_out, int slots_log2, const uint32_t* large_list,
                              hipStream_t s);
 uint64_t small_leaf_max(bool wide);
 
@@ -123,6 +142,27 @@ hipError_t launch_concat(bool wide, const void* bufA, const void* bufB, const ui
                          const Leaf* leaves, const uint32_t* d, const unsigned long long* out_off,
                          const DevState* st, uint64_t max_leaves, uint64_t cap,
                          uint64_t* out_keys, uint32_t* out_counts, hipStream_t s);
+
+// Batch helpers: class concat (k-mer, count, set id within the class), set
+// bounds in a class output, global set offsets and the final gather.
+hipError_t launch_concat_batch(bool wide, const void* bufA, const void* bufB,
+                               const uint32_t* tmp_cnt, const Leaf* leaves, const uint32_t* d,
+                               const unsigned long long* out_off, const DevState* st,
+                               uint64_t max_leaves, uint64_t cap, int k, uint64_t* out_keys,
+                               uint32_t* out_counts, uint32_t* out_set, hipStream_t s);
+hipError_t launch_set_bounds(const uint32_t* set, const DevState* st, uint64_t max_pairs,
+                             uint32_t n_local, unsigned long long* start, hipStream_t s);
+hipError_t launch_batch_offsets(const uint32_t* set_class, const uint32_t* set_local,
+                                const unsigned long long* starts,
+                                const unsigned long long* start_base, uint32_t n_sets,
+                                unsigned long long* set_off, hipStream_t s);
+hipError_t launch_batch_gather(const uint32_t* set_class, const uint32_t* set_local,
+                               const unsigned long long* starts,
+                               const unsigned long long* start_base,
+                               const unsigned long long* class_base, const uint64_t* cls_keys,
+                               const uint32_t* cls_counts, const unsigned long long* set_off,
+                               uint32_t n_sets, uint64_t cap, uint64_t* out_keys,
+                               uint32_t* out_counts, hipStream_t s);
 
 hipError_t launch_check(bool wide, const uint64_t* keys, const uint32_t* counts, uint64_t n,
                         int k, CheckResult* res, hipStream_t s);

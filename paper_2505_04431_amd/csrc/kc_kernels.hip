@@ -335,15 +335,51 @@ __device__ __forceinline__ void canon_run(uint64_t p0, uint64_t p1, uint64_t p2,
 }
 
 template <typename K>
-__device__ __forceinline__ uint32_t shard_of(K key, int k, int shard_bits) {
-  return (uint32_t)(key >> (2 * k - shard_bits));
+__device__ __forceinline__ uint32_t shard_of(K key, int keybits, int shard_bits) {
+  return (uint32_t)(key >> (keybits - shard_bits));
 }
 
-template <typename K, int S, int TB>
+// Keys of a thread's S window starts. Plain counting: the canonical k-mer. In
+// a batch of read sets, the key of a window is (set id within its k-class <<
+// 2k) | canonical k-mer, so that sorting keys sorts by set, then k-mer; windows
+// of sets outside the class are dropped from vm. Returns the updated vm.
+template <typename K, typename Kc, int S, bool BATCH>
+__device__ __forceinline__ uint32_t window_keys(const uint64_t* __restrict__ packed, uint64_t g,
+                                                int k, uint32_t vm, const BatchSets& bs,
+                                                K (&key)[S]) {
+  uint64_t p0, p1, p2;
+  load_window_words<Kc, S>(packed, g, p0, p1, p2);
+  Kc c[S];
+  canon_run<Kc, S>(p0, p1, p2, g, k, c);
+  if (!BATCH) {
+#pragma unroll
+    for (int i = 0; i < S; ++i) key[i] = (K)c[i];
+    return vm;
+  }
+  uint32_t lo = 0, hi = bs.n_sets - 1;  // last set whose first byte is <= g
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (bs.set_byte_off[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  uint32_t set = lo;
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    if (!(vm & (1u << i))) continue;
+    while (set + 1 < bs.n_sets && g + i >= bs.set_byte_off[set + 1]) ++set;
+    const uint32_t loc = bs.set_local[set];
+    if (loc == kNoSet) vm &= ~(1u << i);
+    else key[i] = ((K)loc << (2 * k)) | (K)c[i];
+  }
+  return vm;
+}
+
+// Threads t in [t_begin, t_end) each take window starts [t*S, t*S + S).
+template <typename K, typename Kc, int S, int TB, bool BATCH>
 __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__ packed,
                                                     const uint64_t* __restrict__ inv,
                                                     const uint64_t* __restrict__ endm,
-                                                    uint64_t n_threads, int k, int shard_bits,
+                                                    uint64_t t_begin, uint64_t t_end, int k,
+                                                    int keybits, int shard_bits, BatchSets bs,
                                                     unsigned long long* __restrict__ hist,
                                                     unsigned long long* __restrict__ wcount) {
   __shared__ uint32_t sh[1 << kMaxShardBits];
@@ -351,18 +387,16 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
   for (int i = threadIdx.x; i < nb; i += TB) sh[i] = 0;
   __syncthreads();
   uint32_t w = 0;
-  for (uint64_t t = (uint64_t)blockIdx.x * TB + threadIdx.x; t < n_threads;
+  for (uint64_t t = t_begin + (uint64_t)blockIdx.x * TB + threadIdx.x; t < t_end;
        t += (uint64_t)gridDim.x * TB) {
     const uint64_t g = t * S;
     uint32_t vm = valid_starts<S>(inv, endm, g, k);
     if (!vm) continue;
-    uint64_t p0, p1, p2;
-    load_window_words<K, S>(packed, g, p0, p1, p2);
     K keys[S];
-    canon_run<K, S>(p0, p1, p2, g, k, keys);
+    vm = window_keys<K, Kc, S, BATCH>(packed, g, k, vm, bs, keys);
 #pragma unroll
     for (int i = 0; i < S; ++i)
-      if (vm & (1u << i)) atomicAdd(&sh[shard_of(keys[i], k, shard_bits)], 1u);
+      if (vm & (1u << i)) atomicAdd(&sh[shard_of(keys[i], keybits, shard_bits)], 1u);
     w += __builtin_popcount(vm);
   }
   // per-wave sum of valid windows, one global atomic per wave
@@ -375,11 +409,12 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
 
 // Owner-major scatter of window records into shard slices (cursor[i] starts at
 // shard i's slice begin). One tile = TB*S window starts.
-template <typename K, int S, int TB>
+template <typename K, typename Kc, int S, int TB, bool BATCH>
 __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restrict__ packed,
                                                        const uint64_t* __restrict__ inv,
                                                        const uint64_t* __restrict__ endm,
-                                                       uint64_t n_threads, int k, int shard_bits,
+                                                       uint64_t t_begin, uint64_t t_end, int k,
+                                                       int keybits, int shard_bits, BatchSets bs,
                                                        unsigned long long* __restrict__ cursor,
                                                        K* __restrict__ out) {
   constexpr int NBMAX = 1 << kMaxShardBits;
@@ -390,23 +425,21 @@ __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restric
   __shared__ unsigned long long gbase[NBMAX];
   __shared__ uint32_t wsum[TB / 64];
   const int nb = 1 << shard_bits;
-  const uint64_t n_tiles = (n_threads + TB - 1) / TB;
+  const uint64_t n_tiles = (t_end - t_begin + TB - 1) / TB;
   for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     for (int i = threadIdx.x; i < nb; i += TB) hist[i] = 0;
     __syncthreads();
-    const uint64_t t = tile * TB + threadIdx.x;
+    const uint64_t t = t_begin + tile * TB + threadIdx.x;
     const uint64_t g = t * S;
-    uint32_t vm = t < n_threads ? valid_starts<S>(inv, endm, g, k) : 0u;
+    uint32_t vm = t < t_end ? valid_starts<S>(inv, endm, g, k) : 0u;
     K key[S];
     uint32_t bin[S], rank[S];
     if (vm) {
-      uint64_t p0, p1, p2;
-      load_window_words<K, S>(packed, g, p0, p1, p2);
-      canon_run<K, S>(p0, p1, p2, g, k, key);
+      vm = window_keys<K, Kc, S, BATCH>(packed, g, k, vm, bs, key);
 #pragma unroll
       for (int i = 0; i < S; ++i) {
         if (vm & (1u << i)) {
-          bin[i] = shard_of(key[i], k, shard_bits);
+          bin[i] = shard_of(key[i], keybits, shard_bits);
           rank[i] = atomicAdd(&hist[bin[i]], 1u);
         }
       }
@@ -852,7 +885,7 @@ __device__ bool occ64(unsigned long long c) { return c != 0; }
 // slot is claimed by a 64-bit CAS of the key word itself; the count is then
 // added with an atomic add.
 template <int TB, int CMAX, int R>
-__global__ void __launch_bounds__(TB) k_leaf_count64(int k, uint64_t* bufA, uint64_t* bufB,
+__global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA, uint64_t* bufB,
                                                      uint32_t* __restrict__ tmp_cnt,
                                                      const Leaf* __restrict__ leaves,
                                                      DevState* __restrict__ st,
@@ -949,9 +982,15 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int k, uint64_t* bufA, uint
       continue;
     }
     const uint32_t d = leaf_sort_write<unsigned long long, uint32_t, TB, CMAX / TB>(
-        tk, tc, aux, wsum, &s_max, Cn, 2 * k, (int)lf.bits, (unsigned long long*)dst, tmp_cnt,
+        tk, tc, aux, wsum, &s_max, Cn, keybits, (int)lf.bits, (unsigned long long*)dst, tmp_cnt,
         lf.begin, occ32);
-    if (threadIdx.x == 0) d_out[l] = d;
+    if (threadIdx.x == 0) {
+      d_out[l] = d;
+      if (list) {
+        atomicAdd(&st->large_records, (unsigned long long)n);
+        atomicAdd(&st->large_distinct, (unsigned long long)d);
+      }
+    }
     __syncthreads();
   }
 }
@@ -961,7 +1000,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int k, uint64_t* bufA, uint
 // publishes the count. Others seeing LOCK retry the same slot; the claimer
 // publishes in the same pass without waiting on anyone, so the retry ends.
 template <int TB, int CMAX, int R>
-__global__ void __launch_bounds__(TB) k_leaf_count128(int k, u128* bufA, u128* bufB,
+__global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u128* bufB,
                                                       uint32_t* __restrict__ tmp_cnt,
                                                       const Leaf* __restrict__ leaves,
                                                       DevState* __restrict__ st,
@@ -1071,10 +1110,14 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int k, u128* bufA, u128* b
     for (uint32_t i = threadIdx.x; i < Cn; i += TB)
       if (tc[i] > 0xFFFFFFFFull) s_cov = 1;
     const uint32_t d = leaf_sort_write<u128, unsigned long long, TB, CMAX / TB>(
-        tk, tc, aux, wsum, &s_max, Cn, 2 * k, (int)lf.bits, dst, tmp_cnt, lf.begin, occ64);
+        tk, tc, aux, wsum, &s_max, Cn, keybits, (int)lf.bits, dst, tmp_cnt, lf.begin, occ64);
     if (threadIdx.x == 0) {
       d_out[l] = d;
       if (s_cov) atomicOr(&st->count_overflow, 1u);
+      if (list) {
+        atomicAdd(&st->large_records, (unsigned long long)n);
+        atomicAdd(&st->large_distinct, (unsigned long long)d);
+      }
     }
     __syncthreads();
   }
@@ -1114,6 +1157,106 @@ __global__ void __launch_bounds__(256) k_concat(const K* __restrict__ bufA,
         out_keys[o] = (uint64_t)key;
       }
       out_counts[o] = tmp_cnt[lf.begin + i];
+    }
+  }
+}
+
+// Batch form of concat: writes the k-mer (low 2k bits) and the set id within
+// the class (the bits above) of every pair, in key order.
+template <typename K>
+__global__ void __launch_bounds__(256) k_concat_batch(
+    const K* __restrict__ bufA, const K* __restrict__ bufB, const uint32_t* __restrict__ tmp_cnt,
+    const Leaf* __restrict__ leaves, const uint32_t* __restrict__ d,
+    const unsigned long long* __restrict__ out_off, const DevState* __restrict__ st, uint64_t cap,
+    int k, uint64_t* __restrict__ out_keys, uint32_t* __restrict__ out_counts,
+    uint32_t* __restrict__ out_set) {
+  const unsigned long long n_leaves = st->n_leaves;
+  const unsigned lane = threadIdx.x & 63;
+  const unsigned long long nw = (unsigned long long)gridDim.x * 4;
+  const K kmask = ((K)1 << (2 * k)) - 1;
+  for (unsigned long long l = (unsigned long long)blockIdx.x * 4 + (threadIdx.x >> 6); l < n_leaves;
+       l += nw) {
+    const uint32_t n = d[l];
+    if (n == 0 || n == kLeafOverflow) continue;
+    const Leaf lf = leaves[l];
+    const K* src = lf.buf ? bufA : bufB;
+    const unsigned long long base = out_off[l];
+    for (uint32_t i = lane; i < n; i += 64) {
+      const uint64_t o = base + i;
+      if (o >= cap) break;
+      const K key = src[lf.begin + i];
+      out_keys[o] = (uint64_t)(key & kmask);
+      out_set[o] = (uint32_t)(key >> (2 * k));
+      out_counts[o] = tmp_cnt[lf.begin + i];
+    }
+  }
+}
+
+// start[s] = index of the first pair of set s (within a class output sorted
+// by set); sets without pairs get the index of the next pair. start has
+// n_local + 1 entries; start[n_local] = number of pairs.
+__global__ void k_set_bounds(const uint32_t* __restrict__ set, const DevState* __restrict__ st,
+                             uint32_t n_local, unsigned long long* __restrict__ start) {
+  const unsigned long long n = st->D;
+  if (n == 0) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= n_local; t += gridDim.x * blockDim.x)
+      start[t] = 0;
+    return;
+  }
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const uint32_t s = set[i];
+    const uint32_t from = i == 0 ? 0u : set[i - 1] + 1;
+    for (uint32_t t = from; t <= s; ++t) start[t] = i;
+    if (i == n - 1)
+      for (uint32_t t = s + 1; t <= n_local; ++t) start[t] = n;
+  }
+}
+
+// Global output offsets of the sets (one block): set g is set_local[g] of
+// class set_class[g], whose bounds start at start_base[class] in starts[].
+__global__ void __launch_bounds__(kPlanTB) k_batch_offsets(
+    const uint32_t* __restrict__ set_class, const uint32_t* __restrict__ set_local,
+    const unsigned long long* __restrict__ starts, const unsigned long long* __restrict__ start_base,
+    uint32_t n_sets, unsigned long long* __restrict__ set_off) {
+  __shared__ unsigned long long wsum[kPlanTB / 64];
+  const uint32_t per = (n_sets + kPlanTB - 1) / kPlanTB;
+  const uint32_t b = threadIdx.x * per, e = min(n_sets, b + per);
+  unsigned long long s = 0;
+  for (uint32_t g = b; g < e; ++g) {
+    const unsigned long long* st = starts + start_base[set_class[g]];
+    s += st[set_local[g] + 1] - st[set_local[g]];
+  }
+  unsigned long long total;
+  unsigned long long run = block_exscan<kPlanTB, unsigned long long>(s, wsum, &total);
+  for (uint32_t g = b; g < e; ++g) {
+    set_off[g] = run;
+    const unsigned long long* st = starts + start_base[set_class[g]];
+    run += st[set_local[g] + 1] - st[set_local[g]];
+  }
+  if (threadIdx.x == 0) set_off[n_sets] = total;
+}
+
+// Copy each set's pairs from its class output to its place in the batch
+// output (one wave per set).
+__global__ void __launch_bounds__(256) k_batch_gather(
+    const uint32_t* __restrict__ set_class, const uint32_t* __restrict__ set_local,
+    const unsigned long long* __restrict__ starts, const unsigned long long* __restrict__ start_base,
+    const unsigned long long* __restrict__ class_base, const uint64_t* __restrict__ cls_keys,
+    const uint32_t* __restrict__ cls_counts, const unsigned long long* __restrict__ set_off,
+    uint32_t n_sets, uint64_t cap, uint64_t* __restrict__ out_keys,
+    uint32_t* __restrict__ out_counts) {
+  const unsigned lane = threadIdx.x & 63;
+  for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < n_sets; g += gridDim.x * 4) {
+    const uint32_t c = set_class[g];
+    const unsigned long long* st = starts + start_base[c];
+    const unsigned long long a = st[set_local[g]], e = st[set_local[g] + 1];
+    const unsigned long long o = set_off[g];
+    for (unsigned long long i = a + lane; i < e; i += 64) {
+      const unsigned long long dst = o + (i - a);
+      if (dst >= cap) break;
+      out_keys[dst] = cls_keys[class_base[c] + i];
+      out_counts[dst] = cls_counts[class_base[c] + i];
     }
   }
 }
@@ -1202,38 +1345,58 @@ hipError_t launch_pack(const uint8_t* src, uint64_t n_bytes, const uint64_t* off
   return hipGetLastError();
 }
 
+#define KC_WINDOW_LAUNCH(KERNEL, K, KC, TB, BATCH, GRID)                                    \
+  hipLaunchKernelGGL((KERNEL<K, KC, kWinStarts, TB, BATCH>), dim3(GRID), dim3(TB), 0, s, packed, \
+                     inv, endm, t_begin, t_end, k, keybits, shard_bits, bs, ARG0, ARG1)
+
 hipError_t launch_window_hist(bool wide, const uint64_t* packed, const uint64_t* inv,
-                              const uint64_t* endm, uint64_t n_bytes, int k, int shard_bits,
+                              const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end, int k,
+                              int keybits, int shard_bits, const BatchSets* batch,
                               unsigned long long* hist, unsigned long long* wcount,
                               hipStream_t s) {
-  const uint64_t nthr = (n_bytes + kWinStarts - 1) / kWinStarts;
-  const unsigned grid = grid_for(nthr, kHistTB, 2048);
-  if (wide)
-    hipLaunchKernelGGL((k_window_hist<u128, kWinStarts, kHistTB>), dim3(grid), dim3(kHistTB), 0,
-                       s, packed, inv, endm, nthr, k, shard_bits, hist, wcount);
-  else
-    hipLaunchKernelGGL((k_window_hist<uint64_t, kWinStarts, kHistTB>), dim3(grid), dim3(kHistTB),
-                       0, s, packed, inv, endm, nthr, k, shard_bits, hist, wcount);
+  const uint64_t t_begin = byte_begin / kWinStarts;
+  const uint64_t t_end = (byte_end + kWinStarts - 1) / kWinStarts;
+  const unsigned grid = grid_for(t_end - t_begin, kHistTB, 2048);
+  const BatchSets bs = batch ? *batch : BatchSets{nullptr, nullptr, 0};
+#define ARG0 hist
+#define ARG1 wcount
+  if (batch) {
+    if (wide) KC_WINDOW_LAUNCH(k_window_hist, u128, uint64_t, kHistTB, true, grid);
+    else KC_WINDOW_LAUNCH(k_window_hist, uint64_t, uint64_t, kHistTB, true, grid);
+  } else {
+    if (wide) KC_WINDOW_LAUNCH(k_window_hist, u128, u128, kHistTB, false, grid);
+    else KC_WINDOW_LAUNCH(k_window_hist, uint64_t, uint64_t, kHistTB, false, grid);
+  }
+#undef ARG0
+#undef ARG1
   return hipGetLastError();
 }
 
 hipError_t launch_window_scatter(bool wide, const uint64_t* packed, const uint64_t* inv,
-                                 const uint64_t* endm, uint64_t n_bytes, int k, int shard_bits,
+                                 const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end,
+                                 int k, int keybits, int shard_bits, const BatchSets* batch,
                                  unsigned long long* cursor, void* out, hipStream_t s) {
-  const uint64_t nthr = (n_bytes + kWinStarts - 1) / kWinStarts;
+  const uint64_t t_begin = byte_begin / kWinStarts;
+  const uint64_t t_end = (byte_end + kWinStarts - 1) / kWinStarts;
+  const BatchSets bs = batch ? *batch : BatchSets{nullptr, nullptr, 0};
+#define ARG0 cursor
   if (wide) {
-    const unsigned grid = grid_for(nthr, kScatterTB128, 1u << 20);
-    hipLaunchKernelGGL((k_window_scatter<u128, kWinStarts, kScatterTB128>), dim3(grid),
-                       dim3(kScatterTB128), 0, s, packed, inv, endm, nthr, k, shard_bits, cursor,
-                       (u128*)out);
+    const unsigned grid = grid_for(t_end - t_begin, kScatterTB128, 1u << 20);
+#define ARG1 (u128*)out
+    if (batch) KC_WINDOW_LAUNCH(k_window_scatter, u128, uint64_t, kScatterTB128, true, grid);
+    else KC_WINDOW_LAUNCH(k_window_scatter, u128, u128, kScatterTB128, false, grid);
+#undef ARG1
   } else {
-    const unsigned grid = grid_for(nthr, kScatterTB64, 1u << 20);
-    hipLaunchKernelGGL((k_window_scatter<uint64_t, kWinStarts, kScatterTB64>), dim3(grid),
-                       dim3(kScatterTB64), 0, s, packed, inv, endm, nthr, k, shard_bits, cursor,
-                       (uint64_t*)out);
+    const unsigned grid = grid_for(t_end - t_begin, kScatterTB64, 1u << 20);
+#define ARG1 (uint64_t*)out
+    if (batch) KC_WINDOW_LAUNCH(k_window_scatter, uint64_t, uint64_t, kScatterTB64, true, grid);
+    else KC_WINDOW_LAUNCH(k_window_scatter, uint64_t, uint64_t, kScatterTB64, false, grid);
+#undef ARG1
   }
+#undef ARG0
   return hipGetLastError();
 }
+#undef KC_WINDOW_LAUNCH
 
 hipError_t launch_plan_shards(const unsigned long long* hist, const int* order, int shard_bits,
                               int keybits, uint64_t leaf_target, uint64_t leaf_attempt,
@@ -1293,31 +1456,39 @@ uint64_t small_leaf_max(bool wide) {
   return wide ? 447 : 895;
 }
 
-hipError_t launch_leaf_count(bool wide, int k, void* bufA, void* bufB, uint32_t* tmp_cnt,
+hipError_t launch_leaf_small(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
-                             uint32_t* d_out, int slots_log2, uint32_t* large_list,
-                             hipStream_t s) {
+                             uint32_t* d_out, uint32_t* large_list, hipStream_t s) {
   const uint64_t small_max = small_leaf_max(wide);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &st->n_large, (uint64_t)1, 0ull);
   hipLaunchKernelGGL(k_classify_leaves, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s,
                      leaves, st, small_max, large_list);
   const unsigned gsmall = persistent(max_leaves, kSmallGrid);
-  const unsigned glarge = persistent(max_leaves, kPersistentGrid);
-  if (wide) {
-    hipLaunchKernelGGL((k_leaf_count128<64, kSmallCmax128, 8>), dim3(gsmall), dim3(64), 0, s, k,
+  if (wide)
+    hipLaunchKernelGGL((k_leaf_count128<64, kSmallCmax128, 8>), dim3(gsmall), dim3(64), 0, s, keybits,
                        (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
                        __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max);
-    hipLaunchKernelGGL((k_leaf_count128<kLeafTB, kLeafCmax128, 4>), dim3(glarge), dim3(kLeafTB), 0,
-                       s, k, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out, slots_log2,
-                       (const uint32_t*)large_list, small_max);
-  } else {
-    hipLaunchKernelGGL((k_leaf_count64<64, kSmallCmax64, 8>), dim3(gsmall), dim3(64), 0, s, k,
+  else
+    hipLaunchKernelGGL((k_leaf_count64<64, kSmallCmax64, 8>), dim3(gsmall), dim3(64), 0, s, keybits,
                        (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
                        __builtin_ctz(kSmallCmax64), (const uint32_t*)nullptr, small_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_large(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
+                             const Leaf* leaves, DevState* st, uint64_t max_leaves,
+                             uint32_t* d_out, int slots_log2, const uint32_t* large_list,
+                             hipStream_t s) {
+  const uint64_t small_max = small_leaf_max(wide);
+  const unsigned glarge = persistent(max_leaves, kPersistentGrid);
+  if (wide)
+    hipLaunchKernelGGL((k_leaf_count128<kLeafTB, kLeafCmax128, 4>), dim3(glarge), dim3(kLeafTB), 0,
+                       s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out, slots_log2,
+                       large_list, small_max);
+  else
     hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4>), dim3(glarge), dim3(kLeafTB), 0,
-                       s, k, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
-                       slots_log2, (const uint32_t*)large_list, small_max);
-  }
+                       s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
+                       slots_log2, large_list, small_max);
   return hipGetLastError();
 }
 
@@ -1357,6 +1528,56 @@ hipError_t launch_check(bool wide, const uint64_t* keys, const uint32_t* counts,
     hipLaunchKernelGGL(k_check<u128>, dim3(grid), dim3(256), 0, s, keys, counts, n, k, res);
   else
     hipLaunchKernelGGL(k_check<uint64_t>, dim3(grid), dim3(256), 0, s, keys, counts, n, k, res);
+  return hipGetLastError();
+}
+
+}  // namespace kc
+
+namespace kc {
+
+hipError_t launch_concat_batch(bool wide, const void* bufA, const void* bufB,
+                               const uint32_t* tmp_cnt, const Leaf* leaves, const uint32_t* d,
+                               const unsigned long long* out_off, const DevState* st,
+                               uint64_t max_leaves, uint64_t cap, int k, uint64_t* out_keys,
+                               uint32_t* out_counts, uint32_t* out_set, hipStream_t s) {
+  const unsigned grid = persistent((max_leaves + 3) / 4, 16384);
+  if (wide)
+    hipLaunchKernelGGL(k_concat_batch<u128>, dim3(grid), dim3(256), 0, s, (const u128*)bufA,
+                       (const u128*)bufB, tmp_cnt, leaves, d, out_off, st, cap, k, out_keys,
+                       out_counts, out_set);
+  else
+    hipLaunchKernelGGL(k_concat_batch<uint64_t>, dim3(grid), dim3(256), 0, s,
+                       (const uint64_t*)bufA, (const uint64_t*)bufB, tmp_cnt, leaves, d, out_off,
+                       st, cap, k, out_keys, out_counts, out_set);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_bounds(const uint32_t* set, const DevState* st, uint64_t max_pairs,
+                             uint32_t n_local, unsigned long long* start, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_bounds, dim3(grid_for(max_pairs + n_local + 1, 256, 4096)), dim3(256),
+                     0, s, set, st, n_local, start);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_offsets(const uint32_t* set_class, const uint32_t* set_local,
+                                const unsigned long long* starts,
+                                const unsigned long long* start_base, uint32_t n_sets,
+                                unsigned long long* set_off, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_offsets, dim3(1), dim3(kPlanTB), 0, s, set_class, set_local, starts,
+                     start_base, n_sets, set_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(const uint32_t* set_class, const uint32_t* set_local,
+                               const unsigned long long* starts,
+                               const unsigned long long* start_base,
+                               const unsigned long long* class_base, const uint64_t* cls_keys,
+                               const uint32_t* cls_counts, const unsigned long long* set_off,
+                               uint32_t n_sets, uint64_t cap, uint64_t* out_keys,
+                               uint32_t* out_counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_gather, dim3(grid_for(n_sets, 4, 8192)), dim3(256), 0, s, set_class,
+                     set_local, starts, start_base, class_base, cls_keys, cls_counts, set_off,
+                     n_sets, cap, out_keys, out_counts);
   return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ struct Ctx {
   int order_P = -1, order_sb = -1;
   void* host = nullptr;  // pinned staging for small device<->host copies
   size_t host_cap = 0;
-  hipEvent_t ev[16] = {};
+  hipEvent_t ev[32] = {};
   bool ev_ok = false;
 
   ~Ctx() {
@@ -155,7 +155,7 @@ struct Timer {
   hipStream_t s;
   bool on;
   int n = 0;
-  int stage[16];
+  int stage[32];
   Timer(Ctx& c_, hipStream_t s_, bool on_) : c(c_), s(s_), on(on_) {
     if (on && !c.ev_ok) {
       for (hipEvent_t& e : c.ev) hipchk(hipEventCreate(&e), "hipEventCreate");
@@ -163,7 +163,7 @@ struct Timer {
     }
   }
   void mark(int st) {  // the interval from the previous mark to this one is charged to `st`
-    if (!on || n >= 16) return;
+    if (!on || n >= 32) return;
     stage[n] = st;
     hipchk(hipEventRecord(c.ev[n], s), "hipEventRecord");
     ++n;
@@ -174,13 +174,22 @@ struct Timer {
     for (int i = 1; i < n; ++i) {
       float ms = 0;
       hipchk(hipEventElapsedTime(&ms, c.ev[i - 1], c.ev[i]), "hipEventElapsedTime");
-      if (stage[i] >= 0 && stage[i] < 8) out.ms_stage[stage[i]] += ms;
+      if (stage[i] >= 0 && stage[i] < 12) out.ms_stage[stage[i]] += ms;
     }
   }
 };
 
-enum { ST_PACK = 0, ST_HIST = 1, ST_SCATTER = 2, ST_SPLIT = 3, ST_LEAF = 4, ST_CONCAT = 5,
-       ST_CHECK = 6, ST_NONE = -1 };
+enum { ST_PACK = 0, ST_HIST = 1, ST_SCATTER = 2, ST_SPLIT_HIST = 3, ST_SPLIT = 4,
+       ST_LEAF_SMALL = 5, ST_LEAF = 6, ST_OUT = 7, ST_CONCAT = 8, ST_CHECK = 9, ST_NONE = -1 };
+
+// Batch layout check: set s must own the bytes [set_byte_off[s], set_byte_off[s+1])
+// of the stream, i.e. offsets[set_first_read[s]] - offsets[0] == set_byte_off[s].
+__global__ void k_batch_layout_ok(const uint64_t* off, const unsigned long long* set_first_read,
+                                  const unsigned long long* set_byte_off, uint32_t n_sets,
+                                  unsigned int* bad) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s <= n_sets && off[set_first_read[s]] - off[0] != set_byte_off[s]) atomicOr(bad, 1u);
+}
 
 __global__ void k_offsets_ok(const uint64_t* off, uint64_t n, unsigned int* bad) {  // sets *bad if decreasing
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -273,7 +282,7 @@ void general_path(Ctx& c, Call& q, kc_stats& S, Timer& tm) {
   const uint64_t W = run;
   upload_sync(c.cursor.p, sbegin.data(), (size_t)q.nb * 8, st);
   hipchk(kc::launch_window_scatter(q.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
-                                   (uint64_t*)c.endm.p, q.N, q.k, q.sb,
+                                   (uint64_t*)c.endm.p, 0, q.N, q.k, q.keybits, q.sb, nullptr,
                                    (unsigned long long*)c.cursor.p, c.bufA.p, st),
          "owner scatter launch");
   tm.mark(ST_SCATTER);
@@ -313,7 +322,11 @@ void general_path(Ctx& c, Call& q, kc_stats& S, Timer& tm) {
       upload_sync(c.leaves.p, lv.data(), na * sizeof(kc::Leaf), st);
       unsigned long long nl = na;
       upload_sync(&dst_state->n_leaves, &nl, 8, st);
-      hipchk(kc::launch_leaf_count(q.wide, q.k, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+      hipchk(kc::launch_leaf_small(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                                   (kc::Leaf*)c.leaves.p, dst_state, na, (uint32_t*)c.dcnt.p,
+                                   (uint32_t*)c.large.p, st),
+             "leaf count launch");
+      hipchk(kc::launch_leaf_large(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                    (kc::Leaf*)c.leaves.p, dst_state, na, (uint32_t*)c.dcnt.p,
                                    q.slots_log2, (uint32_t*)c.large.p, st),
              "leaf count launch");
@@ -433,6 +446,157 @@ void general_path(Ctx& c, Call& q, kc_stats& S, Timer& tm) {
   (void)D;
 }
 
+// One run of the device-planned partitioning over bytes [byte_begin,
+// byte_end) of the packed stream: shard histogram, shard plan, owner scatter,
+// one split level, leaf counts, output offsets and concat. No host
+// synchronization and no allocation happens here (buffers are prepared by
+// pipeline_prepare), so a run can be captured into a graph.
+struct Pipe {
+  bool wide = false;
+  int k = 0, keybits = 0, sb = 0, slots_log2 = 0;
+  uint64_t byte_begin = 0, byte_end = 0;  // bytes scanned for windows
+  uint64_t rec_bound = 0;                 // upper bound of the records (windows)
+  uint64_t T = 0, H = 0;
+  uint64_t max_items = 0, max_leaves = 0;
+  const kc::BatchSets* batch = nullptr;   // batch form (composite keys)
+  const int* order = nullptr;             // device, owner-major shard order
+};
+
+void pipe_bounds(Pipe& p) {
+  const uint64_t tile = (uint64_t)kc::split_tile(p.wide);
+  const uint64_t nb = 1ull << p.sb;
+  p.max_items = p.rec_bound / tile + nb + 1;
+  p.max_leaves = std::min<uint64_t>(nb << kc::kSplitMaxBits, 2 * p.rec_bound / p.T + 2 * nb) + 1;
+}
+
+void pipeline_prepare(Ctx& c, const Pipe& p) {
+  const size_t ksz = p.wide ? 16 : 8;
+  const uint64_t nb = 1ull << p.sb;
+  ensure(c.bufA, std::max<uint64_t>(p.rec_bound, 1) * ksz, "record buffer A");
+  ensure(c.bufB, std::max<uint64_t>(p.rec_bound, 1) * ksz, "record buffer B");
+  ensure(c.tmpcnt, std::max<uint64_t>(p.rec_bound, 1) * 4, "pair counts");
+  ensure(c.hist, nb * 8, "shard histogram");
+  ensure(c.sbegin, nb * 8, "shard begins");
+  ensure(c.cursor, nb * 8, "shard cursors");
+  ensure(c.bins, nb * sizeof(kc::SplitBin), "split bins");
+  ensure(c.items, p.max_items * sizeof(kc::SplitItem), "split items");
+  ensure(c.itemoff, (nb + 1) * 8, "split item offsets");
+  ensure(c.subhist, p.max_leaves * 8, "sub-bin histogram");
+  ensure(c.cursor2, p.max_leaves * 8, "sub-bin cursors");
+  ensure(c.leaves, p.max_leaves * sizeof(kc::Leaf), "leaf table");
+  ensure(c.dcnt, p.max_leaves * 4, "leaf counts");
+  ensure(c.outoff, p.max_leaves * 8, "output offsets");
+  ensure(c.large, p.max_leaves * 4, "large-leaf list");
+  ensure(c.bsum, kc::scan_blocks(p.max_leaves) * 8, "scan block sums");
+}
+
+// Output of a pipeline run: plain (keys of 1 or 2 words, counts) or batch
+// class output (k-mer word, count, set id within the class).
+struct PipeOut {
+  uint64_t* keys;
+  uint32_t* counts;
+  uint32_t* set;  // batch form only
+  uint64_t cap;
+};
+
+void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, const PipeOut& out,
+                      hipStream_t st) {
+  hipchk(kc::launch_fill_u64((unsigned long long*)c.hist.p, 1ull << p.sb, 0, st), "fill launch");
+  hipchk(kc::launch_window_hist(p.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
+                                (uint64_t*)c.endm.p, p.byte_begin, p.byte_end, p.k, p.keybits,
+                                p.sb, p.batch, (unsigned long long*)c.hist.p, &dstate->W, st),
+         "window histogram launch");
+  tm.mark(ST_HIST);
+  hipchk(kc::launch_plan_shards((unsigned long long*)c.hist.p, p.order, p.sb, p.keybits, p.T, p.H,
+                                kc::split_tile(p.wide), (unsigned long long*)c.sbegin.p,
+                                (unsigned long long*)c.cursor.p, (kc::SplitBin*)c.bins.p,
+                                (kc::SplitItem*)c.items.p, (unsigned long long*)c.itemoff.p,
+                                (unsigned long long*)c.subhist.p, p.max_leaves, p.max_items,
+                                dstate, st),
+         "plan_shards launch");
+  hipchk(kc::launch_window_scatter(p.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
+                                   (uint64_t*)c.endm.p, p.byte_begin, p.byte_end, p.k, p.keybits,
+                                   p.sb, p.batch, (unsigned long long*)c.cursor.p, c.bufA.p, st),
+         "owner scatter launch");
+  tm.mark(ST_SCATTER);
+  hipchk(kc::launch_split_hist(p.wide, c.bufA.p, (kc::SplitItem*)c.items.p, dstate, p.max_items,
+                               (kc::SplitBin*)c.bins.p, (unsigned long long*)c.subhist.p, st),
+         "split histogram launch");
+  tm.mark(ST_SPLIT_HIST);
+  hipchk(kc::launch_plan_leaves((unsigned long long*)c.hist.p, (unsigned long long*)c.sbegin.p,
+                                (kc::SplitBin*)c.bins.p, p.sb, (unsigned long long*)c.subhist.p,
+                                (kc::Leaf*)c.leaves.p, (unsigned long long*)c.cursor2.p, st),
+         "plan_leaves launch");
+  hipchk(kc::launch_split_scatter(p.wide, c.bufA.p, c.bufB.p, (kc::SplitItem*)c.items.p, dstate,
+                                  p.max_items, (kc::SplitBin*)c.bins.p,
+                                  (unsigned long long*)c.cursor2.p, st),
+         "split scatter launch");
+  tm.mark(ST_SPLIT);
+  hipchk(kc::launch_leaf_small(p.wide, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                               (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
+                               (uint32_t*)c.large.p, st),
+         "leaf count launch");
+  tm.mark(ST_LEAF_SMALL);
+  hipchk(kc::launch_leaf_large(p.wide, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                               (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
+                               p.slots_log2, (uint32_t*)c.large.p, st),
+         "leaf count launch");
+  tm.mark(ST_LEAF);
+  hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dstate, (unsigned long long*)c.bsum.p,
+                             p.max_leaves, (unsigned long long*)c.outoff.p, st),
+         "plan_out launch");
+  tm.mark(ST_OUT);
+  if (out.set)
+    hipchk(kc::launch_concat_batch(p.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                                   (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
+                                   (unsigned long long*)c.outoff.p, dstate, p.max_leaves, out.cap,
+                                   p.k, out.keys, out.counts, out.set, st),
+           "concat launch");
+  else
+    hipchk(kc::launch_concat(p.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                             (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
+                             (unsigned long long*)c.outoff.p, dstate, p.max_leaves, out.cap,
+                             out.keys, out.counts, st),
+           "concat launch");
+  tm.mark(ST_CONCAT);
+}
+
+// Leaf table size and leaf size targets from the options.
+void table_params(const kc_options& o, bool wide, int& slots_log2, uint64_t& C, uint64_t& T,
+                  uint64_t& H) {
+  const int max_slots = kc::max_leaf_slots_log2(wide);
+  slots_log2 = o.table_slots_log2 > 0 ? std::min(std::max(o.table_slots_log2, 10), max_slots)
+                                      : max_slots;
+  C = 1ull << slots_log2;
+  // default leaf size: three quarters of the largest table, so that after the
+  // size spread of the split nearly every leaf fits one table
+  T = o.leaf_target > 0 ? (uint64_t)o.leaf_target : (C * 3) / 4;
+  H = o.leaf_attempt > 0 ? (uint64_t)o.leaf_attempt : (C * 7) / 8;
+}
+
+int shard_bits_for(const kc_options& o, int P, uint64_t rec_bound, uint64_t T, int keybits) {
+  int sb = o.shard_bits;
+  if (sb <= 0) {
+    sb = std::max(8, ceil_log2((uint64_t)P));
+    sb = std::max(sb, ceil_log2(rec_bound / (T << kc::kSplitMaxBits) + 1));
+  }
+  sb = std::min(sb, kc::max_shard_bits());
+  return std::max(1, std::min(sb, keybits));
+}
+
+// Owner-major shard order on the device, cached in the context per (P, sb).
+const int* device_order(Ctx& c, const Call& q, kc_stats& S, hipStream_t st) {
+  if (c.order_P != q.P || c.order_sb != q.sb) {
+    ensure(c.order, (size_t)q.nb * 4, "owner order");
+    const std::vector<int>& order = owner_order(c, q, S, nullptr);
+    c.order_host.assign(order.begin(), order.end());
+    upload_sync(c.order.p, c.order_host.data(), (size_t)q.nb * 4, st);
+    c.order_P = q.P;
+    c.order_sb = q.sb;
+  }
+  return (const int*)c.order.p;
+}
+
 int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
                uint64_t* out_keys, uint32_t* out_counts, uint64_t cap, uint64_t* n_out,
                const kc_options* opt, hipStream_t st) {
@@ -484,61 +648,28 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   q.wide = k > 32;
   q.keybits = 2 * k;
   q.ksz = q.wide ? 16 : 8;
-  const int max_slots = kc::max_leaf_slots_log2(q.wide);
-  q.slots_log2 = q.o.table_slots_log2 > 0
-                     ? std::min(std::max(q.o.table_slots_log2, 10), max_slots)
-                     : max_slots;
-  q.C = 1ull << q.slots_log2;
-  // default leaf size: about half of what the one-wave leaf kernel takes, so
-  // that nearly all leaves (after the split's size spread) stay in that kernel
-  // default leaf size: half of the largest table, so that the size spread of
-  // the split leaves nearly every leaf within one table
-  q.T = q.o.leaf_target > 0 ? (uint64_t)q.o.leaf_target : (q.C * 3) / 4;
-  q.H = q.o.leaf_attempt > 0 ? (uint64_t)q.o.leaf_attempt : (q.C * 7) / 8;
-  int sb = q.o.shard_bits;
-  if (sb <= 0) {
-    sb = std::max(8, ceil_log2((uint64_t)P));
-    sb = std::max(sb, ceil_log2(q.N / (q.T << kc::kSplitMaxBits) + 1));
-  }
-  sb = std::min(sb, kc::max_shard_bits());
-  sb = std::min(sb, q.keybits);
-  q.sb = sb;
-  q.nb = 1 << sb;
+  table_params(q.o, q.wide, q.slots_log2, q.C, q.T, q.H);
+  q.sb = shard_bits_for(q.o, P, q.N, q.T, q.keybits);
+  q.nb = 1 << q.sb;
 
+  Pipe p;
+  p.wide = q.wide;
+  p.k = k;
+  p.keybits = q.keybits;
+  p.sb = q.sb;
+  p.slots_log2 = q.slots_log2;
+  p.byte_begin = 0;
+  p.byte_end = q.N;
+  p.rec_bound = q.N;  // byte count: an upper bound of the window count
+  p.T = q.T;
+  p.H = q.H;
+  pipe_bounds(p);
   const uint64_t nchunks = (q.N + 63) / 64 + 2;
   ensure(c.packed, nchunks * 16, "packed bases");
   ensure(c.inv, nchunks * 8, "invalid mask");
   ensure(c.endm, nchunks * 8, "end mask");
-  // record buffers sized by the byte count, an upper bound of the window count
-  ensure(c.bufA, q.N * q.ksz, "record buffer A");
-  ensure(c.bufB, q.N * q.ksz, "record buffer B");
-  ensure(c.tmpcnt, q.N * 4, "pair counts");
-  const uint64_t tile = (uint64_t)kc::split_tile(q.wide);
-  const uint64_t max_items = q.N / tile + (uint64_t)q.nb + 1;
-  const uint64_t max_leaves =
-      std::min<uint64_t>((uint64_t)q.nb << kc::kSplitMaxBits, 2 * q.N / q.T + 2 * (uint64_t)q.nb) +
-      1;
-  ensure(c.hist, (size_t)q.nb * 8, "shard histogram");
-  ensure(c.sbegin, (size_t)q.nb * 8, "shard begins");
-  ensure(c.cursor, (size_t)q.nb * 8, "shard cursors");
-  ensure(c.order, (size_t)q.nb * 4, "owner order");
-  ensure(c.bins, (size_t)q.nb * sizeof(kc::SplitBin), "split bins");
-  ensure(c.items, max_items * sizeof(kc::SplitItem), "split items");
-  ensure(c.itemoff, ((size_t)q.nb + 1) * 8, "split item offsets");
-  ensure(c.subhist, max_leaves * 8, "sub-bin histogram");
-  ensure(c.cursor2, max_leaves * 8, "sub-bin cursors");
-  ensure(c.leaves, max_leaves * sizeof(kc::Leaf), "leaf table");
-  ensure(c.dcnt, max_leaves * 4, "leaf counts");
-  ensure(c.outoff, max_leaves * 8, "output offsets");
-  ensure(c.large, max_leaves * 4, "large-leaf list");
-  ensure(c.bsum, kc::scan_blocks(max_leaves) * 8, "scan block sums");
-  if (c.order_P != P || c.order_sb != sb) {
-    const std::vector<int>& order = owner_order(c, q, S, nullptr);
-    c.order_host.assign(order.begin(), order.end());
-    upload_sync(c.order.p, c.order_host.data(), (size_t)q.nb * 4, st);
-    c.order_P = P;
-    c.order_sb = sb;
-  }
+  pipeline_prepare(c, p);
+  p.order = device_order(c, q, S, st);
   kc::DevState* dstate = (kc::DevState*)c.state.p;
 
   tm.mark(ST_NONE);
@@ -546,51 +677,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
                          (uint64_t*)c.inv.p, (uint64_t*)c.endm.p, nchunks, st),
          "pack launch");
   tm.mark(ST_PACK);
-  hipchk(kc::launch_fill_u64((unsigned long long*)c.hist.p, q.nb, 0, st), "fill launch");
-  hipchk(kc::launch_window_hist(q.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
-                                (uint64_t*)c.endm.p, q.N, k, sb, (unsigned long long*)c.hist.p,
-                                &dstate->W, st),
-         "window histogram launch");
-  tm.mark(ST_HIST);
-  // ---- device-planned partitioning: shard plan, scatter, one split level, leaves
-  hipchk(kc::launch_plan_shards((unsigned long long*)c.hist.p, (const int*)c.order.p, sb,
-                                q.keybits, q.T, q.H, (int)tile, (unsigned long long*)c.sbegin.p,
-                                (unsigned long long*)c.cursor.p, (kc::SplitBin*)c.bins.p,
-                                (kc::SplitItem*)c.items.p, (unsigned long long*)c.itemoff.p,
-                                (unsigned long long*)c.subhist.p, max_leaves, max_items, dstate,
-                                st),
-         "plan_shards launch");
-  hipchk(kc::launch_window_scatter(q.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
-                                   (uint64_t*)c.endm.p, q.N, k, sb,
-                                   (unsigned long long*)c.cursor.p, c.bufA.p, st),
-         "owner scatter launch");
-  tm.mark(ST_SCATTER);
-  hipchk(kc::launch_split_hist(q.wide, c.bufA.p, (kc::SplitItem*)c.items.p, dstate, max_items,
-                               (kc::SplitBin*)c.bins.p, (unsigned long long*)c.subhist.p, st),
-         "split histogram launch");
-  hipchk(kc::launch_plan_leaves((unsigned long long*)c.hist.p, (unsigned long long*)c.sbegin.p,
-                                (kc::SplitBin*)c.bins.p, sb, (unsigned long long*)c.subhist.p,
-                                (kc::Leaf*)c.leaves.p, (unsigned long long*)c.cursor2.p, st),
-         "plan_leaves launch");
-  hipchk(kc::launch_split_scatter(q.wide, c.bufA.p, c.bufB.p, (kc::SplitItem*)c.items.p, dstate,
-                                  max_items, (kc::SplitBin*)c.bins.p,
-                                  (unsigned long long*)c.cursor2.p, st),
-         "split scatter launch");
-  tm.mark(ST_SPLIT);
-  hipchk(kc::launch_leaf_count(q.wide, k, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
-                               (kc::Leaf*)c.leaves.p, dstate, max_leaves, (uint32_t*)c.dcnt.p,
-                               q.slots_log2, (uint32_t*)c.large.p, st),
-         "leaf count launch");
-  tm.mark(ST_LEAF);
-  hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dstate, (unsigned long long*)c.bsum.p, max_leaves,
-                             (unsigned long long*)c.outoff.p, st),
-         "plan_out launch");
-  hipchk(kc::launch_concat(q.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
-                           (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
-                           (unsigned long long*)c.outoff.p, dstate, max_leaves, cap, out_keys,
-                           out_counts, st),
-         "concat launch");
-  tm.mark(ST_CONCAT);
+  enqueue_pipeline(c, p, dstate, tm, PipeOut{out_keys, out_counts, nullptr, cap}, st);
   kc::DevState ds = read_state(c, st);  // host sync 2 of 2
   S.n_levels = 1;
   S.n_leaves = ds.n_leaves;
@@ -604,6 +691,8 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   }
   S.valid_windows = ds.W;
   S.distinct = ds.D;
+  S.large_records = ds.large_records;
+  S.large_distinct = ds.large_distinct;
   if (ds.count_overflow) fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
   if (ds.D > cap) {
     *n_out = ds.D;
@@ -638,9 +727,384 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   return KC_OK;
 }
 
+void free_buf(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+}  // namespace
+
+// A planned batch of read sets (opaque in the C ABI).
+struct kc_batch {
+  int device = 0;
+  uint32_t n_sets = 0;
+  int P = 1;
+  kc_options o{};
+  uint64_t n_reads = 0, N = 0;
+  std::vector<unsigned long long> set_first_read, set_byte_off;  // n_sets + 1 each
+  std::vector<int> ks;
+  struct Class {
+    int k = 0, set_bits = 0;
+    std::vector<uint32_t> sets;
+    Pipe pipe;
+    uint64_t out_base = 0, out_cap = 0, start_base = 0;
+    DevBuf order, set_local;
+    kc::BatchSets bs{};
+  };
+  std::vector<Class> cls;
+  Ctx ctx;
+  DevBuf set_first_read_dev, set_byte_off_dev, set_class_dev, set_local_dev, starts,
+      start_base_dev, class_base_dev, cls_keys, cls_counts, cls_set, set_off, states, flag;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  const void* key[5] = {};
+  uint64_t key_cap = 0, key_off0 = 0;
+  kc_stats stats{};
+
+  ~kc_batch() {
+    int prev = -1;
+    if (hipGetDevice(&prev) == hipSuccess) (void)hipSetDevice(device);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (Class& c : cls) {
+      free_buf(c.order);
+      free_buf(c.set_local);
+    }
+    DevBuf* all[] = {&set_first_read_dev, &set_byte_off_dev, &set_class_dev, &set_local_dev,
+                     &starts, &start_base_dev, &class_base_dev, &cls_keys, &cls_counts, &cls_set,
+                     &set_off, &states, &flag};
+    for (DevBuf* b : all) free_buf(*b);
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+namespace {
+
+int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_bytes,
+                    const int* host_ks, uint32_t n_sets, int P, const kc_options* opt,
+                    kc_batch** out) {
+  if (!out) fail(KC_E_INVAL, "plan pointer is NULL");
+  *out = nullptr;
+  if (!host_set_reads || !host_set_bytes || !host_ks || n_sets == 0)
+    fail(KC_E_INVAL, "batch needs at least one set and host arrays");
+  if (P < 1) fail(KC_E_INVAL, "P must be >= 1");
+  std::unique_ptr<kc_batch> b(new kc_batch());
+  hipchk(hipGetDevice(&b->device), "hipGetDevice");
+  b->n_sets = n_sets;
+  b->P = P;
+  std::memset(&b->o, 0, sizeof(b->o));
+  if (opt) b->o = *opt;
+  if (b->o.mode != 0) fail(KC_E_INVAL, "mode must be 0");
+  b->ks.assign(host_ks, host_ks + n_sets);
+  b->set_first_read.assign(n_sets + 1, 0);
+  b->set_byte_off.assign(n_sets + 1, 0);
+  for (uint32_t s = 0; s < n_sets; ++s) {
+    if (b->ks[s] < 1 || b->ks[s] > 32) fail(KC_E_INVAL, "batched counting takes 1 <= k <= 32");
+    b->set_first_read[s + 1] = b->set_first_read[s] + host_set_reads[s];
+    b->set_byte_off[s + 1] = b->set_byte_off[s] + host_set_bytes[s];
+  }
+  b->n_reads = b->set_first_read[n_sets];
+  b->N = b->set_byte_off[n_sets];
+  // one class per distinct k; a class is counted with keys (set id << 2k) | k-mer
+  std::vector<int> kv(b->ks);
+  std::sort(kv.begin(), kv.end());
+  kv.erase(std::unique(kv.begin(), kv.end()), kv.end());
+  std::vector<uint32_t> set_class(n_sets), set_local(n_sets);
+  uint64_t out_base = 0, start_base = 0;
+  Ctx& c = b->ctx;
+  c.device = b->device;
+  const uint64_t nchunks = (b->N + 63) / 64 + 2;
+  ensure(c.packed, nchunks * 16, "packed bases");
+  ensure(c.inv, nchunks * 8, "invalid mask");
+  ensure(c.endm, nchunks * 8, "end mask");
+  b->cls.resize(kv.size());
+  for (size_t ci = 0; ci < kv.size(); ++ci) {
+    kc_batch::Class& C = b->cls[ci];
+    C.k = kv[ci];
+    uint64_t bytes = 0, lo = ~0ull, hi = 0;
+    for (uint32_t s = 0; s < n_sets; ++s) {
+      if (b->ks[s] != C.k) continue;
+      set_class[s] = (uint32_t)ci;
+      set_local[s] = (uint32_t)C.sets.size();
+      C.sets.push_back(s);
+      bytes += host_set_bytes[s];
+      lo = std::min<uint64_t>(lo, b->set_byte_off[s]);
+      hi = std::max<uint64_t>(hi, b->set_byte_off[s + 1]);
+    }
+    C.set_bits = ceil_log2(C.sets.size());
+    Pipe& p = C.pipe;
+    p.k = C.k;
+    p.keybits = 2 * C.k + C.set_bits;
+    p.wide = p.keybits > 64;
+    uint64_t Cslots;
+    table_params(b->o, p.wide, p.slots_log2, Cslots, p.T, p.H);
+    p.rec_bound = std::max<uint64_t>(bytes, 1);
+    p.sb = shard_bits_for(b->o, P, p.rec_bound, p.T, p.keybits);
+    p.byte_begin = lo & ~31ull;
+    p.byte_end = hi;
+    pipe_bounds(p);
+    pipeline_prepare(c, p);
+    C.out_base = out_base;
+    C.out_cap = p.rec_bound;
+    out_base += C.out_cap;
+    C.start_base = start_base;
+    start_base += C.sets.size() + 1;
+  }
+  // device tables
+  ensure(b->set_first_read_dev, (n_sets + 1) * 8, "batch tables");
+  ensure(b->set_byte_off_dev, (n_sets + 1) * 8, "batch tables");
+  ensure(b->set_class_dev, n_sets * 4, "batch tables");
+  ensure(b->set_local_dev, n_sets * 4, "batch tables");
+  ensure(b->starts, start_base * 8, "set bounds");
+  ensure(b->start_base_dev, kv.size() * 8, "batch tables");
+  ensure(b->class_base_dev, kv.size() * 8, "batch tables");
+  ensure(b->cls_keys, out_base * 8, "class outputs");
+  ensure(b->cls_counts, out_base * 4, "class outputs");
+  ensure(b->cls_set, out_base * 4, "class outputs");
+  ensure(b->set_off, (n_sets + 1) * 8, "set offsets");
+  ensure(b->states, kv.size() * sizeof(kc::DevState), "device states");
+  ensure(b->flag, 64, "flags");
+  hipStream_t st = nullptr;
+  upload_sync(b->set_first_read_dev.p, b->set_first_read.data(), (n_sets + 1) * 8, st);
+  upload_sync(b->set_byte_off_dev.p, b->set_byte_off.data(), (n_sets + 1) * 8, st);
+  upload_sync(b->set_class_dev.p, set_class.data(), n_sets * 4, st);
+  upload_sync(b->set_local_dev.p, set_local.data(), n_sets * 4, st);
+  std::vector<unsigned long long> sbase(kv.size()), cbase(kv.size());
+  kc_stats dummy;
+  std::memset(&dummy, 0, sizeof(dummy));
+  for (size_t ci = 0; ci < kv.size(); ++ci) {
+    kc_batch::Class& C = b->cls[ci];
+    sbase[ci] = C.start_base;
+    cbase[ci] = C.out_base;
+    std::vector<uint32_t> loc(n_sets, kc::kNoSet);
+    for (size_t j = 0; j < C.sets.size(); ++j) loc[C.sets[j]] = (uint32_t)j;
+    ensure(C.set_local, n_sets * 4, "batch tables");
+    upload_sync(C.set_local.p, loc.data(), n_sets * 4, st);
+    Call q{};
+    q.P = P;
+    q.sb = C.pipe.sb;
+    q.nb = 1 << C.pipe.sb;
+    const std::vector<int>& order = owner_order(c, q, dummy, nullptr);
+    ensure(C.order, (size_t)q.nb * 4, "owner order");
+    upload_sync(C.order.p, order.data(), (size_t)q.nb * 4, st);
+    C.pipe.order = (const int*)C.order.p;
+    C.bs = kc::BatchSets{(const unsigned long long*)b->set_byte_off_dev.p,
+                         (const uint32_t*)C.set_local.p, n_sets};
+    C.pipe.batch = &C.bs;
+  }
+  upload_sync(b->start_base_dev.p, sbase.data(), kv.size() * 8, st);
+  upload_sync(b->class_base_dev.p, cbase.data(), kv.size() * 8, st);
+  *out = b.release();
+  return KC_OK;
+}
+
+// Per-set plain counts of a whole batch (used when a class overflowed).
+void batch_by_sets(kc_batch* b, const uint8_t* reads, const uint64_t* offsets, uint64_t* out_keys,
+                   uint32_t* out_counts, uint64_t cap, uint64_t* set_off, uint64_t* n_out,
+                   hipStream_t st) {
+  uint64_t o = 0;
+  for (uint32_t s = 0; s < b->n_sets; ++s) {
+    set_off[s] = o;
+    uint64_t n = 0;
+    const uint64_t r0 = b->set_first_read[s], r1 = b->set_first_read[s + 1];
+    const int rc = count_impl(reads, offsets + r0, r1 - r0, b->ks[s], b->P, out_keys + o,
+                              out_counts + o, o <= cap ? cap - o : 0, &n, &b->o, st);
+    if (rc == KC_E_CAPACITY) {
+      // keep counting the sizes so that the caller learns the total needed
+      o += n;
+      cap = 0;
+      continue;
+    }
+    if (rc != KC_OK) throw Fail{rc};
+    o += n;
+  }
+  set_off[b->n_sets] = o;
+  *n_out = o;
+  if (cap == 0 && o > 0) fail(KC_E_CAPACITY, "output capacity too small for the batch");
+}
+
+int batch_run_impl(kc_batch* b, const uint8_t* reads, const uint64_t* offsets, uint64_t* out_keys,
+                   uint32_t* out_counts, uint64_t cap, uint64_t* host_set_off, uint64_t* n_out,
+                   hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!b || !n_out || !host_set_off) fail(KC_E_INVAL, "NULL argument");
+  *n_out = 0;
+  if (!reads || !offsets) fail(KC_E_INVAL, "NULL input pointer");
+  if (cap && (!out_keys || !out_counts)) fail(KC_E_INVAL, "output pointer is NULL");
+  Ctx& c = b->ctx;
+  // inputs must have the layout the plan describes
+  ensure(c.state, sizeof(kc::DevState), "device state");
+  hipchk(kc::launch_fill_u64((unsigned long long*)b->flag.p, 8, 0, st), "fill launch");
+  if (b->n_reads) {
+    hipLaunchKernelGGL(k_offsets_ok, dim3((unsigned)((b->n_reads + 255) / 256)), dim3(256), 0, st,
+                       offsets, b->n_reads, (unsigned int*)b->flag.p);
+    hipchk(hipGetLastError(), "offsets check launch");
+  }
+  hipLaunchKernelGGL(k_batch_layout_ok, dim3((b->n_sets + 256) / 256), dim3(256), 0, st, offsets,
+                     (const unsigned long long*)b->set_first_read_dev.p,
+                     (const unsigned long long*)b->set_byte_off_dev.p, b->n_sets,
+                     (unsigned int*)b->flag.p);
+  hipchk(hipGetLastError(), "layout check launch");
+  uint64_t* h = (uint64_t*)host_stage(c, 64);
+  hipchk(hipMemcpyAsync(h, offsets, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  hipchk(hipMemcpyAsync(h + 1, b->flag.p, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+  const uint64_t off0 = h[0];
+  if (h[1] != 0) fail(KC_E_INVAL, "reads and offsets do not match the batch plan");
+  const void* key[5] = {reads, offsets, out_keys, out_counts, nullptr};
+  const bool same = std::equal(key, key + 5, b->key) && b->key_cap == cap && b->key_off0 == off0;
+  if (!b->exec || !same) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    if (!b->cap_stream) hipchk(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking),
+                               "hipStreamCreate");
+    hipStream_t cs = b->cap_stream;
+    hipchk(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+      Timer off(c, cs, false);
+      const size_t nst = b->cls.size();
+      hipchk(kc::launch_fill_u64((unsigned long long*)b->states.p,
+                                 nst * sizeof(kc::DevState) / 8, 0, cs),
+             "fill launch");
+      const uint64_t nchunks = (b->N + 63) / 64 + 2;
+      hipchk(kc::launch_pack(reads + off0, b->N, offsets, b->n_reads, off0, (uint64_t*)c.packed.p,
+                             (uint64_t*)c.inv.p, (uint64_t*)c.endm.p, nchunks, cs),
+             "pack launch");
+      for (size_t ci = 0; ci < nst; ++ci) {
+        kc_batch::Class& C = b->cls[ci];
+        kc::DevState* ds = (kc::DevState*)b->states.p + ci;
+        PipeOut po{(uint64_t*)b->cls_keys.p + C.out_base, (uint32_t*)b->cls_counts.p + C.out_base,
+                   (uint32_t*)b->cls_set.p + C.out_base, C.out_cap};
+        enqueue_pipeline(c, C.pipe, ds, off, po, cs);
+        hipchk(kc::launch_set_bounds(po.set, ds, C.out_cap, (uint32_t)C.sets.size(),
+                                     (unsigned long long*)b->starts.p + C.start_base, cs),
+               "set bounds launch");
+      }
+      hipchk(kc::launch_batch_offsets((const uint32_t*)b->set_class_dev.p,
+                                      (const uint32_t*)b->set_local_dev.p,
+                                      (const unsigned long long*)b->starts.p,
+                                      (const unsigned long long*)b->start_base_dev.p, b->n_sets,
+                                      (unsigned long long*)b->set_off.p, cs),
+             "batch offsets launch");
+      hipchk(kc::launch_batch_gather(
+                 (const uint32_t*)b->set_class_dev.p, (const uint32_t*)b->set_local_dev.p,
+                 (const unsigned long long*)b->starts.p,
+                 (const unsigned long long*)b->start_base_dev.p,
+                 (const unsigned long long*)b->class_base_dev.p, (const uint64_t*)b->cls_keys.p,
+                 (const uint32_t*)b->cls_counts.p, (const unsigned long long*)b->set_off.p,
+                 b->n_sets, cap, out_keys, out_counts, cs),
+             "batch gather launch");
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    hipchk(hipStreamEndCapture(cs, &b->graph), "hipStreamEndCapture");
+    hipchk(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    std::copy(key, key + 5, b->key);
+    b->key_cap = cap;
+    b->key_off0 = off0;
+  }
+  hipchk(hipGraphLaunch(b->exec, st), "hipGraphLaunch");
+  const size_t nst = b->cls.size();
+  const size_t bytes = nst * sizeof(kc::DevState) + (b->n_sets + 1) * 8;
+  char* hs = (char*)host_stage(c, bytes);
+  hipchk(hipMemcpyAsync(hs, b->states.p, nst * sizeof(kc::DevState), hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync");
+  hipchk(hipMemcpyAsync(hs + nst * sizeof(kc::DevState), b->set_off.p, (b->n_sets + 1) * 8,
+                        hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync");
+  hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+  std::memset(&b->stats, 0, sizeof(b->stats));
+  bool overflow = false;
+  for (size_t ci = 0; ci < nst; ++ci) {
+    kc::DevState ds;
+    std::memcpy(&ds, hs + ci * sizeof(kc::DevState), sizeof(ds));
+    if (ds.count_overflow) fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
+    overflow |= ds.overflow != 0;
+    b->stats.valid_windows += ds.W;
+    b->stats.distinct += ds.D;
+    b->stats.n_leaves += ds.n_leaves;
+    b->stats.large_records += ds.large_records;
+    b->stats.large_distinct += ds.large_distinct;
+  }
+  b->stats.n_bases = b->N;
+  std::memcpy(host_set_off, hs + nst * sizeof(kc::DevState), (b->n_sets + 1) * 8);
+  if (overflow) {
+    // a class had a leaf too large for the device-planned split: count set by set
+    ++b->stats.n_overflow;
+    batch_by_sets(b, reads, offsets, out_keys, out_counts, cap, host_set_off, n_out, st);
+  }
+  const uint64_t D = host_set_off[b->n_sets];
+  if (D > cap) {
+    *n_out = D;
+    fail(KC_E_CAPACITY, "output capacity " + std::to_string(cap) + " < " + std::to_string(D) +
+                            " pairs in the batch");
+  }
+  *n_out = D;
+  b->stats.ms_total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return KC_OK;
+}
+
+template <class F>
+int guarded(F f) {
+  g_err.clear();
+  try {
+    return f();
+  } catch (const Fail& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return KC_E_NOMEM;
+  } catch (...) {
+    g_err = "unexpected C++ exception";
+    return KC_E_INTERNAL;
+  }
+}
+
 }  // namespace
 
 extern "C" {
+
+int kc_batch_plan(const uint64_t* host_set_reads, const uint64_t* host_set_bytes,
+                  const int* host_ks, uint32_t n_sets, int P, const kc_options* opt,
+                  kc_batch** plan) {
+  return guarded([&] {
+    return batch_plan_impl(host_set_reads, host_set_bytes, host_ks, n_sets, P, opt, plan);
+  });
+}
+
+int kc_batch_run(kc_batch* plan, const uint8_t* reads, const uint64_t* offsets,
+                 uint64_t* out_keys, uint32_t* out_counts, uint64_t out_capacity,
+                 uint64_t* host_out_set_offsets, uint64_t* n_out, void* stream) {
+  return guarded([&] {
+    return batch_run_impl(plan, reads, offsets, out_keys, out_counts, out_capacity,
+                          host_out_set_offsets, n_out, (hipStream_t)stream);
+  });
+}
+
+int kc_batch_stats(const kc_batch* plan, kc_stats* out) {
+  if (!plan || !out) return KC_E_INVAL;
+  *out = plan->stats;
+  return KC_OK;
+}
+
+uint64_t kc_batch_max_outputs(const kc_batch* plan) { return plan ? plan->N : 0; }
+
+void kc_batch_free(kc_batch* plan) {
+  try {
+    delete plan;
+  } catch (...) {
+  }
+}
+
 
 int kc_count_ex(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
                 uint64_t* out_keys, uint32_t* out_counts, uint64_t out_capacity, uint64_t* n_out,

@@ -20,7 +20,9 @@ STATUS = {0: "KC_OK", -1: "KC_E_INVAL", -2: "KC_E_NOMEM", -3: "KC_E_CAPACITY",
           -4: "KC_E_OVERFLOW", -5: "KC_E_DEVICE", -6: "KC_E_INTERNAL"}
 
 EXPORTED_SYMBOLS = ["kc_count", "kc_count_ex", "kc_max_outputs", "kc_last_stats",
-                    "kc_release_scratch", "kc_strerror", "kc_last_error", "kc_version"]
+                    "kc_release_scratch", "kc_strerror", "kc_last_error", "kc_version",
+                    "kc_batch_plan", "kc_batch_run", "kc_batch_max_outputs", "kc_batch_stats",
+                    "kc_batch_free"]
 
 
 class KcOptions(ctypes.Structure):
@@ -35,12 +37,13 @@ class KcStats(ctypes.Structure):
                 ("distinct", ctypes.c_uint64), ("n_leaves", ctypes.c_uint64),
                 ("n_levels", ctypes.c_uint64), ("n_overflow", ctypes.c_uint64),
                 ("max_leaf_windows", ctypes.c_uint64), ("max_owner_windows", ctypes.c_uint64),
-                ("table_slots", ctypes.c_uint64), ("ms_total", ctypes.c_double),
-                ("ms_stage", ctypes.c_double * 8)]
+                ("table_slots", ctypes.c_uint64), ("large_records", ctypes.c_uint64),
+                ("large_distinct", ctypes.c_uint64), ("ms_total", ctypes.c_double),
+                ("ms_stage", ctypes.c_double * 12)]
 
 
-STAGES = ["pack", "window_hist", "owner_scatter", "split", "leaf_count", "concat", "check",
-          "global_table"]
+STAGES = ["pack", "window_hist", "owner_scatter", "split_hist", "split_scatter", "leaf_small",
+          "leaf_large", "out_offsets", "concat", "check", "unused10", "unused11"]
 
 
 class KcError(RuntimeError):
@@ -80,6 +83,16 @@ def lib():
             L.kc_last_error.argtypes = []
             L.kc_version.restype = ctypes.c_char_p
             L.kc_version.argtypes = []
+            L.kc_batch_plan.restype = i32
+            L.kc_batch_plan.argtypes = [p, p, p, ctypes.c_uint32, i32, p, p]
+            L.kc_batch_run.restype = i32
+            L.kc_batch_run.argtypes = [p, p, p, p, p, u64, p, p, p]
+            L.kc_batch_max_outputs.restype = u64
+            L.kc_batch_max_outputs.argtypes = [p]
+            L.kc_batch_stats.restype = i32
+            L.kc_batch_stats.argtypes = [p, p]
+            L.kc_batch_free.restype = None
+            L.kc_batch_free.argtypes = [p]
             _lib = L
     return _lib
 
@@ -153,3 +166,72 @@ def count(reads, offsets, k: int, P: int = 1, opts: KcOptions | None = None, str
     counts = torch.empty(capacity, dtype=torch.int32, device=reads.device)
     n = count_into(reads, offsets, k, P, keys, counts, capacity, opts, stream)
     return keys[:n], counts[:n]
+
+
+def _stats_dict(s: KcStats) -> dict:
+    d = {name: getattr(s, name) for name, _ in KcStats._fields_ if name != "ms_stage"}
+    d["ms_stage"] = {n: s.ms_stage[i] for i, n in enumerate(STAGES)}
+    return d
+
+
+class BatchPlan:
+    """A planned batch of read sets (kc_batch_plan / kc_batch_run).
+
+    set_reads, set_bytes, ks: per set (host sequences). The reads of all sets
+    are consecutive in one stream; set s has its own k (1..32).
+    """
+
+    def __init__(self, set_reads, set_bytes, ks, P: int = 1, opts: KcOptions | None = None):
+        self.set_reads = np.ascontiguousarray(set_reads, dtype=np.uint64)
+        self.set_bytes = np.ascontiguousarray(set_bytes, dtype=np.uint64)
+        self.ks = np.ascontiguousarray(ks, dtype=np.int32)
+        self.n_sets = int(self.ks.size)
+        self._h = ctypes.c_void_p()
+        st = lib().kc_batch_plan(self.set_reads.ctypes.data, self.set_bytes.ctypes.data,
+                                 self.ks.ctypes.data, self.n_sets, P,
+                                 ctypes.byref(opts) if opts is not None else None,
+                                 ctypes.byref(self._h))
+        if st != 0:
+            raise KcError(st, lib().kc_last_error().decode())
+        self.max_outputs = int(lib().kc_batch_max_outputs(self._h))
+
+    def run_into(self, reads, offsets, out_keys, out_counts, capacity: int, stream=None):
+        """Run on device tensors; returns (n_pairs, set_offsets as a numpy uint64 array)."""
+        import torch
+        _check_tensor(reads, "reads", (torch.uint8,))
+        _check_tensor(offsets, "offsets", (torch.int64, torch.uint64))
+        if stream is None:
+            stream = torch.cuda.current_stream(reads.device).cuda_stream
+        set_off = np.zeros(self.n_sets + 1, dtype=np.uint64)
+        n_out = ctypes.c_uint64(0)
+        with torch.cuda.device(reads.device):
+            st = lib().kc_batch_run(self._h, reads.data_ptr(), offsets.data_ptr(),
+                                    out_keys.data_ptr(), out_counts.data_ptr(), capacity,
+                                    set_off.ctypes.data, ctypes.byref(n_out), stream)
+        if st != 0:
+            raise KcError(st, lib().kc_last_error().decode(), int(n_out.value))
+        return int(n_out.value), set_off
+
+    def run(self, reads, offsets, stream=None):
+        import torch
+        cap = max(1, self.max_outputs)
+        keys = torch.empty(cap, dtype=torch.int64, device=reads.device)
+        counts = torch.empty(cap, dtype=torch.int32, device=reads.device)
+        n, set_off = self.run_into(reads, offsets, keys, counts, cap, stream)
+        return keys[:n], counts[:n], set_off
+
+    def stats(self) -> dict:
+        s = KcStats()
+        lib().kc_batch_stats(self._h, ctypes.byref(s))
+        return _stats_dict(s)
+
+    def close(self):
+        if self._h:
+            lib().kc_batch_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -45,6 +45,6 @@ def test_max_outputs_and_strerror():
 
 
 def test_options_layout_matches_header():
-    # kc_options: 7 ints + 5 reserved; kc_stats: 9 uint64 + 9 doubles
+    # kc_options: 7 ints + 5 reserved; kc_stats: 11 uint64 + 13 doubles
     assert ctypes.sizeof(kc.kc.KcOptions) == 12 * 4
-    assert ctypes.sizeof(kc.kc.KcStats) == 9 * 8 + 9 * 8
+    assert ctypes.sizeof(kc.kc.KcStats) == 11 * 8 + 13 * 8
