@@ -50,6 +50,107 @@ def stage_bytes(st: dict, k: int) -> dict:
     }
 
 
+def batched_leg(n_sample: int, wave_bytes: int, tune: bool) -> dict:
+    """Batched workload: read sets of the 4,096-set recipe (genomes log-uniform in
+    10 kbp..10 Mbp, 20x of 150 bp reads, 0.5% errors, k in {21, 31}); a seeded
+    sample of n_sample sets with the same size distribution. Sets are grouped
+    into memory waves of at most wave_bytes; each wave is one recorded-graph
+    replay (batched) and, on the same resident inputs, one plain call per set."""
+    import torch
+
+    import paper_2505_04431_amd as kc
+    import synth
+    from paper_2505_04431_amd import tuner
+
+    dev = torch.device("cuda:0")
+    spec = synth.c4_sets()
+    idx = synth.c4_sample(n_sample, len(spec))
+    sizes = [max(1, spec[i][0] * 20 // 150) * 150 for i in idx]
+    groups = synth.waves(sizes, wave_bytes)
+    tot = dict(windows=0, bytes=0, t_batched=0.0, t_plain=0.0, t_gen=0.0, pairs=0)
+    tuned = None
+    for gi, grp in enumerate(groups):
+        t0 = time.time()
+        parts, offs, set_reads, set_bytes, ks = [], [np.zeros(1, np.uint64)], [], [], []
+        base = 0
+        from concurrent.futures import ThreadPoolExecutor
+        # sets of a wave are laid out by (k, size) so that the plan's classes,
+        # which group sets of one k by size, cover contiguous byte ranges
+        grp = sorted(grp, key=lambda j: (spec[idx[j]][1], -spec[idx[j]][0]))
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            gen = list(ex.map(lambda j: synth.c4_set_reads(idx[j], spec[idx[j]][0], threads=1), grp))
+        for j, (r, o) in zip(grp, gen):
+            s = idx[j]
+            parts.append(r)
+            offs.append(o[1:] + np.uint64(base))
+            base += r.size
+            set_reads.append(o.size - 1)
+            set_bytes.append(r.size)
+            ks.append(spec[s][1])
+        reads = np.concatenate(parts)
+        offsets = np.concatenate(offs)
+        del parts, gen
+        rt = torch.from_numpy(reads).to(dev)
+        ot = torch.from_numpy(offsets.view(np.int64)).to(dev)
+        del reads
+        tot["t_gen"] += time.time() - t0
+        cap = int(sum(set_bytes))
+        keys = torch.empty(cap, dtype=torch.int64, device=dev)
+        cnts = torch.empty(cap, dtype=torch.int32, device=dev)
+        if tuned is None:
+            if tune:
+                def run(o):
+                    p = kc.BatchPlan(set_reads, set_bytes, ks, P=1, opts=kc.options(**o))
+                    p.run_into(rt, ot, keys, cnts, cap)
+                    torch.cuda.synchronize()
+                    p.close()
+                tuned = tuner.tune(tuner.class_key("batch", ks, cap), run, reps=1)["options"]
+            else:
+                tuned = {}
+        plan = kc.BatchPlan(set_reads, set_bytes, ks, P=1, opts=kc.options(**tuned))
+        plan.run_into(rt, ot, keys, cnts, cap)  # records the graph
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        n, _ = plan.run_into(rt, ot, keys, cnts, cap)
+        torch.cuda.synchronize()
+        tot["t_batched"] += time.perf_counter() - t
+        tot["windows"] += plan.stats()["valid_windows"]
+        tot["bytes"] += cap
+        tot["pairs"] += n
+        plan.close()
+        # plain: one call per set on the same resident inputs
+        st = torch.cuda.current_stream(dev).cuda_stream
+        r0 = 0
+        bounds = []
+        for nr in set_reads:
+            bounds.append((r0, r0 + nr))
+            r0 += nr
+        kc.count_into(rt, ot[bounds[0][0]:bounds[0][1] + 1], ks[0], 1, keys, cnts, cap, None, st)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for (a, b), k in zip(bounds, ks):
+            kc.count_into(rt, ot[a:b + 1], k, 1, keys, cnts, cap, None, st)
+        torch.cuda.synchronize()
+        tot["t_plain"] += time.perf_counter() - t
+        print("bench: batched wave %d/%d: %d sets, %.2f GB" % (gi + 1, len(groups), len(grp),
+                                                              cap / 1e9), file=sys.stderr,
+              flush=True)
+        del rt, ot, keys, cnts
+        torch.cuda.empty_cache()
+    return {
+        "workload": "c4_batched_4096_sets_sample", "sets": len(idx), "of_sets": len(spec),
+        "waves": len(groups), "wave_bytes": wave_bytes, "bytes": tot["bytes"],
+        "valid_windows": tot["windows"], "pairs": tot["pairs"],
+        "value": round(tot["windows"] / tot["t_batched"], 1), "unit": "k-mers/s",
+        "plain_per_set_value": round(tot["windows"] / tot["t_plain"], 1),
+        "speedup_vs_plain_launches": round(tot["t_plain"] / tot["t_batched"], 3),
+        "ms_batched": round(tot["t_batched"] * 1e3, 3), "ms_plain": round(tot["t_plain"] * 1e3, 3),
+        "tuned_options": tuned,
+        "note": "seeded sample of the 4,096 sets (same size distribution); inputs resident; "
+                "one graph replay per wave vs one plain call per set",
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +159,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--batched-sets", type=int, default=256,
+                    help="sets of the batched workload to run (0: skip the batched leg)")
+    ap.add_argument("--wave-gb", type=float, default=2.0)
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build counts on one GPU only; --gpus %d is not supported "
@@ -133,6 +238,10 @@ def main() -> int:
                "sample": "first %d of %d reads (%d valid windows), sort-based oracle, %d threads"
                          % (n_s, len(offs) - 1, w_s, threads)}
 
+    batched = None
+    if args.batched_sets > 0:
+        batched = batched_leg(args.batched_sets, int(args.wave_gb * 1e9), not args.no_tune)
+
     line = {
         "metric": "canonical k-mers counted/sec on 1 MI355X + % HBM roofline; batched vs plain",
         "value": round(value, 1), "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
@@ -143,6 +252,7 @@ def main() -> int:
                    "read_len": 150, "valid_windows": W, "distinct": n_out, "mode": "plain"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
     return 0

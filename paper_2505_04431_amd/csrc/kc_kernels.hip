@@ -1238,7 +1238,10 @@ __global__ void __launch_bounds__(kPlanTB) k_batch_offsets(
 }
 
 // Copy each set's pairs from its class output to its place in the batch
-// output (one wave per set).
+// output. Waves take chunks of consecutive output positions (coalesced
+// reads and writes); the set of a chunk's first position is found by binary
+// search in set_off, later positions move to the next set when they pass its
+// start.
 __global__ void __launch_bounds__(256) k_batch_gather(
     const uint32_t* __restrict__ set_class, const uint32_t* __restrict__ set_local,
     const unsigned long long* __restrict__ starts, const unsigned long long* __restrict__ start_base,
@@ -1246,17 +1249,34 @@ __global__ void __launch_bounds__(256) k_batch_gather(
     const uint32_t* __restrict__ cls_counts, const unsigned long long* __restrict__ set_off,
     uint32_t n_sets, uint64_t cap, uint64_t* __restrict__ out_keys,
     uint32_t* __restrict__ out_counts) {
+  constexpr int kChunk = 64 * 16;
   const unsigned lane = threadIdx.x & 63;
-  for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < n_sets; g += gridDim.x * 4) {
-    const uint32_t c = set_class[g];
-    const unsigned long long* st = starts + start_base[c];
-    const unsigned long long a = st[set_local[g]], e = st[set_local[g] + 1];
-    const unsigned long long o = set_off[g];
-    for (unsigned long long i = a + lane; i < e; i += 64) {
-      const unsigned long long dst = o + (i - a);
-      if (dst >= cap) break;
-      out_keys[dst] = cls_keys[class_base[c] + i];
-      out_counts[dst] = cls_counts[class_base[c] + i];
+  const unsigned long long D = min((unsigned long long)cap, set_off[n_sets]);
+  const unsigned long long nchunks = (D + kChunk - 1) / kChunk;
+  for (unsigned long long ch = (unsigned long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+       ch < nchunks; ch += (unsigned long long)gridDim.x * 4) {
+    const unsigned long long o0 = ch * kChunk;
+    uint32_t lo = 0, hi = n_sets - 1;  // last set starting at or before o0
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (set_off[mid] <= o0) lo = mid; else hi = mid - 1;
+    }
+    uint32_t g = lo;
+    unsigned long long src0 = class_base[set_class[g]] +
+                              starts[start_base[set_class[g]] + set_local[g]] - set_off[g];
+    for (int j = 0; j < 16; ++j) {
+      const unsigned long long o = o0 + (unsigned long long)j * 64 + lane;
+      if (o >= D) break;
+      bool moved = false;
+      while (g + 1 < n_sets && o >= set_off[g + 1]) {
+        ++g;
+        moved = true;
+      }
+      if (moved)
+        src0 = class_base[set_class[g]] + starts[start_base[set_class[g]] + set_local[g]] -
+               set_off[g];
+      out_keys[o] = cls_keys[src0 + o];
+      out_counts[o] = cls_counts[src0 + o];
     }
   }
 }
@@ -1575,7 +1595,7 @@ hipError_t launch_batch_gather(const uint32_t* set_class, const uint32_t* set_lo
                                const uint32_t* cls_counts, const unsigned long long* set_off,
                                uint32_t n_sets, uint64_t cap, uint64_t* out_keys,
                                uint32_t* out_counts, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_gather, dim3(grid_for(n_sets, 4, 8192)), dim3(256), 0, s, set_class,
+  hipLaunchKernelGGL(k_batch_gather, dim3(2048), dim3(256), 0, s, set_class,
                      set_local, starts, start_base, class_base, cls_keys, cls_counts, set_off,
                      n_sets, cap, out_keys, out_counts);
   return hipGetLastError();

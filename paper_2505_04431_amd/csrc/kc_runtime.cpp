@@ -808,10 +808,45 @@ int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_byt
   }
   b->n_reads = b->set_first_read[n_sets];
   b->N = b->set_byte_off[n_sets];
-  // one class per distinct k; a class is counted with keys (set id << 2k) | k-mer
-  std::vector<int> kv(b->ks);
-  std::sort(kv.begin(), kv.end());
-  kv.erase(std::unique(kv.begin(), kv.end()), kv.end());
+  // Classes: sets of one k counted together with keys (set id << 2k) | k-mer.
+  // Every set of a class gets the same share of the first-level shards, so a
+  // class holds at most as many sets as its largest set can afford: the sets
+  // of each k are taken largest first, and a class is closed once 2^set_bits
+  // sets are in it, set_bits being the most that still leaves the largest set
+  // enough shards for leaves of the target size (at half of full use).
+  std::vector<std::vector<uint32_t>> groups;
+  std::vector<int> group_k;
+  {
+    std::vector<int> kv(b->ks);
+    std::sort(kv.begin(), kv.end());
+    kv.erase(std::unique(kv.begin(), kv.end()), kv.end());
+    for (int k : kv) {
+      std::vector<uint32_t> sk;
+      for (uint32_t s = 0; s < n_sets; ++s)
+        if (b->ks[s] == k) sk.push_back(s);
+      std::stable_sort(sk.begin(), sk.end(), [&](uint32_t x, uint32_t y) {
+        return host_set_bytes[x] > host_set_bytes[y];
+      });
+      int slots_log2;
+      uint64_t Cs, Tw, Hw;
+      table_params(b->o, true, slots_log2, Cs, Tw, Hw);  // the smaller (wide) leaf target
+      const uint64_t per_shard = (Tw << kc::kSplitMaxBits) / 2;
+      size_t i = 0;
+      while (i < sk.size()) {
+        const uint64_t w = std::max<uint64_t>(host_set_bytes[sk[i]], 1);
+        int need = 0;  // shard bits the largest set needs
+        while (need < kc::kMaxShardBits && ((uint64_t)per_shard << need) < w) ++need;
+        int sbits = std::max(0, kc::kMaxShardBits - need);
+        sbits = std::min(sbits, 128 - 2 * k);
+        const size_t take = std::min(sk.size() - i, (size_t)1 << sbits);
+        std::vector<uint32_t> g(sk.begin() + i, sk.begin() + i + take);
+        std::sort(g.begin(), g.end());  // set order inside a class
+        groups.push_back(g);
+        group_k.push_back(k);
+        i += take;
+      }
+    }
+  }
   std::vector<uint32_t> set_class(n_sets), set_local(n_sets);
   uint64_t out_base = 0, start_base = 0;
   Ctx& c = b->ctx;
@@ -820,13 +855,14 @@ int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_byt
   ensure(c.packed, nchunks * 16, "packed bases");
   ensure(c.inv, nchunks * 8, "invalid mask");
   ensure(c.endm, nchunks * 8, "end mask");
-  b->cls.resize(kv.size());
-  for (size_t ci = 0; ci < kv.size(); ++ci) {
+  std::vector<int> kv(groups.size());
+  b->cls.resize(groups.size());
+  for (size_t ci = 0; ci < groups.size(); ++ci) {
     kc_batch::Class& C = b->cls[ci];
-    C.k = kv[ci];
+    C.k = group_k[ci];
+    kv[ci] = C.k;
     uint64_t bytes = 0, lo = ~0ull, hi = 0;
-    for (uint32_t s = 0; s < n_sets; ++s) {
-      if (b->ks[s] != C.k) continue;
+    for (uint32_t s : groups[ci]) {
       set_class[s] = (uint32_t)ci;
       set_local[s] = (uint32_t)C.sets.size();
       C.sets.push_back(s);
@@ -842,7 +878,10 @@ int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_byt
     uint64_t Cslots;
     table_params(b->o, p.wide, p.slots_log2, Cslots, p.T, p.H);
     p.rec_bound = std::max<uint64_t>(bytes, 1);
-    p.sb = shard_bits_for(b->o, P, p.rec_bound, p.T, p.keybits);
+    p.sb = b->o.shard_bits > 0 ? std::min(b->o.shard_bits, kc::max_shard_bits())
+                               : std::max(shard_bits_for(b->o, P, p.rec_bound, p.T, p.keybits),
+                                          std::min(kc::max_shard_bits(), C.set_bits + 3));
+    p.sb = std::max(1, std::min(p.sb, p.keybits));
     p.byte_begin = lo & ~31ull;
     p.byte_end = hi;
     pipe_bounds(p);

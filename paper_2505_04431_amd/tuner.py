@@ -1,0 +1,85 @@
+"""Autotuner for the counting knobs (leaf size, shard bits, table size).
+
+The knobs change how the work is partitioned, never the result. For a
+workload class (key width, k, size bucket) the tuner times each candidate on
+the actual inputs and keeps the fastest; results are cached in a JSON file
+(KC_TUNE_CACHE, default ~/.cache/kc_tune.json) keyed by that class and the
+device name, so later runs of the same class reuse them without timing.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+from . import kc
+
+DEFAULT_CANDIDATES = [
+    {},
+    {"leaf_target": 2048},
+    {"leaf_target": 3400},
+    {"leaf_target": 2560, "shard_bits": 9},
+    {"leaf_target": 3400, "shard_bits": 10},
+]
+
+
+def cache_path() -> str:
+    return os.environ.get("KC_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
+                                                        "kc_tune.json"))
+
+
+def class_key(kind: str, ks, n_bytes: int) -> str:
+    import torch
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    kk = ",".join(str(k) for k in sorted(set(int(x) for x in ks)))
+    return "%s|k=%s|log2bytes=%d|%s" % (kind, kk, int(math.log2(max(1, n_bytes))), dev)
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d: dict) -> None:
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        tmp = p + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass
+
+
+def tune(key: str, run, candidates=None, reps: int = 3, use_cache: bool = True) -> dict:
+    """Pick the fastest option set for `run(opts_dict) -> None` (which must
+    synchronize). Returns dict(options=..., ms=..., timings=[...])."""
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        return cache[key]
+    results = []
+    for cand in candidates or DEFAULT_CANDIDATES:
+        try:
+            run(cand)  # warm-up (records graphs, grows buffers)
+            best = math.inf
+            for _ in range(reps):
+                t = time.perf_counter()
+                run(cand)
+                best = min(best, time.perf_counter() - t)
+            results.append((best, cand))
+        except kc.KcError:
+            continue
+    if not results:
+        raise RuntimeError("no tuning candidate ran")
+    results.sort(key=lambda x: x[0])
+    out = {"options": results[0][1], "ms": results[0][0] * 1e3,
+           "timings": [{"options": c, "ms": t * 1e3} for t, c in results]}
+    if use_cache:
+        cache[key] = out
+        _store(cache)
+    return out

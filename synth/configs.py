@@ -71,3 +71,44 @@ def make_config(idx: int, frac: float = 1.0, threads: int | None = None):
                    seed=seed, threads=threads)
     name = c["name"] if frac == 1.0 else "%s@%g" % (c["name"], frac)
     return dict(reads=r, offsets=off, ks=c["ks"], P=c["P"], name=name, genome_len=int(g.shape[0]))
+
+
+# ---- the batched workload: 4,096 independent read sets
+
+def c4_sets(n_sets: int = 4096, seed: int = CONFIG_SEED_BASE + 4):
+    """Per-set (genome length, k) of the batched workload: genome lengths
+    log-uniform in [10 kbp, 10 Mbp], k drawn from {21, 31}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    G = np.exp(rng.uniform(math.log(1e4), math.log(1e7), size=n_sets)).astype(np.int64)
+    ks = rng.choice(np.array([21, 31]), size=n_sets)
+    return [(int(g), int(k)) for g, k in zip(G, ks)]
+
+
+def c4_set_reads(s: int, genome_len: int, coverage: int = 20, read_len: int = 150,
+                 err: float = 0.005, seed: int = CONFIG_SEED_BASE + 4, threads: int | None = None):
+    """Reads of set s: its own uniform genome sampled at `coverage`."""
+    g = genome(seed * 1000003 + s, genome_len)
+    n = max(1, genome_len * coverage // read_len)
+    return reads(g, n, read_len, err_rate=err, seed=seed + 17 * s + 1, threads=threads)
+
+
+def c4_sample(n_sample: int, n_sets: int = 4096, seed: int = CONFIG_SEED_BASE + 4):
+    """A seeded subset of the set indices (same size distribution)."""
+    if n_sample >= n_sets:
+        return list(range(n_sets))
+    rng = np.random.Generator(np.random.PCG64(seed ^ 0x5A))
+    return sorted(rng.choice(n_sets, size=n_sample, replace=False).tolist())
+
+
+def waves(sizes, budget: int):
+    """Greedy consecutive grouping of sizes into waves of at most `budget`."""
+    out, cur, acc = [], [], 0
+    for i, b in enumerate(sizes):
+        if cur and acc + b > budget:
+            out.append(cur)
+            cur, acc = [], 0
+        cur.append(i)
+        acc += b
+    if cur:
+        out.append(cur)
+    return out
