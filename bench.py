@@ -50,6 +50,50 @@ def stage_bytes(st: dict, k: int) -> dict:
     }
 
 
+def copy_rate(torch, dev, gib: float):
+    """Achievable HBM rate: a plain elementwise kernel (bitwise NOT of int64)
+    that reads and writes gib GiB each, timed with events on its stream.
+    The same kernel calibrates the FETCH_SIZE / WRITE_SIZE counters."""
+    if gib <= 0:
+        return None
+    n = int(gib * (1 << 30)) // 8
+    a = torch.empty(n, dtype=torch.int64, device=dev).fill_(0x5A5A)
+    b = torch.empty_like(a)
+    torch.bitwise_not(a, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        torch.bitwise_not(a, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * n * 8 / (ms / 1e3) / 1e9, 1)
+
+
+def traffic_per_launch(kernel: str, config: int, k: int):
+    """Measured HBM bytes per launch of `kernel`, from the committed counter
+    summary (profiles/traffic.json, written from two rocprofv3 --pmc runs
+    scaled by the copy kernel's reading), if it was taken on this workload and
+    on the current kernel source; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2505_04431_amd", "csrc", "kc_kernels.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    ent = rec.get("%s|config%d|k%d" % (kernel, config, k))
+    if not ent or ent.get("kernel_source_sha256") != digest:
+        return None
+    return ent.get("bytes_per_launch")
+
+
 def batched_leg(n_sample: int, wave_bytes: int, tune: bool) -> dict:
     """Batched workload: read sets of the 4,096-set recipe (genomes log-uniform in
     10 kbp..10 Mbp, 20x of 150 bp reads, 0.5% errors, k in {21, 31}); a seeded
@@ -163,6 +207,8 @@ def main() -> int:
                     help="sets of the batched workload to run (0: skip the batched leg)")
     ap.add_argument("--wave-gb", type=float, default=2.0)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-gib", type=float, default=1.0,
+                    help="size of the plain copy kernel timed for the achievable HBM rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build counts on one GPU only; --gpus %d is not supported "
@@ -197,10 +243,14 @@ def main() -> int:
         kc.count_into(rt, ot, k, P, keys, cnts, cap, opts, stream.cuda_stream)
     torch.cuda.synchronize()
     stage_ms: dict = {}
+    step_ms = []
     t_start = time.perf_counter()
     n_out = 0
     for _ in range(args.steps):
+        # each call returns with its output complete (it synchronises its stream)
+        t1 = time.perf_counter()
         n_out = kc.count_into(rt, ot, k, P, keys, cnts, cap, opts, stream.cuda_stream)
+        step_ms.append((time.perf_counter() - t1) * 1e3)
         st = kc.last_stats()
         for name, ms in st["ms_stage"].items():
             stage_ms[name] = stage_ms.get(name, 0.0) + ms
@@ -216,10 +266,16 @@ def main() -> int:
     achieved = sb[dom] / (avg[dom] / 1e3) / 1e9
     kernel_names = {"leaf_large": "k_leaf_count64<512, 4096, 4>" if k <= 32 else
                     "k_leaf_count128<512, 2048, 4>"}
-    roofline = {"bound": "hbm", "kernel": kernel_names.get(dom, dom), "stage": dom,
+    copy_gbs = copy_rate(torch, dev, args.copy_gib)
+    kname = kernel_names.get(dom, dom)
+    roofline = {"bound": "hbm", "kernel": kname, "stage": dom,
                 "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
+                "traffic": traffic_per_launch(kname, args.config, k),
+                "copy_gbs": copy_gbs,
+                "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
+                "leaf_records_per_s": round(st["large_records"] / (avg[dom] / 1e3), 1)
+                if dom == "leaf_large" else None,
                 "stage_ms": {n: round(v, 4) for n, v in avg.items()},
                 "stage_gbs": {n: round(sb[n] / (avg[n] / 1e3) / 1e9, 1) for n in avg if n in sb}}
 
@@ -245,7 +301,9 @@ def main() -> int:
     line = {
         "metric": "canonical k-mers counted/sec on 1 MI355X + % HBM roofline; batched vs plain",
         "value": round(value, 1), "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "ms_median": round(float(np.median(step_ms)), 4), "ms_best": round(min(step_ms), 4),
+        "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64" if k <= 32 else "u128",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "k": k, "P": P, "reads": len(offs) - 1,

@@ -116,5 +116,5 @@ def ragged_reads(seed: int, n_reads: int, min_len: int, max_len: int,
     return text, offsets
 
 
-from .configs import (CONFIGS, c4_sample, c4_set_reads, c4_sets, family_layout,  # noqa: E402,F401
-                      make_config, waves)
+from .configs import (CONFIGS, c4_sample, c4_set_reads, c4_sets, c5_job_reads,  # noqa: E402,F401
+                      c5_jobs, c5_sample, family_layout, make_config, waves)

@@ -112,3 +112,53 @@ def waves(sizes, budget: int):
     if cur:
         out.append(cur)
     return out
+
+
+# ---- the served workload: a stream of independent counting jobs
+
+def c5_jobs(n_jobs: int = 10_000, seed: int = CONFIG_SEED_BASE + 5):
+    """Per-job recipe of the served workload: genome length log-uniform in
+    [50 kbp, 50 Mbp] with 10% of it from repeat families, coverage U[10, 30],
+    80% of jobs short reads (150 bp, 0.5% substitutions) and 20% long reads
+    (10 kbp, 1% substitutions), k drawn from {31, 55}.
+
+    Returns a list of dicts (job, genome_len, coverage, read_len, err, k)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    G = np.exp(rng.uniform(math.log(5e4), math.log(5e7), size=n_jobs)).astype(np.int64)
+    cov = rng.integers(10, 31, size=n_jobs)
+    long_reads = rng.random(n_jobs) < 0.2
+    ks = rng.choice(np.array([31, 55]), size=n_jobs)
+    out = []
+    for j in range(n_jobs):
+        out.append(dict(job=j, genome_len=int(G[j]), coverage=int(cov[j]),
+                        read_len=10_000 if long_reads[j] else 150,
+                        err=0.01 if long_reads[j] else 0.005, k=int(ks[j])))
+    return out
+
+
+def c5_job_reads(spec: dict, seed: int = CONFIG_SEED_BASE + 5, threads: int | None = None):
+    """Reads of one served job: a uniform backbone of 90% of its genome plus
+    repeat families (length U[1, 6] kbp, 2% divergence) whose copies make up
+    the other 10%, sampled at the job's coverage."""
+    j = spec["job"]
+    G = spec["genome_len"]
+    rng = np.random.Generator(np.random.PCG64((seed * 7919 + j) & ((1 << 63) - 1)))
+    rep = G // 10
+    fams = []
+    if rep >= 1000:
+        n_f = int(min(5, max(1, rep // 6000)))
+        lens = rng.integers(1000, 6001, size=n_f)
+        per = rep // n_f
+        fams = [(int(l), max(1, int(per // l)), 0.02) for l in lens]
+    g = genome(seed * 1000003 + j, max(1000, G - rep), fams)
+    rl = spec["read_len"]
+    n = max(1, int(g.shape[0]) * spec["coverage"] // rl)
+    return reads(g, n, rl, err_rate=spec["err"], seed=seed + 31 * j + 3, threads=threads)
+
+
+def c5_sample(n_sample: int, n_jobs: int = 10_000, seed: int = CONFIG_SEED_BASE + 5):
+    """A seeded subset of the job indices (same distribution)."""
+    if n_sample >= n_jobs:
+        return list(range(n_jobs))
+    rng = np.random.Generator(np.random.PCG64(seed ^ 0xC5))
+    return sorted(rng.choice(n_jobs, size=n_sample, replace=False).tolist())
