@@ -141,6 +141,82 @@ uint64_t kc_batch_max_outputs(const kc_batch* plan);
 int kc_batch_stats(const kc_batch* plan, kc_stats* out);
 void kc_batch_free(kc_batch* plan);
 
+/* ---- Served form: a request server counting many jobs side by side.
+ * Each job is a plain count (same arguments and result as kc_count). A fixed
+ * pool of worker threads, each with its own HIP stream and scratch memory,
+ * takes jobs from one arrival-ordered queue; a worker starts the first queued
+ * job whose device bytes fit in what the budget has left (the growth of the
+ * worker's scratch plus a reservation for the result); a job passed over 8
+ * times holds back the later ones until it fits. Results are allocated at
+ * their exact size when the job's number of distinct keys is known and stay
+ * on the device, owned by the server, until kc_server_release. A job's result
+ * does not depend on what else runs beside it.
+ *
+ * kc_server_create: hbm_budget_bytes caps the device bytes the server
+ *   accounts for (scratch, reservations, held results); n_workers in [1, 16]
+ *   (streams run concurrently); opt as in kc_count_ex (NULL = automatic),
+ *   applied to every job. The calling thread's current device is used.
+ * kc_server_submit: reads/offsets are DEVICE arrays as in kc_count that must
+ *   hold their final contents at submission and stay allocated until the job
+ *   has finished. distinct_hint: 0, or an estimate of the job's distinct keys
+ *   (reserves distinct_hint pairs instead of one pair per input byte; a low
+ *   hint is still correct: the result is allocated at its true size and the
+ *   miss is counted in kc_server_stats). Returns KC_E_NOMEM at once if the
+ *   job alone needs more than the budget; *job_id receives the job's id.
+ * kc_server_poll / kc_server_wait: the job's state (KC_JOB_*); wait blocks
+ *   until it is DONE or FAILED.
+ * kc_server_result: device pointers to the sorted keys (1 or 2 words each, as
+ *   in kc_count) and counts, and their number. A FAILED job returns its status
+ *   (message in kc_last_error).
+ * kc_server_result_copy: copies a finished job's result into caller DEVICE
+ *   arrays of out_capacity keys (1 or 2 words each) and counts, on `stream`,
+ *   and returns when the copy is complete; KC_E_CAPACITY (with *n_out set)
+ *   if they are too small.
+ * kc_server_release: frees a finished job's result and forgets the job.
+ * kc_server_destroy: waits for running jobs, drops queued ones, frees all. */
+#define KC_JOB_QUEUED 0
+#define KC_JOB_RUNNING 1
+#define KC_JOB_DONE 2
+#define KC_JOB_FAILED 3
+
+typedef struct kc_server kc_server;
+
+typedef struct kc_job_info {
+  int state, status, worker, k;
+  uint64_t n_bytes, valid_windows, distinct;
+  uint64_t result_estimate_bytes; /* reserved at admission */
+  uint64_t result_bytes;          /* allocated for the result */
+  double t_submit_ms, t_start_ms, t_end_ms; /* host clock, since the server was created */
+} kc_job_info;
+
+typedef struct kc_server_stats {
+  uint64_t submitted, completed, failed, queued, running;
+  uint64_t valid_windows;          /* of completed jobs */
+  uint64_t budget, bytes_in_use, bytes_peak;
+  uint64_t estimate_misses;        /* results larger than their reservation */
+  uint64_t result_bytes_reserved;  /* sum over finished jobs */
+  uint64_t result_bytes_actual;
+  double latency_p50_ms, latency_p99_ms; /* completion - submission, completed jobs */
+  double wait_p50_ms, wait_p99_ms;       /* start - submission */
+  double busy_ms;                        /* first start to last completion */
+} kc_serve_stats;
+
+int kc_server_create(uint64_t hbm_budget_bytes, int n_workers, const kc_options* opt,
+                     kc_server** server);
+int kc_server_submit(kc_server* server, const uint8_t* reads, const uint64_t* offsets,
+                     uint64_t n_reads, int k, int P, uint64_t distinct_hint, uint64_t* job_id);
+int kc_server_poll(kc_server* server, uint64_t job_id, int* state);
+int kc_server_wait(kc_server* server, uint64_t job_id, int* state);
+int kc_server_result(kc_server* server, uint64_t job_id, const uint64_t** keys,
+                     const uint32_t** counts, uint64_t* n_out);
+int kc_server_result_copy(kc_server* server, uint64_t job_id, uint64_t* out_keys,
+                          uint32_t* out_counts, uint64_t out_capacity, uint64_t* n_out,
+                          void* stream);
+int kc_server_job_info(kc_server* server, uint64_t job_id, kc_job_info* out);
+int kc_server_release(kc_server* server, uint64_t job_id);
+int kc_server_stats(kc_server* server, kc_serve_stats* out);
+void kc_server_destroy(kc_server* server);
+
 /* Upper bound on the number of output keys (= number of length-k windows,
  * valid or not): sum over reads of max(0, len - k + 1). host_offsets is a
  * HOST array of n_reads+1 offsets. Returns 0 for bad arguments. */

@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libkc.so")
-SOURCES = ["kc_kernels.hip", "kc_runtime.cpp"]
-HEADERS = ["kc_internal.h", os.path.join("..", "..", "include", "kc.h")]
+SOURCES = ["kc_kernels.hip", "kc_runtime.cpp", "kc_server.cpp"]
+HEADERS = ["kc_internal.h", "kc_host.h", "kc_sched.h", os.path.join("..", "..", "include", "kc.h")]
 ARCH = os.environ.get("KC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -44,7 +44,7 @@ def build(verbose: bool = False) -> str:
             print(err, file=sys.stderr)
         objs.append(obj)
     tmp = SO + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "-pthread", "--offload-arch=" + ARCH, "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr)

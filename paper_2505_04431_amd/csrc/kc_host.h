@@ -1,0 +1,43 @@
+// Host-side interface between the counting runtime (kc_runtime.cpp) and the
+// request server (kc_server.cpp). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/kc.h"
+
+namespace kc {
+
+// Output allocation of a count whose result size is only known on the device:
+// fn is called once the number of distinct keys is known (before the pairs are
+// written) and must return device memory for `distinct` keys of `key_words`
+// uint64 words each and as many uint32 counts, or a KC_E_* status.
+struct OutAlloc {
+  int (*fn)(void* user, uint64_t distinct, int key_words, uint64_t** keys, uint32_t** counts);
+  void* user;
+};
+
+// kc_count_ex with the output allocated through `oa` instead of passed in.
+// Returns a status; on error *err receives the message. Synchronous on `st`.
+int count_with_alloc(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k,
+                     int P, const kc_options* opt, hipStream_t st, const OutAlloc& oa,
+                     uint64_t* n_out, kc_stats* stats, std::string* err);
+
+// Device bytes the calling thread's scratch arena (current device) grows by
+// for a plain count of n_bytes input bytes. Exact for the device-planned
+// path; the recursive fallback taken after a leaf overflow may need more.
+uint64_t scratch_growth(uint64_t n_bytes, int k, int P, const kc_options* opt);
+
+// The same for an empty arena.
+uint64_t scratch_bytes(uint64_t n_bytes, int k, int P, const kc_options* opt);
+
+// Device bytes held by the calling thread's arena on the current device.
+uint64_t arena_bytes();
+
+// Sets the message kc_last_error() returns on the calling thread.
+void set_last_error(const std::string& msg);
+
+}  // namespace kc

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/kc.h"
+#include "kc_host.h"
 #include "kc_internal.h"
 
 namespace {
@@ -73,6 +74,12 @@ void hipchk(hipError_t e, const char* what) {
   }
 }
 
+// Bytes ensure() allocates for a request (1/8 headroom against regrowth).
+size_t alloc_size(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  return bytes + bytes / 8;
+}
+
 void ensure(DevBuf& b, size_t bytes, const char* name) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return;
@@ -81,7 +88,7 @@ void ensure(DevBuf& b, size_t bytes, const char* name) {
     b.p = nullptr;
     b.cap = 0;
   }
-  size_t want = bytes + bytes / 8;
+  size_t want = alloc_size(bytes);
   hipError_t e = hipMalloc(&b.p, want);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -207,6 +214,8 @@ struct Call {
   uint64_t cap;
   kc_options o;
   hipStream_t st;
+  const kc::OutAlloc* oa = nullptr;  // output allocated once D is known (no concat before)
+  uint64_t concat_leaves = 0;        // leaf slots the deferred concat covers
   // derived
   uint64_t N = 0, off0 = 0;
   bool wide = false;
@@ -437,6 +446,8 @@ void general_path(Ctx& c, Call& q, kc_stats& S, Timer& tm) {
   hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dst_state, (unsigned long long*)c.bsum.p, nl,
                              (unsigned long long*)c.outoff.p, st),
          "plan_out launch");
+  q.concat_leaves = nl;
+  if (q.oa) return;  // the caller allocates the output, then runs the concat
   hipchk(kc::launch_concat(q.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                            (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
                            (unsigned long long*)c.outoff.p, dst_state, nl, q.cap, q.out_keys,
@@ -469,25 +480,48 @@ void pipe_bounds(Pipe& p) {
   p.max_leaves = std::min<uint64_t>(nb << kc::kSplitMaxBits, 2 * p.rec_bound / p.T + 2 * nb) + 1;
 }
 
-void pipeline_prepare(Ctx& c, const Pipe& p) {
+// 64-base chunks of the packed stream (two chunks of padding).
+uint64_t packed_chunks(uint64_t n_bytes) { return (n_bytes + 63) / 64 + 2; }
+
+// The arena buffers a pipeline run needs: f(member, bytes, name) per buffer.
+// The one list both allocation (pipeline_prepare) and the memory estimates of
+// the server (scratch_growth) read.
+template <class F>
+void pipeline_needs(const Pipe& p, F&& f) {
   const size_t ksz = p.wide ? 16 : 8;
   const uint64_t nb = 1ull << p.sb;
-  ensure(c.bufA, std::max<uint64_t>(p.rec_bound, 1) * ksz, "record buffer A");
-  ensure(c.bufB, std::max<uint64_t>(p.rec_bound, 1) * ksz, "record buffer B");
-  ensure(c.tmpcnt, std::max<uint64_t>(p.rec_bound, 1) * 4, "pair counts");
-  ensure(c.hist, nb * 8, "shard histogram");
-  ensure(c.sbegin, nb * 8, "shard begins");
-  ensure(c.cursor, nb * 8, "shard cursors");
-  ensure(c.bins, nb * sizeof(kc::SplitBin), "split bins");
-  ensure(c.items, p.max_items * sizeof(kc::SplitItem), "split items");
-  ensure(c.itemoff, (nb + 1) * 8, "split item offsets");
-  ensure(c.subhist, p.max_leaves * 8, "sub-bin histogram");
-  ensure(c.cursor2, p.max_leaves * 8, "sub-bin cursors");
-  ensure(c.leaves, p.max_leaves * sizeof(kc::Leaf), "leaf table");
-  ensure(c.dcnt, p.max_leaves * 4, "leaf counts");
-  ensure(c.outoff, p.max_leaves * 8, "output offsets");
-  ensure(c.large, p.max_leaves * 4, "large-leaf list");
-  ensure(c.bsum, kc::scan_blocks(p.max_leaves) * 8, "scan block sums");
+  f(&Ctx::bufA, std::max<uint64_t>(p.rec_bound, 1) * ksz, "record buffer A");
+  f(&Ctx::bufB, std::max<uint64_t>(p.rec_bound, 1) * ksz, "record buffer B");
+  f(&Ctx::tmpcnt, std::max<uint64_t>(p.rec_bound, 1) * 4, "pair counts");
+  f(&Ctx::hist, nb * 8, "shard histogram");
+  f(&Ctx::sbegin, nb * 8, "shard begins");
+  f(&Ctx::cursor, nb * 8, "shard cursors");
+  f(&Ctx::bins, nb * sizeof(kc::SplitBin), "split bins");
+  f(&Ctx::items, p.max_items * sizeof(kc::SplitItem), "split items");
+  f(&Ctx::itemoff, (nb + 1) * 8, "split item offsets");
+  f(&Ctx::subhist, p.max_leaves * 8, "sub-bin histogram");
+  f(&Ctx::cursor2, p.max_leaves * 8, "sub-bin cursors");
+  f(&Ctx::leaves, p.max_leaves * sizeof(kc::Leaf), "leaf table");
+  f(&Ctx::dcnt, p.max_leaves * 4, "leaf counts");
+  f(&Ctx::outoff, p.max_leaves * 8, "output offsets");
+  f(&Ctx::large, p.max_leaves * 4, "large-leaf list");
+  f(&Ctx::bsum, kc::scan_blocks(p.max_leaves) * 8, "scan block sums");
+}
+
+void pipeline_prepare(Ctx& c, const Pipe& p) {
+  pipeline_needs(p, [&](DevBuf Ctx::*m, size_t bytes, const char* name) { ensure(c.*m, bytes, name); });
+}
+
+// Plain calls add the packed input, the device state and the owner order.
+template <class F>
+void plain_needs(const Pipe& p, F&& f) {
+  const uint64_t nchunks = packed_chunks(p.byte_end);
+  f(&Ctx::packed, nchunks * 16, "packed bases");
+  f(&Ctx::inv, nchunks * 8, "invalid mask");
+  f(&Ctx::endm, nchunks * 8, "end mask");
+  f(&Ctx::state, sizeof(kc::DevState), "device state");
+  f(&Ctx::order, (size_t)(1ull << p.sb) * 4, "owner order");
+  pipeline_needs(p, f);
 }
 
 // Output of a pipeline run: plain (keys of 1 or 2 words, counts) or batch
@@ -497,6 +531,7 @@ struct PipeOut {
   uint32_t* counts;
   uint32_t* set;  // batch form only
   uint64_t cap;
+  bool concat = true;  // false: stop after the output offsets
 };
 
 void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, const PipeOut& out,
@@ -546,6 +581,7 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
                              p.max_leaves, (unsigned long long*)c.outoff.p, st),
          "plan_out launch");
   tm.mark(ST_OUT);
+  if (!out.concat) return;
   if (out.set)
     hipchk(kc::launch_concat_batch(p.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                    (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
@@ -584,6 +620,22 @@ int shard_bits_for(const kc_options& o, int P, uint64_t rec_bound, uint64_t T, i
   return std::max(1, std::min(sb, keybits));
 }
 
+// The pipeline of a plain call over n_bytes bytes.
+Pipe plain_pipe(uint64_t n_bytes, int k, int P, const kc_options& o) {
+  Pipe p;
+  p.wide = k > 32;
+  p.k = k;
+  p.keybits = 2 * k;
+  uint64_t C = 0;
+  table_params(o, p.wide, p.slots_log2, C, p.T, p.H);
+  p.sb = shard_bits_for(o, P, n_bytes, p.T, p.keybits);
+  p.byte_begin = 0;
+  p.byte_end = n_bytes;
+  p.rec_bound = n_bytes;  // byte count: an upper bound of the window count
+  pipe_bounds(p);
+  return p;
+}
+
 // Owner-major shard order on the device, cached in the context per (P, sb).
 const int* device_order(Ctx& c, const Call& q, kc_stats& S, hipStream_t st) {
   if (c.order_P != q.P || c.order_sb != q.sb) {
@@ -599,7 +651,7 @@ const int* device_order(Ctx& c, const Call& q, kc_stats& S, hipStream_t st) {
 
 int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
                uint64_t* out_keys, uint32_t* out_counts, uint64_t cap, uint64_t* n_out,
-               const kc_options* opt, hipStream_t st) {
+               const kc_options* opt, hipStream_t st, const kc::OutAlloc* oa = nullptr) {
   auto t_host0 = std::chrono::steady_clock::now();
   if (!n_out) fail(KC_E_INVAL, "n_out is NULL");
   *n_out = 0;
@@ -608,7 +660,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   if (!offsets) fail(KC_E_INVAL, "offsets is NULL");
   if (n_reads && !reads) fail(KC_E_INVAL, "reads is NULL");
   if (cap && (!out_keys || !out_counts)) fail(KC_E_INVAL, "output pointer is NULL");
-  Call q{reads, offsets, n_reads, k, P, out_keys, out_counts, cap, {}, st};
+  Call q{reads, offsets, n_reads, k, P, out_keys, out_counts, cap, {}, st, oa};
   std::memset(&q.o, 0, sizeof(q.o));
   if (opt) q.o = *opt;
   if (q.o.mode != 0) fail(KC_E_INVAL, "mode must be 0");
@@ -645,30 +697,16 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
     g_stats = S;
     return KC_OK;
   }
-  q.wide = k > 32;
-  q.keybits = 2 * k;
+  const Pipe p0 = plain_pipe(q.N, k, P, q.o);
+  q.wide = p0.wide;
+  q.keybits = p0.keybits;
   q.ksz = q.wide ? 16 : 8;
   table_params(q.o, q.wide, q.slots_log2, q.C, q.T, q.H);
-  q.sb = shard_bits_for(q.o, P, q.N, q.T, q.keybits);
+  q.sb = p0.sb;
   q.nb = 1 << q.sb;
-
-  Pipe p;
-  p.wide = q.wide;
-  p.k = k;
-  p.keybits = q.keybits;
-  p.sb = q.sb;
-  p.slots_log2 = q.slots_log2;
-  p.byte_begin = 0;
-  p.byte_end = q.N;
-  p.rec_bound = q.N;  // byte count: an upper bound of the window count
-  p.T = q.T;
-  p.H = q.H;
-  pipe_bounds(p);
-  const uint64_t nchunks = (q.N + 63) / 64 + 2;
-  ensure(c.packed, nchunks * 16, "packed bases");
-  ensure(c.inv, nchunks * 8, "invalid mask");
-  ensure(c.endm, nchunks * 8, "end mask");
-  pipeline_prepare(c, p);
+  Pipe p = p0;
+  const uint64_t nchunks = packed_chunks(q.N);
+  plain_needs(p, [&](DevBuf Ctx::*m, size_t bytes, const char* name) { ensure(c.*m, bytes, name); });
   p.order = device_order(c, q, S, st);
   kc::DevState* dstate = (kc::DevState*)c.state.p;
 
@@ -677,8 +715,9 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
                          (uint64_t*)c.inv.p, (uint64_t*)c.endm.p, nchunks, st),
          "pack launch");
   tm.mark(ST_PACK);
-  enqueue_pipeline(c, p, dstate, tm, PipeOut{out_keys, out_counts, nullptr, cap}, st);
-  kc::DevState ds = read_state(c, st);  // host sync 2 of 2
+  enqueue_pipeline(c, p, dstate, tm, PipeOut{out_keys, out_counts, nullptr, cap, !oa}, st);
+  q.concat_leaves = p.max_leaves;
+  kc::DevState ds = read_state(c, st);  // host sync 2 of 2 (3 with an output allocator)
   S.n_levels = 1;
   S.n_leaves = ds.n_leaves;
   if (ds.overflow) {
@@ -694,6 +733,18 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   S.large_records = ds.large_records;
   S.large_distinct = ds.large_distinct;
   if (ds.count_overflow) fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
+  if (oa) {
+    const int r = oa->fn(oa->user, ds.D, q.wide ? 2 : 1, &out_keys, &out_counts);
+    if (r != KC_OK) fail(r, "output allocation of " + std::to_string(ds.D) + " pairs failed");
+    cap = ds.D;
+    tm.mark(ST_NONE);
+    hipchk(kc::launch_concat(q.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                             (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
+                             (unsigned long long*)c.outoff.p, dstate, q.concat_leaves, cap,
+                             out_keys, out_counts, st),
+           "concat launch");
+    tm.mark(ST_CONCAT);
+  }
   if (ds.D > cap) {
     *n_out = ds.D;
     fail(KC_E_CAPACITY, "output capacity " + std::to_string(cap) + " < " + std::to_string(ds.D) +
@@ -719,6 +770,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
       fail(KC_E_INTERNAL, msg);
     }
   }
+  if (oa) hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
   tm.collect(S);
   *n_out = ds.D;
   S.ms_total =
@@ -1109,6 +1161,69 @@ int guarded(F f) {
 }
 
 }  // namespace
+
+namespace kc {
+
+int count_with_alloc(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k,
+                     int P, const kc_options* opt, hipStream_t st, const OutAlloc& oa,
+                     uint64_t* n_out, kc_stats* stats, std::string* err) {
+  const int r = guarded([&] {
+    return count_impl(reads, offsets, n_reads, k, P, nullptr, nullptr, 0, n_out, opt, st, &oa);
+  });
+  if (r == KC_OK && stats) *stats = g_stats;
+  if (r != KC_OK && err) *err = g_err;
+  return r;
+}
+
+namespace {
+uint64_t growth_of(const Ctx* c, uint64_t n_bytes, int k, int P, const kc_options* opt) {
+  if (n_bytes == 0 || k < 1 || k > 64 || P < 1) return 0;
+  kc_options o;
+  std::memset(&o, 0, sizeof(o));
+  if (opt) o = *opt;
+  const Pipe p = plain_pipe(n_bytes, k, P, o);
+  uint64_t g = 0;
+  plain_needs(p, [&](DevBuf Ctx::*m, size_t bytes, const char*) {
+    const size_t have = c ? (c->*m).cap : 0;
+    if (have < std::max<size_t>(bytes, 1)) g += alloc_size(bytes) - have;
+  });
+  return g;
+}
+}  // namespace
+
+uint64_t scratch_growth(uint64_t n_bytes, int k, int P, const kc_options* opt) {
+  try {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return growth_of(nullptr, n_bytes, k, P, opt);
+    auto it = g_ctx.find(dev);
+    return growth_of(it == g_ctx.end() ? nullptr : it->second.get(), n_bytes, k, P, opt);
+  } catch (...) {
+    return growth_of(nullptr, n_bytes, k, P, opt);
+  }
+}
+
+void set_last_error(const std::string& msg) { g_err = msg; }
+
+uint64_t scratch_bytes(uint64_t n_bytes, int k, int P, const kc_options* opt) {
+  return growth_of(nullptr, n_bytes, k, P, opt);
+}
+
+uint64_t arena_bytes() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  auto it = g_ctx.find(dev);
+  if (it == g_ctx.end() || !it->second) return 0;
+  const Ctx& c = *it->second;
+  const DevBuf* all[] = {&c.packed, &c.inv,    &c.endm,  &c.bufA,   &c.bufB,  &c.tmpcnt,
+                         &c.hist,   &c.sbegin, &c.cursor, &c.cursor2, &c.order, &c.items,
+                         &c.bins,   &c.subhist, &c.leaves, &c.dcnt,  &c.outoff, &c.state,
+                         &c.large,  &c.bsum,   &c.itemoff};
+  uint64_t t = 0;
+  for (const DevBuf* b : all) t += b->cap;
+  return t;
+}
+
+}  // namespace kc
 
 extern "C" {
 

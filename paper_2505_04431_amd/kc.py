@@ -22,7 +22,12 @@ STATUS = {0: "KC_OK", -1: "KC_E_INVAL", -2: "KC_E_NOMEM", -3: "KC_E_CAPACITY",
 EXPORTED_SYMBOLS = ["kc_count", "kc_count_ex", "kc_max_outputs", "kc_last_stats",
                     "kc_release_scratch", "kc_strerror", "kc_last_error", "kc_version",
                     "kc_batch_plan", "kc_batch_run", "kc_batch_max_outputs", "kc_batch_stats",
-                    "kc_batch_free"]
+                    "kc_batch_free", "kc_server_create", "kc_server_submit", "kc_server_poll",
+                    "kc_server_wait", "kc_server_result", "kc_server_result_copy",
+                    "kc_server_job_info", "kc_server_release", "kc_server_stats",
+                    "kc_server_destroy"]
+
+JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
 
 class KcOptions(ctypes.Structure):
@@ -40,6 +45,24 @@ class KcStats(ctypes.Structure):
                 ("table_slots", ctypes.c_uint64), ("large_records", ctypes.c_uint64),
                 ("large_distinct", ctypes.c_uint64), ("ms_total", ctypes.c_double),
                 ("ms_stage", ctypes.c_double * 12)]
+
+
+class KcJobInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("status", ctypes.c_int), ("worker", ctypes.c_int),
+                ("k", ctypes.c_int), ("n_bytes", ctypes.c_uint64),
+                ("valid_windows", ctypes.c_uint64), ("distinct", ctypes.c_uint64),
+                ("result_estimate_bytes", ctypes.c_uint64), ("result_bytes", ctypes.c_uint64),
+                ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
+                ("t_end_ms", ctypes.c_double)]
+
+
+class KcServeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("submitted", "completed", "failed", "queued", "running", "valid_windows",
+                 "budget", "bytes_in_use", "bytes_peak", "estimate_misses",
+                 "result_bytes_reserved", "result_bytes_actual")] + \
+               [(n, ctypes.c_double) for n in
+                ("latency_p50_ms", "latency_p99_ms", "wait_p50_ms", "wait_p99_ms", "busy_ms")]
 
 
 STAGES = ["pack", "window_hist", "owner_scatter", "split_hist", "split_scatter", "leaf_small",
@@ -93,6 +116,26 @@ def lib():
             L.kc_batch_stats.argtypes = [p, p]
             L.kc_batch_free.restype = None
             L.kc_batch_free.argtypes = [p]
+            L.kc_server_create.restype = i32
+            L.kc_server_create.argtypes = [u64, i32, p, p]
+            L.kc_server_submit.restype = i32
+            L.kc_server_submit.argtypes = [p, p, p, u64, i32, i32, u64, p]
+            L.kc_server_poll.restype = i32
+            L.kc_server_poll.argtypes = [p, u64, p]
+            L.kc_server_wait.restype = i32
+            L.kc_server_wait.argtypes = [p, u64, p]
+            L.kc_server_result.restype = i32
+            L.kc_server_result.argtypes = [p, u64, p, p, p]
+            L.kc_server_result_copy.restype = i32
+            L.kc_server_result_copy.argtypes = [p, u64, p, p, u64, p, p]
+            L.kc_server_job_info.restype = i32
+            L.kc_server_job_info.argtypes = [p, u64, p]
+            L.kc_server_release.restype = i32
+            L.kc_server_release.argtypes = [p, u64]
+            L.kc_server_stats.restype = i32
+            L.kc_server_stats.argtypes = [p, p]
+            L.kc_server_destroy.restype = None
+            L.kc_server_destroy.argtypes = [p]
             _lib = L
     return _lib
 
@@ -229,6 +272,94 @@ class BatchPlan:
         if self._h:
             lib().kc_batch_free(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server (kc_server_*): jobs counted side by side on the device
+    under a byte budget; results stay on the device until released.
+
+    Inputs of a submitted job must stay alive (and unchanged) until the job
+    has finished; this wrapper keeps a reference to them until release().
+    """
+
+    def __init__(self, budget_bytes: int, workers: int = 4, opts: KcOptions | None = None):
+        self._h = ctypes.c_void_p()
+        self._inputs = {}
+        st = lib().kc_server_create(int(budget_bytes), int(workers),
+                                    ctypes.byref(opts) if opts is not None else None,
+                                    ctypes.byref(self._h))
+        if st != 0:
+            raise KcError(st, lib().kc_last_error().decode())
+
+    def _chk(self, st):
+        if st != 0:
+            raise KcError(st, lib().kc_last_error().decode())
+
+    def submit(self, reads, offsets, k: int, P: int = 1, distinct_hint: int = 0) -> int:
+        import torch
+        _check_tensor(reads, "reads", (torch.uint8,))
+        _check_tensor(offsets, "offsets", (torch.int64, torch.uint64))
+        jid = ctypes.c_uint64(0)
+        self._chk(lib().kc_server_submit(self._h, reads.data_ptr(), offsets.data_ptr(),
+                                         offsets.numel() - 1, k, P, int(distinct_hint),
+                                         ctypes.byref(jid)))
+        self._inputs[jid.value] = (reads, offsets)
+        return int(jid.value)
+
+    def poll(self, job: int) -> str:
+        s = ctypes.c_int(0)
+        self._chk(lib().kc_server_poll(self._h, job, ctypes.byref(s)))
+        return JOB_STATES[s.value]
+
+    def wait(self, job: int) -> str:
+        s = ctypes.c_int(0)
+        self._chk(lib().kc_server_wait(self._h, job, ctypes.byref(s)))
+        return JOB_STATES[s.value]
+
+    def info(self, job: int) -> dict:
+        i = KcJobInfo()
+        self._chk(lib().kc_server_job_info(self._h, job, ctypes.byref(i)))
+        d = {n: getattr(i, n) for n, _ in KcJobInfo._fields_}
+        d["state"] = JOB_STATES[d["state"]]
+        return d
+
+    def result(self, job: int, stream=None):
+        """Copy of a finished job's (keys, counts) as new device tensors."""
+        import torch
+        self.wait(job)
+        info = self.info(job)
+        n, words = int(info["distinct"]), (2 if info["k"] > 32 else 1)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        keys = torch.empty((max(n, 1), words) if words == 2 else (max(n, 1),), dtype=torch.int64,
+                           device=dev)
+        counts = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        n_out = ctypes.c_uint64(0)
+        self._chk(lib().kc_server_result_copy(self._h, job, keys.data_ptr(), counts.data_ptr(),
+                                              max(n, 1), ctypes.byref(n_out), stream))
+        return keys[:n_out.value], counts[:n_out.value]
+
+    def release(self, job: int):
+        self._chk(lib().kc_server_release(self._h, job))
+        self._inputs.pop(job, None)
+
+    def stats(self) -> dict:
+        s = KcServeStats()
+        self._chk(lib().kc_server_stats(self._h, ctypes.byref(s)))
+        return {n: getattr(s, n) for n, _ in KcServeStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().kc_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._inputs.clear()
 
     def __del__(self):
         try:

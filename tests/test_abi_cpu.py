@@ -48,3 +48,27 @@ def test_options_layout_matches_header():
     # kc_options: 7 ints + 5 reserved; kc_stats: 11 uint64 + 13 doubles
     assert ctypes.sizeof(kc.kc.KcOptions) == 12 * 4
     assert ctypes.sizeof(kc.kc.KcStats) == 11 * 8 + 13 * 8
+
+
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """sizeof/offsetof of every public struct, as gcc lays out include/kc.h,
+    equal the ctypes mirrors of the binding."""
+    mirrors = {"kc_options": kc.kc.KcOptions, "kc_stats": kc.kc.KcStats,
+               "kc_job_info": kc.kc.KcJobInfo, "kc_serve_stats": kc.kc.KcServeStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kc.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                           str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for cname, py in mirrors.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)

@@ -1,0 +1,126 @@
+"""Served counting: jobs submitted to the request server run side by side on
+the device; each result must equal what the job gives alone (plain call) and
+what the oracle gives. Integer work: bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2505_04431_amd as kc
+import synth
+from gpu_util import assert_same, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def served_jobs(seed, n, max_genome=400_000):
+    """Jobs shaped like the served workload (short and long reads, k in
+    {31, 55}, 10% repeats), genomes scaled down so the oracle stays fast."""
+    specs = synth.c5_jobs(n, seed=synth.CONFIG_SEED_BASE + 5 + seed)
+    out = []
+    for sp in specs:
+        sp = dict(sp)
+        sp["genome_len"] = int(min(max_genome, max(2_000, sp["genome_len"] // 200)))
+        sp["coverage"] = min(sp["coverage"], 12)
+        sp["read_len"] = min(sp["read_len"], max(150, sp["genome_len"] // 4))
+        r, o = synth.c5_job_reads(sp, seed=synth.CONFIG_SEED_BASE + 5 + seed, threads=4)
+        out.append((r, o, sp["k"]))
+    return out
+
+
+def host(keys, counts):
+    return keys.cpu().numpy().view(np.uint64), counts.cpu().numpy().view(np.uint32)
+
+
+def test_server_alone_vs_mix():
+    import torch
+    jobs = served_jobs(1, 14)
+    # plus ragged reads of random bytes with N and lowercase, k from 1 to 64
+    for i, k in enumerate((1, 9, 32, 33, 64)):
+        r, o = synth.ragged_reads(900 + i, 300, 0, 400, alphabet=b"ACGTNacgt")
+        jobs.append((r, o, k))
+    dev_in = [to_device(r, o) for r, o, _ in jobs]
+    torch.cuda.synchronize()
+    srv = kc.Server(budget_bytes=48 << 30, workers=4)
+    try:
+        ids = [srv.submit(rt, ot, k, P=(7 if i % 2 else 64)) for i, ((rt, ot), (_, _, k))
+               in enumerate(zip(dev_in, jobs))]
+        for j in ids:
+            assert srv.wait(j) == "done", srv.info(j)
+        for i, (j, (rt, ot), (r, o, k)) in enumerate(zip(ids, dev_in, jobs)):
+            got = host(*srv.result(j))
+            alone = host(*kc.count(rt, ot, k, P=1))
+            assert_same(got, alone, "job %d (k=%d) served vs alone" % (i, k))
+            if i % 3 == 0 or r.size < 2_000_000:
+                assert_same(got, oracle.count(r, o, k), "job %d (k=%d) vs oracle" % (i, k))
+            info = srv.info(j)
+            assert info["distinct"] == got[0].shape[0]
+            assert info["valid_windows"] == int(got[1].astype(np.uint64).sum())
+            srv.release(j)
+        st = srv.stats()
+        assert st["completed"] == len(jobs) and st["failed"] == 0
+        assert st["bytes_peak"] <= st["budget"]
+        assert st["latency_p99_ms"] >= st["latency_p50_ms"] > 0
+    finally:
+        srv.close()
+
+
+def test_server_tight_budget_and_hints():
+    """A budget that holds about one job's scratch at a time: jobs queue and
+    still finish; low hints are corrected (result sized to its true D)."""
+    import torch
+    jobs = served_jobs(2, 8, max_genome=200_000)
+    dev_in = [to_device(r, o) for r, o, _ in jobs]
+    torch.cuda.synchronize()
+    biggest = max(r.size for r, _, _ in jobs)
+    budget = int(biggest * 120)  # about two jobs' scratch (up to 36 B/byte) plus results
+    srv = kc.Server(budget_bytes=budget, workers=3)
+    try:
+        ids = [srv.submit(rt, ot, k, P=16, distinct_hint=(1 if i % 2 else 0))
+               for i, ((rt, ot), (_, _, k)) in enumerate(zip(dev_in, jobs))]
+        for j, (r, o, k) in zip(ids, jobs):
+            assert srv.wait(j) == "done"
+            assert_same(host(*srv.result(j)), oracle.count(r, o, k), "k=%d" % k)
+        st = srv.stats()
+        assert st["completed"] == len(jobs)
+        assert st["estimate_misses"] >= 1  # the hint-1 jobs
+        for j in ids:
+            srv.release(j)
+        assert srv.stats()["bytes_in_use"] <= budget
+    finally:
+        srv.close()
+
+
+def test_server_errors():
+    import torch
+    r, o = synth.ragged_reads(5, 2000, 100, 200)
+    rt, ot = to_device(r, o)
+    torch.cuda.synchronize()
+    srv = kc.Server(budget_bytes=1 << 20, workers=1)
+    try:
+        with pytest.raises(kc.KcError) as e:
+            srv.submit(rt, ot, 31)  # needs far more than 1 MiB
+        assert e.value.status == -2
+        with pytest.raises(kc.KcError) as e:
+            srv.submit(rt, ot, 0)
+        assert e.value.status == -1
+        with pytest.raises(kc.KcError) as e:
+            srv.poll(12345)
+        assert e.value.status == -1
+    finally:
+        srv.close()
+    with pytest.raises(kc.KcError):
+        kc.Server(budget_bytes=0)
+    # an empty job and a job whose reads are all shorter than k
+    srv = kc.Server(budget_bytes=1 << 30, workers=2)
+    try:
+        e_rt, e_ot = to_device(np.zeros(0, np.uint8), np.zeros(1, np.uint64))
+        s_rt, s_ot = to_device(*synth.ragged_reads(6, 50, 0, 20))
+        torch.cuda.synchronize()
+        a = srv.submit(e_rt, e_ot, 5)
+        b = srv.submit(s_rt, s_ot, 25)
+        assert srv.wait(a) == "done" and srv.wait(b) == "done"
+        assert srv.result(a)[0].numel() == 0 and srv.result(b)[0].numel() == 0
+        srv.release(a)
+        srv.release(b)
+    finally:
+        srv.close()
