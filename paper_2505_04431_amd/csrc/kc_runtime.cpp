@@ -143,20 +143,6 @@ int ceil_log2(uint64_t x) {
   return b;
 }
 
-struct Bin {
-  uint64_t begin, end;
-  u128 prefix;  // value of the key bits consumed so far
-  int bits;     // number of key bits consumed (from the most significant end)
-  int buf;      // buffer holding its records
-};
-
-struct LeafDone {
-  u128 start;  // first key of its range
-  uint64_t begin, end;
-  uint32_t d;
-  int buf, bits;
-};
-
 struct Timer {
   Ctx& c;
   hipStream_t s;
@@ -268,177 +254,185 @@ kc::DevState read_state(Ctx& c, hipStream_t st) {
   return *h;
 }
 
-// Host-driven partitioning with any number of split levels: used when a leaf
-// of the device-planned path overflowed its table. Starts from the packed
-// input and the shard histogram already on the device.
-void general_path(Ctx& c, Call& q, kc_stats& S, Timer& tm) {
+// Recovery after leaves of the device-planned path overflowed their tables:
+// only those leaves are partitioned further, level by level under host
+// control (split their records on the next key bits into the other buffer,
+// count every non-empty part, split again what overflows), and the parts
+// replace their parent in the leaf list, which stays in key order. Every part
+// is counted as soon as it exists, so a part dominated by one frequent key
+// is settled at once however many records it holds. Ends with the output
+// offsets (and the concat unless the caller allocates the output first).
+void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0) {
   const hipStream_t st = q.st;
-  std::vector<uint64_t> hist(q.nb);
+  std::vector<kc::Leaf> lv(nl0);
+  std::vector<uint32_t> dv(nl0);
   {
-    uint64_t* hh = (uint64_t*)host_stage(c, (size_t)q.nb * 8);
-    hipchk(hipMemcpyAsync(hh, c.hist.p, (size_t)q.nb * 8, hipMemcpyDeviceToHost, st),
+    char* h = (char*)host_stage(c, nl0 * (sizeof(kc::Leaf) + 4) + 64);
+    hipchk(hipMemcpyAsync(h, c.leaves.p, nl0 * sizeof(kc::Leaf), hipMemcpyDeviceToHost, st),
+           "hipMemcpyAsync");
+    hipchk(hipMemcpyAsync(h + nl0 * sizeof(kc::Leaf), c.dcnt.p, nl0 * 4, hipMemcpyDeviceToHost, st),
            "hipMemcpyAsync");
     hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-    std::memcpy(hist.data(), hh, (size_t)q.nb * 8);
+    std::memcpy(lv.data(), h, nl0 * sizeof(kc::Leaf));
+    std::memcpy(dv.data(), h + nl0 * sizeof(kc::Leaf), nl0 * 4);
   }
-  const std::vector<int>& order = owner_order(c, q, S, &hist);
-  std::vector<uint64_t> sbegin(q.nb);
-  uint64_t run = 0;
-  for (int i : order) {
-    sbegin[i] = run;
-    run += hist[i];
-  }
-  const uint64_t W = run;
-  upload_sync(c.cursor.p, sbegin.data(), (size_t)q.nb * 8, st);
-  hipchk(kc::launch_window_scatter(q.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
-                                   (uint64_t*)c.endm.p, 0, q.N, q.k, q.keybits, q.sb, nullptr,
-                                   (unsigned long long*)c.cursor.p, c.bufA.p, st),
-         "owner scatter launch");
-  tm.mark(ST_SCATTER);
-
-  std::vector<Bin> cur;
-  for (int i = 0; i < q.nb; ++i)
-    if (hist[i]) cur.push_back(Bin{sbegin[i], sbegin[i] + hist[i], (u128)i, q.sb, 0});
-  std::vector<LeafDone> done;
+  struct Part {
+    uint64_t begin, end;
+    u128 rel;     // key bits below the parent leaf's prefix consumed so far
+    int bits;     // key bits consumed in total (from the most significant end)
+    int buf;      // buffer holding its records
+    uint32_t root;
+  };
+  struct Done {
+    uint32_t root;
+    u128 start;  // first key of its range, relative to the parent's prefix
+    kc::Leaf leaf;
+    uint32_t d;
+  };
+  std::vector<Part> split;
+  for (uint64_t i = 0; i < nl0; ++i)
+    if (dv[i] == kc::kLeafOverflow) {
+      if ((int)lv[i].bits >= q.keybits) fail(KC_E_INTERNAL, "single-key partition overflowed its table");
+      split.push_back(Part{lv[i].begin, lv[i].end, 0, (int)lv[i].bits, (int)lv[i].buf, (uint32_t)i});
+      ++S.n_overflow;
+    }
+  std::vector<Done> done;
   void* bufs[2] = {c.bufA.p, c.bufB.p};
   kc::DevState* dst_state = (kc::DevState*)c.state.p;
-  const uint64_t T = std::min<uint64_t>(q.T, q.C / 4);  // finer leaves than the fast path
-  const uint64_t H = q.C / 2;
+  const uint64_t T = std::min<uint64_t>(q.T, q.C / 4);
+  const uint64_t tile = (uint64_t)kc::split_tile(q.wide);
   int level = 0;
-  while (!cur.empty()) {
-    std::vector<Bin> attempt, split;
-    std::vector<bool> was_ovf;
-    for (const Bin& b : cur) {
-      const uint64_t n = b.end - b.begin;
-      if (b.bits >= q.keybits || n <= H) {
-        if (b.bits >= q.keybits && n > 0xFFFFFFFFull)
-          fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
-        attempt.push_back(b);
-      } else {
-        split.push_back(b);
-        was_ovf.push_back(false);
-      }
-    }
-    if (!attempt.empty()) {
-      const size_t na = attempt.size();
-      std::vector<kc::Leaf> lv(na);
-      for (size_t i = 0; i < na; ++i)
-        lv[i] = kc::Leaf{attempt[i].begin, attempt[i].end, (uint32_t)attempt[i].buf,
-                         (uint32_t)attempt[i].bits};
-      ensure(c.leaves, na * sizeof(kc::Leaf), "leaf table");
-      ensure(c.dcnt, na * 4, "leaf counts");
-      ensure(c.large, na * 4, "large-leaf list");
-      upload_sync(c.leaves.p, lv.data(), na * sizeof(kc::Leaf), st);
-      unsigned long long nl = na;
-      upload_sync(&dst_state->n_leaves, &nl, 8, st);
-      hipchk(kc::launch_leaf_small(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
-                                   (kc::Leaf*)c.leaves.p, dst_state, na, (uint32_t*)c.dcnt.p,
-                                   (uint32_t*)c.large.p, st),
-             "leaf count launch");
-      hipchk(kc::launch_leaf_large(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
-                                   (kc::Leaf*)c.leaves.p, dst_state, na, (uint32_t*)c.dcnt.p,
-                                   q.slots_log2, (uint32_t*)c.large.p, st),
-             "leaf count launch");
-      tm.mark(ST_LEAF);
-      uint32_t* hd = (uint32_t*)host_stage(c, na * 4);
-      hipchk(hipMemcpyAsync(hd, c.dcnt.p, na * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-      hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-      for (size_t i = 0; i < na; ++i) {
-        const Bin& b = attempt[i];
-        if (hd[i] == kc::kLeafOverflow) {
-          if (b.bits >= q.keybits) fail(KC_E_INTERNAL, "single-key partition overflowed its table");
-          ++S.n_overflow;
-          split.push_back(b);
-          was_ovf.push_back(true);
-        } else {
-          done.push_back(LeafDone{b.prefix << (q.keybits - b.bits), b.begin, b.end, hd[i], b.buf,
-                                  b.bits});
-          S.max_leaf_windows = std::max(S.max_leaf_windows, b.end - b.begin);
-        }
-      }
-    }
-    if (split.empty()) break;
+  while (!split.empty()) {
     ++level;
+    // split every part on its next key bits (at least 2, so each level narrows it)
     const size_t ns = split.size();
     std::vector<kc::SplitBin> sbins(ns);
     std::vector<kc::SplitItem> items;
     uint64_t hoff = 0;
-    const uint64_t tile = (uint64_t)kc::split_tile(q.wide);
     for (size_t i = 0; i < ns; ++i) {
-      const Bin& b = split[i];
+      const Part& b = split[i];
       const uint64_t n = b.end - b.begin;
       const int remaining = q.keybits - b.bits;
-      int nbits = ceil_log2((n + T - 1) / T);
-      if (was_ovf[i]) nbits = std::max(nbits, 2);
+      int nbits = std::max(2, ceil_log2((n + T - 1) / T));
       nbits = std::max(1, std::min(nbits, std::min(kc::kSplitMaxBits, remaining)));
-      sbins[i] = kc::SplitBin{hoff, (uint32_t)(q.keybits - b.bits - nbits), (uint32_t)nbits};
+      sbins[i] = kc::SplitBin{hoff, (uint32_t)(remaining - nbits), (uint32_t)nbits};
       hoff += 1ull << nbits;
       for (uint64_t a = b.begin; a < b.end; a += tile)
         items.push_back(kc::SplitItem{a, std::min(b.end, a + tile), (uint32_t)i, 0});
     }
-    ensure(c.bins, ns * sizeof(kc::SplitBin), "split bins");
-    ensure(c.items, items.size() * sizeof(kc::SplitItem), "split items");
-    ensure(c.subhist, hoff * 8, "sub-bin histogram");
-    ensure(c.cursor2, hoff * 8, "sub-bin cursors");
-    upload_sync(c.items.p, items.data(), items.size() * sizeof(kc::SplitItem), st);
-    upload_sync(c.bins.p, sbins.data(), ns * sizeof(kc::SplitBin), st);
-    unsigned long long ni = items.size();
-    upload_sync(&dst_state->n_items, &ni, 8, st);
-    hipchk(kc::launch_fill_u64((unsigned long long*)c.subhist.p, hoff, 0, st), "fill launch");
-    const int src = split[0].buf;
-    hipchk(kc::launch_split_hist(q.wide, bufs[src], (kc::SplitItem*)c.items.p, dst_state,
-                                 items.size(), (kc::SplitBin*)c.bins.p,
-                                 (unsigned long long*)c.subhist.p, st),
-           "split histogram launch");
-    uint64_t* hsub = (uint64_t*)host_stage(c, hoff * 8 + 64);
-    hipchk(hipMemcpyAsync(hsub, c.subhist.p, hoff * 8, hipMemcpyDeviceToHost, st),
-           "hipMemcpyAsync");
-    hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-    std::vector<Bin> next;
-    std::vector<uint64_t> hcur(hoff);
-    for (size_t i = 0; i < ns; ++i) {
-      const Bin& b = split[i];
-      const kc::SplitBin& sbn = sbins[i];
-      uint64_t r = b.begin;
-      for (uint64_t j = 0; j < (1ull << sbn.nbits); ++j) {
-        const uint64_t cnt = hsub[sbn.hist_off + j];
-        hcur[sbn.hist_off + j] = r;
-        if (cnt)
-          next.push_back(Bin{r, r + cnt, (b.prefix << sbn.nbits) | (u128)j,
-                             b.bits + (int)sbn.nbits, 1 - b.buf});
-        r += cnt;
+    // parts of one level may sit in different buffers: one pass per source buffer
+    std::vector<Part> next;
+    for (int src = 0; src < 2; ++src) {
+      std::vector<kc::SplitItem> it_src;
+      for (const kc::SplitItem& it : items)
+        if (split[it.bin].buf == src) it_src.push_back(it);
+      if (it_src.empty()) continue;
+      ensure(c.bins, ns * sizeof(kc::SplitBin), "split bins");
+      ensure(c.items, it_src.size() * sizeof(kc::SplitItem), "split items");
+      ensure(c.subhist, hoff * 8, "sub-bin histogram");
+      ensure(c.cursor2, hoff * 8, "sub-bin cursors");
+      upload_sync(c.items.p, it_src.data(), it_src.size() * sizeof(kc::SplitItem), st);
+      upload_sync(c.bins.p, sbins.data(), ns * sizeof(kc::SplitBin), st);
+      unsigned long long ni = it_src.size();
+      upload_sync(&dst_state->n_items, &ni, 8, st);
+      hipchk(kc::launch_fill_u64((unsigned long long*)c.subhist.p, hoff, 0, st), "fill launch");
+      hipchk(kc::launch_split_hist(q.wide, bufs[src], (kc::SplitItem*)c.items.p, dst_state,
+                                   it_src.size(), (kc::SplitBin*)c.bins.p,
+                                   (unsigned long long*)c.subhist.p, st),
+             "split histogram launch");
+      uint64_t* hsub = (uint64_t*)host_stage(c, hoff * 8 + 64);
+      hipchk(hipMemcpyAsync(hsub, c.subhist.p, hoff * 8, hipMemcpyDeviceToHost, st),
+             "hipMemcpyAsync");
+      hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+      std::vector<uint64_t> hcur(hoff, 0);
+      for (size_t i = 0; i < ns; ++i) {
+        const Part& b = split[i];
+        if (b.buf != src) continue;
+        const kc::SplitBin& sbn = sbins[i];
+        uint64_t r = b.begin;
+        for (uint64_t j = 0; j < (1ull << sbn.nbits); ++j) {
+          const uint64_t cnt = hsub[sbn.hist_off + j];
+          hcur[sbn.hist_off + j] = r;
+          if (cnt)
+            next.push_back(Part{r, r + cnt, (b.rel << sbn.nbits) | (u128)j,
+                                b.bits + (int)sbn.nbits, 1 - b.buf, b.root});
+          r += cnt;
+        }
+        if (r != b.end) fail(KC_E_INTERNAL, "split histogram does not match partition size");
       }
-      if (r != b.end) fail(KC_E_INTERNAL, "split histogram does not match partition size");
+      upload_sync(c.cursor2.p, hcur.data(), hoff * 8, st);
+      hipchk(kc::launch_split_scatter(q.wide, bufs[src], bufs[1 - src],
+                                      (kc::SplitItem*)c.items.p, dst_state, it_src.size(),
+                                      (kc::SplitBin*)c.bins.p, (unsigned long long*)c.cursor2.p,
+                                      st),
+             "split scatter launch");
     }
-    upload_sync(c.cursor2.p, hcur.data(), hoff * 8, st);
-    hipchk(kc::launch_split_scatter(q.wide, bufs[src], bufs[1 - src], (kc::SplitItem*)c.items.p,
-                                    dst_state, items.size(), (kc::SplitBin*)c.bins.p,
-                                    (unsigned long long*)c.cursor2.p, st),
-           "split scatter launch");
     tm.mark(ST_SPLIT);
+    // count every part
+    const size_t na = next.size();
+    std::vector<kc::Leaf> al(na);
+    for (size_t i = 0; i < na; ++i)
+      al[i] = kc::Leaf{next[i].begin, next[i].end, (uint32_t)next[i].buf, (uint32_t)next[i].bits};
+    ensure(c.leaves, na * sizeof(kc::Leaf), "leaf table");
+    ensure(c.dcnt, na * 4, "leaf counts");
+    ensure(c.large, na * 4, "large-leaf list");
+    upload_sync(c.leaves.p, al.data(), na * sizeof(kc::Leaf), st);
+    unsigned long long nlu = na;
+    upload_sync(&dst_state->n_leaves, &nlu, 8, st);
+    hipchk(kc::launch_leaf_small(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                                 (kc::Leaf*)c.leaves.p, dst_state, na, (uint32_t*)c.dcnt.p,
+                                 (uint32_t*)c.large.p, st),
+           "leaf count launch");
+    hipchk(kc::launch_leaf_large(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                                 (kc::Leaf*)c.leaves.p, dst_state, na, (uint32_t*)c.dcnt.p,
+                                 q.slots_log2, (uint32_t*)c.large.p, st),
+           "leaf count launch");
+    tm.mark(ST_LEAF);
+    uint32_t* hd = (uint32_t*)host_stage(c, na * 4 + 64);
+    hipchk(hipMemcpyAsync(hd, c.dcnt.p, na * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
     hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-    cur.swap(next);
+    split.clear();
+    for (size_t i = 0; i < na; ++i) {
+      const Part& b = next[i];
+      if (hd[i] == kc::kLeafOverflow) {
+        if (b.bits >= q.keybits) fail(KC_E_INTERNAL, "single-key partition overflowed its table");
+        ++S.n_overflow;
+        split.push_back(b);
+      } else {
+        done.push_back(Done{b.root, b.rel << (q.keybits - b.bits), al[i], hd[i]});
+        S.max_leaf_windows = std::max(S.max_leaf_windows, b.end - b.begin);
+      }
+    }
   }
-  S.n_levels = level;
-  std::sort(done.begin(), done.end(),
-            [](const LeafDone& a, const LeafDone& b) { return a.start < b.start; });
-  const size_t nl = done.size();
-  std::vector<kc::Leaf> lv(nl);
-  std::vector<uint32_t> dv(nl);
-  uint64_t D = 0;
-  for (size_t i = 0; i < nl; ++i) {
-    lv[i] = kc::Leaf{done[i].begin, done[i].end, (uint32_t)done[i].buf, (uint32_t)done[i].bits};
-    dv[i] = done[i].d;
-    D += done[i].d;
+  S.n_levels = 1 + level;
+  // splice the parts into the leaf list in place of their parents
+  std::sort(done.begin(), done.end(), [](const Done& a, const Done& b) {
+    return a.root != b.root ? a.root < b.root : a.start < b.start;
+  });
+  std::vector<kc::Leaf> nlv;
+  std::vector<uint32_t> ndv;
+  nlv.reserve(nl0 + done.size());
+  ndv.reserve(nl0 + done.size());
+  size_t j = 0;
+  for (uint64_t i = 0; i < nl0; ++i) {
+    if (dv[i] != kc::kLeafOverflow) {
+      nlv.push_back(lv[i]);
+      ndv.push_back(dv[i]);
+      continue;
+    }
+    for (; j < done.size() && done[j].root == i; ++j) {
+      nlv.push_back(done[j].leaf);
+      ndv.push_back(done[j].d);
+    }
   }
-  (void)W;
+  const uint64_t nl = nlv.size();
   S.n_leaves = nl;
   ensure(c.leaves, nl * sizeof(kc::Leaf), "leaf table");
   ensure(c.dcnt, nl * 4, "leaf counts");
   ensure(c.outoff, nl * 8, "output offsets");
   ensure(c.bsum, kc::scan_blocks(nl) * 8, "scan block sums");
-  upload_sync(c.leaves.p, lv.data(), nl * sizeof(kc::Leaf), st);
-  upload_sync(c.dcnt.p, dv.data(), nl * 4, st);
+  upload_sync(c.leaves.p, nlv.data(), nl * sizeof(kc::Leaf), st);
+  upload_sync(c.dcnt.p, ndv.data(), nl * 4, st);
   unsigned long long nlu = nl;
   upload_sync(&dst_state->n_leaves, &nlu, 8, st);
   unsigned int zero = 0;
@@ -446,6 +440,7 @@ void general_path(Ctx& c, Call& q, kc_stats& S, Timer& tm) {
   hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dst_state, (unsigned long long*)c.bsum.p, nl,
                              (unsigned long long*)c.outoff.p, st),
          "plan_out launch");
+  tm.mark(ST_OUT);
   q.concat_leaves = nl;
   if (q.oa) return;  // the caller allocates the output, then runs the concat
   hipchk(kc::launch_concat(q.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
@@ -454,7 +449,6 @@ void general_path(Ctx& c, Call& q, kc_stats& S, Timer& tm) {
                            q.out_counts, st),
          "concat launch");
   tm.mark(ST_CONCAT);
-  (void)D;
 }
 
 // One run of the device-planned partitioning over bytes [byte_begin,
@@ -721,12 +715,11 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   S.n_levels = 1;
   S.n_leaves = ds.n_leaves;
   if (ds.overflow) {
-    // some leaf had more distinct keys than its table holds: redo the
-    // partitioning with host-planned recursive splits
-    ++S.n_overflow;
-    general_path(c, q, S, tm);
+    // some leaves had more distinct keys than their tables hold: partition
+    // those further and count their parts
+    refine_overflowed(c, q, S, tm, ds.n_leaves);
     ds = read_state(c, st);
-    if (ds.overflow) fail(KC_E_INTERNAL, "leaf overflow in the recursive path");
+    if (ds.overflow) fail(KC_E_INTERNAL, "leaf overflow after refinement");
   }
   S.valid_windows = ds.W;
   S.distinct = ds.D;

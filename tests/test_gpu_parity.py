@@ -67,6 +67,8 @@ def test_p_invariance(P):
     dict(leaf_attempt=1 << 30),                           # overflow -> split path
     dict(shard_bits=1),
     dict(shard_bits=10, leaf_target=64, leaf_attempt=128),
+    # split and unsplit shards whose leaves overflow: refinement from both buffers
+    dict(shard_bits=6, leaf_target=30_000, leaf_attempt=40_000),
 ])
 def test_knob_invariance(opts):
     c = synth.make_config(2, frac=0.02)
@@ -78,7 +80,7 @@ def test_knob_invariance(opts):
 
 def test_fast_path_and_recursive_fallback_agree():
     """Default settings finish in the device-planned path; huge unsplit leaves
-    overflow their tables and take the host-planned recursive path."""
+    overflow their tables and only those are partitioned further."""
     import paper_2505_04431_amd as kc
     c = synth.make_config(2, frac=0.05)
     want = oracle.count(c["reads"], c["offsets"], 31)
@@ -90,6 +92,22 @@ def test_fast_path_and_recursive_fallback_agree():
                           shard_bits=4), want, "fallback path")
     st = kc.last_stats()
     assert st["n_overflow"] >= 1
+
+
+def test_refinement_settles_frequent_keys():
+    """One k-mer with 200,000 copies next to many distinct ones in a leaf that
+    overflows: the part holding the frequent key is counted whole."""
+    import paper_2505_04431_amd as kc
+    rnd, ro = synth.ragged_reads(77, 600, 100, 200)
+    reads = np.concatenate([np.full(200_030, ord("A"), np.uint8), rnd])
+    offs = np.concatenate([[0], ro + np.uint64(200_030)]).astype(np.uint64)
+    want = oracle.count(reads, offs, 31)
+    for k, opts in ((31, dict(shard_bits=1, leaf_attempt=1 << 30, table_slots_log2=10)),
+                    (55, dict(shard_bits=2, leaf_attempt=1 << 30, table_slots_log2=10))):
+        w = want if k == 31 else oracle.count(reads, offs, k)
+        assert_same(gpu_count(reads, offs, k, check=1, **opts), w, "k=%d" % k)
+        st = kc.last_stats()
+        assert st["n_overflow"] >= 1 and st["max_leaf_windows"] >= 200_030 - k + 1
 
 
 def test_strand_flip_permutation_and_unaligned_base():
