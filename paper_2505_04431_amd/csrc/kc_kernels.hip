@@ -904,6 +904,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
   // list != nullptr: the leaves listed there (large ones); else every leaf of
   // at most small_max records.
   const unsigned long long count = list ? st->n_large : st->n_leaves;
+  unsigned long long my_records = 0, my_distinct = 0;  // thread 0: this workgroup's totals
   for (unsigned long long it = blockIdx.x; it < count; it += gridDim.x) {
     const unsigned long long l = list ? (unsigned long long)list[it] : it;
     const Leaf lf = leaves[l];
@@ -986,12 +987,16 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
         lf.begin, occ32);
     if (threadIdx.x == 0) {
       d_out[l] = d;
-      if (list) {
-        atomicAdd(&st->large_records, (unsigned long long)n);
-        atomicAdd(&st->large_distinct, (unsigned long long)d);
-      }
+      my_records += n;
+      my_distinct += d;
     }
     __syncthreads();
+  }
+  // one update of the shared totals per workgroup (not per leaf: same-address
+  // atomics from every workgroup would serialise)
+  if (list && threadIdx.x == 0 && my_records) {
+    atomicAdd(&st->large_records, my_records);
+    atomicAdd(&st->large_distinct, my_distinct);
   }
 }
 
@@ -1019,6 +1024,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
   // list != nullptr: the leaves listed there (large ones); else every leaf of
   // at most small_max records.
   const unsigned long long count = list ? st->n_large : st->n_leaves;
+  unsigned long long my_records = 0, my_distinct = 0;  // thread 0: this workgroup's totals
   for (unsigned long long it = blockIdx.x; it < count; it += gridDim.x) {
     const unsigned long long l = list ? (unsigned long long)list[it] : it;
     const Leaf lf = leaves[l];
@@ -1114,12 +1120,14 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
     if (threadIdx.x == 0) {
       d_out[l] = d;
       if (s_cov) atomicOr(&st->count_overflow, 1u);
-      if (list) {
-        atomicAdd(&st->large_records, (unsigned long long)n);
-        atomicAdd(&st->large_distinct, (unsigned long long)d);
-      }
+      my_records += n;
+      my_distinct += d;
     }
     __syncthreads();
+  }
+  if (list && threadIdx.x == 0 && my_records) {
+    atomicAdd(&st->large_records, my_records);
+    atomicAdd(&st->large_distinct, my_distinct);
   }
 }
 
