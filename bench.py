@@ -50,6 +50,33 @@ def stage_bytes(st: dict, k: int) -> dict:
     }
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def h2d_ms(torch, dev, reads: np.ndarray, offs: np.ndarray) -> float:
+    """Host-to-device copy of the inputs from pinned host memory (median of 3)."""
+    hr = torch.from_numpy(reads).pin_memory()
+    ho = torch.from_numpy(offs.view(np.int64)).pin_memory()
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        a = hr.to(dev, non_blocking=True)
+        b = ho.to(dev, non_blocking=True)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1e3)
+        del a, b
+    return float(np.median(ts))
+
+
 def copy_rate(torch, dev, gib: float):
     """Achievable HBM rate: a plain elementwise kernel (bitwise NOT of int64)
     that reads and writes gib GiB each, timed with events on its stream.
@@ -363,6 +390,8 @@ def main() -> int:
     kernel_names = {"leaf_large": "k_leaf_count64<512, 4096, 4>" if k <= 32 else
                     "k_leaf_count128<512, 2048, 4>"}
     copy_gbs = copy_rate(torch, dev, args.copy_gib)
+    ceil = kc.kc.measure_ceilings(4 << 30, stream.cuda_stream)
+    t_h2d = h2d_ms(torch, dev, reads, offs)
     kname = kernel_names.get(dom, dom)
     roofline = {"bound": "hbm", "kernel": kname, "stage": dom,
                 "achieved": round(achieved, 1),
@@ -371,6 +400,11 @@ def main() -> int:
                 "copy_gbs": copy_gbs,
                 "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
                 "leaf_records_per_s": round(st["large_records"] / (avg[dom] / 1e3), 1)
+                if dom == "leaf_large" else None,
+                "ceilings": {n: (round(v, 2) if isinstance(v, float) else v)
+                             for n, v in ceil.items()},
+                "leaf_inserts_frac_of_lds_ceiling": round(
+                    st["large_records"] / (avg[dom] / 1e3) / (ceil["lds_insert_gops"] * 1e9), 4)
                 if dom == "leaf_large" else None,
                 "stage_ms": {n: round(v, 4) for n, v in avg.items()},
                 "stage_gbs": {n: round(sb[n] / (avg[n] / 1e3) / 1e9, 1) for n in avg if n in sb}}
@@ -386,9 +420,19 @@ def main() -> int:
         tc = time.perf_counter()
         oracle.count(r_s, o_s, k, threads=threads)
         dt = time.perf_counter() - tc
+        # one thread on a sixteenth of the reads
+        n_1 = max(1, n_s // 16)
+        r_1, o_1 = reads[:int(offs[n_1])], offs[:n_1 + 1]
+        w_1 = oracle.valid_windows(r_1, o_1, k)
+        tc = time.perf_counter()
+        oracle.count(r_1, o_1, k, threads=1)
+        dt1 = time.perf_counter() - tc
         cpu = {"value": round(w_s / dt, 1), "unit": "k-mers/s", "cores": threads, "kind": "oracle",
                "sample": "first %d of %d reads (%d valid windows), sort-based oracle, %d threads"
-                         % (n_s, len(offs) - 1, w_s, threads)}
+                         % (n_s, len(offs) - 1, w_s, threads),
+               "one_thread_value": round(w_1 / dt1, 1),
+               "one_thread_sample": "first %d reads (%d valid windows)" % (n_1, w_1),
+               "cpu_model": cpu_model()}
 
     batched = None
     if args.batched_sets > 0:
@@ -404,6 +448,8 @@ def main() -> int:
         "value": round(value, 1), "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "ms_median": round(float(np.median(step_ms)), 4), "ms_best": round(min(step_ms), 4),
+        "h2d_ms": round(t_h2d, 4),
+        "end_to_end_value": round(W / ((ms_step + t_h2d) / 1e3), 1),
         "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64" if k <= 32 else "u128",
         "data": "synthetic",

@@ -217,6 +217,35 @@ int kc_server_release(kc_server* server, uint64_t job_id);
 int kc_server_stats(kc_server* server, kc_serve_stats* out);
 void kc_server_destroy(kc_server* server);
 
+/* ---- Size predictor: an estimate of a job's number of distinct keys.
+ * A two-layer fp32 perceptron y = w2 . relu(W1 x + b1) + b2 whose forward and
+ * backward passes and Adam updates run on the device. It never touches a
+ * count: its only use is the result reservation of a served job
+ * (distinct_hint of kc_server_submit), where a miss costs memory accounting,
+ * not correctness. Parameters are one fp32 array: W1 [hidden][n_features]
+ * row-major, b1 [hidden], w2 [hidden], b2. Loss: mean of (y - t)^2 / 2.
+ *
+ * kc_pred_create: n_features in [1, 32], hidden in [1, 128]; seeded init.
+ * kc_pred_forward: x DEVICE [batch][n_features] fp32, y DEVICE [batch];
+ *   synchronous on `stream`.
+ * kc_pred_gradient: x, target DEVICE; computes the loss gradient of the batch
+ *   into the predictor (deterministic order); *host_loss (if not NULL)
+ *   receives the loss (then synchronous).
+ * kc_pred_adam_step: one Adam step (beta 0.9 / 0.999) with the last gradient.
+ * kc_pred_get_params / _set_params / _get_grads: host copies of n floats
+ *   (n = kc_pred_num_params); set_params restarts the optimiser state. */
+typedef struct kc_predictor kc_predictor;
+int kc_pred_create(int n_features, int hidden, uint64_t seed, kc_predictor** pred);
+uint64_t kc_pred_num_params(const kc_predictor* pred);
+int kc_pred_get_params(const kc_predictor* pred, float* host, uint64_t n);
+int kc_pred_set_params(kc_predictor* pred, const float* host, uint64_t n);
+int kc_pred_get_grads(const kc_predictor* pred, float* host, uint64_t n);
+int kc_pred_forward(kc_predictor* pred, const float* x, uint64_t batch, float* y, void* stream);
+int kc_pred_gradient(kc_predictor* pred, const float* x, const float* target, uint64_t batch,
+                     float* host_loss, void* stream);
+int kc_pred_adam_step(kc_predictor* pred, float lr, void* stream);
+void kc_pred_free(kc_predictor* pred);
+
 /* Upper bound on the number of output keys (= number of length-k windows,
  * valid or not): sum over reads of max(0, len - k + 1). host_offsets is a
  * HOST array of n_reads+1 offsets. Returns 0 for bad arguments. */

@@ -25,7 +25,10 @@ EXPORTED_SYMBOLS = ["kc_count", "kc_count_ex", "kc_max_outputs", "kc_last_stats"
                     "kc_batch_free", "kc_server_create", "kc_server_submit", "kc_server_poll",
                     "kc_server_wait", "kc_server_result", "kc_server_result_copy",
                     "kc_server_job_info", "kc_server_release", "kc_server_stats",
-                    "kc_server_destroy"]
+                    "kc_server_destroy", "kc_pred_create", "kc_pred_num_params",
+                    "kc_pred_get_params", "kc_pred_set_params", "kc_pred_get_grads",
+                    "kc_pred_forward", "kc_pred_gradient", "kc_pred_adam_step", "kc_pred_free",
+                    "kc_measure_ceilings"]
 
 JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
@@ -63,6 +66,22 @@ class KcServeStats(ctypes.Structure):
                  "result_bytes_reserved", "result_bytes_actual")] + \
                [(n, ctypes.c_double) for n in
                 ("latency_p50_ms", "latency_p99_ms", "wait_p50_ms", "wait_p99_ms", "busy_ms")]
+
+
+class KcCeilings(ctypes.Structure):
+    _fields_ = [("copy_gbs", ctypes.c_double), ("hbm_insert_gops", ctypes.c_double),
+                ("mall_insert_gops", ctypes.c_double), ("lds_insert_gops", ctypes.c_double),
+                ("hbm_table_bytes", ctypes.c_uint64), ("mall_table_bytes", ctypes.c_uint64),
+                ("lost", ctypes.c_uint64)]
+
+
+def measure_ceilings(table_bytes: int = 4 << 30, stream=None) -> dict:
+    """kc_measure_ceilings: copy, HBM / cache / LDS insert rates on this device."""
+    c = KcCeilings()
+    st = lib().kc_measure_ceilings(int(table_bytes), ctypes.byref(c), stream)
+    if st != 0:
+        raise KcError(st, lib().kc_last_error().decode())
+    return {n: getattr(c, n) for n, _ in KcCeilings._fields_}
 
 
 STAGES = ["pack", "window_hist", "owner_scatter", "split_hist", "split_scatter", "leaf_small",
@@ -136,6 +155,23 @@ def lib():
             L.kc_server_stats.argtypes = [p, p]
             L.kc_server_destroy.restype = None
             L.kc_server_destroy.argtypes = [p]
+            L.kc_pred_create.restype = i32
+            L.kc_pred_create.argtypes = [i32, i32, u64, p]
+            L.kc_pred_num_params.restype = u64
+            L.kc_pred_num_params.argtypes = [p]
+            for name in ("kc_pred_get_params", "kc_pred_set_params", "kc_pred_get_grads"):
+                getattr(L, name).restype = i32
+                getattr(L, name).argtypes = [p, p, u64]
+            L.kc_pred_forward.restype = i32
+            L.kc_pred_forward.argtypes = [p, p, u64, p, p]
+            L.kc_pred_gradient.restype = i32
+            L.kc_pred_gradient.argtypes = [p, p, p, u64, p, p]
+            L.kc_pred_adam_step.restype = i32
+            L.kc_pred_adam_step.argtypes = [p, ctypes.c_float, p]
+            L.kc_pred_free.restype = None
+            L.kc_pred_free.argtypes = [p]
+            L.kc_measure_ceilings.restype = i32
+            L.kc_measure_ceilings.argtypes = [u64, p, p]
             _lib = L
     return _lib
 
@@ -360,6 +396,83 @@ class Server:
             lib().kc_server_destroy(self._h)
             self._h = ctypes.c_void_p()
             self._inputs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Predictor:
+    """The device perceptron of kc_pred_* (forward, gradient, Adam step).
+
+    Inputs are fp32 CUDA tensors: x [batch, n_features], targets [batch]."""
+
+    def __init__(self, n_features: int, hidden: int = 32, seed: int = 1):
+        self._h = ctypes.c_void_p()
+        st = lib().kc_pred_create(n_features, hidden, seed, ctypes.byref(self._h))
+        if st != 0:
+            raise KcError(st, lib().kc_last_error().decode())
+        self.n_features, self.hidden = n_features, hidden
+        self.n_params = int(lib().kc_pred_num_params(self._h))
+
+    def _chk(self, st):
+        if st != 0:
+            raise KcError(st, lib().kc_last_error().decode())
+
+    def _x(self, x):
+        import torch
+        _check_tensor(x, "x", (torch.float32,))
+        if x.dim() != 2 or x.shape[1] != self.n_features:
+            raise ValueError("x must be [batch, %d]" % self.n_features)
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._chk(lib().kc_pred_get_params(self._h, out.ctypes.data, self.n_params))
+        return out
+
+    def set_params(self, values):
+        v = np.ascontiguousarray(values, dtype=np.float32)
+        if v.size != self.n_params:
+            raise ValueError("expected %d parameters" % self.n_params)
+        self._chk(lib().kc_pred_set_params(self._h, v.ctypes.data, self.n_params))
+
+    def grads(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._chk(lib().kc_pred_get_grads(self._h, out.ctypes.data, self.n_params))
+        return out
+
+    def forward(self, x, stream=None):
+        import torch
+        self._x(x)
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+        self._chk(lib().kc_pred_forward(self._h, x.data_ptr(), x.shape[0], y.data_ptr(), stream))
+        return y
+
+    def gradient(self, x, target, want_loss: bool = True, stream=None):
+        import torch
+        self._x(x)
+        _check_tensor(target, "target", (torch.float32,))
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+        loss = ctypes.c_float(0.0)
+        self._chk(lib().kc_pred_gradient(self._h, x.data_ptr(), target.data_ptr(), x.shape[0],
+                                         ctypes.byref(loss) if want_loss else None, stream))
+        return float(loss.value) if want_loss else None
+
+    def adam_step(self, lr: float, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(torch.cuda.current_device()).cuda_stream
+        self._chk(lib().kc_pred_adam_step(self._h, ctypes.c_float(lr), stream))
+
+    def close(self):
+        if self._h:
+            lib().kc_pred_free(self._h)
+            self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:

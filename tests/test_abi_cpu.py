@@ -12,7 +12,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_symbols():
-    text = open(os.path.join(ROOT, "include", "kc.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc))
+                   if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(kc_[a-z_0-9]+)\s*\(", text)))
 
@@ -54,8 +56,10 @@ def test_struct_layouts_match_c_compiler(tmp_path):
     """sizeof/offsetof of every public struct, as gcc lays out include/kc.h,
     equal the ctypes mirrors of the binding."""
     mirrors = {"kc_options": kc.kc.KcOptions, "kc_stats": kc.kc.KcStats,
-               "kc_job_info": kc.kc.KcJobInfo, "kc_serve_stats": kc.kc.KcServeStats}
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kc.h"', "int main(void) {"]
+               "kc_job_info": kc.kc.KcJobInfo, "kc_serve_stats": kc.kc.KcServeStats,
+               "kc_ceilings": kc.kc.KcCeilings}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kc.h"', '#include "kc_bench.h"',
+             "int main(void) {"]
     for cname, py in mirrors.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
         for fname, _ in py._fields_:
