@@ -138,6 +138,21 @@ hipError_t launch_plan_out(const uint32_t* d, DevState* st, unsigned long long* 
                            uint64_t max_leaves, unsigned long long* out_off, hipStream_t s);
 uint64_t scan_blocks(uint64_t max_leaves);
 
+// Overflow refinement: list the overflowed leaves (indices and entries; *count
+// receives their number), and splice refined parts into the leaf list:
+// old leaf i (of n, st->n_leaves == n) keeps one slot, or nparts[r] slots if it
+// is root_leaf[r]; parts of root r are parts[part_begin[r] ..] with counts
+// part_d. Writes the new list to out / out_d (st->D receives its length).
+hipError_t launch_list_overflowed(const uint32_t* d, uint64_t n, const Leaf* leaves,
+                                  uint32_t* list, Leaf* out, unsigned long long* count,
+                                  hipStream_t s);
+hipError_t launch_splice(const Leaf* leaves, const uint32_t* d, uint64_t n,
+                         const uint32_t* root_leaf, const uint32_t* part_begin,
+                         const uint32_t* nparts, uint32_t R, const Leaf* parts,
+                         const uint32_t* part_d, uint32_t* cnt, DevState* st,
+                         unsigned long long* bsum, unsigned long long* pos, Leaf* out,
+                         uint32_t* out_d, hipStream_t s);
+
 hipError_t launch_concat(bool wide, const void* bufA, const void* bufB, const uint32_t* tmp_cnt,
                          const Leaf* leaves, const uint32_t* d, const unsigned long long* out_off,
                          const DevState* st, uint64_t max_leaves, uint64_t cap,

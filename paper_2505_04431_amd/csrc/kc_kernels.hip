@@ -419,7 +419,6 @@ __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restric
                                                        K* __restrict__ out) {
   constexpr int NBMAX = 1 << kMaxShardBits;
   __shared__ K stage[TB * S];
-  __shared__ uint16_t sbin[TB * S];
   __shared__ uint32_t hist[NBMAX];
   __shared__ uint32_t loff[NBMAX];
   __shared__ unsigned long long gbase[NBMAX];
@@ -453,13 +452,13 @@ __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restric
       if (vm & (1u << i)) {
         const uint32_t p = loff[bin[i]] + rank[i];
         stage[p] = key[i];
-        sbin[p] = (uint16_t)bin[i];
       }
     }
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < total; j += TB) {
-      const uint32_t b = sbin[j];
-      out[gbase[b] + (j - loff[b])] = stage[j];
+      const K kk = stage[j];  // its shard again from the key: cheaper than staging it
+      const uint32_t b = shard_of(kk, keybits, shard_bits);
+      out[gbase[b] + (j - loff[b])] = kk;
     }
     __syncthreads();
   }
@@ -563,6 +562,73 @@ __global__ void __launch_bounds__(kPlanTB) k_plan_leaves(
     const unsigned long long run = sbegin[c] + off;
     leaves[b.hist_off + j] = Leaf{run, run + n, 1u, (uint32_t)(shard_bits + b.nbits)};
     cursor[b.hist_off + j] = run;
+  }
+}
+
+// ---------------------------------------------------------------- refinement support
+
+// Indices (any order) and entries of the leaves whose tables overflowed.
+__global__ void k_list_overflowed(const uint32_t* __restrict__ d, uint64_t n,
+                                  const Leaf* __restrict__ leaves, uint32_t* __restrict__ list,
+                                  Leaf* __restrict__ out, unsigned long long* __restrict__ count) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
+    const uint64_t i = i0 + threadIdx.x;
+    const bool ovf = i < n && d[i] == kLeafOverflow;
+    const unsigned long long m = __ballot(ovf);
+    if (!m) continue;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader);
+    if (ovf) {
+      const unsigned long long at = base + __popcll(m & ((1ull << lane) - 1));
+      list[at] = (uint32_t)i;
+      out[at] = leaves[i];
+    }
+  }
+}
+
+// Entries each old leaf occupies in the refined list: 1, or (for an
+// overflowed leaf) the number of its parts, set by k_splice_root_counts.
+__global__ void k_splice_counts(const uint32_t* __restrict__ d, uint64_t n,
+                                uint32_t* __restrict__ cnt) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cnt[i] = d[i] == kLeafOverflow ? 0u : 1u;
+}
+
+__global__ void k_splice_root_counts(const uint32_t* __restrict__ root_leaf,
+                                     const uint32_t* __restrict__ nparts, uint32_t R,
+                                     uint32_t* __restrict__ cnt) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < R) cnt[root_leaf[r]] = nparts[r];
+}
+
+// Kept leaves move to pos[i]; the parts of root r fill pos[root_leaf[r]] onwards.
+__global__ void k_splice_keep(const Leaf* __restrict__ leaves, const uint32_t* __restrict__ d,
+                              const unsigned long long* __restrict__ pos, uint64_t n,
+                              Leaf* __restrict__ out, uint32_t* __restrict__ out_d) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && d[i] != kLeafOverflow) {
+    out[pos[i]] = leaves[i];
+    out_d[pos[i]] = d[i];
+  }
+}
+
+__global__ void k_splice_parts(const uint32_t* __restrict__ root_leaf,
+                               const uint32_t* __restrict__ part_begin,
+                               const uint32_t* __restrict__ nparts, uint32_t R,
+                               const Leaf* __restrict__ parts, const uint32_t* __restrict__ part_d,
+                               const unsigned long long* __restrict__ pos, Leaf* __restrict__ out,
+                               uint32_t* __restrict__ out_d) {
+  for (uint32_t r = blockIdx.x; r < R; r += gridDim.x) {
+    const unsigned long long at = pos[root_leaf[r]];
+    const uint32_t b = part_begin[r];
+    for (uint32_t p = threadIdx.x; p < nparts[r]; p += blockDim.x) {
+      out[at + p] = parts[b + p];
+      out_d[at + p] = part_d[b + p];
+    }
   }
 }
 
@@ -692,7 +758,6 @@ __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
                                                       unsigned long long* __restrict__ cursor) {
   constexpr int NS = 1 << kSplitMaxBits;
   __shared__ K stage[TB * R];
-  __shared__ uint16_t ssub[TB * R];
   __shared__ uint32_t hist[NS];
   __shared__ uint32_t loff[NS];
   __shared__ unsigned long long gbase[NS];
@@ -725,13 +790,13 @@ __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
       if (r < it.end) {
         const uint32_t p = loff[sub[j]] + rank[j];
         stage[p] = key[j];
-        ssub[p] = (uint16_t)sub[j];
       }
     }
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < total; j += TB) {
-      const uint32_t b = ssub[j];
-      dst[gbase[b] + (j - loff[b])] = stage[j];
+      const K kk = stage[j];
+      const uint32_t b = Key<K>::bits(kk, bn.shift, bn.nbits);
+      dst[gbase[b] + (j - loff[b])] = kk;
     }
     __syncthreads();
   }
@@ -1517,6 +1582,37 @@ hipError_t launch_leaf_large(bool wide, int keybits, void* bufA, void* bufB, uin
     hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4>), dim3(glarge), dim3(kLeafTB), 0,
                        s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
                        slots_log2, large_list, small_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_list_overflowed(const uint32_t* d, uint64_t n, const Leaf* leaves,
+                                  uint32_t* list, Leaf* out, unsigned long long* count,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, count, (uint64_t)1, 0ull);
+  if (n)
+    hipLaunchKernelGGL(k_list_overflowed, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, d, n,
+                       leaves, list, out, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_splice(const Leaf* leaves, const uint32_t* d, uint64_t n,
+                         const uint32_t* root_leaf, const uint32_t* part_begin,
+                         const uint32_t* nparts, uint32_t R, const Leaf* parts,
+                         const uint32_t* part_d, uint32_t* cnt, DevState* st,
+                         unsigned long long* bsum, unsigned long long* pos, Leaf* out,
+                         uint32_t* out_d, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_splice_counts, dim3(g), dim3(256), 0, s, d, n, cnt);
+  if (R)
+    hipLaunchKernelGGL(k_splice_root_counts, dim3((R + 255) / 256), dim3(256), 0, s, root_leaf,
+                       nparts, R, cnt);
+  // st->n_leaves == n here: the scan gives every old leaf its first new slot
+  hipError_t e = launch_plan_out(cnt, st, bsum, n, pos, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_splice_keep, dim3(g), dim3(256), 0, s, leaves, d, pos, n, out, out_d);
+  if (R)
+    hipLaunchKernelGGL(k_splice_parts, dim3(R < 4096u ? R : 4096u), dim3(64), 0, s, root_leaf,
+                       part_begin, nparts, R, parts, part_d, pos, out, out_d);
   return hipGetLastError();
 }
 

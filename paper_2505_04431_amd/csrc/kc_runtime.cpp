@@ -34,6 +34,8 @@ struct Ctx {
   DevBuf packed, inv, endm, bufA, bufB, tmpcnt;
   DevBuf hist, sbegin, cursor, cursor2, order, items, bins, subhist, leaves, dcnt, outoff, state;
   DevBuf large, bsum, itemoff;
+  // overflow refinement: overflowed leaves, part attempts, the spliced list
+  DevBuf rlist, rleaves, rcount, aleaves, adcnt, alarge, rparts, rcnt, leaves2, dcnt2;
   std::vector<int> order_host;
   int order_P = -1, order_sb = -1;
   void* host = nullptr;  // pinned staging for small device<->host copies
@@ -44,9 +46,11 @@ struct Ctx {
   ~Ctx() {
     int prev = -1;
     if (hipGetDevice(&prev) == hipSuccess && device >= 0) (void)hipSetDevice(device);
-    DevBuf* all[] = {&packed, &inv, &endm,   &bufA,  &bufB,    &tmpcnt, &hist,   &sbegin, &cursor,
-                     &cursor2, &order, &items, &bins, &subhist, &leaves, &dcnt, &outoff, &state,
-                     &large,   &bsum,  &itemoff};
+    DevBuf* all[] = {&packed,  &inv,     &endm,   &bufA,    &bufB,   &tmpcnt,  &hist,
+                     &sbegin,  &cursor,  &cursor2, &order,  &items,  &bins,    &subhist,
+                     &leaves,  &dcnt,    &outoff, &state,   &large,  &bsum,    &itemoff,
+                     &rlist,   &rleaves, &rcount, &aleaves, &adcnt,  &alarge,  &rparts,
+                     &rcnt,    &leaves2, &dcnt2};
     for (DevBuf* b : all)
       if (b->p) (void)hipFree(b->p);
     if (host) (void)hipHostFree(host);
@@ -262,20 +266,42 @@ kc::DevState read_state(Ctx& c, hipStream_t st) {
 // is counted as soon as it exists, so a part dominated by one frequent key
 // is settled at once however many records it holds. Ends with the output
 // offsets (and the concat unless the caller allocates the output first).
-void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0) {
+// keep_leaves: leaf slots the device-planned path of this call needs (both
+// leaf-list buffers keep at least that many).
+void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
+                       uint64_t keep_leaves) {
   const hipStream_t st = q.st;
-  std::vector<kc::Leaf> lv(nl0);
-  std::vector<uint32_t> dv(nl0);
+  kc::DevState* dst_state = (kc::DevState*)c.state.p;
+  // the overflowed leaves only (the list of all leaves stays on the device)
+  ensure(c.rlist, nl0 * 4, "overflowed leaf list");
+  ensure(c.rleaves, nl0 * sizeof(kc::Leaf), "overflowed leaves");
+  ensure(c.rcount, 8, "overflow count");
+  hipchk(kc::launch_list_overflowed((uint32_t*)c.dcnt.p, nl0, (kc::Leaf*)c.leaves.p,
+                                    (uint32_t*)c.rlist.p, (kc::Leaf*)c.rleaves.p,
+                                    (unsigned long long*)c.rcount.p, st),
+         "overflow list launch");
+  uint64_t R = 0;
   {
-    char* h = (char*)host_stage(c, nl0 * (sizeof(kc::Leaf) + 4) + 64);
-    hipchk(hipMemcpyAsync(h, c.leaves.p, nl0 * sizeof(kc::Leaf), hipMemcpyDeviceToHost, st),
-           "hipMemcpyAsync");
-    hipchk(hipMemcpyAsync(h + nl0 * sizeof(kc::Leaf), c.dcnt.p, nl0 * 4, hipMemcpyDeviceToHost, st),
+    uint64_t* h = (uint64_t*)host_stage(c, 64);
+    hipchk(hipMemcpyAsync(h, c.rcount.p, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+    R = h[0];
+  }
+  std::vector<uint32_t> ridx(R);
+  std::vector<kc::Leaf> rlv(R);
+  if (R) {
+    char* h = (char*)host_stage(c, R * (4 + sizeof(kc::Leaf)) + 64);
+    hipchk(hipMemcpyAsync(h, c.rlist.p, R * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    hipchk(hipMemcpyAsync(h + R * 4, c.rleaves.p, R * sizeof(kc::Leaf), hipMemcpyDeviceToHost, st),
            "hipMemcpyAsync");
     hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-    std::memcpy(lv.data(), h, nl0 * sizeof(kc::Leaf));
-    std::memcpy(dv.data(), h + nl0 * sizeof(kc::Leaf), nl0 * 4);
+    std::memcpy(ridx.data(), h, R * 4);
+    std::memcpy(rlv.data(), h + R * 4, R * sizeof(kc::Leaf));
   }
+  // roots in leaf order (the list came in any order)
+  std::vector<uint32_t> ord(R);
+  for (uint32_t i = 0; i < R; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return ridx[a] < ridx[b]; });
   struct Part {
     uint64_t begin, end;
     u128 rel;     // key bits below the parent leaf's prefix consumed so far
@@ -290,16 +316,15 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0) {
     uint32_t d;
   };
   std::vector<Part> split;
-  for (uint64_t i = 0; i < nl0; ++i)
-    if (dv[i] == kc::kLeafOverflow) {
-      if ((int)lv[i].bits >= q.keybits) fail(KC_E_INTERNAL, "single-key partition overflowed its table");
-      split.push_back(Part{lv[i].begin, lv[i].end, 0, (int)lv[i].bits, (int)lv[i].buf, (uint32_t)i});
-      ++S.n_overflow;
-    }
+  for (uint32_t r = 0; r < R; ++r) {
+    const kc::Leaf& lf = rlv[ord[r]];
+    if ((int)lf.bits >= q.keybits) fail(KC_E_INTERNAL, "single-key partition overflowed its table");
+    split.push_back(Part{lf.begin, lf.end, 0, (int)lf.bits, (int)lf.buf, r});  // root = rank r
+    ++S.n_overflow;
+  }
   std::vector<Done> done;
   void* bufs[2] = {c.bufA.p, c.bufB.p};
-  kc::DevState* dst_state = (kc::DevState*)c.state.p;
-  const uint64_t T = std::min<uint64_t>(q.T, q.C / 4);
+  constexpr int kRefineBits = 2;
   const uint64_t tile = (uint64_t)kc::split_tile(q.wide);
   int level = 0;
   while (!split.empty()) {
@@ -313,8 +338,12 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0) {
       const Part& b = split[i];
       const uint64_t n = b.end - b.begin;
       const int remaining = q.keybits - b.bits;
-      int nbits = std::max(2, ceil_log2((n + T - 1) / T));
-      nbits = std::max(1, std::min(nbits, std::min(kc::kSplitMaxBits, remaining)));
+      // A part overflowed because of its distinct keys, not its records (a
+      // part of many records and few keys counts fine), so it is cut in a
+      // few pieces by key, not by record count; pieces too rich in keys are
+      // cut again at the next level.
+      (void)n;
+      const int nbits = std::max(1, std::min(kRefineBits, remaining));
       sbins[i] = kc::SplitBin{hoff, (uint32_t)(remaining - nbits), (uint32_t)nbits};
       hoff += 1ull << nbits;
       for (uint64_t a = b.begin; a < b.end; a += tile)
@@ -373,23 +402,23 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0) {
     std::vector<kc::Leaf> al(na);
     for (size_t i = 0; i < na; ++i)
       al[i] = kc::Leaf{next[i].begin, next[i].end, (uint32_t)next[i].buf, (uint32_t)next[i].bits};
-    ensure(c.leaves, na * sizeof(kc::Leaf), "leaf table");
-    ensure(c.dcnt, na * 4, "leaf counts");
-    ensure(c.large, na * 4, "large-leaf list");
-    upload_sync(c.leaves.p, al.data(), na * sizeof(kc::Leaf), st);
+    ensure(c.aleaves, na * sizeof(kc::Leaf), "part table");
+    ensure(c.adcnt, na * 4, "part counts");
+    ensure(c.alarge, na * 4, "large-part list");
+    upload_sync(c.aleaves.p, al.data(), na * sizeof(kc::Leaf), st);
     unsigned long long nlu = na;
     upload_sync(&dst_state->n_leaves, &nlu, 8, st);
     hipchk(kc::launch_leaf_small(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
-                                 (kc::Leaf*)c.leaves.p, dst_state, na, (uint32_t*)c.dcnt.p,
-                                 (uint32_t*)c.large.p, st),
+                                 (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
+                                 (uint32_t*)c.alarge.p, st),
            "leaf count launch");
     hipchk(kc::launch_leaf_large(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
-                                 (kc::Leaf*)c.leaves.p, dst_state, na, (uint32_t*)c.dcnt.p,
-                                 q.slots_log2, (uint32_t*)c.large.p, st),
+                                 (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
+                                 q.slots_log2, (uint32_t*)c.alarge.p, st),
            "leaf count launch");
     tm.mark(ST_LEAF);
     uint32_t* hd = (uint32_t*)host_stage(c, na * 4 + 64);
-    hipchk(hipMemcpyAsync(hd, c.dcnt.p, na * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    hipchk(hipMemcpyAsync(hd, c.adcnt.p, na * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
     hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
     split.clear();
     for (size_t i = 0; i < na; ++i) {
@@ -405,34 +434,55 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0) {
     }
   }
   S.n_levels = 1 + level;
-  // splice the parts into the leaf list in place of their parents
+  // splice the parts into the leaf list in place of their parents (on the
+  // device: only the parts travel)
   std::sort(done.begin(), done.end(), [](const Done& a, const Done& b) {
     return a.root != b.root ? a.root < b.root : a.start < b.start;
   });
-  std::vector<kc::Leaf> nlv;
-  std::vector<uint32_t> ndv;
-  nlv.reserve(nl0 + done.size());
-  ndv.reserve(nl0 + done.size());
-  size_t j = 0;
-  for (uint64_t i = 0; i < nl0; ++i) {
-    if (dv[i] != kc::kLeafOverflow) {
-      nlv.push_back(lv[i]);
-      ndv.push_back(dv[i]);
-      continue;
-    }
-    for (; j < done.size() && done[j].root == i; ++j) {
-      nlv.push_back(done[j].leaf);
-      ndv.push_back(done[j].d);
-    }
+  const uint64_t P = done.size();
+  // one upload: parts, part counts, then per root its leaf, first part, part count
+  const size_t off_d = P * sizeof(kc::Leaf), off_root = off_d + P * 4;
+  const size_t bytes = off_root + 3 * R * 4;
+  std::vector<char> hb(bytes);
+  kc::Leaf* hp = (kc::Leaf*)hb.data();
+  uint32_t* hpd = (uint32_t*)(hb.data() + off_d);
+  uint32_t* hroot = (uint32_t*)(hb.data() + off_root);
+  uint32_t* hbeg = hroot + R;
+  uint32_t* hnp = hbeg + R;
+  for (uint32_t r = 0; r < R; ++r) {
+    hroot[r] = ridx[ord[r]];
+    hbeg[r] = 0;
+    hnp[r] = 0;
   }
-  const uint64_t nl = nlv.size();
+  for (uint64_t i = 0; i < P; ++i) {
+    hp[i] = done[i].leaf;
+    hpd[i] = done[i].d;
+    if (hnp[done[i].root]++ == 0) hbeg[done[i].root] = (uint32_t)i;
+  }
+  ensure(c.rparts, bytes, "refined parts");
+  upload_sync(c.rparts.p, hb.data(), bytes, st);
+  const char* dp = (const char*)c.rparts.p;
+  const uint64_t nl = nl0 - R + P;
+  ensure(c.rcnt, nl0 * 4, "splice counts");
+  // the spliced list is built beside the old one and the two are swapped;
+  // both keep the larger capacity so that the next call does not reallocate
+  ensure(c.leaves2, std::max(nl, keep_leaves) * sizeof(kc::Leaf), "leaf table");
+  ensure(c.dcnt2, std::max(nl, keep_leaves) * 4, "leaf counts");
+  ensure(c.bsum, kc::scan_blocks(std::max(nl0, nl)) * 8, "scan block sums");
+  ensure(c.outoff, std::max(nl0, nl) * 8, "output offsets");
+  unsigned long long n0 = nl0;
+  upload_sync(&dst_state->n_leaves, &n0, 8, st);
+  hipchk(kc::launch_splice((const kc::Leaf*)c.leaves.p, (const uint32_t*)c.dcnt.p, nl0,
+                           (const uint32_t*)(dp + off_root), (const uint32_t*)(dp + off_root) + R,
+                           (const uint32_t*)(dp + off_root) + 2 * R, (uint32_t)R,
+                           (const kc::Leaf*)dp, (const uint32_t*)(dp + off_d),
+                           (uint32_t*)c.rcnt.p, dst_state, (unsigned long long*)c.bsum.p,
+                           (unsigned long long*)c.outoff.p, (kc::Leaf*)c.leaves2.p,
+                           (uint32_t*)c.dcnt2.p, st),
+         "splice launch");
+  std::swap(c.leaves, c.leaves2);
+  std::swap(c.dcnt, c.dcnt2);
   S.n_leaves = nl;
-  ensure(c.leaves, nl * sizeof(kc::Leaf), "leaf table");
-  ensure(c.dcnt, nl * 4, "leaf counts");
-  ensure(c.outoff, nl * 8, "output offsets");
-  ensure(c.bsum, kc::scan_blocks(nl) * 8, "scan block sums");
-  upload_sync(c.leaves.p, nlv.data(), nl * sizeof(kc::Leaf), st);
-  upload_sync(c.dcnt.p, ndv.data(), nl * 4, st);
   unsigned long long nlu = nl;
   upload_sync(&dst_state->n_leaves, &nlu, 8, st);
   unsigned int zero = 0;
@@ -717,7 +767,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   if (ds.overflow) {
     // some leaves had more distinct keys than their tables hold: partition
     // those further and count their parts
-    refine_overflowed(c, q, S, tm, ds.n_leaves);
+    refine_overflowed(c, q, S, tm, ds.n_leaves, p.max_leaves);
     ds = read_state(c, st);
     if (ds.overflow) fail(KC_E_INTERNAL, "leaf overflow after refinement");
   }
@@ -1207,10 +1257,12 @@ uint64_t arena_bytes() {
   auto it = g_ctx.find(dev);
   if (it == g_ctx.end() || !it->second) return 0;
   const Ctx& c = *it->second;
-  const DevBuf* all[] = {&c.packed, &c.inv,    &c.endm,  &c.bufA,   &c.bufB,  &c.tmpcnt,
-                         &c.hist,   &c.sbegin, &c.cursor, &c.cursor2, &c.order, &c.items,
-                         &c.bins,   &c.subhist, &c.leaves, &c.dcnt,  &c.outoff, &c.state,
-                         &c.large,  &c.bsum,   &c.itemoff};
+  const DevBuf* all[] = {&c.packed,  &c.inv,     &c.endm,   &c.bufA,    &c.bufB,   &c.tmpcnt,
+                         &c.hist,    &c.sbegin,  &c.cursor, &c.cursor2, &c.order,  &c.items,
+                         &c.bins,    &c.subhist, &c.leaves, &c.dcnt,    &c.outoff, &c.state,
+                         &c.large,   &c.bsum,    &c.itemoff, &c.rlist,  &c.rleaves, &c.rcount,
+                         &c.aleaves, &c.adcnt,   &c.alarge, &c.rparts,  &c.rcnt,   &c.leaves2,
+                         &c.dcnt2};
   uint64_t t = 0;
   for (const DevBuf* b : all) t += b->cap;
   return t;

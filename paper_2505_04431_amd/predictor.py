@@ -74,11 +74,19 @@ class SizePredictor:
     def _norm(self, X):
         return ((np.asarray(X, np.float32) - self.mu) / self.sd).astype(np.float32)
 
-    def fit(self, X, ln_d, steps: int = 3000, lr: float = 3e-3, device=None) -> list[float]:
-        """Full-batch Adam on the device. Returns the loss every 100 steps."""
+    def fit(self, X, ln_d, steps: int = 3000, lr: float = 3e-3, val_frac: float = 0.2,
+            device=None) -> list[float]:
+        """Full-batch Adam on the device over all but a seeded val_frac of the
+        jobs; the spread of the errors on those held-out jobs sets the margin
+        of hint(). Returns the training loss every 100 steps."""
         import torch
-        X = np.asarray(X, np.float32)
-        y = (np.asarray(ln_d, np.float64) - baseline_ln(X)).astype(np.float32)
+        X_all = np.asarray(X, np.float32)
+        ln_all = np.asarray(ln_d, np.float64)
+        perm = np.random.Generator(np.random.PCG64(len(ln_all))).permutation(len(ln_all))
+        n_val = int(len(ln_all) * val_frac) if len(ln_all) >= 10 else 0
+        val, tr = perm[:n_val], perm[n_val:]
+        X = X_all[tr]
+        y = (ln_all[tr] - baseline_ln(X)).astype(np.float32)
         self.mu = X.mean(axis=0)
         self.sd = np.maximum(X.std(axis=0), 1e-3).astype(np.float32)
         self.t_mu, self.t_sd = float(y.mean()), float(max(y.std(), 1e-3))
@@ -91,8 +99,9 @@ class SizePredictor:
             if loss is not None:
                 hist.append(loss)
             self.net.adam_step(lr)
-        pred = self.predict_ln(X, device=dev)
-        self.resid_sd = float(max(np.std(pred - np.asarray(ln_d, np.float64)), 1e-3))
+        chk = val if n_val else tr
+        err = self.predict_ln(X_all[chk], device=dev) - ln_all[chk]
+        self.resid_sd = float(max(np.sqrt(np.mean(err * err)), 1e-3))
         return hist
 
     def predict_ln(self, X, device=None) -> np.ndarray:
