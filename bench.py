@@ -393,10 +393,13 @@ def main() -> int:
     ceil = kc.kc.measure_ceilings(4 << 30, stream.cuda_stream)
     t_h2d = h2d_ms(torch, dev, reads, offs)
     kname = kernel_names.get(dom, dom)
+    traffic = traffic_per_launch(kname, args.config, k)
     roofline = {"bound": "hbm", "kernel": kname, "stage": dom,
                 "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_per_launch(kname, args.config, k),
+                "traffic": traffic,
+                "traffic_unit": "bytes per launch",
+                "traffic_gbs": round(traffic / (avg[dom] / 1e3) / 1e9, 1) if traffic else None,
                 "copy_gbs": copy_gbs,
                 "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
                 "leaf_records_per_s": round(st["large_records"] / (avg[dom] / 1e3), 1)
