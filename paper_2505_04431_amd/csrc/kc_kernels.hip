@@ -187,6 +187,25 @@ __device__ __forceinline__ uint32_t block_exscan_array(const uint32_t* a, uint32
   return total;
 }
 
+// In-place exclusive scan of a[0..n) (counts become offsets); returns the total.
+template <int TB>
+__device__ __forceinline__ uint32_t block_exscan_inplace(uint32_t* a, int n, uint32_t* wsum) {
+  const int per = (n + TB - 1) / TB;
+  const int b = threadIdx.x * per;
+  const int e = min(n, b + per);
+  uint32_t s = 0;
+  for (int i = b; i < e; ++i) s += a[i];
+  uint32_t total;
+  uint32_t run = block_exscan<TB, uint32_t>(s, wsum, &total);
+  for (int i = b; i < e; ++i) {
+    const uint32_t x = a[i];
+    a[i] = run;
+    run += x;
+  }
+  __syncthreads();
+  return total;
+}
+
 __global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
@@ -408,52 +427,47 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
 }
 
 // Owner-major scatter of window records into shard slices (cursor[i] starts at
-// shard i's slice begin). One tile = TB*S window starts.
+// shard i's slice begin). One tile = TB*S window starts: the tile's records
+// are ranked per shard in LDS, each shard's run reserves its place with one
+// global atomic, and the runs leave LDS as coalesced writes.
 template <typename K, typename Kc, int S, int TB, bool BATCH>
-__global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restrict__ packed,
-                                                       const uint64_t* __restrict__ inv,
-                                                       const uint64_t* __restrict__ endm,
-                                                       uint64_t t_begin, uint64_t t_end, int k,
-                                                       int keybits, int shard_bits, BatchSets bs,
-                                                       unsigned long long* __restrict__ cursor,
-                                                       K* __restrict__ out) {
+__device__ __forceinline__ void window_scatter_body(const uint64_t* __restrict__ packed,
+                                                    const uint64_t* __restrict__ inv,
+                                                    const uint64_t* __restrict__ endm,
+                                                    uint64_t t_begin, uint64_t t_end, int k,
+                                                    int keybits, int shard_bits, BatchSets bs,
+                                                    unsigned long long* __restrict__ cursor,
+                                                    K* __restrict__ out) {
   constexpr int NBMAX = 1 << kMaxShardBits;
   __shared__ K stage[TB * S];
-  __shared__ uint32_t hist[NBMAX];
-  __shared__ uint32_t loff[NBMAX];
+  __shared__ uint32_t loff[NBMAX];  // per shard: records in the tile, then their run offsets
   __shared__ unsigned long long gbase[NBMAX];
   __shared__ uint32_t wsum[TB / 64];
   const int nb = 1 << shard_bits;
   const uint64_t n_tiles = (t_end - t_begin + TB - 1) / TB;
   for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    for (int i = threadIdx.x; i < nb; i += TB) hist[i] = 0;
+    for (int i = threadIdx.x; i < nb; i += TB) loff[i] = 0;
     __syncthreads();
     const uint64_t t = t_begin + tile * TB + threadIdx.x;
     const uint64_t g = t * S;
     uint32_t vm = t < t_end ? valid_starts<S>(inv, endm, g, k) : 0u;
     K key[S];
-    uint32_t bin[S], rank[S];
+    uint32_t rank[S];  // (the shard is recomputed from the key: fewer live registers)
     if (vm) {
       vm = window_keys<K, Kc, S, BATCH>(packed, g, k, vm, bs, key);
 #pragma unroll
-      for (int i = 0; i < S; ++i) {
-        if (vm & (1u << i)) {
-          bin[i] = shard_of(key[i], keybits, shard_bits);
-          rank[i] = atomicAdd(&hist[bin[i]], 1u);
-        }
-      }
+      for (int i = 0; i < S; ++i)
+        if (vm & (1u << i)) rank[i] = atomicAdd(&loff[shard_of(key[i], keybits, shard_bits)], 1u);
     }
     __syncthreads();
-    const uint32_t total = block_exscan_array<TB>(hist, loff, nb, wsum);
-    for (int i = threadIdx.x; i < nb; i += TB)
-      if (hist[i]) gbase[i] = atomicAdd(&cursor[i], (unsigned long long)hist[i]);
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-      if (vm & (1u << i)) {
-        const uint32_t p = loff[bin[i]] + rank[i];
-        stage[p] = key[i];
-      }
+    const uint32_t total = block_exscan_inplace<TB>(loff, nb, wsum);
+    for (int i = threadIdx.x; i < nb; i += TB) {
+      const uint32_t cnt = (i + 1 < nb ? loff[i + 1] : total) - loff[i];
+      if (cnt) gbase[i] = atomicAdd(&cursor[i], (unsigned long long)cnt);
     }
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+      if (vm & (1u << i)) stage[loff[shard_of(key[i], keybits, shard_bits)] + rank[i]] = key[i];
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < total; j += TB) {
       const K kk = stage[j];  // its shard again from the key: cheaper than staging it
@@ -462,6 +476,31 @@ __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restric
     }
     __syncthreads();
   }
+}
+
+template <typename K, typename Kc, int S, int TB, bool BATCH>
+__global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restrict__ packed,
+                                                       const uint64_t* __restrict__ inv,
+                                                       const uint64_t* __restrict__ endm,
+                                                       uint64_t t_begin, uint64_t t_end, int k,
+                                                       int keybits, int shard_bits, BatchSets bs,
+                                                       unsigned long long* __restrict__ cursor,
+                                                       K* __restrict__ out) {
+  window_scatter_body<K, Kc, S, TB, BATCH>(packed, inv, endm, t_begin, t_end, k, keybits,
+                                           shard_bits, bs, cursor, out);
+}
+
+// Plain 64-bit keys: registers capped so that two 1024-thread workgroups
+// share a CU (their LDS fits twice), which hides the per-tile barriers and
+// atomics. (The batch form keeps more values live and stays uncapped.)
+template <typename K, typename Kc, int S, int TB, bool BATCH>
+__global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_window_scatter64(const uint64_t* __restrict__ packed, const uint64_t* __restrict__ inv,
+                   const uint64_t* __restrict__ endm, uint64_t t_begin, uint64_t t_end, int k,
+                   int keybits, int shard_bits, BatchSets bs,
+                   unsigned long long* __restrict__ cursor, K* __restrict__ out) {
+  window_scatter_body<K, Kc, S, TB, BATCH>(packed, inv, endm, t_begin, t_end, k, keybits,
+                                           shard_bits, bs, cursor, out);
 }
 
 // ---------------------------------------------------------------- planning (one block)
@@ -758,8 +797,8 @@ __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
                                                       unsigned long long* __restrict__ cursor) {
   constexpr int NS = 1 << kSplitMaxBits;
   __shared__ K stage[TB * R];
-  __shared__ uint32_t hist[NS];
-  __shared__ uint32_t loff[NS];
+  __shared__ uint32_t hist[NS];  // per sub-bin: records in the tile, then their run offsets
+  uint32_t* const loff = hist;
   __shared__ unsigned long long gbase[NS];
   __shared__ uint32_t wsum[TB / 64];
   const unsigned long long n_items = st->n_items;
@@ -781,9 +820,11 @@ __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
       }
     }
     __syncthreads();
-    const uint32_t total = block_exscan_array<TB>(hist, loff, nsub, wsum);
-    for (int i = threadIdx.x; i < nsub; i += TB)
-      if (hist[i]) gbase[i] = atomicAdd(&cursor[bn.hist_off + i], (unsigned long long)hist[i]);
+    const uint32_t total = block_exscan_inplace<TB>(hist, nsub, wsum);
+    for (int i = threadIdx.x; i < nsub; i += TB) {
+      const uint32_t cnt = (i + 1 < nsub ? loff[i + 1] : total) - loff[i];
+      if (cnt) gbase[i] = atomicAdd(&cursor[bn.hist_off + i], (unsigned long long)cnt);
+    }
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const uint64_t r = it.begin + threadIdx.x + (uint64_t)j * TB;
@@ -1483,7 +1524,7 @@ hipError_t launch_window_scatter(bool wide, const uint64_t* packed, const uint64
     const unsigned grid = grid_for(t_end - t_begin, kScatterTB64, 1u << 20);
 #define ARG1 (uint64_t*)out
     if (batch) KC_WINDOW_LAUNCH(k_window_scatter, uint64_t, uint64_t, kScatterTB64, true, grid);
-    else KC_WINDOW_LAUNCH(k_window_scatter, uint64_t, uint64_t, kScatterTB64, false, grid);
+    else KC_WINDOW_LAUNCH(k_window_scatter64, uint64_t, uint64_t, kScatterTB64, false, grid);
 #undef ARG1
   }
 #undef ARG0
