@@ -1146,7 +1146,14 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
     uint32_t Cn = leaf_slots<TB, CMAX>(n / 2, cmax_rt);
     for (;;) {
     const uint32_t cmask = Cn - 1;
-    for (uint32_t i = threadIdx.x; i < Cn; i += TB) tc[i] = 0;
+    // For k <= 63 the high word of a key is never all ones, so a slot is
+    // claimed by a CAS of its high word (all ones = empty); k = 64 claims it
+    // through the count word instead.
+    const bool hiclaim = keybits <= 126;
+    for (uint32_t i = threadIdx.x; i < Cn; i += TB) {
+      tc[i] = 0;
+      if (hiclaim) reinterpret_cast<unsigned long long*>(&tk[i])[1] = ~0ull;
+    }
     if (threadIdx.x == 0) {
       s_nd = 0;
       __hip_atomic_store(&s_ovf, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1172,6 +1179,45 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
       uint32_t pos = (uint32_t)Key<u128>::hash(key) & cmask;
       uint32_t probe = 0, spins = 0;
       bool done = false;
+      if (hiclaim) {
+        // Claim by the high word, then publish the low word with the count
+        // (release); a lane that finds its high word in a slot whose count
+        // is still 0 waits for that publication (made in the claimer's same
+        // pass), then compares the low word.
+        const unsigned long long khi = (unsigned long long)(key >> 64);
+        const unsigned long long klo = (unsigned long long)key;
+        bool todo = true;
+        while (todo) {
+          unsigned long long* w = reinterpret_cast<unsigned long long*>(&tk[pos]);
+          const unsigned long long prev = atomicCAS(&w[1], ~0ull, khi);
+          bool hit = false, wait = false;
+          if (prev == ~0ull) {
+            w[0] = klo;
+            __hip_atomic_store(&tc[pos], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (track && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
+            hit = true;
+          } else if (prev == khi) {
+            const unsigned long long c =
+                __hip_atomic_load(&tc[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (c == 0) {
+              // the bound only guards against a hang; giving up marks the
+              // leaf overflowed, so it is counted again by refinement
+              wait = ++spins <= (1u << 22);
+              if (!wait) probe = Cn;
+            } else if (w[0] == klo) {
+              __hip_atomic_fetch_add(&tc[pos], 1ull, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+              hit = true;
+            }
+          }
+          done |= hit;
+          if (!hit && !wait && probe < Cn) {
+            pos = (pos + 1) & cmask;
+            ++probe;
+          }
+          todo = !hit && probe < Cn;
+        }
+      } else
       while (probe < Cn) {
         unsigned long long c =
             __hip_atomic_load(&tc[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
