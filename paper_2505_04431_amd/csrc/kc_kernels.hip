@@ -779,8 +779,21 @@ __global__ void __launch_bounds__(TB) k_split_hist(const K* __restrict__ src,
     const int nsub = 1 << bn.nbits;
     for (int i = threadIdx.x; i < nsub; i += TB) h[i] = 0;
     __syncthreads();
-    for (uint64_t r = it.begin + threadIdx.x; r < it.end; r += TB)
-      atomicAdd(&h[Key<K>::bits(src[r], bn.shift, bn.nbits)], 1u);
+    // loads of a batch are issued together, then counted
+    constexpr int RB = 8;
+    for (uint64_t r0 = it.begin; r0 < it.end; r0 += (uint64_t)TB * RB) {
+      K kb[RB];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        const uint64_t r = r0 + (uint64_t)j * TB + threadIdx.x;
+        if (r < it.end) kb[j] = src[r];
+      }
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        const uint64_t r = r0 + (uint64_t)j * TB + threadIdx.x;
+        if (r < it.end) atomicAdd(&h[Key<K>::bits(kb[j], bn.shift, bn.nbits)], 1u);
+      }
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < nsub; i += TB)
       if (h[i]) atomicAdd(&subhist[bn.hist_off + i], (unsigned long long)h[i]);
@@ -934,6 +947,7 @@ __device__ __forceinline__ uint32_t leaf_sort_write(K* tk, C* tc, uint32_t* aux,
   __syncthreads();  // table copied to registers; group counters cleared
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
+    if ((uint32_t)j * TB >= Cn) break;  // uniform: Cn is a multiple of TB
     // every slot adds 0 or 1 (empty slots add 0 to a spread-out counter), so
     // no branch per slot
     const bool o = occupied(rc[j]);
