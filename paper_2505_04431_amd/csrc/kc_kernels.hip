@@ -1017,7 +1017,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
   __shared__ uint32_t tc[CMAX];
   __shared__ uint32_t aux[CMAX];
   __shared__ uint32_t wsum[TB / 64];
-  __shared__ uint32_t s_nd, s_max;
+  __shared__ uint32_t s_nd, s_max, s_cov;
   __shared__ uint32_t s_ovf;  // accessed only through ovf_get / ovf_set
   const unsigned long long EMPTY = ~0ull;
   const uint32_t cmax_rt = 1u << slots_log2;
@@ -1049,11 +1049,13 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
     }
     if (threadIdx.x == 0) {
       s_nd = 0;
+      s_cov = 0;
       __hip_atomic_store(&s_ovf, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
     const uint32_t limit = Cn - (Cn >> 3);
     const bool track = n >= limit;  // fewer records than the limit cannot overflow
+    const bool huge = n > 0xFFFFFFFFull;
     // records are loaded R per thread before inserting, so that the loads of a
     // batch are in flight together instead of one round trip per insert. The
     // probe loop has a single exit flag (always-CAS: a CAS on a slot holding
@@ -1077,7 +1079,13 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
           const unsigned long long prev = atomicCAS(&tk[pos], EMPTY, key);
           const bool hit = (prev == EMPTY) | (prev == key);
           if (hit) {
-            atomicAdd(&tc[pos], 1u);
+            // a leaf of 2^32 records or more may hold a count that does not fit
+            // 32 bits: only there is the previous count looked at
+            if (huge) {
+              if (atomicAdd(&tc[pos], 1u) == 0xFFFFFFFFu) s_cov = 1;
+            } else {
+              atomicAdd(&tc[pos], 1u);
+            }
             if (track && prev == EMPTY && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
           }
           pos = (pos + 1) & cmask;
@@ -1107,6 +1115,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
         lf.begin, occ32);
     if (threadIdx.x == 0) {
       d_out[l] = d;
+      if (s_cov) atomicOr(&st->count_overflow, 1u);
       my_records += n;
       my_distinct += d;
     }

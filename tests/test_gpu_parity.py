@@ -176,3 +176,22 @@ def test_k55_long_reads():
     g = synth.genome(55, 200_000, [(3000, 5, 0.01)])
     r, o = synth.reads(g, 300, 10_000, err_rate=0.01, seed=5)
     assert_same(gpu_count(r, o, 55, P=8, check=1), oracle.count(r, o, 55), "k=55 long reads")
+
+
+def test_count_beyond_32_bits_is_reported():
+    """A k-mer seen 2^32 + 1 times: the call fails with KC_E_OVERFLOW instead of
+    returning a wrapped count."""
+    import torch
+    import paper_2505_04431_amd as kc
+    n = (1 << 32) + 31  # k = 31: 2^32 + 1 windows, all the same key
+    dev = torch.device("cuda:0")
+    rt = torch.full((n,), ord("A"), dtype=torch.uint8, device=dev)
+    ot = torch.tensor([0, n], dtype=torch.int64, device=dev)
+    keys = torch.empty(16, dtype=torch.int64, device=dev)
+    cnts = torch.empty(16, dtype=torch.int32, device=dev)
+    with pytest.raises(kc.KcError) as e:
+        kc.count_into(rt, ot, 31, 1, keys, cnts, 16)
+    assert e.value.status == -4
+    del rt
+    kc.lib().kc_release_scratch()
+    torch.cuda.empty_cache()
