@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
 def stage_bytes(st: dict, k: int) -> dict:
-    """Algorithmic HBM bytes of each stage of one call (the bytes model in the design doc).
+    """Algorithmic HBM bytes of each stage of one call.
 
     N bases, W valid windows, D distinct keys, K key bytes (8 for k <= 32, else 16).
     Records are written once by the owner scatter, read by the split histogram,
@@ -294,22 +294,31 @@ def served_leg(n_jobs: int, budget_gib: float, workers: int, load: float) -> dic
     cal = run_pass([0.0] * len(inputs))
     busy = (max(i["t_end_ms"] for i in cal) - min(i["t_start_ms"] for i in cal)) / 1e3
     capacity = len(inputs) / busy
-    rate = load * capacity
-    rng = random.Random(0x5E7)
-    arr, t = [], 0.0
-    for _ in inputs:
-        arr.append(t)
-        t += rng.expovariate(rate)
-    infos = run_pass(arr)
-    st = srv.stats()
-    srv.close()
-    lat = sorted(i["t_end_ms"] - i["t_submit_ms"] for i in infos)
-    wait = sorted(i["t_start_ms"] - i["t_submit_ms"] for i in infos)
-    span = (max(i["t_end_ms"] for i in infos) - min(i["t_submit_ms"] for i in infos)) / 1e3
-    W = sum(i["valid_windows"] for i in infos)
-
     def pct(v, q):
         return round(v[min(len(v) - 1, max(0, int(np.ceil(q * len(v))) - 1))], 3)
+
+    def poisson_pass(ld):
+        rng = random.Random(0x5E7)
+        arr, t = [], 0.0
+        for _ in inputs:
+            arr.append(t)
+            t += rng.expovariate(ld * capacity)
+        infos = run_pass(arr)
+        lat = sorted(i["t_end_ms"] - i["t_submit_ms"] for i in infos)
+        wait = sorted(i["t_start_ms"] - i["t_submit_ms"] for i in infos)
+        span = (max(i["t_end_ms"] for i in infos) - min(i["t_submit_ms"] for i in infos)) / 1e3
+        W = sum(i["valid_windows"] for i in infos)
+        return infos, lat, wait, span, W
+
+    sweep = []
+    for ld in (0.5, 0.9):  # the other arrival rates, beside the headline one
+        _, lat_s, _, span_s, W_s = poisson_pass(ld)
+        sweep.append({"load": ld, "value": round(W_s / span_s, 1),
+                      "latency_p50_ms": pct(lat_s, 0.5), "latency_p99_ms": pct(lat_s, 0.99)})
+    rate = load * capacity
+    infos, lat, wait, span, W = poisson_pass(load)
+    st = srv.stats()
+    srv.close()
 
     return {
         "workload": "c5_served_10000_jobs_sample", "jobs": len(inputs), "of_jobs": len(specs),
@@ -320,7 +329,7 @@ def served_leg(n_jobs: int, budget_gib: float, workers: int, load: float) -> dic
         "load": load, "latency_p50_ms": pct(lat, 0.5), "latency_p99_ms": pct(lat, 0.99),
         "wait_p50_ms": pct(wait, 0.5), "wait_p99_ms": pct(wait, 0.99),
         "peak_bytes": st["bytes_peak"], "estimate_misses": st["estimate_misses"],
-        "gen_s": round(t_gen, 1),
+        "gen_s": round(t_gen, 1), "load_sweep": sweep,
         "note": "seeded sample of the 10,000 jobs (same distribution); inputs resident; Poisson "
                 "arrivals at load x capacity measured by a calibration pass; latency = "
                 "completion - submission",
@@ -348,7 +357,7 @@ def main() -> int:
                     help="size of the plain copy kernel timed for the achievable HBM rate")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build counts on one GPU only; --gpus %d is not supported "
+        print("bench.py: this path counts on one GPU only; --gpus %d is not supported "
               "(run with --gpus 1)" % args.gpus, file=sys.stderr)
         return 2
 
