@@ -1018,6 +1018,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
   __shared__ uint32_t aux[CMAX];
   __shared__ uint32_t wsum[TB / 64];
   __shared__ uint32_t s_nd, s_max, s_cov;
+  __shared__ unsigned long long s_sum;
   __shared__ uint32_t s_ovf;  // accessed only through ovf_get / ovf_set
   const unsigned long long EMPTY = ~0ull;
   const uint32_t cmax_rt = 1u << slots_log2;
@@ -1055,7 +1056,6 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
     __syncthreads();
     const uint32_t limit = Cn - (Cn >> 3);
     const bool track = n >= limit;  // fewer records than the limit cannot overflow
-    const bool huge = n > 0xFFFFFFFFull;
     // records are loaded R per thread before inserting, so that the loads of a
     // batch are in flight together instead of one round trip per insert. The
     // probe loop has a single exit flag (always-CAS: a CAS on a slot holding
@@ -1079,13 +1079,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
           const unsigned long long prev = atomicCAS(&tk[pos], EMPTY, key);
           const bool hit = (prev == EMPTY) | (prev == key);
           if (hit) {
-            // a leaf of 2^32 records or more may hold a count that does not fit
-            // 32 bits: only there is the previous count looked at
-            if (huge) {
-              if (atomicAdd(&tc[pos], 1u) == 0xFFFFFFFFu) s_cov = 1;
-            } else {
-              atomicAdd(&tc[pos], 1u);
-            }
+            atomicAdd(&tc[pos], 1u);
             if (track && prev == EMPTY && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
           }
           pos = (pos + 1) & cmask;
@@ -1109,6 +1103,17 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
       }
       __syncthreads();
       continue;
+    }
+    if (n > 0xFFFFFFFFull) {
+      // a leaf of 2^32 records or more may hold a count that wrapped past 32
+      // bits; the counts then sum to less than the records
+      if (threadIdx.x == 0) s_sum = 0;
+      __syncthreads();
+      unsigned long long part = 0;
+      for (uint32_t i = threadIdx.x; i < Cn; i += TB) part += tc[i];
+      atomicAdd(&s_sum, part);
+      __syncthreads();
+      if (threadIdx.x == 0 && s_sum != n) s_cov = 1;
     }
     const uint32_t d = leaf_sort_write<unsigned long long, uint32_t, TB, CMAX / TB>(
         tk, tc, aux, wsum, &s_max, Cn, keybits, (int)lf.bits, (unsigned long long*)dst, tmp_cnt,
