@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "kc_internal.h"
 
 namespace kc {
@@ -1134,11 +1136,18 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
   }
 }
 
-// 128-bit keys: no 128-bit CAS, so a slot is claimed through its count word:
-// 0 = empty, LOCK = being written; the claimer writes the key and then
-// publishes the count. Others seeing LOCK retry the same slot; the claimer
-// publishes in the same pass without waiting on anyone, so the retry ends.
-template <int TB, int CMAX, int R>
+// 128-bit keys: there is no 128-bit CAS.
+// HI = true (k <= 63): the high word of a key is then never all ones, so a
+//   slot is claimed by a CAS of its high word (all ones = empty); the claimer
+//   writes the low word and publishes it with the count (release). A lane
+//   that finds its high word in a slot whose count is still 0 waits for that
+//   publication (made in the claimer's same pass), then compares the low
+//   word. Counts are 32-bit.
+// HI = false (k = 64, where one key has an all-ones high word): a slot is
+//   claimed through its 64-bit count word: 0 = empty, LOCK = being written;
+//   the claimer writes the key and then publishes the count; others seeing
+//   LOCK retry the same slot.
+template <int TB, int CMAX, int R, bool HI>
 __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u128* bufB,
                                                       uint32_t* __restrict__ tmp_cnt,
                                                       const Leaf* __restrict__ leaves,
@@ -1147,11 +1156,13 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
                                                       int slots_log2,
                                                       const uint32_t* __restrict__ list,
                                                       uint64_t small_max) {
+  typedef typename std::conditional<HI, uint32_t, unsigned long long>::type C;
   __shared__ u128 tk[CMAX];
-  __shared__ unsigned long long tc[CMAX];
+  __shared__ C tc[CMAX];
   __shared__ uint32_t aux[CMAX];
   __shared__ uint32_t wsum[TB / 64];
   __shared__ uint32_t s_nd, s_max, s_cov;
+  __shared__ unsigned long long s_sum;
   __shared__ uint32_t s_ovf;  // accessed only through ovf_get / ovf_set
   const unsigned long long LOCK = 1ull << 63;
   const uint32_t cmax_rt = 1u << slots_log2;
@@ -1174,13 +1185,9 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
     uint32_t Cn = leaf_slots<TB, CMAX>(n / 2, cmax_rt);
     for (;;) {
     const uint32_t cmask = Cn - 1;
-    // For k <= 63 the high word of a key is never all ones, so a slot is
-    // claimed by a CAS of its high word (all ones = empty); k = 64 claims it
-    // through the count word instead.
-    const bool hiclaim = keybits <= 126;
     for (uint32_t i = threadIdx.x; i < Cn; i += TB) {
       tc[i] = 0;
-      if (hiclaim) reinterpret_cast<unsigned long long*>(&tk[i])[1] = ~0ull;
+      if (HI) reinterpret_cast<unsigned long long*>(&tk[i])[1] = ~0ull;
     }
     if (threadIdx.x == 0) {
       s_nd = 0;
@@ -1207,11 +1214,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
       uint32_t pos = (uint32_t)Key<u128>::hash(key) & cmask;
       uint32_t probe = 0, spins = 0;
       bool done = false;
-      if (hiclaim) {
-        // Claim by the high word, then publish the low word with the count
-        // (release); a lane that finds its high word in a slot whose count
-        // is still 0 waits for that publication (made in the claimer's same
-        // pass), then compares the low word.
+      if (HI) {
         const unsigned long long khi = (unsigned long long)(key >> 64);
         const unsigned long long klo = (unsigned long long)key;
         bool todo = true;
@@ -1221,19 +1224,18 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
           bool hit = false, wait = false;
           if (prev == ~0ull) {
             w[0] = klo;
-            __hip_atomic_store(&tc[pos], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(&tc[pos], (C)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (track && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
             hit = true;
           } else if (prev == khi) {
-            const unsigned long long c =
-                __hip_atomic_load(&tc[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const C c = __hip_atomic_load(&tc[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (c == 0) {
               // the bound only guards against a hang; giving up marks the
               // leaf overflowed, so it is counted again by refinement
               wait = ++spins <= (1u << 22);
               if (!wait) probe = Cn;
             } else if (w[0] == klo) {
-              __hip_atomic_fetch_add(&tc[pos], 1ull, __ATOMIC_RELAXED,
+              __hip_atomic_fetch_add(&tc[pos], (C)1, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
               hit = true;
             }
@@ -1245,34 +1247,34 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
           }
           todo = !hit && probe < Cn;
         }
-      } else
+      } else {
       while (probe < Cn) {
-        unsigned long long c =
-            __hip_atomic_load(&tc[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        C c = __hip_atomic_load(&tc[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (c == 0) {
-          unsigned long long expect = 0;
-          if (__hip_atomic_compare_exchange_strong(&tc[pos], &expect, LOCK, __ATOMIC_ACQ_REL,
+          C expect = 0;
+          if (__hip_atomic_compare_exchange_strong(&tc[pos], &expect, (C)LOCK, __ATOMIC_ACQ_REL,
                                                    __ATOMIC_ACQUIRE,
                                                    __HIP_MEMORY_SCOPE_WORKGROUP)) {
             tk[pos] = key;
-            __hip_atomic_store(&tc[pos], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(&tc[pos], (C)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (track && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
             done = true;
             break;
           }
           c = expect;
         }
-        if (c == LOCK) {
+        if (c == (C)LOCK) {
           if (++spins > (1u << 22)) break;  // cannot happen; guards against a hang
           continue;
         }
         if (tk[pos] == key) {
-          __hip_atomic_fetch_add(&tc[pos], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_fetch_add(&tc[pos], (C)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           done = true;
           break;
         }
         pos = (pos + 1) & cmask;
         ++probe;
+      }
       }
       if (!done) ovf_set(&s_ovf);
       }
@@ -1293,10 +1295,24 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
       __syncthreads();
       continue;
     }
-    for (uint32_t i = threadIdx.x; i < Cn; i += TB)
-      if (tc[i] > 0xFFFFFFFFull) s_cov = 1;
-    const uint32_t d = leaf_sort_write<u128, unsigned long long, TB, CMAX / TB>(
-        tk, tc, aux, wsum, &s_max, Cn, keybits, (int)lf.bits, dst, tmp_cnt, lf.begin, occ64);
+    if (HI) {
+      if (n > 0xFFFFFFFFull) {
+        // 32-bit counts may have wrapped: they then sum to less than the records
+        if (threadIdx.x == 0) s_sum = 0;
+        __syncthreads();
+        unsigned long long part = 0;
+        for (uint32_t i = threadIdx.x; i < Cn; i += TB) part += tc[i];
+        atomicAdd(&s_sum, part);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_sum != n) s_cov = 1;
+      }
+    } else {
+      for (uint32_t i = threadIdx.x; i < Cn; i += TB)
+        if ((unsigned long long)tc[i] > 0xFFFFFFFFull) s_cov = 1;
+    }
+    const uint32_t d = leaf_sort_write<u128, C, TB, CMAX / TB>(
+        tk, tc, aux, wsum, &s_max, Cn, keybits, (int)lf.bits, dst, tmp_cnt, lf.begin,
+        HI ? (bool (*)(C))occ32 : (bool (*)(C))occ64);
     if (threadIdx.x == 0) {
       d_out[l] = d;
       if (s_cov) atomicOr(&st->count_overflow, 1u);
@@ -1673,9 +1689,14 @@ hipError_t launch_leaf_small(bool wide, int keybits, void* bufA, void* bufB, uin
                      leaves, st, small_max, large_list);
   const unsigned gsmall = persistent(max_leaves, kSmallGrid);
   if (wide)
-    hipLaunchKernelGGL((k_leaf_count128<64, kSmallCmax128, 8>), dim3(gsmall), dim3(64), 0, s, keybits,
-                       (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
-                       __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max);
+    if (keybits <= 126)
+      hipLaunchKernelGGL((k_leaf_count128<64, kSmallCmax128, 8, true>), dim3(gsmall), dim3(64), 0,
+                         s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
+                         __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max);
+    else
+      hipLaunchKernelGGL((k_leaf_count128<64, kSmallCmax128, 8, false>), dim3(gsmall), dim3(64), 0,
+                         s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
+                         __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max);
   else
     hipLaunchKernelGGL((k_leaf_count64<64, kSmallCmax64, 8>), dim3(gsmall), dim3(64), 0, s, keybits,
                        (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
@@ -1690,9 +1711,14 @@ hipError_t launch_leaf_large(bool wide, int keybits, void* bufA, void* bufB, uin
   const uint64_t small_max = small_leaf_max(wide);
   const unsigned glarge = persistent(max_leaves, kPersistentGrid);
   if (wide)
-    hipLaunchKernelGGL((k_leaf_count128<kLeafTB, kLeafCmax128, 4>), dim3(glarge), dim3(kLeafTB), 0,
-                       s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out, slots_log2,
-                       large_list, small_max);
+    if (keybits <= 126)
+      hipLaunchKernelGGL((k_leaf_count128<kLeafTB, kLeafCmax128, 4, true>), dim3(glarge),
+                         dim3(kLeafTB), 0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves,
+                         st, d_out, slots_log2, large_list, small_max);
+    else
+      hipLaunchKernelGGL((k_leaf_count128<kLeafTB, kLeafCmax128, 4, false>), dim3(glarge),
+                         dim3(kLeafTB), 0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves,
+                         st, d_out, slots_log2, large_list, small_max);
   else
     hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4>), dim3(glarge), dim3(kLeafTB), 0,
                        s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
