@@ -268,23 +268,20 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t* __restrict__ src, u
   packed[2 * c] = p[0];
   packed[2 * c + 1] = p[1];
   inv[c] = iv;
-  // Reads whose last byte lies in [g0, g0+64): first the smallest r with
-  // offsets[r+1] > off0 + g0 (binary search), then every further end in range.
-  uint64_t e = 0;
-  if (g0 < n_bytes) {
-    uint64_t lo = 0, hi = n_reads;  // search r in [0, n_reads)
-    const uint64_t target = off0 + g0;
-    while (lo < hi) {
-      uint64_t mid = (lo + hi) >> 1;
-      if (offsets[mid + 1] > target) hi = mid; else lo = mid + 1;
-    }
-    for (uint64_t r = lo; r < n_reads; ++r) {
-      const uint64_t end = offsets[r + 1];
-      if (end > target + 64) break;
-      if (end > offsets[r]) e |= 1ull << (end - 1 - target);
-    }
+  endm[c] = 0;  // read ends are set by k_read_ends, launched after this kernel
+}
+
+// Read-end mask: bit of the last byte of every non-empty read (thread per read).
+__global__ void __launch_bounds__(256) k_read_ends(const uint64_t* __restrict__ offsets,
+                                                   uint64_t n_reads, uint64_t off0,
+                                                   unsigned long long* __restrict__ endm) {
+  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_reads) return;
+  const uint64_t b = offsets[r], e = offsets[r + 1];
+  if (e > b) {
+    const uint64_t pos = e - 1 - off0;
+    atomicOr(&endm[pos >> 6], 1ull << (pos & 63));
   }
-  endm[c] = e;
 }
 
 // ---------------------------------------------------------------- windows
@@ -1566,6 +1563,9 @@ hipError_t launch_pack(const uint8_t* src, uint64_t n_bytes, const uint64_t* off
   const unsigned grid = (unsigned)((nchunks + 255) / 256);
   hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, s, src, n_bytes, offsets, n_reads, off0,
                      packed, inv, endm, nchunks, aligned);
+  if (n_reads)
+    hipLaunchKernelGGL(k_read_ends, dim3((unsigned)((n_reads + 255) / 256)), dim3(256), 0, s,
+                       offsets, n_reads, off0, (unsigned long long*)endm);
   return hipGetLastError();
 }
 
