@@ -121,50 +121,49 @@ def traffic_per_launch(kernel: str, config: int, k: int):
     return ent.get("bytes_per_launch")
 
 
-def batched_leg(n_sample: int, wave_bytes: int, tune: bool) -> dict:
+def batched_leg(n_sample: int, wave_bytes: int, tune: bool, n_small: int = 512) -> dict:
     """Batched workload: read sets of the 4,096-set recipe (genomes log-uniform in
     10 kbp..10 Mbp, 20x of 150 bp reads, 0.5% errors, k in {21, 31}); a seeded
     sample of n_sample sets with the same size distribution. Sets are grouped
     into memory waves of at most wave_bytes; each wave is one recorded-graph
-    replay (batched) and, on the same resident inputs, one plain call per set."""
+    replay (batched) and, on the same resident inputs, one plain call per set.
+    A second figure covers n_small sets of the recipe with genomes of at most
+    100 kbp (a third of all sets), where per-call overheads dominate."""
     import torch
 
     import paper_2505_04431_amd as kc
     import synth
     from paper_2505_04431_amd import tuner
+    from concurrent.futures import ThreadPoolExecutor
 
     dev = torch.device("cuda:0")
     spec = synth.c4_sets()
-    idx = synth.c4_sample(n_sample, len(spec))
-    sizes = [max(1, spec[i][0] * 20 // 150) * 150 for i in idx]
-    groups = synth.waves(sizes, wave_bytes)
-    tot = dict(windows=0, bytes=0, t_batched=0.0, t_plain=0.0, t_gen=0.0, pairs=0)
     tuned = None
-    for gi, grp in enumerate(groups):
+
+    def run_wave(set_ids):
+        nonlocal tuned
         t0 = time.time()
         parts, offs, set_reads, set_bytes, ks = [], [np.zeros(1, np.uint64)], [], [], []
         base = 0
-        from concurrent.futures import ThreadPoolExecutor
         # sets of a wave are laid out by (k, size) so that the plan's classes,
         # which group sets of one k by size, cover contiguous byte ranges
-        grp = sorted(grp, key=lambda j: (spec[idx[j]][1], -spec[idx[j]][0]))
+        set_ids = sorted(set_ids, key=lambda i: (spec[i][1], -spec[i][0]))
         with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-            gen = list(ex.map(lambda j: synth.c4_set_reads(idx[j], spec[idx[j]][0], threads=1), grp))
-        for j, (r, o) in zip(grp, gen):
-            s = idx[j]
+            gen = list(ex.map(lambda i: synth.c4_set_reads(i, spec[i][0], threads=1), set_ids))
+        for i, (r, o) in zip(set_ids, gen):
             parts.append(r)
             offs.append(o[1:] + np.uint64(base))
             base += r.size
             set_reads.append(o.size - 1)
             set_bytes.append(r.size)
-            ks.append(spec[s][1])
+            ks.append(spec[i][1])
         reads = np.concatenate(parts)
         offsets = np.concatenate(offs)
         del parts, gen
         rt = torch.from_numpy(reads).to(dev)
         ot = torch.from_numpy(offsets.view(np.int64)).to(dev)
         del reads
-        tot["t_gen"] += time.time() - t0
+        t_gen = time.time() - t0
         cap = int(sum(set_bytes))
         keys = torch.empty(cap, dtype=torch.int64, device=dev)
         cnts = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -198,10 +197,8 @@ def batched_leg(n_sample: int, wave_bytes: int, tune: bool) -> dict:
         t = time.perf_counter()
         n, _ = plan.run_into(rt, ot, keys, cnts, cap)
         torch.cuda.synchronize()
-        tot["t_batched"] += time.perf_counter() - t
-        tot["windows"] += plan.stats()["valid_windows"]
-        tot["bytes"] += cap
-        tot["pairs"] += n
+        t_batched = time.perf_counter() - t
+        windows = plan.stats()["valid_windows"]
         plan.close()
         # plain: one call per set on the same resident inputs
         st = torch.cuda.current_stream(dev).cuda_stream
@@ -216,12 +213,36 @@ def batched_leg(n_sample: int, wave_bytes: int, tune: bool) -> dict:
         for (a, b), k in zip(bounds, ks):
             kc.count_into(rt, ot[a:b + 1], k, 1, keys, cnts, cap, None, st)
         torch.cuda.synchronize()
-        tot["t_plain"] += time.perf_counter() - t
-        print("bench: batched wave %d/%d: %d sets, %.2f GB" % (gi + 1, len(groups), len(grp),
-                                                              cap / 1e9), file=sys.stderr,
-              flush=True)
+        t_plain = time.perf_counter() - t
         del rt, ot, keys, cnts
         torch.cuda.empty_cache()
+        return dict(windows=windows, bytes=cap, pairs=n, t_batched=t_batched, t_plain=t_plain,
+                    t_gen=t_gen)
+
+    idx = synth.c4_sample(n_sample, len(spec))
+    sizes = [max(1, spec[i][0] * 20 // 150) * 150 for i in idx]
+    groups = synth.waves(sizes, wave_bytes)
+    tot = dict(windows=0, bytes=0, t_batched=0.0, t_plain=0.0, t_gen=0.0, pairs=0)
+    for gi, grp in enumerate(groups):
+        r = run_wave([idx[j] for j in grp])
+        for key in tot:
+            tot[key] += r[key]
+        print("bench: batched wave %d/%d: %d sets, %.2f GB" % (gi + 1, len(groups), len(grp),
+                                                              r["bytes"] / 1e9), file=sys.stderr,
+              flush=True)
+    small = None
+    if n_small > 0:
+        pool = [i for i, (g, _) in enumerate(spec) if g <= 100_000]
+        rng = np.random.Generator(np.random.PCG64(0x5EA11))
+        pick = sorted(rng.choice(len(pool), size=min(n_small, len(pool)), replace=False).tolist())
+        r = run_wave([pool[j] for j in pick])
+        small = {"sets": len(pick), "of_sets_up_to_100kbp": len(pool), "bytes": r["bytes"],
+                 "valid_windows": r["windows"],
+                 "value": round(r["windows"] / r["t_batched"], 1),
+                 "plain_per_set_value": round(r["windows"] / r["t_plain"], 1),
+                 "speedup_vs_plain_launches": round(r["t_plain"] / r["t_batched"], 3),
+                 "ms_batched": round(r["t_batched"] * 1e3, 3),
+                 "ms_plain": round(r["t_plain"] * 1e3, 3)}
     return {
         "workload": "c4_batched_4096_sets_sample", "sets": len(idx), "of_sets": len(spec),
         "waves": len(groups), "wave_bytes": wave_bytes, "bytes": tot["bytes"],
@@ -231,8 +252,10 @@ def batched_leg(n_sample: int, wave_bytes: int, tune: bool) -> dict:
         "speedup_vs_plain_launches": round(tot["t_plain"] / tot["t_batched"], 3),
         "ms_batched": round(tot["t_batched"] * 1e3, 3), "ms_plain": round(tot["t_plain"] * 1e3, 3),
         "tuned_options": tuned,
+        "small_sets": small,
         "note": "seeded sample of the 4,096 sets (same size distribution); inputs resident; "
-                "one graph replay per wave vs one plain call per set",
+                "one graph replay per wave vs one plain call per set; small_sets: sets with "
+                "genomes up to 100 kbp, one wave",
     }
 
 
