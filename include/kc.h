@@ -246,6 +246,22 @@ int kc_pred_gradient(kc_predictor* pred, const float* x, const float* target, ui
 int kc_pred_adam_step(kc_predictor* pred, float lr, void* stream);
 void kc_pred_free(kc_predictor* pred);
 
+/* ---- Uses of a result (keys and counts as kc_count writes them; DEVICE arrays).
+ * kc_spectrum: the k-mer spectrum of a result: host_hist (max_count + 1
+ *   entries) receives in host_hist[c] the number of keys with count c for
+ *   1 <= c < max_count, in host_hist[max_count] the number with count >=
+ *   max_count; host_hist[0] = 0. max_count in [1, 2^24]. Synchronous on stream.
+ * kc_filter_min_count: copies the pairs with count >= min_count, in their
+ *   order, to out_keys / out_counts (room for n pairs; must not overlap the
+ *   inputs); *n_out receives their number. k gives the key width (1 or 2
+ *   words, as in kc_count). Synchronous on stream.
+ * Both return KC_OK, KC_E_INVAL, KC_E_NOMEM or KC_E_DEVICE. */
+int kc_spectrum(const uint32_t* counts, uint64_t n, uint32_t max_count, uint64_t* host_hist,
+                void* stream);
+int kc_filter_min_count(const uint64_t* keys, const uint32_t* counts, uint64_t n, int k,
+                        uint32_t min_count, uint64_t* out_keys, uint32_t* out_counts,
+                        uint64_t* n_out, void* stream);
+
 /* Upper bound on the number of output keys (= number of length-k windows,
  * valid or not): sum over reads of max(0, len - k + 1). host_offsets is a
  * HOST array of n_reads+1 offsets. Returns 0 for bad arguments. */

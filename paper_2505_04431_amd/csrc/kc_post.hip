@@ -1,0 +1,221 @@
+// Uses of a count result (entry points kc_spectrum and kc_filter_min_count of
+// include/kc.h): the k-mer spectrum (how many distinct keys have each count)
+// and the removal of keys below a minimum count, the two most common things
+// done with a k-mer histogram (the paper's Section II surveys counters that
+// avoid counting singletons for the same reason).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/kc.h"
+#include "kc_host.h"
+
+namespace {
+
+constexpr int kTB = 256;
+constexpr int kPer = 16;  // items per thread in the compaction
+constexpr int kTile = kTB * kPer;
+constexpr uint32_t kLdsBins = 4096;
+
+// Spectrum: bins 1..max_count-1 hold exact counts, bin max_count everything
+// at or above it. Small bin indices are counted in LDS first.
+__global__ void __launch_bounds__(kTB) k_spectrum(const uint32_t* __restrict__ counts, uint64_t n,
+                                                  uint32_t max_count,
+                                                  unsigned long long* __restrict__ hist) {
+  __shared__ uint32_t h[kLdsBins];
+  const uint32_t nl = max_count + 1 < kLdsBins ? max_count + 1 : kLdsBins;
+  for (uint32_t i = threadIdx.x; i < nl; i += kTB) h[i] = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * kTB;
+  for (uint64_t i = (uint64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += stride) {
+    const uint32_t c = counts[i];
+    const uint32_t b = c < max_count ? c : max_count;
+    if (b < nl) atomicAdd(&h[b], 1u);
+    else atomicAdd(&hist[b], 1ull);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nl; i += kTB)
+    if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+}
+
+__global__ void k_zero(unsigned long long* p, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Compaction, step 1: kept pairs per tile.
+__global__ void __launch_bounds__(kTB) k_keep_count(const uint32_t* __restrict__ counts,
+                                                    uint64_t n, uint32_t min_count,
+                                                    unsigned long long* __restrict__ tsum) {
+  __shared__ uint32_t s;
+  if (threadIdx.x == 0) s = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  uint32_t c = 0;
+  for (int j = 0; j < kPer; ++j) {
+    const uint64_t i = base + (uint64_t)j * kTB + threadIdx.x;
+    c += (i < n && counts[i] >= min_count) ? 1u : 0u;
+  }
+  atomicAdd(&s, c);
+  __syncthreads();
+  if (threadIdx.x == 0) tsum[blockIdx.x] = s;
+}
+
+// Step 2 (one block): exclusive scan of the tile sums; tsum[nt] = total.
+__global__ void __launch_bounds__(1024) k_scan_tiles(unsigned long long* __restrict__ tsum,
+                                                     uint64_t nt) {
+  __shared__ unsigned long long part[1024];
+  const uint64_t per = (nt + 1023) / 1024;
+  const uint64_t b = threadIdx.x * per, e = b + per < nt ? b + per : nt;
+  unsigned long long s = 0;
+  for (uint64_t i = b; i < e; ++i) s += tsum[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long run = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const unsigned long long x = part[t];
+      part[t] = run;
+      run += x;
+    }
+    tsum[nt] = run;
+  }
+  __syncthreads();
+  unsigned long long run = part[threadIdx.x];
+  for (uint64_t i = b; i < e; ++i) {
+    const unsigned long long x = tsum[i];
+    tsum[i] = run;
+    run += x;
+  }
+}
+
+// Step 3: each tile writes its kept pairs in order from its offset.
+__global__ void __launch_bounds__(kTB) k_keep_write(const uint64_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ counts,
+                                                    uint64_t n, int words, uint32_t min_count,
+                                                    const unsigned long long* __restrict__ tsum,
+                                                    uint64_t* __restrict__ out_keys,
+                                                    uint32_t* __restrict__ out_counts) {
+  __shared__ uint32_t wsum[kTB / 64 + 1];
+  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  unsigned long long at = tsum[blockIdx.x];
+  for (int j = 0; j < kPer; ++j) {
+    const uint64_t i = base + (uint64_t)j * kTB + threadIdx.x;
+    const bool keep = i < n && counts[i] >= min_count;
+    // rank among the kept items of this row of the tile, in index order
+    const unsigned long long m = __ballot(keep);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wsum[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t before = 0, row = 0;
+    for (int v = 0; v < kTB / 64; ++v) {
+      if (v < w) before += wsum[v];
+      row += wsum[v];
+    }
+    if (keep) {
+      const unsigned long long o = at + before + __popcll(m & ((1ull << lane) - 1));
+      out_counts[o] = counts[i];
+      if (words == 1) {
+        out_keys[o] = keys[i];
+      } else {
+        out_keys[2 * o] = keys[2 * i];
+        out_keys[2 * o + 1] = keys[2 * i + 1];
+      }
+    }
+    at += row;
+    __syncthreads();
+  }
+}
+
+struct Fail {
+  int code;
+};
+
+void chk(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    kc::set_last_error(std::string(what) + ": " + hipGetErrorString(e));
+    throw Fail{e == hipErrorOutOfMemory ? KC_E_NOMEM : KC_E_DEVICE};
+  }
+}
+
+int bad(const char* msg) {
+  kc::set_last_error(msg);
+  return KC_E_INVAL;
+}
+
+unsigned grid_of(uint64_t n, uint64_t per, unsigned cap) {
+  const uint64_t g = (n + per - 1) / per;
+  return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+extern "C" {
+
+int kc_spectrum(const uint32_t* counts, uint64_t n, uint32_t max_count, uint64_t* host_hist,
+                void* stream) {
+  kc::set_last_error("");
+  if (!host_hist) return bad("host_hist is NULL");
+  if (n && !counts) return bad("counts is NULL");
+  if (max_count < 1 || max_count > (1u << 24)) return bad("max_count must be in [1, 2^24]");
+  const hipStream_t st = (hipStream_t)stream;
+  void* d = nullptr;
+  try {
+    chk(hipMallocAsync(&d, (size_t)(max_count + 1) * 8, st), "hipMallocAsync");
+    unsigned long long* hist = (unsigned long long*)d;
+    hipLaunchKernelGGL(k_zero, dim3(grid_of(max_count + 1, 256, 1u << 20)), dim3(256), 0, st,
+                       hist, (uint64_t)max_count + 1);
+    if (n)
+      hipLaunchKernelGGL(k_spectrum, dim3(grid_of(n, (uint64_t)kTB * 16, 4096)), dim3(kTB), 0, st,
+                         counts, n, max_count, hist);
+    chk(hipGetLastError(), "spectrum launch");
+    chk(hipMemcpyAsync(host_hist, hist, (size_t)(max_count + 1) * 8, hipMemcpyDeviceToHost, st),
+        "hipMemcpyAsync");
+    chk(hipFreeAsync(d, st), "hipFreeAsync");
+    d = nullptr;
+    chk(hipStreamSynchronize(st), "hipStreamSynchronize");
+  } catch (const Fail& f) {
+    if (d) (void)hipFreeAsync(d, st);
+    return f.code;
+  }
+  return KC_OK;
+}
+
+int kc_filter_min_count(const uint64_t* keys, const uint32_t* counts, uint64_t n, int k,
+                        uint32_t min_count, uint64_t* out_keys, uint32_t* out_counts,
+                        uint64_t* n_out, void* stream) {
+  kc::set_last_error("");
+  if (!n_out) return bad("n_out is NULL");
+  *n_out = 0;
+  if (k < 1 || k > 64) return bad("k must be in [1, 64]");
+  if (n && (!keys || !counts || !out_keys || !out_counts)) return bad("NULL array");
+  if (n == 0) return KC_OK;
+  const int words = k > 32 ? 2 : 1;
+  const hipStream_t st = (hipStream_t)stream;
+  const uint64_t nt = (n + kTile - 1) / kTile;
+  void* d = nullptr;
+  try {
+    chk(hipMallocAsync(&d, (size_t)(nt + 1) * 8, st), "hipMallocAsync");
+    unsigned long long* tsum = (unsigned long long*)d;
+    hipLaunchKernelGGL(k_keep_count, dim3((unsigned)nt), dim3(kTB), 0, st, counts, n, min_count,
+                       tsum);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tsum, nt);
+    hipLaunchKernelGGL(k_keep_write, dim3((unsigned)nt), dim3(kTB), 0, st, keys, counts, n, words,
+                       min_count, tsum, out_keys, out_counts);
+    chk(hipGetLastError(), "filter launch");
+    uint64_t total = 0;
+    chk(hipMemcpyAsync(&total, tsum + nt, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    chk(hipFreeAsync(d, st), "hipFreeAsync");
+    d = nullptr;
+    chk(hipStreamSynchronize(st), "hipStreamSynchronize");
+    *n_out = total;
+  } catch (const Fail& f) {
+    if (d) (void)hipFreeAsync(d, st);
+    return f.code;
+  }
+  return KC_OK;
+}
+
+}  // extern "C"

@@ -28,7 +28,7 @@ EXPORTED_SYMBOLS = ["kc_count", "kc_count_ex", "kc_max_outputs", "kc_last_stats"
                     "kc_server_destroy", "kc_pred_create", "kc_pred_num_params",
                     "kc_pred_get_params", "kc_pred_set_params", "kc_pred_get_grads",
                     "kc_pred_forward", "kc_pred_gradient", "kc_pred_adam_step", "kc_pred_free",
-                    "kc_measure_ceilings"]
+                    "kc_measure_ceilings", "kc_spectrum", "kc_filter_min_count"]
 
 JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
@@ -172,6 +172,10 @@ def lib():
             L.kc_pred_free.argtypes = [p]
             L.kc_measure_ceilings.restype = i32
             L.kc_measure_ceilings.argtypes = [u64, p, p]
+            L.kc_spectrum.restype = i32
+            L.kc_spectrum.argtypes = [p, u64, ctypes.c_uint32, p, p]
+            L.kc_filter_min_count.restype = i32
+            L.kc_filter_min_count.argtypes = [p, p, u64, i32, ctypes.c_uint32, p, p, p, p]
             _lib = L
     return _lib
 
@@ -245,6 +249,37 @@ def count(reads, offsets, k: int, P: int = 1, opts: KcOptions | None = None, str
     counts = torch.empty(capacity, dtype=torch.int32, device=reads.device)
     n = count_into(reads, offsets, k, P, keys, counts, capacity, opts, stream)
     return keys[:n], counts[:n]
+
+
+def spectrum(counts, max_count: int = 1000, stream=None) -> np.ndarray:
+    """kc_spectrum of a count array (CUDA int32/uint32 tensor): uint64[max_count + 1]."""
+    import torch
+    _check_tensor(counts, "counts", (torch.int32, torch.uint32))
+    if stream is None:
+        stream = torch.cuda.current_stream(counts.device).cuda_stream
+    out = np.zeros(max_count + 1, dtype=np.uint64)
+    st = lib().kc_spectrum(counts.data_ptr(), counts.numel(), max_count, out.ctypes.data, stream)
+    if st != 0:
+        raise KcError(st, lib().kc_last_error().decode())
+    return out
+
+
+def filter_min_count(keys, counts, k: int, min_count: int, stream=None):
+    """kc_filter_min_count: the (keys, counts) pairs with count >= min_count."""
+    import torch
+    _check_tensor(keys, "keys", (torch.int64, torch.uint64))
+    _check_tensor(counts, "counts", (torch.int32, torch.uint32))
+    n = counts.numel()
+    ok = torch.empty_like(keys) if n else keys
+    oc = torch.empty_like(counts) if n else counts
+    if stream is None:
+        stream = torch.cuda.current_stream(counts.device).cuda_stream
+    n_out = ctypes.c_uint64(0)
+    st = lib().kc_filter_min_count(keys.data_ptr(), counts.data_ptr(), n, k, min_count,
+                                   ok.data_ptr(), oc.data_ptr(), ctypes.byref(n_out), stream)
+    if st != 0:
+        raise KcError(st, lib().kc_last_error().decode())
+    return ok[:n_out.value], oc[:n_out.value]
 
 
 def _stats_dict(s: KcStats) -> dict:
