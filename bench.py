@@ -376,6 +376,8 @@ def main() -> int:
     ap.add_argument("--served-budget-gib", type=float, default=192.0)
     ap.add_argument("--served-workers", type=int, default=4)
     ap.add_argument("--served-load", type=float, default=0.7)
+    ap.add_argument("--sort-steps", type=int, default=5,
+                    help="calls of the sort-based leaf count to time (0: skip)")
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="size of the plain copy kernel timed for the achievable HBM rate")
     args = ap.parse_args()
@@ -458,6 +460,26 @@ def main() -> int:
                 "stage_ms": {n: round(v, 4) for n, v in avg.items()},
                 "stage_gbs": {n: round(sb[n] / (avg[n] / 1e3) / 1e9, 1) for n in avg if n in sb}}
 
+    # the paper's own counting step (sort + run-length accumulate of each
+    # owner's records) on the same partitions, for comparison
+    sort_mode = None
+    if args.sort_steps > 0:
+        o1 = kc.options(timing=1, mode=1)
+        kc.count_into(rt, ot, k, P, keys, cnts, cap, o1, stream.cuda_stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        leaf1 = 0.0
+        for _ in range(args.sort_steps):
+            kc.count_into(rt, ot, k, P, keys, cnts, cap, o1, stream.cuda_stream)
+            leaf1 += kc.last_stats()["ms_stage"]["leaf_large"]
+        torch.cuda.synchronize()
+        ms1 = (time.perf_counter() - t1) * 1e3 / args.sort_steps
+        sort_mode = {"value": round(W / (ms1 / 1e3), 1), "unit": "k-mers/s",
+                     "ms_per_step": round(ms1, 4),
+                     "leaf_ms": round(leaf1 / args.sort_steps, 4),
+                     "note": "kc_options.mode = 1: each leaf's records sorted in LDS and "
+                             "run-length accumulated instead of counted in a hash table"}
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -506,6 +528,7 @@ def main() -> int:
                    "read_len": 150, "valid_windows": W, "distinct": n_out, "mode": "plain"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "sort_mode": sort_mode,
         "batched": batched,
         "served": served,
     }

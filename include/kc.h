@@ -64,7 +64,11 @@ typedef struct kc_options {
   int check;           /* 1 = run the device self-check of the output (sorted,
                           canonical, in range, sum of counts == valid windows) */
   int timing;          /* 1 = record per-stage times (kc_last_stats) */
-  int mode;            /* must be 0 (partitioned counting in LDS tables) */
+  int mode;            /* how each leaf partition is counted: 0 = LDS open-addressing
+                          table, then a sort of its distinct keys; 1 = sort of its
+                          records and run-length accumulation (Algorithm 1's Sort +
+                          Accumulate, as each owner does in Algorithm 3). Same result.
+                          The batched form takes 0 only. */
   int reserved[5];
 } kc_options;
 

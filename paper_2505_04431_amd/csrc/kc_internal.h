@@ -117,19 +117,21 @@ hipError_t launch_split_scatter(bool wide, const void* src, void* dst, const Spl
                                 const DevState* st, uint64_t max_items, const SplitBin* bins,
                                 unsigned long long* cursor, hipStream_t s);
 
-// Count each of the st->n_leaves leaves in an LDS open-addressing table, sort
-// its distinct keys, write the pairs next to it. d_out[i] = distinct keys of
-// leaf i, or kLeafOverflow (and st->overflow = 1) if its table overflowed.
-// Leaves of at most small_leaf_max() records are handled by one-wave
-// workgroups with private tables; larger ones (listed in large_list, which
-// holds max_leaves entries) by 1024-thread workgroups.
+// Count each of the st->n_leaves leaves, write its sorted pairs next to it.
+// d_out[i] = distinct keys of leaf i, or kLeafOverflow (and st->overflow = 1)
+// if it could not be counted whole. mode 0: LDS open-addressing tables, then
+// an in-LDS sort of the distinct keys; leaves of at most small_leaf_max()
+// records go to one-wave workgroups with private tables, larger ones (listed
+// in large_list, which holds max_leaves entries) to 512-thread workgroups.
+// mode 1: every non-empty leaf's records are sorted in LDS and run-length
+// accumulated (the launch_leaf_small call then only lists the leaves).
 hipError_t launch_leaf_small(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
-                             uint32_t* d_out, uint32_t* large_list, hipStream_t s);
+                             uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode = 0);
 hipError_t launch_leaf_large(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
-                             hipStream_t s);
+                             hipStream_t s, int mode = 0);
 uint64_t small_leaf_max(bool wide);
 
 // Exclusive scan of leaf counts into output offsets; st->D = total. bsum

@@ -1324,6 +1324,113 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
   }
 }
 
+// ---------------------------------------------------------------- sort-based leaf count
+
+// The paper's own way to count an owner's k-mers (Algorithm 1 Sort +
+// Accumulate, run by every owner in Algorithm 3), applied to a leaf: its
+// records are sorted in LDS and each run of equal keys becomes one pair. A
+// leaf of more records than fit is marked overflowed and cut further by key
+// (refinement); a leaf whose key range is a single key is counted without
+// sorting.
+template <typename K, int TB>
+__device__ __forceinline__ void bitonic_keys(K* keys, uint32_t n) {
+  for (uint32_t size = 2; size <= n; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < n / 2; i += TB) {
+        const uint32_t lo = (i / stride) * stride * 2 + (i % stride);
+        const uint32_t hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const K a = keys[lo], b = keys[hi];
+        if ((a > b) == asc) {
+          keys[lo] = b;
+          keys[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename K, int TB, int SMAX>
+__global__ void __launch_bounds__(TB) k_leaf_sort(int keybits, K* bufA, K* bufB,
+                                                  uint32_t* __restrict__ tmp_cnt,
+                                                  const Leaf* __restrict__ leaves,
+                                                  DevState* __restrict__ st,
+                                                  uint32_t* __restrict__ d_out,
+                                                  const uint32_t* __restrict__ list) {
+  __shared__ K sk[SMAX];
+  __shared__ uint32_t sp[SMAX + 1];  // positions of the run starts, then n
+  __shared__ uint32_t wsum[TB / 64];
+  const unsigned long long count = st->n_large;
+  unsigned long long my_records = 0, my_distinct = 0;
+  for (unsigned long long it = blockIdx.x; it < count; it += gridDim.x) {
+    const uint32_t l = list[it];
+    const Leaf lf = leaves[l];
+    const uint64_t n = lf.end - lf.begin;
+    const K* src = lf.buf ? bufB : bufA;
+    K* dst = lf.buf ? bufA : bufB;
+    if ((int)lf.bits >= keybits) {  // the leaf's range is one key
+      if (threadIdx.x == 0) {
+        dst[lf.begin] = src[lf.begin];
+        tmp_cnt[lf.begin] = (uint32_t)n;
+        if (n > 0xFFFFFFFFull) atomicOr(&st->count_overflow, 1u);
+        d_out[l] = 1;
+        my_records += n;
+        my_distinct += 1;
+      }
+      continue;
+    }
+    if (n > SMAX) {
+      if (threadIdx.x == 0) {
+        d_out[l] = kLeafOverflow;
+        atomicOr(&st->overflow, 1u);
+      }
+      continue;
+    }
+    const uint32_t m = (uint32_t)n;
+    const uint32_t n2 = next_pow2(m);
+    for (uint32_t i = threadIdx.x; i < n2; i += TB) sk[i] = i < m ? src[lf.begin + i] : ~(K)0;
+    __syncthreads();
+    bitonic_keys<K, TB>(sk, n2);
+    // run starts: thread t looks at positions [t*per, t*per + per)
+    const uint32_t per = (m + TB - 1) / TB;
+    const uint32_t b = threadIdx.x * per, e = min(m, b + per);
+    uint32_t c = 0;
+    for (uint32_t i = b; i < e; ++i) c += (i == 0 || sk[i] != sk[i - 1]) ? 1u : 0u;
+    uint32_t d = 0;
+    uint32_t at = block_exscan<TB, uint32_t>(c, wsum, &d);
+    for (uint32_t i = b; i < e; ++i)
+      if (i == 0 || sk[i] != sk[i - 1]) sp[at++] = i;
+    if (threadIdx.x == 0) sp[d] = m;
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < d; q += TB) {
+      const uint32_t i = sp[q];
+      dst[lf.begin + q] = sk[i];
+      tmp_cnt[lf.begin + q] = sp[q + 1] - i;
+    }
+    if (threadIdx.x == 0) {
+      d_out[l] = d;
+      my_records += n;
+      my_distinct += d;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && my_records) {
+    atomicAdd(&st->large_records, my_records);
+    atomicAdd(&st->large_distinct, my_distinct);
+  }
+}
+
+// Empty leaves of the sort-based count (the others are all in the list).
+__global__ void k_empty_leaves(const Leaf* __restrict__ leaves, const DevState* __restrict__ st,
+                               uint32_t* __restrict__ d_out) {
+  const unsigned long long n = st->n_leaves;
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += stride)
+    if (leaves[i].end == leaves[i].begin) d_out[i] = 0;
+}
+
 // ---------------------------------------------------------------- concat + check
 
 template <typename K>
@@ -1532,6 +1639,8 @@ constexpr unsigned kPersistentGrid = 1024;  // blocks of the persistent kernels
 constexpr int kSmallCmax64 = 1024;  // one-wave leaf kernel: slots of its private table
 constexpr int kSmallCmax128 = 512;
 constexpr unsigned kSmallGrid = 256 * 20;
+constexpr int kSortMax64 = 8192;   // records per leaf of the sort-based count
+constexpr int kSortMax128 = 4096;
 
 inline unsigned grid_for(uint64_t n, unsigned tb, unsigned cap) {
   uint64_t g = (n + tb - 1) / tb;
@@ -1682,11 +1791,16 @@ uint64_t small_leaf_max(bool wide) {
 
 hipError_t launch_leaf_small(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
-                             uint32_t* d_out, uint32_t* large_list, hipStream_t s) {
-  const uint64_t small_max = small_leaf_max(wide);
+                             uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode) {
+  const uint64_t small_max = mode == 1 ? 0 : small_leaf_max(wide);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &st->n_large, (uint64_t)1, 0ull);
   hipLaunchKernelGGL(k_classify_leaves, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s,
                      leaves, st, small_max, large_list);
+  if (mode == 1) {  // sort-based: every non-empty leaf is in the list
+    hipLaunchKernelGGL(k_empty_leaves, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s,
+                       leaves, st, d_out);
+    return hipGetLastError();
+  }
   const unsigned gsmall = persistent(max_leaves, kSmallGrid);
   if (wide)
     if (keybits <= 126)
@@ -1707,9 +1821,20 @@ hipError_t launch_leaf_small(bool wide, int keybits, void* bufA, void* bufB, uin
 hipError_t launch_leaf_large(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
-                             hipStream_t s) {
+                             hipStream_t s, int mode) {
   const uint64_t small_max = small_leaf_max(wide);
   const unsigned glarge = persistent(max_leaves, kPersistentGrid);
+  if (mode == 1) {
+    if (wide)
+      hipLaunchKernelGGL((k_leaf_sort<u128, kLeafTB, kSortMax128>), dim3(glarge), dim3(kLeafTB),
+                         0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
+                         large_list);
+    else
+      hipLaunchKernelGGL((k_leaf_sort<uint64_t, kLeafTB, kSortMax64>), dim3(glarge),
+                         dim3(kLeafTB), 0, s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt,
+                         leaves, st, d_out, large_list);
+    return hipGetLastError();
+  }
   if (wide)
     if (keybits <= 126)
       hipLaunchKernelGGL((k_leaf_count128<kLeafTB, kLeafCmax128, 4, true>), dim3(glarge),

@@ -410,11 +410,11 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
     upload_sync(&dst_state->n_leaves, &nlu, 8, st);
     hipchk(kc::launch_leaf_small(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
-                                 (uint32_t*)c.alarge.p, st),
+                                 (uint32_t*)c.alarge.p, st, q.o.mode),
            "leaf count launch");
     hipchk(kc::launch_leaf_large(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
-                                 q.slots_log2, (uint32_t*)c.alarge.p, st),
+                                 q.slots_log2, (uint32_t*)c.alarge.p, st, q.o.mode),
            "leaf count launch");
     tm.mark(ST_LEAF);
     uint32_t* hd = (uint32_t*)host_stage(c, na * 4 + 64);
@@ -514,6 +514,7 @@ struct Pipe {
   uint64_t T = 0, H = 0;
   uint64_t max_items = 0, max_leaves = 0;
   const kc::BatchSets* batch = nullptr;   // batch form (composite keys)
+  int mode = 0;                           // leaf count: 0 hash tables, 1 sort
   const int* order = nullptr;             // device, owner-major shard order
 };
 
@@ -613,12 +614,12 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
   tm.mark(ST_SPLIT);
   hipchk(kc::launch_leaf_small(p.wide, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
-                               (uint32_t*)c.large.p, st),
+                               (uint32_t*)c.large.p, st, p.mode),
          "leaf count launch");
   tm.mark(ST_LEAF_SMALL);
   hipchk(kc::launch_leaf_large(p.wide, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
-                               p.slots_log2, (uint32_t*)c.large.p, st),
+                               p.slots_log2, (uint32_t*)c.large.p, st, p.mode),
          "leaf count launch");
   tm.mark(ST_LEAF);
   hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dstate, (unsigned long long*)c.bsum.p,
@@ -676,6 +677,7 @@ Pipe plain_pipe(uint64_t n_bytes, int k, int P, const kc_options& o) {
   p.byte_begin = 0;
   p.byte_end = n_bytes;
   p.rec_bound = n_bytes;  // byte count: an upper bound of the window count
+  p.mode = o.mode;
   pipe_bounds(p);
   return p;
 }
@@ -707,7 +709,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   Call q{reads, offsets, n_reads, k, P, out_keys, out_counts, cap, {}, st, oa};
   std::memset(&q.o, 0, sizeof(q.o));
   if (opt) q.o = *opt;
-  if (q.o.mode != 0) fail(KC_E_INVAL, "mode must be 0");
+  if (q.o.mode != 0 && q.o.mode != 1) fail(KC_E_INVAL, "mode must be 0 or 1");
 
   Ctx& c = context();
   std::memset(&g_stats, 0, sizeof(g_stats));
@@ -892,7 +894,7 @@ int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_byt
   b->P = P;
   std::memset(&b->o, 0, sizeof(b->o));
   if (opt) b->o = *opt;
-  if (b->o.mode != 0) fail(KC_E_INVAL, "mode must be 0");
+  if (b->o.mode != 0) fail(KC_E_INVAL, "mode must be 0 for a batch");
   b->ks.assign(host_ks, host_ks + n_sets);
   b->set_first_read.assign(n_sets + 1, 0);
   b->set_byte_off.assign(n_sets + 1, 0);

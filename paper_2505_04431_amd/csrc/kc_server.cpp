@@ -284,7 +284,7 @@ int kc_server_create(uint64_t hbm_budget_bytes, int n_workers, const kc_options*
     *out = nullptr;
     if (hbm_budget_bytes == 0) return set_err(KC_E_INVAL, "budget must be > 0");
     if (n_workers < 1 || n_workers > 16) return set_err(KC_E_INVAL, "workers must be in [1, 16]");
-    if (opt && opt->mode != 0) return set_err(KC_E_INVAL, "mode must be 0");
+    if (opt && opt->mode != 0 && opt->mode != 1) return set_err(KC_E_INVAL, "mode must be 0 or 1");
     std::unique_ptr<kc_server> s(new kc_server());
     if (hipGetDevice(&s->device) != hipSuccess) return set_err(KC_E_DEVICE, "hipGetDevice failed");
     if (opt) s->opt = *opt;

@@ -195,3 +195,41 @@ def test_count_beyond_32_bits_is_reported():
     del rt
     kc.lib().kc_release_scratch()
     torch.cuda.empty_cache()
+
+
+# ---- sort-based leaf count (mode 1): the same results
+
+@pytest.mark.parametrize("k", [1, 5, 16, 31, 32, 33, 55, 64])
+def test_sort_mode_brute_force(k):
+    text, offs = synth.ragged_reads(7000 + k, 80, 0, 3 * k + 40, b"ACGTACGTACGTacgtNR")
+    want = brute.count_strings(brute.split_reads(text.tobytes(), offs), k)
+    keys, cnt = gpu_count(text, offs, k, P=3, check=1, mode=1)
+    assert _pairs(keys, cnt, k) == want
+
+
+@pytest.mark.parametrize("opts", [
+    dict(mode=1),
+    dict(mode=1, leaf_target=20_000, leaf_attempt=20_000),  # leaves too big to sort: refined
+    dict(mode=1, shard_bits=10, leaf_target=64, leaf_attempt=128),
+])
+def test_sort_mode_options(opts):
+    c = synth.make_config(2, frac=0.02)
+    for k in (31, 55):
+        want = oracle.count(c["reads"], c["offsets"], k)
+        assert_same(gpu_count(c["reads"], c["offsets"], k, P=7, check=1, **opts), want,
+                    "k=%d %s" % (k, opts))
+
+
+def test_sort_mode_single_key_leaves_and_full_size():
+    import paper_2505_04431_amd as kc
+    rnd, ro = synth.ragged_reads(78, 600, 100, 200)
+    reads = np.concatenate([np.full(200_030, ord("A"), np.uint8), rnd])
+    offs = np.concatenate([[0], ro + np.uint64(200_030)]).astype(np.uint64)
+    for k in (31, 55):
+        assert_same(gpu_count(reads, offs, k, check=1, mode=1), oracle.count(reads, offs, k),
+                    "frequent key k=%d" % k)
+    c = synth.make_config(2)
+    assert_same(gpu_count(c["reads"], c["offsets"], 31, P=64, check=1, mode=1),
+                oracle.count(c["reads"], c["offsets"], 31), "config 2, mode 1")
+    st = kc.last_stats()
+    assert st["distinct"] > 0
