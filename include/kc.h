@@ -259,12 +259,22 @@ void kc_pred_free(kc_predictor* pred);
  *   order, to out_keys / out_counts (room for n pairs; must not overlap the
  *   inputs); *n_out receives their number. k gives the key width (1 or 2
  *   words, as in kc_count). Synchronous on stream.
- * Both return KC_OK, KC_E_INVAL, KC_E_NOMEM or KC_E_DEVICE. */
+ * kc_merge_counts: the result of the union of two read collections from their
+ *   two results (sorted, unique keys; the count of a read collection is the
+ *   sum over any split of it): the ordered union of the keys with counts added
+ *   where a key is in both. out arrays have room for na + nb pairs and must
+ *   not overlap the inputs; *n_out receives the number of pairs. KC_E_OVERFLOW
+ *   if a sum exceeds 2^32-1. Lets inputs larger than device memory be counted
+ *   in pieces whose results are merged. Synchronous on stream.
+ * All return KC_OK, KC_E_INVAL, KC_E_NOMEM or KC_E_DEVICE (and as stated). */
 int kc_spectrum(const uint32_t* counts, uint64_t n, uint32_t max_count, uint64_t* host_hist,
                 void* stream);
 int kc_filter_min_count(const uint64_t* keys, const uint32_t* counts, uint64_t n, int k,
                         uint32_t min_count, uint64_t* out_keys, uint32_t* out_counts,
                         uint64_t* n_out, void* stream);
+int kc_merge_counts(const uint64_t* a_keys, const uint32_t* a_counts, uint64_t na,
+                    const uint64_t* b_keys, const uint32_t* b_counts, uint64_t nb, int k,
+                    uint64_t* out_keys, uint32_t* out_counts, uint64_t* n_out, void* stream);
 
 /* Upper bound on the number of output keys (= number of length-k windows,
  * valid or not): sum over reads of max(0, len - k + 1). host_offsets is a

@@ -219,3 +219,176 @@ int kc_filter_min_count(const uint64_t* keys, const uint32_t* counts, uint64_t n
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- merging two results
+
+namespace {
+
+// Key i of a result as a 128-bit value (words = 1: one uint64 per key; 2: lo, hi).
+__device__ __forceinline__ unsigned __int128 key_at(const uint64_t* keys, uint64_t i, int words) {
+  if (words == 1) return keys[i];
+  return ((unsigned __int128)keys[2 * i + 1] << 64) | keys[2 * i];
+}
+
+__device__ __forceinline__ void key_put(uint64_t* keys, uint64_t i, int words,
+                                        unsigned __int128 v) {
+  if (words == 1) {
+    keys[i] = (uint64_t)v;
+  } else {
+    keys[2 * i] = (uint64_t)v;
+    keys[2 * i + 1] = (uint64_t)(v >> 64);
+  }
+}
+
+constexpr int kMergeItems = 8;
+
+// Merge path: thread t writes merged positions [t*items, t*items + items) of
+// the ordered union of a and b (ties: a first). Its start in a is the
+// largest i with i + j = d and a[i-1] <= b[j] ... found by binary search.
+__global__ void __launch_bounds__(kTB) k_merge(const uint64_t* __restrict__ ak,
+                                               const uint32_t* __restrict__ ac, uint64_t na,
+                                               const uint64_t* __restrict__ bk,
+                                               const uint32_t* __restrict__ bc, uint64_t nb,
+                                               int words, uint64_t* __restrict__ mk,
+                                               uint32_t* __restrict__ mc) {
+  const uint64_t total = na + nb;
+  const uint64_t d = ((uint64_t)blockIdx.x * kTB + threadIdx.x) * kMergeItems;
+  if (d >= total) return;
+  // i in [max(0, d - nb), min(d, na)]: number of a's among the first d merged
+  uint64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const uint64_t i = (lo + hi + 1) >> 1;  // candidate: take i items of a
+    // valid iff a[i-1] <= b[d-i] (a first on ties), i.e. not b[d-i] < a[i-1]
+    if (d - i >= nb || !(key_at(bk, d - i, words) < key_at(ak, i - 1, words))) lo = i;
+    else hi = i - 1;
+  }
+  uint64_t i = lo, j = d - lo;
+  for (int t = 0; t < kMergeItems && d + t < total; ++t) {
+    bool take_a;
+    if (i >= na) take_a = false;
+    else if (j >= nb) take_a = true;
+    else take_a = !(key_at(bk, j, words) < key_at(ak, i, words));
+    if (take_a) {
+      key_put(mk, d + t, words, key_at(ak, i, words));
+      mc[d + t] = ac[i];
+      ++i;
+    } else {
+      key_put(mk, d + t, words, key_at(bk, j, words));
+      mc[d + t] = bc[j];
+      ++j;
+    }
+  }
+}
+
+// Dedup of the merged sequence: a key present in both inputs sits at two
+// neighbouring positions (a's first); the first keeps the summed count.
+__global__ void __launch_bounds__(kTB) k_dedup_count(const uint64_t* __restrict__ mk, uint64_t n,
+                                                     int words,
+                                                     unsigned long long* __restrict__ tsum) {
+  __shared__ uint32_t s;
+  if (threadIdx.x == 0) s = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  uint32_t c = 0;
+  for (int j = 0; j < kPer; ++j) {
+    const uint64_t i = base + (uint64_t)j * kTB + threadIdx.x;
+    c += (i < n && (i == 0 || key_at(mk, i, words) != key_at(mk, i - 1, words))) ? 1u : 0u;
+  }
+  atomicAdd(&s, c);
+  __syncthreads();
+  if (threadIdx.x == 0) tsum[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kTB) k_dedup_write(const uint64_t* __restrict__ mk,
+                                                     const uint32_t* __restrict__ mc, uint64_t n,
+                                                     int words,
+                                                     const unsigned long long* __restrict__ tsum,
+                                                     uint64_t* __restrict__ out_keys,
+                                                     uint32_t* __restrict__ out_counts,
+                                                     unsigned int* __restrict__ overflow) {
+  __shared__ uint32_t wsum[kTB / 64 + 1];
+  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  unsigned long long at = tsum[blockIdx.x];
+  for (int j = 0; j < kPer; ++j) {
+    const uint64_t i = base + (uint64_t)j * kTB + threadIdx.x;
+    bool keep = false;
+    unsigned __int128 key = 0;
+    if (i < n) {
+      key = key_at(mk, i, words);
+      keep = i == 0 || key != key_at(mk, i - 1, words);
+    }
+    const unsigned long long m = __ballot(keep);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wsum[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t before = 0, row = 0;
+    for (int v = 0; v < kTB / 64; ++v) {
+      if (v < w) before += wsum[v];
+      row += wsum[v];
+    }
+    if (keep) {
+      unsigned long long c = mc[i];
+      if (i + 1 < n && key_at(mk, i + 1, words) == key) c += mc[i + 1];
+      if (c > 0xFFFFFFFFull) atomicOr(overflow, 1u);
+      const unsigned long long o = at + before + __popcll(m & ((1ull << lane) - 1));
+      key_put(out_keys, o, words, key);
+      out_counts[o] = (uint32_t)c;
+    }
+    at += row;
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+extern "C" int kc_merge_counts(const uint64_t* a_keys, const uint32_t* a_counts, uint64_t na,
+                               const uint64_t* b_keys, const uint32_t* b_counts, uint64_t nb,
+                               int k, uint64_t* out_keys, uint32_t* out_counts, uint64_t* n_out,
+                               void* stream) {
+  kc::set_last_error("");
+  if (!n_out) return bad("n_out is NULL");
+  *n_out = 0;
+  if (k < 1 || k > 64) return bad("k must be in [1, 64]");
+  if ((na && (!a_keys || !a_counts)) || (nb && (!b_keys || !b_counts)))
+    return bad("NULL input array");
+  const uint64_t n = na + nb;
+  if (n && (!out_keys || !out_counts)) return bad("NULL output array");
+  if (n == 0) return KC_OK;
+  const int words = k > 32 ? 2 : 1;
+  const hipStream_t st = (hipStream_t)stream;
+  const uint64_t nt = (n + kTile - 1) / kTile;
+  void* d = nullptr;
+  try {
+    // merged sequence, tile sums and the overflow flag in one allocation
+    const size_t kb = n * 8 * (size_t)words, cb = n * 4, tb = (nt + 1) * 8;
+    chk(hipMallocAsync(&d, kb + cb + tb + 16, st), "hipMallocAsync");
+    uint64_t* mk = (uint64_t*)d;
+    uint32_t* mc = (uint32_t*)((char*)d + kb);
+    unsigned long long* tsum = (unsigned long long*)((char*)d + kb + cb + (8 - (cb & 7)) % 8);
+    unsigned int* ovf = (unsigned int*)(tsum + nt + 1);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (unsigned long long*)ovf, (uint64_t)1);
+    const uint64_t threads = (n + kMergeItems - 1) / kMergeItems;
+    hipLaunchKernelGGL(k_merge, dim3((unsigned)((threads + kTB - 1) / kTB)), dim3(kTB), 0, st,
+                       a_keys, a_counts, na, b_keys, b_counts, nb, words, mk, mc);
+    hipLaunchKernelGGL(k_dedup_count, dim3((unsigned)nt), dim3(kTB), 0, st, mk, n, words, tsum);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tsum, nt);
+    hipLaunchKernelGGL(k_dedup_write, dim3((unsigned)nt), dim3(kTB), 0, st, mk, mc, n, words,
+                       tsum, out_keys, out_counts, ovf);
+    chk(hipGetLastError(), "merge launch");
+    uint64_t h[2] = {0, 0};
+    chk(hipMemcpyAsync(&h[0], tsum + nt, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    chk(hipMemcpyAsync(&h[1], ovf, 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    chk(hipFreeAsync(d, st), "hipFreeAsync");
+    d = nullptr;
+    chk(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if ((uint32_t)h[1]) {
+      kc::set_last_error("a merged count exceeds 2^32-1");
+      return KC_E_OVERFLOW;
+    }
+    *n_out = h[0];
+  } catch (const Fail& f) {
+    if (d) (void)hipFreeAsync(d, st);
+    return f.code;
+  }
+  return KC_OK;
+}

@@ -28,7 +28,8 @@ EXPORTED_SYMBOLS = ["kc_count", "kc_count_ex", "kc_max_outputs", "kc_last_stats"
                     "kc_server_destroy", "kc_pred_create", "kc_pred_num_params",
                     "kc_pred_get_params", "kc_pred_set_params", "kc_pred_get_grads",
                     "kc_pred_forward", "kc_pred_gradient", "kc_pred_adam_step", "kc_pred_free",
-                    "kc_measure_ceilings", "kc_spectrum", "kc_filter_min_count"]
+                    "kc_measure_ceilings", "kc_spectrum", "kc_filter_min_count",
+                    "kc_merge_counts"]
 
 JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
@@ -176,6 +177,8 @@ def lib():
             L.kc_spectrum.argtypes = [p, u64, ctypes.c_uint32, p, p]
             L.kc_filter_min_count.restype = i32
             L.kc_filter_min_count.argtypes = [p, p, u64, i32, ctypes.c_uint32, p, p, p, p]
+            L.kc_merge_counts.restype = i32
+            L.kc_merge_counts.argtypes = [p, p, u64, p, p, u64, i32, p, p, p, p]
             _lib = L
     return _lib
 
@@ -280,6 +283,64 @@ def filter_min_count(keys, counts, k: int, min_count: int, stream=None):
     if st != 0:
         raise KcError(st, lib().kc_last_error().decode())
     return ok[:n_out.value], oc[:n_out.value]
+
+
+def merge_counts(a_keys, a_counts, b_keys, b_counts, k: int, stream=None):
+    """kc_merge_counts of two results (CUDA tensors as count() returns them)."""
+    import torch
+    for t, nm in ((a_keys, "a_keys"), (b_keys, "b_keys")):
+        _check_tensor(t, nm, (torch.int64, torch.uint64))
+    for t, nm in ((a_counts, "a_counts"), (b_counts, "b_counts")):
+        _check_tensor(t, nm, (torch.int32, torch.uint32))
+    na, nb = a_counts.numel(), b_counts.numel()
+    words = 2 if k > 32 else 1
+    if a_keys.numel() != na * words or b_keys.numel() != nb * words:
+        raise ValueError("keys must hold %d word(s) per count" % words)
+    dev = a_counts.device
+    n = max(1, na + nb)
+    ok = torch.empty((n, 2) if words == 2 else (n,), dtype=torch.int64, device=dev)
+    oc = torch.empty(n, dtype=torch.int32, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    n_out = ctypes.c_uint64(0)
+    st = lib().kc_merge_counts(a_keys.data_ptr(), a_counts.data_ptr(), na, b_keys.data_ptr(),
+                               b_counts.data_ptr(), nb, k, ok.data_ptr(), oc.data_ptr(),
+                               ctypes.byref(n_out), stream)
+    if st != 0:
+        raise KcError(st, lib().kc_last_error().decode())
+    return ok[:n_out.value], oc[:n_out.value]
+
+
+def count_chunked(host_reads, host_offsets, k: int, P: int = 1, chunk_bytes: int = 1 << 30,
+                  opts: KcOptions | None = None):
+    """Count reads held in host memory in pieces of about chunk_bytes: each
+    piece is copied to the device and counted, and the results are merged
+    (kc_merge_counts), so the input may exceed device memory (the result must
+    fit). host_reads: uint8 numpy array; host_offsets: uint64 numpy array of
+    n_reads + 1 offsets. Returns (keys, counts) on the current device."""
+    import torch
+    offs = np.ascontiguousarray(host_offsets, dtype=np.uint64)
+    n_reads = offs.size - 1
+    dev = torch.device("cuda", torch.cuda.current_device())
+    words = 2 if k > 32 else 1
+    keys = torch.empty((0, 2) if words == 2 else (0,), dtype=torch.int64, device=dev)
+    counts = torch.empty(0, dtype=torch.int32, device=dev)
+    r = 0
+    while r < n_reads:
+        # reads [r, e): at least one read, then as many as fit in chunk_bytes
+        limit = int(offs[r]) + max(1, int(chunk_bytes))
+        e = int(np.searchsorted(offs, np.uint64(limit), side="right")) - 1
+        e = min(n_reads, max(e, r + 1))
+        b0, b1 = int(offs[r]), int(offs[e])
+        rt = torch.from_numpy(np.ascontiguousarray(host_reads[b0:b1])).to(dev)
+        if rt.numel() == 0:
+            rt = torch.zeros(1, dtype=torch.uint8, device=dev)
+        ot = torch.from_numpy((offs[r:e + 1] - np.uint64(b0)).view(np.int64)).to(dev)
+        pk, pc = count(rt, ot, k, P, opts=opts)
+        del rt, ot
+        keys, counts = merge_counts(keys, counts, pk, pc, k) if counts.numel() else (pk, pc)
+        r = e
+    return keys, counts
 
 
 def _stats_dict(s: KcStats) -> dict:

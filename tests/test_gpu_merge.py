@@ -1,0 +1,157 @@
+"""Merging two count results (kc_merge_counts) and counting in pieces
+(count_chunked). The defining property: the count of a read collection is the
+merge of the counts of any split of it, checked against the oracle's count of
+the whole collection; the merge itself is also checked against a numpy union
+of random sorted results (overlapping, disjoint, empty, 64- and 128-bit keys)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2505_04431_amd as kc
+import synth
+from gpu_util import assert_same, device, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch_keys(keys):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(keys).view(np.int64)).to(device())
+
+
+def _torch_counts(c):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(c, dtype=np.uint32).view(np.int32)).to(device())
+
+
+def _host(keys, counts):
+    return keys.cpu().numpy().view(np.uint64), counts.cpu().numpy().view(np.uint32)
+
+
+def _union(ak, ac, bk, bc):
+    """Ordered union with counts added (numpy; 128-bit keys as (lo, hi) rows)."""
+    keys = np.concatenate([ak, bk])
+    cnt = np.concatenate([ac, bc]).astype(np.uint64)
+    if keys.ndim == 2:
+        order = np.lexsort((keys[:, 0], keys[:, 1]))
+        keys = keys[order]
+        first = np.ones(len(keys), bool)
+        first[1:] = (keys[1:] != keys[:-1]).any(axis=1)
+    else:
+        order = np.argsort(keys, kind="stable")
+        keys = keys[order]
+        first = np.ones(len(keys), bool)
+        first[1:] = keys[1:] != keys[:-1]
+    cnt = cnt[order]
+    grp = np.cumsum(first) - 1
+    sums = np.zeros(int(first.sum()), np.uint64)
+    np.add.at(sums, grp, cnt)
+    return keys[first], sums
+
+
+def _random_result(rng, n, words, universe):
+    lo = np.unique(rng.integers(0, universe, size=n, dtype=np.uint64))
+    if words == 2:
+        # high words from a small set so that equal high words with different
+        # low words (the 128-bit comparison's second word) are common
+        hi = rng.integers(0, 4, size=lo.size, dtype=np.uint64)
+        keys = np.stack([lo, hi], axis=1)
+        keys = keys[np.lexsort((keys[:, 0], keys[:, 1]))]
+        keep = np.ones(len(keys), bool)
+        keep[1:] = (keys[1:] != keys[:-1]).any(axis=1)
+        keys = np.ascontiguousarray(keys[keep])
+    else:
+        keys = lo
+    counts = rng.integers(1, 1 << 20, size=len(keys), dtype=np.uint64).astype(np.uint32)
+    return keys, counts
+
+
+@pytest.mark.parametrize("k", [31, 55])
+@pytest.mark.parametrize("na,nb,universe", [
+    (0, 0, 10), (0, 1000, 1 << 20), (3000, 0, 1 << 20), (1, 1, 2),
+    (50_000, 70_000, 1 << 17),          # heavy overlap
+    (40_000, 40_000, 1 << 62),          # almost disjoint
+    (1_500_000, 900_000, 1 << 22),      # many tiles, ragged tail
+])
+def test_merge_matches_union(k, na, nb, universe):
+    rng = np.random.default_rng(na * 7 + nb + k)
+    words = 2 if k > 32 else 1
+    ak, ac = _random_result(rng, na, words, universe)
+    bk, bc = _random_result(rng, nb, words, universe)
+    if words == 2:
+        ak = ak.reshape(-1, 2)
+        bk = bk.reshape(-1, 2)
+    mk, mc = kc.merge_counts(_torch_keys(ak), _torch_counts(ac), _torch_keys(bk),
+                             _torch_counts(bc), k)
+    wk, wc = _union(ak, ac, bk, bc)
+    assert_same(_host(mk, mc), (wk, wc.astype(np.uint32)), "merge na=%d nb=%d" % (na, nb))
+
+
+def test_merge_interleaved_and_identical():
+    rng = np.random.default_rng(3)
+    keys = np.sort(rng.choice(1 << 40, size=20_000, replace=False).astype(np.uint64))
+    c = np.ones(keys.size, np.uint32)
+    # identical inputs: every key doubles
+    mk, mc = kc.merge_counts(_torch_keys(keys), _torch_counts(c), _torch_keys(keys),
+                             _torch_counts(c), 31)
+    assert_same(_host(mk, mc), (keys, 2 * c), "identical")
+    # strictly alternating inputs: nothing merges
+    a, b = keys[0::2], keys[1::2]
+    mk, mc = kc.merge_counts(_torch_keys(a), _torch_counts(c[0::2]), _torch_keys(b),
+                             _torch_counts(c[1::2]), 31)
+    assert_same(_host(mk, mc), (keys, c), "alternating")
+
+
+def test_merge_count_limit():
+    k1 = np.array([5, 9], np.uint64)
+    ok_c = np.array([0xFFFFFFFE, 7], np.uint32)
+    mk, mc = kc.merge_counts(_torch_keys(k1), _torch_counts(ok_c), _torch_keys(k1[:1]),
+                             _torch_counts(np.array([1], np.uint32)), 31)
+    assert_same(_host(mk, mc), (k1, np.array([0xFFFFFFFF, 7], np.uint32)), "at the limit")
+    with pytest.raises(kc.KcError) as e:
+        kc.merge_counts(_torch_keys(k1), _torch_counts(ok_c), _torch_keys(k1[:1]),
+                        _torch_counts(np.array([2], np.uint32)), 31)
+    assert kc.STATUS[e.value.status] == "KC_E_OVERFLOW"
+
+
+@pytest.mark.parametrize("k", [21, 31, 55, 64])
+def test_merge_of_split_equals_count_of_whole(k):
+    """count(A u B) = merge(count(A), count(B)), the oracle counting A u B."""
+    c = synth.make_config(2, frac=0.03)
+    reads, offs = c["reads"], c["offsets"]
+    n = offs.size - 1
+    cut = n // 3
+    parts = []
+    for r0, r1 in ((0, cut), (cut, n)):
+        b0, b1 = int(offs[r0]), int(offs[r1])
+        rt, ot = to_device(reads[b0:b1], offs[r0:r1 + 1] - np.uint64(b0))
+        parts.append(kc.count(rt, ot, k, P=4))
+    mk, mc = kc.merge_counts(parts[0][0], parts[0][1], parts[1][0], parts[1][1], k)
+    assert_same(_host(mk, mc), oracle.count(reads, offs, k), "k=%d" % k)
+
+
+@pytest.mark.parametrize("k,chunk_bytes", [(31, 1 << 20), (55, 3 << 20), (31, 1 << 40)])
+def test_count_chunked(k, chunk_bytes):
+    c = synth.make_config(2, frac=0.04)
+    keys, cnts = kc.count_chunked(c["reads"], c["offsets"], k, P=8, chunk_bytes=chunk_bytes)
+    assert_same(_host(keys, cnts), oracle.count(c["reads"], c["offsets"], k),
+                "chunk %d" % chunk_bytes)
+
+
+def test_count_chunked_one_read_per_piece():
+    g = synth.genome(11, 5000, [])
+    reads, offs = synth.reads(g, 40, 120, err_rate=0.01, n_rate=0.01, seed=5)
+    keys, cnts = kc.count_chunked(reads, offs, 25, P=1, chunk_bytes=1)
+    assert_same(_host(keys, cnts), oracle.count(reads, offs, 25), "one read per piece")
+
+
+def test_merge_errors():
+    import torch
+    e = torch.empty(0, dtype=torch.int32, device=device())
+    ek = torch.empty(0, dtype=torch.int64, device=device())
+    mk, mc = kc.merge_counts(ek, e, ek, e, 31)
+    assert mk.numel() == 0 and mc.numel() == 0
+    with pytest.raises(kc.KcError):
+        kc.merge_counts(ek, e, ek, e, 0)
+    with pytest.raises(kc.KcError):
+        kc.merge_counts(ek, e, ek, e, 65)
