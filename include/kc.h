@@ -276,6 +276,35 @@ int kc_merge_counts(const uint64_t* a_keys, const uint32_t* a_counts, uint64_t n
                     const uint64_t* b_keys, const uint32_t* b_counts, uint64_t nb, int k,
                     uint64_t* out_keys, uint32_t* out_counts, uint64_t* n_out, void* stream);
 
+/* Text formats of kc_parse_fastx. */
+enum { KC_FASTX_AUTO = 0, KC_FASTQ = 1, KC_FASTA = 2 };
+
+/* kc_parse_fastx: the reads of a FASTQ or FASTA text held in device memory, in
+ * the form kc_count takes (the paper counts k-mers of reads; it leaves reading
+ * them from files out of its measurements, Section VI).
+ *   text, n_bytes: the file's bytes as they are, on the device.
+ *   format: KC_FASTQ (records of exactly four lines: '@' name, sequence, '+'
+ *     [name], quality), KC_FASTA ('>' header line, then any number of
+ *     sequence lines, concatenated), or KC_FASTX_AUTO (FASTQ if the first
+ *     byte that is not CR/LF is '@', FASTA if it is '>'); *format_out (may be
+ *     NULL) receives the format used.
+ *   Line ends at the start and end of the text are ignored; CR bytes are
+ *   dropped from sequence lines (CRLF files); every other sequence byte is
+ *   kept as it is (kc_count treats bytes other than ACGT/acgt as breaks).
+ *   out_reads (room for reads_capacity bytes; n_bytes always suffices) gets the
+ *   sequences concatenated; out_offsets (room for max_records + 1 entries)
+ *   gets the CSR offsets, out_offsets[0] = 0; *n_records and *n_bases get
+ *   their numbers.
+ * Returns KC_E_CAPACITY with *n_records (and *n_bases, once known) set when
+ * the outputs are too small, nothing written to them; KC_E_INVAL for a FASTQ
+ * text whose line count is not a multiple of four or whose header / separator
+ * lines do not start with '@' / '+' (kc_last_error names the line), or a FASTA
+ * text not starting with '>'. Synchronous on stream; uses a small device
+ * allocation on the stream (stream-ordered). */
+int kc_parse_fastx(const uint8_t* text, uint64_t n_bytes, int format, uint8_t* out_reads,
+                   uint64_t reads_capacity, uint64_t* out_offsets, uint64_t max_records,
+                   uint64_t* n_records, uint64_t* n_bases, int* format_out, void* stream);
+
 /* Upper bound on the number of output keys (= number of length-k windows,
  * valid or not): sum over reads of max(0, len - k + 1). host_offsets is a
  * HOST array of n_reads+1 offsets. Returns 0 for bad arguments. */

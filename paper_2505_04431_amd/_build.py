@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libkc.so")
-SOURCES = ["kc_kernels.hip", "kc_runtime.cpp", "kc_server.cpp", "kc_pred.hip", "kc_ceiling.hip", "kc_post.hip"]
+SOURCES = ["kc_kernels.hip", "kc_runtime.cpp", "kc_server.cpp", "kc_pred.hip", "kc_ceiling.hip", "kc_post.hip",
+           "kc_parse.hip"]
 HEADERS = ["kc_internal.h", "kc_host.h", "kc_sched.h", os.path.join("..", "..", "include", "kc.h")]
 ARCH = os.environ.get("KC_OFFLOAD_ARCH", "gfx950")
 

@@ -29,7 +29,7 @@ EXPORTED_SYMBOLS = ["kc_count", "kc_count_ex", "kc_max_outputs", "kc_last_stats"
                     "kc_pred_get_params", "kc_pred_set_params", "kc_pred_get_grads",
                     "kc_pred_forward", "kc_pred_gradient", "kc_pred_adam_step", "kc_pred_free",
                     "kc_measure_ceilings", "kc_spectrum", "kc_filter_min_count",
-                    "kc_merge_counts"]
+                    "kc_merge_counts", "kc_parse_fastx"]
 
 JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
@@ -179,6 +179,8 @@ def lib():
             L.kc_filter_min_count.argtypes = [p, p, u64, i32, ctypes.c_uint32, p, p, p, p]
             L.kc_merge_counts.restype = i32
             L.kc_merge_counts.argtypes = [p, p, u64, p, p, u64, i32, p, p, p, p]
+            L.kc_parse_fastx.restype = i32
+            L.kc_parse_fastx.argtypes = [p, u64, i32, p, u64, p, u64, p, p, p, p]
             _lib = L
     return _lib
 
@@ -309,6 +311,35 @@ def merge_counts(a_keys, a_counts, b_keys, b_counts, k: int, stream=None):
     if st != 0:
         raise KcError(st, lib().kc_last_error().decode())
     return ok[:n_out.value], oc[:n_out.value]
+
+
+FASTX_AUTO, FASTQ, FASTA = 0, 1, 2
+
+
+def parse_fastx(text, fmt: int = FASTX_AUTO, stream=None):
+    """kc_parse_fastx of a FASTQ / FASTA text in a CUDA uint8 tensor.
+    Returns (reads uint8, offsets int64, format) on the text's device, ready
+    for count()."""
+    import torch
+    _check_tensor(text, "text", (torch.uint8,))
+    dev = text.device
+    n = text.numel()
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    reads = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
+    cap = n // 64 + 16
+    while True:
+        offs = torch.empty(cap + 1, dtype=torch.int64, device=dev)
+        nr, nbase, fo = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_int(fmt)
+        st = lib().kc_parse_fastx(text.data_ptr() if n else None, n, fmt, reads.data_ptr(), n,
+                                  offs.data_ptr(), cap, ctypes.byref(nr), ctypes.byref(nbase),
+                                  ctypes.byref(fo), stream)
+        if st == -3 and nr.value > cap:
+            cap = nr.value
+            continue
+        if st != 0:
+            raise KcError(st, lib().kc_last_error().decode())
+        return reads[:nbase.value], offs[:nr.value + 1], fo.value
 
 
 def count_chunked(host_reads, host_offsets, k: int, P: int = 1, chunk_bytes: int = 1 << 30,

@@ -118,3 +118,45 @@ def ragged_reads(seed: int, n_reads: int, min_len: int, max_len: int,
 
 from .configs import (CONFIGS, c4_sample, c4_set_reads, c4_sets, c5_job_reads,  # noqa: E402,F401
                       c5_jobs, c5_sample, family_layout, make_config, waves)
+
+
+def to_fastq(reads_arr: np.ndarray, offsets: np.ndarray, seed: int = 1, crlf: bool = False,
+             plus_name: bool = False, trailing: bytes = b"\n") -> bytes:
+    """FASTQ text of the given reads: four lines per record (@name, sequence,
+    +[name], quality). Qualities are random Phred+33 characters '!'..'J', so
+    they include 'A', 'C' and 'G' and a parser must tell the lines apart by
+    position, not content."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nl = b"\r\n" if crlf else b"\n"
+    offs = np.asarray(offsets, dtype=np.uint64)
+    n = offs.size - 1
+    qual = rng.integers(33, 75, size=int(offs[-1] - offs[0]), dtype=np.uint8).tobytes()
+    data = np.asarray(reads_arr, dtype=np.uint8).tobytes()
+    b0 = int(offs[0])
+    parts = []
+    for i in range(n):
+        s, e = int(offs[i]), int(offs[i + 1])
+        name = b"r%d len=%d" % (i, e - s)
+        parts += [b"@", name, nl, data[s:e], nl, b"+", name if plus_name else b"", nl,
+                  qual[s - b0:e - b0], nl]
+    text = b"".join(parts)
+    return text[:-len(nl)] + trailing if n else trailing
+
+
+def to_fasta(reads_arr: np.ndarray, offsets: np.ndarray, width: int = 60, crlf: bool = False,
+             trailing: bytes = b"\n") -> bytes:
+    """FASTA text of the given reads: a '>' header line per record, the sequence
+    wrapped at ``width`` bases per line (width 0: one line)."""
+    nl = b"\r\n" if crlf else b"\n"
+    offs = np.asarray(offsets, dtype=np.uint64)
+    n = offs.size - 1
+    data = np.asarray(reads_arr, dtype=np.uint8).tobytes()
+    parts = []
+    for i in range(n):
+        s, e = int(offs[i]), int(offs[i + 1])
+        parts += [b">seq%d some description" % i, nl]
+        w = width if width > 0 else max(1, e - s)
+        for p in range(s, e, w):
+            parts += [data[p:min(e, p + w)], nl]
+    text = b"".join(parts)
+    return text[:-len(nl)] + trailing if n else trailing
