@@ -378,6 +378,9 @@ def main() -> int:
     ap.add_argument("--served-load", type=float, default=0.7)
     ap.add_argument("--sort-steps", type=int, default=5,
                     help="calls of the sort-based leaf count to time (0: skip)")
+    ap.add_argument("--fastq-steps", type=int, default=5,
+                    help="calls of the FASTQ parser on the workload's reads as FASTQ text "
+                         "(0: skip)")
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="size of the plain copy kernel timed for the achievable HBM rate")
     args = ap.parse_args()
@@ -480,6 +483,34 @@ def main() -> int:
                      "note": "kc_options.mode = 1: each leaf's records sorted in LDS and "
                              "run-length accumulated instead of counted in a hash table"}
 
+    # the same reads as FASTQ text on the device: parse, then count the parsed reads
+    fastq = None
+    if args.fastq_steps > 0:
+        text = synth.to_fastq(reads, offs, seed=1)
+        tt = torch.frombuffer(bytearray(text), dtype=torch.uint8).to(dev)
+        del text
+        pr, po, _ = kc.parse_fastx(tt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.fastq_steps):
+            pr, po, _ = kc.parse_fastx(tt)
+        torch.cuda.synchronize()
+        ms_p = (time.perf_counter() - t1) * 1e3 / args.fastq_steps
+        ok = pr.numel() == reads.size and po.numel() == offs.size
+        t1 = time.perf_counter()
+        for _ in range(args.fastq_steps):
+            pr, po, _ = kc.parse_fastx(tt)
+            kc.count_into(pr, po, k, P, keys, cnts, cap, None, stream.cuda_stream)
+        torch.cuda.synchronize()
+        ms_pc = (time.perf_counter() - t1) * 1e3 / args.fastq_steps
+        fastq = {"text_bytes": tt.numel(), "records": po.numel() - 1, "parsed_whole": ok,
+                 "parse_ms": round(ms_p, 4), "parse_gbs": round(tt.numel() / (ms_p / 1e3) / 1e9, 1),
+                 "parse_and_count_ms": round(ms_pc, 4),
+                 "from_text_value": round(W / (ms_pc / 1e3), 1), "unit": "k-mers/s",
+                 "note": "kc_parse_fastx on the FASTQ text of the same reads (random "
+                         "qualities), then kc_count on its output"}
+        del tt, pr, po
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -529,6 +560,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sort_mode": sort_mode,
+        "fastq": fastq,
         "batched": batched,
         "served": served,
     }
