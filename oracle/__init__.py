@@ -50,11 +50,11 @@ def lib():
             L.oracle_valid_windows.restype = u64
             L.oracle_valid_windows.argtypes = [p, p, u64, i32]
             L.oracle_count_sort.restype = i32
-            L.oracle_count_sort.argtypes = [p, p, u64, i32, i32, p, p, p, u64, p]
+            L.oracle_count_sort.argtypes = [p, p, u64, i32, i32, p, p, u64, p]
             L.oracle_count_map.restype = i32
-            L.oracle_count_map.argtypes = [p, p, u64, i32, p, p, p, u64, p]
+            L.oracle_count_map.argtypes = [p, p, u64, i32, p, p, u64, p]
             L.oracle_count_selected.restype = i32
-            L.oracle_count_selected.argtypes = [p, p, u64, i32, i32, p, p, u64, p]
+            L.oracle_count_selected.argtypes = [p, p, u64, i32, i32, p, u64, p]
             _lib = L
     return _lib
 
@@ -82,54 +82,54 @@ def valid_windows(reads, offsets, k: int) -> int:
     return int(lib().oracle_valid_windows(_p(reads), _p(offsets), offsets.size - 1, k))
 
 
-def _result(lo, hi, cnt, n, k):
-    lo, cnt = lo[:n].copy(), cnt[:n].copy()
-    if k > 32:
-        return np.stack([lo, hi[:n].copy()], axis=1), cnt
-    return lo, cnt
+def key_words(k: int) -> int:
+    """64-bit words per key: 1 (k <= 32), 2 (k <= 64), 4 (k <= 128)."""
+    return 1 if k <= 32 else (2 if k <= 64 else 4)
 
 
 def count(reads, offsets, k: int, threads: int | None = None, method: str = "sort"):
     """Sorted canonical (k-mer, count) pairs.
 
-    Returns (keys, counts): keys uint64[D] for k <= 32, uint64[D, 2] as (lo, hi)
-    for k > 32; counts uint32[D].
+    Returns (keys, counts): keys uint64[D] for k <= 32, uint64[D, w] with the
+    w = 2 (k <= 64) or 4 (k <= 128) words of a key least significant first;
+    counts uint32[D].
     """
     reads, offsets = _prep(reads, offsets)
     n = offsets.size - 1
+    words = key_words(k) if 1 <= k <= 128 else 1
     cap = max(1, max_windows(offsets, k))
-    lo = np.empty(cap, dtype=np.uint64)
-    hi = np.empty(cap, dtype=np.uint64)
+    keys = np.empty(cap * words, dtype=np.uint64)
     cnt = np.empty(cap, dtype=np.uint32)
     n_out = np.zeros(1, dtype=np.uint64)
     if threads is None:
         threads = min(16, os.cpu_count() or 1)
     if method == "sort":
-        rc = lib().oracle_count_sort(_p(reads), _p(offsets), n, k, threads, _p(lo), _p(hi),
-                                     _p(cnt), cap, _p(n_out))
+        rc = lib().oracle_count_sort(_p(reads), _p(offsets), n, k, threads, _p(keys), _p(cnt),
+                                     cap, _p(n_out))
     elif method == "map":
-        rc = lib().oracle_count_map(_p(reads), _p(offsets), n, k, _p(lo), _p(hi), _p(cnt), cap,
+        rc = lib().oracle_count_map(_p(reads), _p(offsets), n, k, _p(keys), _p(cnt), cap,
                                     _p(n_out))
     else:
         raise ValueError(method)
     if rc != 0:
         raise RuntimeError("oracle error %d" % rc)
-    return _result(lo, hi, cnt, int(n_out[0]), k)
+    d = int(n_out[0])
+    keys = keys[:d * words].copy()
+    return (keys.reshape(d, words) if words > 1 else keys), cnt[:d].copy()
 
 
 def count_selected(reads, offsets, k: int, keys, threads: int | None = None):
-    """Count only the given canonical keys (uint64[m] or uint64[m, 2]). Returns uint64[m]."""
+    """Count only the given canonical keys (uint64[m] or uint64[m, w] as count()
+    returns them). Returns uint64[m]."""
     reads, offsets = _prep(reads, offsets)
-    keys = np.asarray(keys, dtype=np.uint64)
-    if keys.ndim == 2:
-        lo, hi = np.ascontiguousarray(keys[:, 0]), np.ascontiguousarray(keys[:, 1])
-    else:
-        lo, hi = np.ascontiguousarray(keys), None
-    out = np.zeros(lo.shape[0], dtype=np.uint64)
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    m = keys.shape[0]
+    assert keys.size == m * key_words(k), "keys must hold %d word(s) each" % key_words(k)
+    out = np.zeros(m, dtype=np.uint64)
     if threads is None:
         threads = min(16, os.cpu_count() or 1)
     rc = lib().oracle_count_selected(_p(reads), _p(offsets), offsets.size - 1, k, threads,
-                                     _p(lo), _p(hi), lo.shape[0], _p(out))
+                                     _p(keys) if m else None, m, _p(out))
     if rc != 0:
         raise RuntimeError("oracle error %d" % rc)
     return out

@@ -19,8 +19,10 @@
 //     form min(kmer, rc) as an unsigned integer.
 //   * All keys are appended to T, T is sorted, and Accumulate sweeps the sorted
 //     T into (k-mer, count) pairs in ascending key order (Algorithm 1).
-// Keys are held as unsigned __int128 for every k in [1, 64]. Counts are summed
-// in 64 bits and reported as uint32 (an error is returned above 2^32-1).
+// Keys are held as unsigned __int128 for k in [1, 64] and as a pair of them
+// (U256 below) for k in [65, 128]; they are written out as 1 (k <= 32), 2
+// (k <= 64) or 4 (k <= 128) little-endian 64-bit words. Counts are summed in
+// 64 bits and reported as uint32 (an error is returned above 2^32-1).
 //
 // Multi-threading: T threads each run the steps above on a contiguous range of
 // reads; the per-thread sorted (k-mer, count) lists are merged with a k-way
@@ -48,6 +50,44 @@ typedef unsigned __int128 u128;
 
 namespace {
 
+// 256-bit unsigned integer for k-mers of more than 64 bases: only the
+// operations the counting steps use (shifts by 0..255, OR, AND, order).
+struct U256 {
+  u128 lo = 0, hi = 0;
+  U256() {}
+  explicit U256(u128 x) : lo(x), hi(0) {}
+  U256(u128 l, u128 h) : lo(l), hi(h) {}
+  U256 operator<<(int s) const {
+    if (s == 0) return *this;
+    if (s >= 128) return U256(0, lo << (s - 128));
+    return U256(lo << s, (hi << s) | (lo >> (128 - s)));
+  }
+  U256 operator>>(int s) const {
+    if (s == 0) return *this;
+    if (s >= 128) return U256(hi >> (s - 128), 0);
+    return U256((lo >> s) | (hi << (128 - s)), hi >> s);
+  }
+  U256 operator|(const U256& o) const { return U256(lo | o.lo, hi | o.hi); }
+  U256 operator&(const U256& o) const { return U256(lo & o.lo, hi & o.hi); }
+  bool operator<(const U256& o) const { return hi != o.hi ? hi < o.hi : lo < o.lo; }
+  bool operator==(const U256& o) const { return hi == o.hi && lo == o.lo; }
+  bool operator!=(const U256& o) const { return !(*this == o); }
+};
+
+inline int key_words(int k) { return k <= 32 ? 1 : (k <= 64 ? 2 : 4); }
+
+inline uint64_t word_of(const u128& x, int i) { return i < 2 ? (uint64_t)(x >> (64 * i)) : 0; }
+inline uint64_t word_of(const U256& x, int i) {
+  return i < 2 ? (uint64_t)(x.lo >> (64 * i)) : (uint64_t)(x.hi >> (64 * (i - 2)));
+}
+template <typename K> K key_from_words(const uint64_t* w, int words);
+template <> u128 key_from_words<u128>(const uint64_t* w, int words) {
+  return (u128)w[0] | (words > 1 ? (u128)w[1] << 64 : (u128)0);
+}
+template <> U256 key_from_words<U256>(const uint64_t* w, int words) {
+  return U256((u128)w[0] | ((u128)w[1] << 64), (u128)w[2] | ((u128)w[3] << 64));
+}
+
 // Encode (Algorithm 1): 2-bit code of a base, -1 for a byte that is not a base.
 inline int Encode(uint8_t c) {
   switch (c) {
@@ -59,20 +99,28 @@ inline int Encode(uint8_t c) {
   }
 }
 
-inline u128 kmer_mask(int k) { return k == 64 ? ~(u128)0 : (((u128)1 << (2 * k)) - 1); }
+// 4^k - 1: the low 2k bits set.
+inline u128 mask_bits128(int bits) { return bits >= 128 ? ~(u128)0 : (((u128)1 << bits) - 1); }
+template <typename K> K kmer_mask(int k);
+template <> u128 kmer_mask<u128>(int k) { return mask_bits128(2 * k); }
+template <> U256 kmer_mask<U256>(int k) {
+  return 2 * k <= 128 ? U256(mask_bits128(2 * k), 0) : U256(~(u128)0, mask_bits128(2 * k - 128));
+}
 
 // GetFirstKmer (Algorithm 1): the first k bases of s, first base most significant.
-inline u128 GetFirstKmer(const uint8_t* s, int k) {
-  u128 kmer = 0;
-  for (int i = 0; i < k; ++i) kmer = (kmer << 2) | (u128)Encode(s[i]);
+template <typename K>
+K GetFirstKmer(const uint8_t* s, int k) {
+  K kmer(0);
+  for (int i = 0; i < k; ++i) kmer = (kmer << 2) | K((u128)Encode(s[i]));
   return kmer;
 }
 
 // Reverse complement of the first k bases of s, built directly from its definition:
 // base j of the window contributes (3 - x_j) * 4^j.
-inline u128 FirstRevComp(const uint8_t* s, int k) {
-  u128 rc = 0;
-  for (int j = 0; j < k; ++j) rc |= (u128)(3 - Encode(s[j])) << (2 * j);
+template <typename K>
+K FirstRevComp(const uint8_t* s, int k) {
+  K rc(0);
+  for (int j = 0; j < k; ++j) rc = rc | (K((u128)(3 - Encode(s[j]))) << (2 * j));
   return rc;
 }
 
@@ -80,8 +128,9 @@ inline u128 FirstRevComp(const uint8_t* s, int k) {
 // A read is cut into maximal runs of valid bases; each run of length >= k is
 // processed as Algorithm 1 processes a read: GetFirstKmer, then one rolling
 // update per further base.
-void ParseRead(const uint8_t* R, uint64_t m, int k, const std::function<void(u128)>& add) {
-  const u128 mask = kmer_mask(k);
+template <typename K>
+void ParseRead(const uint8_t* R, uint64_t m, int k, const std::function<void(const K&)>& add) {
+  const K mask = kmer_mask<K>(k);
   uint64_t i = 0;
   while (i < m) {
     while (i < m && Encode(R[i]) < 0) ++i;  // skip invalid bytes
@@ -90,23 +139,25 @@ void ParseRead(const uint8_t* R, uint64_t m, int k, const std::function<void(u12
     uint64_t len = i - a;  // run [a, i) of valid bases
     if (len < (uint64_t)k) continue;
     const uint8_t* s = R + a;
-    u128 kmer = GetFirstKmer(s, k);
-    u128 rc = FirstRevComp(s, k);
+    K kmer = GetFirstKmer<K>(s, k);
+    K rc = FirstRevComp<K>(s, k);
     add(kmer < rc ? kmer : rc);
     for (uint64_t j = k; j < len; ++j) {
-      u128 x = (u128)Encode(s[j]);
-      kmer = ((kmer << 2) | x) & mask;
-      rc = (rc >> 2) | ((3 - x) << (2 * (k - 1)));
+      const u128 x = (u128)Encode(s[j]);
+      kmer = ((kmer << 2) | K(x)) & mask;
+      rc = (rc >> 2) | (K(3 - x) << (2 * (k - 1)));
       add(kmer < rc ? kmer : rc);
     }
   }
 }
 
-typedef std::vector<std::pair<u128, uint64_t>> Counts;
+template <typename K>
+using Counts = std::vector<std::pair<K, uint64_t>>;
 
 // Accumulate (Algorithm 1): sweep a sorted array, emit (k-mer, count).
-Counts Accumulate(const std::vector<u128>& T) {
-  Counts C;
+template <typename K>
+Counts<K> Accumulate(const std::vector<K>& T) {
+  Counts<K> C;
   for (size_t i = 0; i < T.size();) {
     size_t j = i;
     while (j < T.size() && T[j] == T[i]) ++j;
@@ -117,10 +168,13 @@ Counts Accumulate(const std::vector<u128>& T) {
 }
 
 // KmerCounting (Algorithm 1) over reads [r0, r1).
-Counts KmerCountingRange(const uint8_t* reads, const uint64_t* off, uint64_t r0, uint64_t r1, int k) {
-  std::vector<u128> T;
+template <typename K>
+Counts<K> KmerCountingRange(const uint8_t* reads, const uint64_t* off, uint64_t r0, uint64_t r1,
+                            int k) {
+  std::vector<K> T;
   for (uint64_t r = r0; r < r1; ++r)
-    ParseRead(reads + (off[r] - off[0]), off[r + 1] - off[r], k, [&](u128 x) { T.push_back(x); });
+    ParseRead<K>(reads + (off[r] - off[0]), off[r + 1] - off[r], k,
+                 [&](const K& x) { T.push_back(x); });
   std::sort(T.begin(), T.end());
   return Accumulate(T);
 }
@@ -141,13 +195,17 @@ std::vector<uint64_t> SplitReads(const uint64_t* off, uint64_t n, int parts) {
 }
 
 // k-way merge of sorted count lists, summing equal keys.
-Counts MergeSum(std::vector<Counts>& parts) {
-  typedef std::pair<u128, size_t> Head;  // (key, part)
-  std::priority_queue<Head, std::vector<Head>, std::greater<Head>> pq;
+template <typename K>
+Counts<K> MergeSum(std::vector<Counts<K>>& parts) {
+  typedef std::pair<K, size_t> Head;  // (key, part)
+  auto later = [](const Head& a, const Head& b) {
+    return b.first < a.first || (a.first == b.first && b.second < a.second);
+  };
+  std::priority_queue<Head, std::vector<Head>, decltype(later)> pq(later);
   std::vector<size_t> pos(parts.size(), 0);
   for (size_t p = 0; p < parts.size(); ++p)
     if (!parts[p].empty()) pq.push({parts[p][0].first, p});
-  Counts out;
+  Counts<K> out;
   while (!pq.empty()) {
     Head h = pq.top(); pq.pop();
     uint64_t c = parts[h.second][pos[h.second]].second;
@@ -158,30 +216,85 @@ Counts MergeSum(std::vector<Counts>& parts) {
   return out;
 }
 
-int Emit(const Counts& C, uint64_t* lo, uint64_t* hi, uint32_t* cnt, uint64_t cap, uint64_t* n_out) {
+// Keys as `words` 64-bit words each (row i at out_keys[i * words]).
+template <typename K>
+int Emit(const Counts<K>& C, int words, uint64_t* out_keys, uint32_t* cnt, uint64_t cap,
+         uint64_t* n_out) {
   *n_out = C.size();
   if (C.size() > cap) return -3;
   for (size_t i = 0; i < C.size(); ++i) {
     if (C[i].second > 0xFFFFFFFFull) return -4;
-    lo[i] = (uint64_t)C[i].first;
-    if (hi) hi[i] = (uint64_t)(C[i].first >> 64);
+    for (int w = 0; w < words; ++w) out_keys[i * words + w] = word_of(C[i].first, w);
     cnt[i] = (uint32_t)C[i].second;
   }
   return 0;
 }
 
 int CheckArgs(const uint8_t* reads, const uint64_t* off, uint64_t n, int k) {
-  if (k < 1 || k > 64 || !off || (n && !reads)) return -1;
+  if (k < 1 || k > 128 || !off || (n && !reads)) return -1;
   for (uint64_t i = 0; i < n; ++i) if (off[i + 1] < off[i]) return -1;
   return 0;
 }
 
-struct U128Hash {
-  size_t operator()(const u128& x) const {
-    uint64_t a = (uint64_t)x, b = (uint64_t)(x >> 64);
+struct KeyHash {
+  static size_t mix(uint64_t a, uint64_t b) {
     return (size_t)(a * 0x9E3779B97F4A7C15ULL ^ (b + 0x7F4A7C159E3779B9ULL + (a >> 29)));
   }
+  size_t operator()(const u128& x) const { return mix((uint64_t)x, (uint64_t)(x >> 64)); }
+  size_t operator()(const U256& x) const {
+    return mix((uint64_t)x.lo ^ (uint64_t)(x.hi >> 64) * 31, (uint64_t)(x.lo >> 64) ^ (uint64_t)x.hi);
+  }
 };
+
+template <typename K>
+int CountSort(const uint8_t* reads, const uint64_t* off, uint64_t n, int k, int threads,
+              uint64_t* out_keys, uint32_t* out_cnt, uint64_t cap, uint64_t* n_out) {
+  std::vector<uint64_t> cut = SplitReads(off, n, threads);
+  std::vector<Counts<K>> parts(threads);
+  std::vector<std::thread> ts;
+  for (int t = 0; t < threads; ++t)
+    ts.emplace_back([&, t] { parts[t] = KmerCountingRange<K>(reads, off, cut[t], cut[t + 1], k); });
+  for (auto& t : ts) t.join();
+  Counts<K> C = threads == 1 ? std::move(parts[0]) : MergeSum(parts);
+  return Emit(C, key_words(k), out_keys, out_cnt, cap, n_out);
+}
+
+template <typename K>
+int CountMap(const uint8_t* reads, const uint64_t* off, uint64_t n, int k, uint64_t* out_keys,
+             uint32_t* out_cnt, uint64_t cap, uint64_t* n_out) {
+  std::unordered_map<K, uint64_t, KeyHash> M;
+  for (uint64_t r = 0; r < n; ++r)
+    ParseRead<K>(reads + (off[r] - off[0]), off[r + 1] - off[r], k, [&](const K& x) { ++M[x]; });
+  Counts<K> C(M.begin(), M.end());
+  std::sort(C.begin(), C.end());
+  return Emit(C, key_words(k), out_keys, out_cnt, cap, n_out);
+}
+
+template <typename K>
+int CountSelected(const uint8_t* reads, const uint64_t* off, uint64_t n, int k, int threads,
+                  const uint64_t* keys, uint64_t nkeys, uint64_t* out_cnt) {
+  const int words = key_words(k);
+  std::unordered_map<K, uint64_t, KeyHash> idx;
+  for (uint64_t i = 0; i < nkeys; ++i) idx[key_from_words<K>(keys + i * words, words)] = i;
+  std::vector<uint64_t> cut = SplitReads(off, n, threads);
+  std::vector<std::vector<uint64_t>> acc(threads, std::vector<uint64_t>(nkeys, 0));
+  std::vector<std::thread> ts;
+  for (int t = 0; t < threads; ++t)
+    ts.emplace_back([&, t] {
+      for (uint64_t r = cut[t]; r < cut[t + 1]; ++r)
+        ParseRead<K>(reads + (off[r] - off[0]), off[r + 1] - off[r], k, [&](const K& x) {
+          auto it = idx.find(x);
+          if (it != idx.end()) ++acc[t][it->second];
+        });
+    });
+  for (auto& t : ts) t.join();
+  for (uint64_t i = 0; i < nkeys; ++i) {
+    uint64_t s = 0;
+    for (int t = 0; t < threads; ++t) s += acc[t][i];
+    out_cnt[i] = s;
+  }
+  return 0;
+}
 
 }  // namespace
 
@@ -202,65 +315,35 @@ uint64_t oracle_valid_windows(const uint8_t* reads, const uint64_t* off, uint64_
 }
 
 // Sorted (k-mer, count) output of Algorithm 1 (canonical, masked, N skipped).
-// keys are written as out_lo[i] (bits 0..63) and, when out_hi is not NULL,
-// out_hi[i] (bits 64..127). Returns 0, -1 bad args, -3 capacity (n_out set), -4 count overflow.
+// Key i is written to out_keys[i * w .. i * w + w), w = 1 (k <= 32), 2
+// (k <= 64) or 4 (k <= 128) 64-bit words, least significant first. Returns 0,
+// -1 bad args, -3 capacity (n_out set), -4 count overflow.
 int oracle_count_sort(const uint8_t* reads, const uint64_t* off, uint64_t n, int k, int threads,
-                      uint64_t* out_lo, uint64_t* out_hi, uint32_t* out_cnt, uint64_t cap,
-                      uint64_t* n_out) {
+                      uint64_t* out_keys, uint32_t* out_cnt, uint64_t cap, uint64_t* n_out) {
   if (CheckArgs(reads, off, n, k)) return -1;
   if (threads < 1) threads = 1;
-  std::vector<uint64_t> cut = SplitReads(off, n, threads);
-  std::vector<Counts> parts(threads);
-  std::vector<std::thread> ts;
-  for (int t = 0; t < threads; ++t)
-    ts.emplace_back([&, t] { parts[t] = KmerCountingRange(reads, off, cut[t], cut[t + 1], k); });
-  for (auto& t : ts) t.join();
-  Counts C = threads == 1 ? std::move(parts[0]) : MergeSum(parts);
-  return Emit(C, out_lo, out_hi, out_cnt, cap, n_out);
+  return k <= 64 ? CountSort<u128>(reads, off, n, k, threads, out_keys, out_cnt, cap, n_out)
+                 : CountSort<U256>(reads, off, n, k, threads, out_keys, out_cnt, cap, n_out);
 }
 
 // Cross-check counter: hash map instead of sort-and-accumulate, then sort the keys.
 int oracle_count_map(const uint8_t* reads, const uint64_t* off, uint64_t n, int k,
-                     uint64_t* out_lo, uint64_t* out_hi, uint32_t* out_cnt, uint64_t cap,
-                     uint64_t* n_out) {
+                     uint64_t* out_keys, uint32_t* out_cnt, uint64_t cap, uint64_t* n_out) {
   if (CheckArgs(reads, off, n, k)) return -1;
-  std::unordered_map<u128, uint64_t, U128Hash> M;
-  for (uint64_t r = 0; r < n; ++r)
-    ParseRead(reads + (off[r] - off[0]), off[r + 1] - off[r], k, [&](u128 x) { ++M[x]; });
-  Counts C(M.begin(), M.end());
-  std::sort(C.begin(), C.end());
-  return Emit(C, out_lo, out_hi, out_cnt, cap, n_out);
+  return k <= 64 ? CountMap<u128>(reads, off, n, k, out_keys, out_cnt, cap, n_out)
+                 : CountMap<U256>(reads, off, n, k, out_keys, out_cnt, cap, n_out);
 }
 
 // Counts of selected keys only (for inputs too large to count in full):
 // every window is parsed as above, and its canonical key is looked up in the
-// set of requested keys. out_cnt[i] receives the count of key i (0 if absent).
+// set of requested keys (nkeys keys of w words each, as written above).
+// out_cnt[i] receives the count of key i (0 if absent).
 int oracle_count_selected(const uint8_t* reads, const uint64_t* off, uint64_t n, int k, int threads,
-                          const uint64_t* keys_lo, const uint64_t* keys_hi, uint64_t nkeys,
-                          uint64_t* out_cnt) {
+                          const uint64_t* keys, uint64_t nkeys, uint64_t* out_cnt) {
   if (CheckArgs(reads, off, n, k)) return -1;
   if (threads < 1) threads = 1;
-  std::unordered_map<u128, uint64_t, U128Hash> idx;
-  for (uint64_t i = 0; i < nkeys; ++i)
-    idx[(u128)keys_lo[i] | (keys_hi ? (u128)keys_hi[i] << 64 : (u128)0)] = i;
-  std::vector<uint64_t> cut = SplitReads(off, n, threads);
-  std::vector<std::vector<uint64_t>> acc(threads, std::vector<uint64_t>(nkeys, 0));
-  std::vector<std::thread> ts;
-  for (int t = 0; t < threads; ++t)
-    ts.emplace_back([&, t] {
-      for (uint64_t r = cut[t]; r < cut[t + 1]; ++r)
-        ParseRead(reads + (off[r] - off[0]), off[r + 1] - off[r], k, [&](u128 x) {
-          auto it = idx.find(x);
-          if (it != idx.end()) ++acc[t][it->second];
-        });
-    });
-  for (auto& t : ts) t.join();
-  for (uint64_t i = 0; i < nkeys; ++i) {
-    uint64_t s = 0;
-    for (int t = 0; t < threads; ++t) s += acc[t][i];
-    out_cnt[i] = s;
-  }
-  return 0;
+  return k <= 64 ? CountSelected<u128>(reads, off, n, k, threads, keys, nkeys, out_cnt)
+                 : CountSelected<U256>(reads, off, n, k, threads, keys, nkeys, out_cnt);
 }
 
 }  // extern "C"

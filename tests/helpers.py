@@ -44,9 +44,19 @@ def rc_int(key: int, k: int) -> int:
 
 
 def keys_as_ints(keys: np.ndarray, k: int) -> list[int]:
-    if k > 32:
-        return [int(lo) | (int(hi) << 64) for lo, hi in keys]
+    """Keys as Python ints: one word each (k <= 32), or rows of words, least
+    significant first."""
+    if keys.ndim == 2:
+        return [sum(int(w) << (64 * i) for i, w in enumerate(row)) for row in keys]
     return [int(x) for x in keys]
+
+
+def ints_as_keys(ints: list[int], k: int) -> np.ndarray:
+    """Inverse of keys_as_ints for the width k uses (1, 2 or 4 words)."""
+    w = 1 if k <= 32 else (2 if k <= 64 else 4)
+    rows = [[(x >> (64 * i)) & (2**64 - 1) for i in range(w)] for x in ints]
+    arr = np.array(rows, dtype=np.uint64).reshape(len(ints), w)
+    return arr[:, 0].copy() if w == 1 else arr
 
 
 def revcomp_bytes(reads: np.ndarray, offsets: np.ndarray):
@@ -69,7 +79,7 @@ def merge_sum(parts):
         kk = [tuple(x) for x in keys.tolist()] if keys.ndim == 2 else keys.tolist()
         for key, c in zip(kk, cnt.tolist()):
             acc[key] = acc.get(key, 0) + c
-    items = sorted(acc.items(), key=lambda kv: (kv[0][1], kv[0][0]) if isinstance(kv[0], tuple) else kv[0])
+    items = sorted(acc.items(), key=lambda kv: kv[0][::-1] if isinstance(kv[0], tuple) else kv[0])
     return items
 
 

@@ -14,11 +14,11 @@ import pytest
 import oracle
 import synth
 from oracle import brute
-from helpers import (de_bruijn, keys_as_ints, merge_sum, rc_int, revcomp_bytes, to_arrays,
-                     valid_windows_np)
+from helpers import (de_bruijn, ints_as_keys, keys_as_ints, merge_sum, rc_int, revcomp_bytes,
+                     to_arrays, valid_windows_np)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")
-KS = [1, 2, 3, 4, 5, 8, 15, 16, 17, 21, 31, 32, 33, 55, 63, 64]
+KS = [1, 2, 3, 4, 5, 8, 15, 16, 17, 21, 31, 32, 33, 55, 63, 64, 65, 77, 96, 97, 127, 128]
 
 
 def _pairs(keys, cnt, k):
@@ -63,9 +63,9 @@ def test_de_bruijn_closed_form(k):
         assert c == (1 if rc_int(key, k) == key else 2)
 
 
-@pytest.mark.parametrize("k", [1, 5, 31, 32, 33, 64])
+@pytest.mark.parametrize("k", [1, 5, 31, 32, 33, 64, 65, 100, 128])
 def test_homopolymers(k):
-    L = 100
+    L = 300
     for base, enc in [("A", 0), ("T", 0), ("C", brute.encode("C" * k)), ("G", brute.encode("C" * k))]:
         r, o = to_arrays([base * L])
         keys, cnt = oracle.count(r, o, k)
@@ -73,7 +73,7 @@ def test_homopolymers(k):
         assert cnt.tolist() == [L - k + 1]
 
 
-@pytest.mark.parametrize("k", [3, 21, 31, 32, 33, 55])
+@pytest.mark.parametrize("k", [3, 21, 31, 32, 33, 55, 65, 99, 128])
 def test_invariants_on_synthetic_reads(k):
     g = synth.genome(11, 3000, [(200, 5, 0.02)])
     r, o = synth.reads(g, 300, 150, err_rate=0.01, n_rate=0.002, seed=5)
@@ -120,21 +120,19 @@ def test_thread_count_and_nonzero_offset_base():
 def test_selected_counts_match_full():
     g = synth.genome(13, 5000, [(300, 8, 0.01)])
     r, o = synth.reads(g, 500, 150, err_rate=0.01, n_rate=0.001, seed=2)
-    for k in (21, 55):
+    for k in (21, 55, 100):
         keys, cnt = oracle.count(r, o, k)
         sel = np.arange(0, len(cnt), 7)
         got = oracle.count_selected(r, o, k, keys[sel])
         assert np.array_equal(got, cnt[sel].astype(np.uint64))
         # keys that cannot occur (not canonical: bigger than their revcomp) count 0
         absent = [x for x in (4 ** k - 1, 4 ** k - 2) if rc_int(x, k) < x]
-        arr = (np.array([[x & (2**64 - 1), x >> 64] for x in absent], dtype=np.uint64)
-               if k > 32 else np.array(absent, dtype=np.uint64))
-        assert oracle.count_selected(r, o, k, arr).tolist() == [0] * len(absent)
+        assert oracle.count_selected(r, o, k, ints_as_keys(absent, k)).tolist() == [0] * len(absent)
 
 
 def test_bad_arguments():
     r, o = to_arrays(["ACGT"])
-    for k in (0, 65):
+    for k in (0, 129):
         with pytest.raises(RuntimeError):
             oracle.count(r, o, k)
     with pytest.raises(RuntimeError):
