@@ -22,7 +22,9 @@
  *     (memory from hipMalloc, or a torch CUDA tensor's data pointer) unless
  *     named host_*. n_out is a host pointer.
  *   - Keys: k <= 32 -> one uint64 per key (key in the low 2k bits);
- *           33 <= k <= 64 -> two uint64 per key, low word first (lo, hi).
+ *           33 <= k <= 64 -> two uint64 per key, low word first (lo, hi);
+ *           65 <= k <= 128 -> four uint64 per key, least significant first
+ *           (keys wider than 64 bits, named future work in Section VII).
  *   - The caller owns inputs and outputs. The library owns its scratch memory
  *     (a per-host-thread, per-device arena kept between calls) and keeps no
  *     caller pointer after a call returns.
@@ -44,7 +46,7 @@ extern "C" {
 
 /* Status codes. */
 #define KC_OK 0
-#define KC_E_INVAL (-1)    /* bad argument: NULL pointer, k outside [1,64], P < 1,
+#define KC_E_INVAL (-1)    /* bad argument: NULL pointer, k outside [1,128], P < 1,
                               offsets decreasing */
 #define KC_E_NOMEM (-2)    /* device or host allocation failed */
 #define KC_E_CAPACITY (-3) /* output arrays too small; *n_out holds the size needed */
@@ -68,7 +70,8 @@ typedef struct kc_options {
                           table, then a sort of its distinct keys; 1 = sort of its
                           records and run-length accumulation (Algorithm 1's Sort +
                           Accumulate, as each owner does in Algorithm 3). Same result.
-                          The batched form takes 0 only. */
+                          Keys of more than 64 bases are always counted by sorting.
+                          The batched form takes 0 only (and k <= 32). */
   int reserved[5];
 } kc_options;
 
@@ -97,9 +100,9 @@ typedef struct kc_stats {
  *   reads      device, ASCII bytes; read i = reads[offsets[i] .. offsets[i+1])
  *   offsets    device, n_reads+1 non-decreasing byte offsets (offsets[0] may be > 0)
  *   n_reads    number of reads (0 allowed)
- *   k          1..64
+ *   k          1..128
  *   P          number of owner partitions (>= 1)
- *   out_keys   device, room for kc_max_outputs() keys (1 or 2 uint64 each, see above)
+ *   out_keys   device, room for kc_max_outputs() keys (1, 2 or 4 uint64 each, see above)
  *   out_counts device, room for kc_max_outputs() counts
  *   n_out      host; receives the number of distinct keys written
  * Returns KC_OK or a negative status. */
@@ -169,11 +172,11 @@ void kc_batch_free(kc_batch* plan);
  *   job alone needs more than the budget; *job_id receives the job's id.
  * kc_server_poll / kc_server_wait: the job's state (KC_JOB_*); wait blocks
  *   until it is DONE or FAILED.
- * kc_server_result: device pointers to the sorted keys (1 or 2 words each, as
+ * kc_server_result: device pointers to the sorted keys (1, 2 or 4 words each, as
  *   in kc_count) and counts, and their number. A FAILED job returns its status
  *   (message in kc_last_error).
  * kc_server_result_copy: copies a finished job's result into caller DEVICE
- *   arrays of out_capacity keys (1 or 2 words each) and counts, on `stream`,
+ *   arrays of out_capacity keys (1, 2 or 4 words each) and counts, on `stream`,
  *   and returns when the copy is complete; KC_E_CAPACITY (with *n_out set)
  *   if they are too small.
  * kc_server_release: frees a finished job's result and forgets the job.
@@ -257,7 +260,7 @@ void kc_pred_free(kc_predictor* pred);
  *   max_count; host_hist[0] = 0. max_count in [1, 2^24]. Synchronous on stream.
  * kc_filter_min_count: copies the pairs with count >= min_count, in their
  *   order, to out_keys / out_counts (room for n pairs; must not overlap the
- *   inputs); *n_out receives their number. k gives the key width (1 or 2
+ *   inputs); *n_out receives their number. k gives the key width (1, 2 or 4
  *   words, as in kc_count). Synchronous on stream.
  * kc_merge_counts: the result of the union of two read collections from their
  *   two results (sorted, unique keys; the count of a read collection is the

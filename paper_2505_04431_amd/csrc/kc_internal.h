@@ -65,9 +65,9 @@ constexpr int kSplitMaxBits = 10;  // sub-bins per split step: up to 1024
 constexpr int kWinStarts = 8;      // window starts per thread in the window kernels
 constexpr uint32_t kLeafOverflow = 0xFFFFFFFFu;
 
-int max_leaf_slots_log2(bool wide);
+int max_leaf_slots_log2(int words);
 int max_shard_bits();
-int split_tile(bool wide);  // records per split work item
+int split_tile(int words);  // records per split work item
 
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 
@@ -77,13 +77,13 @@ hipError_t launch_pack(const uint8_t* src, uint64_t n_bytes, const uint64_t* off
 
 // Window kernels over the bytes [byte_begin, byte_end) of the packed stream.
 // keybits = 2k (plain) or 2k + set id bits (batch: batch != nullptr).
-hipError_t launch_window_hist(bool wide, const uint64_t* packed, const uint64_t* inv,
+hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t* inv,
                               const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end, int k,
                               int keybits, int shard_bits, const BatchSets* batch,
                               unsigned long long* hist, unsigned long long* wcount,
                               hipStream_t s);
 
-hipError_t launch_window_scatter(bool wide, const uint64_t* packed, const uint64_t* inv,
+hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* inv,
                                  const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end,
                                  int k, int keybits, int shard_bits, const BatchSets* batch,
                                  unsigned long long* cursor, void* out, hipStream_t s);
@@ -109,11 +109,11 @@ hipError_t launch_plan_leaves(const unsigned long long* hist, const unsigned lon
                               unsigned long long* cursor, hipStream_t s);
 
 // Split kernels loop over st->n_items items (persistent grid of at most max_items blocks).
-hipError_t launch_split_hist(bool wide, const void* src, const SplitItem* items,
+hipError_t launch_split_hist(int words, const void* src, const SplitItem* items,
                              const DevState* st, uint64_t max_items, const SplitBin* bins,
                              unsigned long long* subhist, hipStream_t s);
 
-hipError_t launch_split_scatter(bool wide, const void* src, void* dst, const SplitItem* items,
+hipError_t launch_split_scatter(int words, const void* src, void* dst, const SplitItem* items,
                                 const DevState* st, uint64_t max_items, const SplitBin* bins,
                                 unsigned long long* cursor, hipStream_t s);
 
@@ -125,14 +125,14 @@ hipError_t launch_split_scatter(bool wide, const void* src, void* dst, const Spl
 // in large_list, which holds max_leaves entries) to 512-thread workgroups.
 // mode 1: every non-empty leaf's records are sorted in LDS and run-length
 // accumulated (the launch_leaf_small call then only lists the leaves).
-hipError_t launch_leaf_small(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
+hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode = 0);
-hipError_t launch_leaf_large(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
+hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
                              hipStream_t s, int mode = 0);
-uint64_t small_leaf_max(bool wide);
+uint64_t small_leaf_max(int words);
 
 // Exclusive scan of leaf counts into output offsets; st->D = total. bsum
 // holds scan_blocks(max_leaves) values.
@@ -155,14 +155,14 @@ hipError_t launch_splice(const Leaf* leaves, const uint32_t* d, uint64_t n,
                          unsigned long long* bsum, unsigned long long* pos, Leaf* out,
                          uint32_t* out_d, hipStream_t s);
 
-hipError_t launch_concat(bool wide, const void* bufA, const void* bufB, const uint32_t* tmp_cnt,
+hipError_t launch_concat(int words, const void* bufA, const void* bufB, const uint32_t* tmp_cnt,
                          const Leaf* leaves, const uint32_t* d, const unsigned long long* out_off,
                          const DevState* st, uint64_t max_leaves, uint64_t cap,
                          uint64_t* out_keys, uint32_t* out_counts, hipStream_t s);
 
 // Batch helpers: class concat (k-mer, count, set id within the class), set
 // bounds in a class output, global set offsets and the final gather.
-hipError_t launch_concat_batch(bool wide, const void* bufA, const void* bufB,
+hipError_t launch_concat_batch(int words, const void* bufA, const void* bufB,
                                const uint32_t* tmp_cnt, const Leaf* leaves, const uint32_t* d,
                                const unsigned long long* out_off, const DevState* st,
                                uint64_t max_leaves, uint64_t cap, int k, uint64_t* out_keys,
@@ -181,7 +181,7 @@ hipError_t launch_batch_gather(const uint32_t* set_class, const uint32_t* set_lo
                                uint32_t n_sets, uint64_t cap, uint64_t* out_keys,
                                uint32_t* out_counts, hipStream_t s);
 
-hipError_t launch_check(bool wide, const uint64_t* keys, const uint32_t* counts, uint64_t n,
+hipError_t launch_check(int words, const uint64_t* keys, const uint32_t* counts, uint64_t n,
                         int k, CheckResult* res, hipStream_t s);
 
 }  // namespace kc

@@ -60,6 +60,7 @@ template <typename K> struct Key;
 
 template <> struct Key<uint64_t> {
   static constexpr bool kWide = false;
+  static constexpr int kWords = 1;
   __device__ static uint64_t empty() { return ~0ull; }
   __device__ static uint64_t hash(uint64_t x) { return fmix64(x); }
   __device__ static uint32_t bits(uint64_t x, int shift, int nbits) {
@@ -93,6 +94,7 @@ template <> struct Key<unsigned long long> : Key<uint64_t> {};
 
 template <> struct Key<u128> {
   static constexpr bool kWide = true;
+  static constexpr int kWords = 2;
   __device__ static u128 empty() { return ~(u128)0; }
   __device__ static uint64_t hash(u128 x) {
     return fmix64((uint64_t)x ^ fmix64((uint64_t)(x >> 64) + 0x9E3779B97F4A7C15ull));
@@ -128,6 +130,87 @@ template <> struct Key<u128> {
     return r >> (128 - 2 * k);
   }
   __device__ static bool in_range(u128 x, int k) { return (x & ~mask128(k)) == 0; }
+};
+
+// 256-bit keys (k in [65, 128]): two 128-bit halves with the operations the
+// key-generic kernels apply to keys (shifts by 0..255, bitwise logic, order).
+struct u256 {
+  u128 lo, hi;
+  u256() = default;
+  __device__ constexpr u256(u128 l, u128 h) : lo(l), hi(h) {}
+  __device__ constexpr u256(u128 x) : lo(x), hi(0) {}
+  __device__ constexpr u256(uint64_t x) : lo(x), hi(0) {}
+  __device__ constexpr u256(unsigned long long x) : lo(x), hi(0) {}
+  __device__ constexpr u256(uint32_t x) : lo(x), hi(0) {}
+  __device__ constexpr u256(int x) : lo((u128)(uint32_t)x), hi(0) {}
+  __device__ explicit operator uint32_t() const { return (uint32_t)lo; }
+  __device__ explicit operator uint64_t() const { return (uint64_t)lo; }
+  __device__ explicit operator unsigned long long() const { return (unsigned long long)lo; }
+};
+__device__ __forceinline__ u256 operator<<(const u256& a, int s) {
+  if (s == 0) return a;
+  if (s >= 128) return u256((u128)0, a.lo << (s - 128));
+  return u256(a.lo << s, (a.hi << s) | (a.lo >> (128 - s)));
+}
+__device__ __forceinline__ u256 operator>>(const u256& a, int s) {
+  if (s == 0) return a;
+  if (s >= 128) return u256(a.hi >> (s - 128), (u128)0);
+  return u256((a.lo >> s) | (a.hi << (128 - s)), a.hi >> s);
+}
+__device__ __forceinline__ u256 operator|(const u256& a, const u256& b) {
+  return u256(a.lo | b.lo, a.hi | b.hi);
+}
+__device__ __forceinline__ u256 operator&(const u256& a, const u256& b) {
+  return u256(a.lo & b.lo, a.hi & b.hi);
+}
+__device__ __forceinline__ u256 operator~(const u256& a) { return u256(~a.lo, ~a.hi); }
+__device__ __forceinline__ u256& operator|=(u256& a, const u256& b) { return a = a | b; }
+__device__ __forceinline__ bool operator==(const u256& a, const u256& b) {
+  return a.lo == b.lo && a.hi == b.hi;
+}
+__device__ __forceinline__ bool operator!=(const u256& a, const u256& b) { return !(a == b); }
+__device__ __forceinline__ bool operator<(const u256& a, const u256& b) {
+  return a.hi != b.hi ? a.hi < b.hi : a.lo < b.lo;
+}
+__device__ __forceinline__ bool operator>(const u256& a, const u256& b) { return b < a; }
+
+// Reverse the order of the 128 two-bit groups.
+__device__ __forceinline__ u256 rev2_256(const u256& v) {
+  const u128 lo = ((u128)rev2((uint64_t)(v.hi >> 64)) << 0) | ((u128)rev2((uint64_t)v.hi) << 64);
+  const u128 hi = ((u128)rev2((uint64_t)(v.lo >> 64)) << 0) | ((u128)rev2((uint64_t)v.lo) << 64);
+  return u256(lo, hi);
+}
+
+__device__ __forceinline__ u128 low_bits128(int bits) {
+  return bits >= 128 ? ~(u128)0 : (((u128)1 << bits) - 1);
+}
+
+// Keys of more than 64 bases: built from five packed words (up to 128 bases
+// starting anywhere in the first word).
+template <> struct Key<u256> {
+  static constexpr bool kWide = true;
+  static constexpr int kWords = 4;
+  __device__ static u256 mask(int k) {
+    const int b = 2 * k;
+    return b <= 128 ? u256(low_bits128(b), (u128)0) : u256(~(u128)0, low_bits128(b - 128));
+  }
+  __device__ static uint32_t bits(const u256& x, int shift, int nbits) {
+    return (uint32_t)(x >> shift) & ((1u << nbits) - 1u);
+  }
+  // Bases [s/2, s/2 + k) of the little-endian base stream in p[0..4] (base j
+  // of the window at bits 2j), s even, 0 <= s <= 62.
+  __device__ static u256 window(const uint64_t (&p)[5], int s, int k) {
+    uint64_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = s ? (p[i] >> s) | (p[i + 1] << (64 - s)) : p[i];
+    return u256(((u128)w[1] << 64) | w[0], ((u128)w[3] << 64) | w[2]) & mask(k);
+  }
+  __device__ static u256 fwd_of_window(const u256& v, int k) { return rev2_256(v) >> (256 - 2 * k); }
+  __device__ static u256 rc_of_window(const u256& v, int k) { return ~v & mask(k); }
+  __device__ static u256 revcomp(const u256& x, int k) {
+    return rev2_256(~x & mask(k)) >> (256 - 2 * k);
+  }
+  __device__ static bool in_range(const u256& x, int k) { return (x & ~mask(k)) == u256(0); }
 };
 
 // ---------------------------------------------------------------- block scans
@@ -318,6 +401,48 @@ __device__ __forceinline__ uint32_t valid_starts(const uint64_t* __restrict__ in
   return ~(uint32_t)bad & (S >= 32 ? 0xFFFFFFFFu : ((1u << S) - 1u));
 }
 
+// The same for keys of more than 64 bases: S + k - 1 may pass 128 bits, so
+// the masks are read and smeared as 256-bit values (the mask arrays are padded
+// by five words).
+__device__ __forceinline__ u256 load_bits256(const uint64_t* __restrict__ m, uint64_t g) {
+  const uint64_t w = g >> 6;
+  const int off = (int)(g & 63);
+  uint64_t a[5], r[4];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) a[i] = m[w + i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r[i] = off ? (a[i] >> off) | (a[i + 1] << (64 - off)) : a[i];
+  return u256(((u128)r[1] << 64) | r[0], ((u128)r[3] << 64) | r[2]);
+}
+
+__device__ __forceinline__ u256 smear256(u256 x, int len) {
+  int l = 1;
+  while (2 * l <= len) {
+    x |= x >> l;
+    l <<= 1;
+  }
+  if (l < len) x |= x >> (len - l);
+  return x;
+}
+
+template <int S>
+__device__ __forceinline__ uint32_t valid_starts256(const uint64_t* __restrict__ inv,
+                                                    const uint64_t* __restrict__ endm, uint64_t g,
+                                                    int k) {
+  u256 bad = smear256(load_bits256(inv, g), k);
+  if (k > 1) bad |= smear256(load_bits256(endm, g), k - 1);
+  return ~(uint32_t)bad & (S >= 32 ? 0xFFFFFFFFu : ((1u << S) - 1u));
+}
+
+// Valid starts for the key width of Kc.
+template <typename Kc, int S>
+__device__ __forceinline__ uint32_t valid_starts_for(const uint64_t* __restrict__ inv,
+                                                     const uint64_t* __restrict__ endm,
+                                                     uint64_t g, int k) {
+  if constexpr (Key<Kc>::kWords == 4) return valid_starts256<S>(inv, endm, g, k);
+  else return valid_starts<S>(inv, endm, g, k);
+}
+
 template <typename K, int S>
 __device__ __forceinline__ void load_window_words(const uint64_t* __restrict__ packed, uint64_t g,
                                                   uint64_t& p0, uint64_t& p1, uint64_t& p2) {
@@ -352,8 +477,32 @@ __device__ __forceinline__ void canon_run(uint64_t p0, uint64_t p1, uint64_t p2,
   }
 }
 
+// canon_run for keys of more than 64 bases, from five packed words (the
+// incoming base of window i sits at most 158 bases past the first word).
+template <int S>
+__device__ __forceinline__ void canon_run256(const uint64_t (&p)[5], uint64_t g, int k,
+                                             u256 (&out)[S]) {
+  const int s0 = (int)(g & 31);
+  const u256 v = Key<u256>::window(p, 2 * s0, k);
+  u256 fwd = Key<u256>::fwd_of_window(v, k);
+  u256 rc = Key<u256>::rc_of_window(v, k);
+  out[0] = fwd < rc ? fwd : rc;
+  const u256 mask = Key<u256>::mask(k);
+  const int top = 2 * (k - 1);
+#pragma unroll
+  for (int i = 1; i < S; ++i) {
+    const int q = s0 + i + k - 1;  // position of the incoming base within p[0..4]
+    const int wi = q >> 5;
+    const uint64_t w = wi == 0 ? p[0] : wi == 1 ? p[1] : wi == 2 ? p[2] : wi == 3 ? p[3] : p[4];
+    const uint32_t x = (uint32_t)(w >> (2 * (q & 31))) & 3u;
+    fwd = ((fwd << 2) | u256(x)) & mask;
+    rc = (rc >> 2) | (u256(3u - x) << top);
+    out[i] = fwd < rc ? fwd : rc;
+  }
+}
+
 template <typename K>
-__device__ __forceinline__ uint32_t shard_of(K key, int keybits, int shard_bits) {
+__device__ __forceinline__ uint32_t shard_of(const K& key, int keybits, int shard_bits) {
   return (uint32_t)(key >> (keybits - shard_bits));
 }
 
@@ -365,15 +514,23 @@ template <typename K, typename Kc, int S, bool BATCH>
 __device__ __forceinline__ uint32_t window_keys(const uint64_t* __restrict__ packed, uint64_t g,
                                                 int k, uint32_t vm, const BatchSets& bs,
                                                 K (&key)[S]) {
-  uint64_t p0, p1, p2;
-  load_window_words<Kc, S>(packed, g, p0, p1, p2);
   Kc c[S];
-  canon_run<Kc, S>(p0, p1, p2, g, k, c);
-  if (!BATCH) {
+  if constexpr (Key<Kc>::kWords == 4) {
+    const uint64_t w = g >> 5;
+    uint64_t p[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) p[i] = packed[w + i];
+    canon_run256<S>(p, g, k, c);
+  } else {
+    uint64_t p0, p1, p2;
+    load_window_words<Kc, S>(packed, g, p0, p1, p2);
+    canon_run<Kc, S>(p0, p1, p2, g, k, c);
+  }
+  if constexpr (!BATCH) {
 #pragma unroll
     for (int i = 0; i < S; ++i) key[i] = (K)c[i];
     return vm;
-  }
+  } else {
   uint32_t lo = 0, hi = bs.n_sets - 1;  // last set whose first byte is <= g
   while (lo < hi) {
     const uint32_t mid = (lo + hi + 1) >> 1;
@@ -389,6 +546,7 @@ __device__ __forceinline__ uint32_t window_keys(const uint64_t* __restrict__ pac
     else key[i] = ((K)loc << (2 * k)) | (K)c[i];
   }
   return vm;
+  }
 }
 
 // Threads t in [t_begin, t_end) each take window starts [t*S, t*S + S).
@@ -408,7 +566,7 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
   for (uint64_t t = t_begin + (uint64_t)blockIdx.x * TB + threadIdx.x; t < t_end;
        t += (uint64_t)gridDim.x * TB) {
     const uint64_t g = t * S;
-    uint32_t vm = valid_starts<S>(inv, endm, g, k);
+    uint32_t vm = valid_starts_for<Kc, S>(inv, endm, g, k);
     if (!vm) continue;
     K keys[S];
     vm = window_keys<K, Kc, S, BATCH>(packed, g, k, vm, bs, keys);
@@ -449,7 +607,7 @@ __device__ __forceinline__ void window_scatter_body(const uint64_t* __restrict__
     __syncthreads();
     const uint64_t t = t_begin + tile * TB + threadIdx.x;
     const uint64_t g = t * S;
-    uint32_t vm = t < t_end ? valid_starts<S>(inv, endm, g, k) : 0u;
+    uint32_t vm = t < t_end ? valid_starts_for<Kc, S>(inv, endm, g, k) : 0u;
     K key[S];
     uint32_t rank[S];  // (the shard is recomputed from the key: fewer live registers)
     if (vm) {
@@ -1458,7 +1616,12 @@ __global__ void __launch_bounds__(256) k_concat(const K* __restrict__ bufA,
       const uint64_t o = base + i;
       if (o >= cap) break;
       const K key = src[lf.begin + i];
-      if (Key<K>::kWide) {
+      if constexpr (Key<K>::kWords == 4) {
+        out_keys[4 * o] = (uint64_t)key.lo;
+        out_keys[4 * o + 1] = (uint64_t)(key.lo >> 64);
+        out_keys[4 * o + 2] = (uint64_t)key.hi;
+        out_keys[4 * o + 3] = (uint64_t)(key.hi >> 64);
+      } else if constexpr (Key<K>::kWords == 2) {
         out_keys[2 * o] = (uint64_t)key;
         out_keys[2 * o + 1] = (uint64_t)((u128)key >> 64);
       } else {
@@ -1591,8 +1754,12 @@ __global__ void __launch_bounds__(256) k_batch_gather(
 
 template <typename K>
 __device__ __forceinline__ K load_out_key(const uint64_t* keys, uint64_t i) {
-  if (Key<K>::kWide) return (K)(((u128)keys[2 * i + 1] << 64) | keys[2 * i]);
-  return (K)keys[i];
+  if constexpr (Key<K>::kWords == 4)
+    return K(((u128)keys[4 * i + 1] << 64) | keys[4 * i], ((u128)keys[4 * i + 3] << 64) | keys[4 * i + 2]);
+  else if constexpr (Key<K>::kWords == 2)
+    return (K)(((u128)keys[2 * i + 1] << 64) | keys[2 * i]);
+  else
+    return (K)keys[i];
 }
 
 template <typename K>
@@ -1631,6 +1798,8 @@ constexpr int kScatterTB64 = 1024;
 constexpr int kScatterTB128 = 512;
 constexpr int kSplitTB64 = 1024;
 constexpr int kSplitTB128 = 512;
+constexpr int kScatterTB256 = 256;  // 256-bit keys: LDS staging of 64 KiB per tile
+constexpr int kSplitTB256 = 256;
 constexpr int kSplitR = 8;
 constexpr int kLeafTB = 512;
 constexpr int kLeafCmax64 = 4096;
@@ -1641,6 +1810,7 @@ constexpr int kSmallCmax128 = 512;
 constexpr unsigned kSmallGrid = 256 * 20;
 constexpr int kSortMax64 = 8192;   // records per leaf of the sort-based count
 constexpr int kSortMax128 = 4096;
+constexpr int kSortMax256 = 2048;
 
 inline unsigned grid_for(uint64_t n, unsigned tb, unsigned cap) {
   uint64_t g = (n + tb - 1) / tb;
@@ -1654,9 +1824,11 @@ inline unsigned persistent(uint64_t max_n, unsigned cap) {
 
 }  // namespace
 
-int max_leaf_slots_log2(bool wide) { return wide ? 11 : 12; }
+int max_leaf_slots_log2(int words) { return words > 1 ? 11 : 12; }
 int max_shard_bits() { return kMaxShardBits; }
-int split_tile(bool wide) { return wide ? kSplitTB128 * kSplitR : kSplitTB64 * kSplitR; }
+int split_tile(int words) {
+  return (words == 4 ? kSplitTB256 : words == 2 ? kSplitTB128 : kSplitTB64) * kSplitR;
+}
 
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v,
                            hipStream_t s) {
@@ -1682,7 +1854,7 @@ hipError_t launch_pack(const uint8_t* src, uint64_t n_bytes, const uint64_t* off
   hipLaunchKernelGGL((KERNEL<K, KC, kWinStarts, TB, BATCH>), dim3(GRID), dim3(TB), 0, s, packed, \
                      inv, endm, t_begin, t_end, k, keybits, shard_bits, bs, ARG0, ARG1)
 
-hipError_t launch_window_hist(bool wide, const uint64_t* packed, const uint64_t* inv,
+hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t* inv,
                               const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end, int k,
                               int keybits, int shard_bits, const BatchSets* batch,
                               unsigned long long* hist, unsigned long long* wcount,
@@ -1693,11 +1865,14 @@ hipError_t launch_window_hist(bool wide, const uint64_t* packed, const uint64_t*
   const BatchSets bs = batch ? *batch : BatchSets{nullptr, nullptr, 0};
 #define ARG0 hist
 #define ARG1 wcount
+  const bool wide = words == 2;
   if (batch) {
+    if (words == 4) return hipErrorInvalidValue;
     if (wide) KC_WINDOW_LAUNCH(k_window_hist, u128, uint64_t, kHistTB, true, grid);
     else KC_WINDOW_LAUNCH(k_window_hist, uint64_t, uint64_t, kHistTB, true, grid);
   } else {
-    if (wide) KC_WINDOW_LAUNCH(k_window_hist, u128, u128, kHistTB, false, grid);
+    if (words == 4) KC_WINDOW_LAUNCH(k_window_hist, u256, u256, kHistTB, false, grid);
+    else if (wide) KC_WINDOW_LAUNCH(k_window_hist, u128, u128, kHistTB, false, grid);
     else KC_WINDOW_LAUNCH(k_window_hist, uint64_t, uint64_t, kHistTB, false, grid);
   }
 #undef ARG0
@@ -1705,7 +1880,7 @@ hipError_t launch_window_hist(bool wide, const uint64_t* packed, const uint64_t*
   return hipGetLastError();
 }
 
-hipError_t launch_window_scatter(bool wide, const uint64_t* packed, const uint64_t* inv,
+hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* inv,
                                  const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end,
                                  int k, int keybits, int shard_bits, const BatchSets* batch,
                                  unsigned long long* cursor, void* out, hipStream_t s) {
@@ -1713,7 +1888,13 @@ hipError_t launch_window_scatter(bool wide, const uint64_t* packed, const uint64
   const uint64_t t_end = (byte_end + kWinStarts - 1) / kWinStarts;
   const BatchSets bs = batch ? *batch : BatchSets{nullptr, nullptr, 0};
 #define ARG0 cursor
-  if (wide) {
+  if (words == 4) {
+    if (batch) return hipErrorInvalidValue;
+    const unsigned grid = grid_for(t_end - t_begin, kScatterTB256, 1u << 20);
+#define ARG1 (u256*)out
+    KC_WINDOW_LAUNCH(k_window_scatter, u256, u256, kScatterTB256, false, grid);
+#undef ARG1
+  } else if (words == 2) {
     const unsigned grid = grid_for(t_end - t_begin, kScatterTB128, 1u << 20);
 #define ARG1 (u128*)out
     if (batch) KC_WINDOW_LAUNCH(k_window_scatter, u128, uint64_t, kScatterTB128, true, grid);
@@ -1756,11 +1937,14 @@ hipError_t launch_plan_leaves(const unsigned long long* hist, const unsigned lon
   return hipGetLastError();
 }
 
-hipError_t launch_split_hist(bool wide, const void* src, const SplitItem* items,
+hipError_t launch_split_hist(int words, const void* src, const SplitItem* items,
                              const DevState* st, uint64_t max_items, const SplitBin* bins,
                              unsigned long long* subhist, hipStream_t s) {
   const unsigned grid = persistent(max_items, 4096);
-  if (wide)
+  if (words == 4)
+    hipLaunchKernelGGL((k_split_hist<u256, 256>), dim3(grid), dim3(256), 0, s, (const u256*)src,
+                       items, st, bins, subhist);
+  else if (words == 2)
     hipLaunchKernelGGL((k_split_hist<u128, 256>), dim3(grid), dim3(256), 0, s, (const u128*)src,
                        items, st, bins, subhist);
   else
@@ -1769,11 +1953,15 @@ hipError_t launch_split_hist(bool wide, const void* src, const SplitItem* items,
   return hipGetLastError();
 }
 
-hipError_t launch_split_scatter(bool wide, const void* src, void* dst, const SplitItem* items,
+hipError_t launch_split_scatter(int words, const void* src, void* dst, const SplitItem* items,
                                 const DevState* st, uint64_t max_items, const SplitBin* bins,
                                 unsigned long long* cursor, hipStream_t s) {
   const unsigned grid = persistent(max_items, 2048);
-  if (wide)
+  if (words == 4)
+    hipLaunchKernelGGL((k_split_scatter<u256, kSplitTB256, kSplitR>), dim3(grid),
+                       dim3(kSplitTB256), 0, s, (const u256*)src, (u256*)dst, items, st, bins,
+                       cursor);
+  else if (words == 2)
     hipLaunchKernelGGL((k_split_scatter<u128, kSplitTB128, kSplitR>), dim3(grid),
                        dim3(kSplitTB128), 0, s, (const u128*)src, (u128*)dst, items, st, bins,
                        cursor);
@@ -1784,15 +1972,17 @@ hipError_t launch_split_scatter(bool wide, const void* src, void* dst, const Spl
   return hipGetLastError();
 }
 
-uint64_t small_leaf_max(bool wide) {
-  // n + n/7 + 1 <= slots of the one-wave kernel
-  return wide ? 447 : 895;
+uint64_t small_leaf_max(int words) {
+  // n + n/7 + 1 <= slots of the one-wave kernel (256-bit keys: sort-based only)
+  return words == 4 ? 0 : words == 2 ? 447 : 895;
 }
 
-hipError_t launch_leaf_small(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
+hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode) {
-  const uint64_t small_max = mode == 1 ? 0 : small_leaf_max(wide);
+  if (words == 4 && mode != 1) return hipErrorInvalidValue;
+  const bool wide = words == 2;
+  const uint64_t small_max = mode == 1 ? 0 : small_leaf_max(words);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &st->n_large, (uint64_t)1, 0ull);
   hipLaunchKernelGGL(k_classify_leaves, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s,
                      leaves, st, small_max, large_list);
@@ -1818,14 +2008,20 @@ hipError_t launch_leaf_small(bool wide, int keybits, void* bufA, void* bufB, uin
   return hipGetLastError();
 }
 
-hipError_t launch_leaf_large(bool wide, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
+hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
                              hipStream_t s, int mode) {
-  const uint64_t small_max = small_leaf_max(wide);
+  if (words == 4 && mode != 1) return hipErrorInvalidValue;
+  const bool wide = words == 2;
+  const uint64_t small_max = small_leaf_max(words);
   const unsigned glarge = persistent(max_leaves, kPersistentGrid);
   if (mode == 1) {
-    if (wide)
+    if (words == 4)
+      hipLaunchKernelGGL((k_leaf_sort<u256, kLeafTB, kSortMax256>), dim3(glarge), dim3(kLeafTB),
+                         0, s, keybits, (u256*)bufA, (u256*)bufB, tmp_cnt, leaves, st, d_out,
+                         large_list);
+    else if (wide)
       hipLaunchKernelGGL((k_leaf_sort<u128, kLeafTB, kSortMax128>), dim3(glarge), dim3(kLeafTB),
                          0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
                          large_list);
@@ -1894,12 +2090,16 @@ hipError_t launch_plan_out(const uint32_t* d, DevState* st, unsigned long long* 
   return hipGetLastError();
 }
 
-hipError_t launch_concat(bool wide, const void* bufA, const void* bufB, const uint32_t* tmp_cnt,
+hipError_t launch_concat(int words, const void* bufA, const void* bufB, const uint32_t* tmp_cnt,
                          const Leaf* leaves, const uint32_t* d, const unsigned long long* out_off,
                          const DevState* st, uint64_t max_leaves, uint64_t cap,
                          uint64_t* out_keys, uint32_t* out_counts, hipStream_t s) {
   const unsigned grid = persistent((max_leaves + 3) / 4, 16384);
-  if (wide)
+  if (words == 4)
+    hipLaunchKernelGGL(k_concat<u256>, dim3(grid), dim3(256), 0, s, (const u256*)bufA,
+                       (const u256*)bufB, tmp_cnt, leaves, d, out_off, st, cap, out_keys,
+                       out_counts);
+  else if (words == 2)
     hipLaunchKernelGGL(k_concat<u128>, dim3(grid), dim3(256), 0, s, (const u128*)bufA,
                        (const u128*)bufB, tmp_cnt, leaves, d, out_off, st, cap, out_keys,
                        out_counts);
@@ -1910,11 +2110,13 @@ hipError_t launch_concat(bool wide, const void* bufA, const void* bufB, const ui
   return hipGetLastError();
 }
 
-hipError_t launch_check(bool wide, const uint64_t* keys, const uint32_t* counts, uint64_t n,
+hipError_t launch_check(int words, const uint64_t* keys, const uint32_t* counts, uint64_t n,
                         int k, CheckResult* res, hipStream_t s) {
   if (!n) return hipSuccess;
   const unsigned grid = grid_for(n, 256, 4096);
-  if (wide)
+  if (words == 4)
+    hipLaunchKernelGGL(k_check<u256>, dim3(grid), dim3(256), 0, s, keys, counts, n, k, res);
+  else if (words == 2)
     hipLaunchKernelGGL(k_check<u128>, dim3(grid), dim3(256), 0, s, keys, counts, n, k, res);
   else
     hipLaunchKernelGGL(k_check<uint64_t>, dim3(grid), dim3(256), 0, s, keys, counts, n, k, res);
@@ -1925,13 +2127,14 @@ hipError_t launch_check(bool wide, const uint64_t* keys, const uint32_t* counts,
 
 namespace kc {
 
-hipError_t launch_concat_batch(bool wide, const void* bufA, const void* bufB,
+hipError_t launch_concat_batch(int words, const void* bufA, const void* bufB,
                                const uint32_t* tmp_cnt, const Leaf* leaves, const uint32_t* d,
                                const unsigned long long* out_off, const DevState* st,
                                uint64_t max_leaves, uint64_t cap, int k, uint64_t* out_keys,
                                uint32_t* out_counts, uint32_t* out_set, hipStream_t s) {
   const unsigned grid = persistent((max_leaves + 3) / 4, 16384);
-  if (wide)
+  if (words == 4) return hipErrorInvalidValue;
+  if (words == 2)
     hipLaunchKernelGGL(k_concat_batch<u128>, dim3(grid), dim3(256), 0, s, (const u128*)bufA,
                        (const u128*)bufB, tmp_cnt, leaves, d, out_off, st, cap, k, out_keys,
                        out_counts, out_set);

@@ -116,12 +116,7 @@ __global__ void __launch_bounds__(kTB) k_keep_write(const uint64_t* __restrict__
     if (keep) {
       const unsigned long long o = at + before + __popcll(m & ((1ull << lane) - 1));
       out_counts[o] = counts[i];
-      if (words == 1) {
-        out_keys[o] = keys[i];
-      } else {
-        out_keys[2 * o] = keys[2 * i];
-        out_keys[2 * o + 1] = keys[2 * i + 1];
-      }
+      for (int q = 0; q < words; ++q) out_keys[words * o + q] = keys[words * i + q];
     }
     at += row;
     __syncthreads();
@@ -189,10 +184,10 @@ int kc_filter_min_count(const uint64_t* keys, const uint32_t* counts, uint64_t n
   kc::set_last_error("");
   if (!n_out) return bad("n_out is NULL");
   *n_out = 0;
-  if (k < 1 || k > 64) return bad("k must be in [1, 64]");
+  if (k < 1 || k > 128) return bad("k must be in [1, 128]");
   if (n && (!keys || !counts || !out_keys || !out_counts)) return bad("NULL array");
   if (n == 0) return KC_OK;
-  const int words = k > 32 ? 2 : 1;
+  const int words = k <= 32 ? 1 : (k <= 64 ? 2 : 4);
   const hipStream_t st = (hipStream_t)stream;
   const uint64_t nt = (n + kTile - 1) / kTile;
   void* d = nullptr;
@@ -224,19 +219,47 @@ int kc_filter_min_count(const uint64_t* keys, const uint32_t* counts, uint64_t n
 
 namespace {
 
-// Key i of a result as a 128-bit value (words = 1: one uint64 per key; 2: lo, hi).
-__device__ __forceinline__ unsigned __int128 key_at(const uint64_t* keys, uint64_t i, int words) {
-  if (words == 1) return keys[i];
-  return ((unsigned __int128)keys[2 * i + 1] << 64) | keys[2 * i];
+// Key i of a result (W = 1, 2 or 4 words, least significant first) as one
+// comparable value.
+struct Key4 {
+  unsigned __int128 lo, hi;
+};
+__device__ __forceinline__ bool operator<(const Key4& a, const Key4& b) {
+  return a.hi != b.hi ? a.hi < b.hi : a.lo < b.lo;
+}
+__device__ __forceinline__ bool operator==(const Key4& a, const Key4& b) {
+  return a.hi == b.hi && a.lo == b.lo;
+}
+__device__ __forceinline__ bool operator!=(const Key4& a, const Key4& b) { return !(a == b); }
+
+template <int W> struct KeyOf { typedef unsigned __int128 type; };
+template <> struct KeyOf<4> { typedef Key4 type; };
+
+template <int W>
+__device__ __forceinline__ typename KeyOf<W>::type key_at(const uint64_t* keys, uint64_t i) {
+  if constexpr (W == 4) {
+    const uint64_t* p = keys + 4 * i;
+    return Key4{((unsigned __int128)p[1] << 64) | p[0], ((unsigned __int128)p[3] << 64) | p[2]};
+  } else if constexpr (W == 2) {
+    return ((unsigned __int128)keys[2 * i + 1] << 64) | keys[2 * i];
+  } else {
+    return keys[i];
+  }
 }
 
-__device__ __forceinline__ void key_put(uint64_t* keys, uint64_t i, int words,
-                                        unsigned __int128 v) {
-  if (words == 1) {
-    keys[i] = (uint64_t)v;
-  } else {
+template <int W>
+__device__ __forceinline__ void key_put(uint64_t* keys, uint64_t i,
+                                        const typename KeyOf<W>::type& v) {
+  if constexpr (W == 4) {
+    keys[4 * i] = (uint64_t)v.lo;
+    keys[4 * i + 1] = (uint64_t)(v.lo >> 64);
+    keys[4 * i + 2] = (uint64_t)v.hi;
+    keys[4 * i + 3] = (uint64_t)(v.hi >> 64);
+  } else if constexpr (W == 2) {
     keys[2 * i] = (uint64_t)v;
     keys[2 * i + 1] = (uint64_t)(v >> 64);
+  } else {
+    keys[i] = (uint64_t)v;
   }
 }
 
@@ -245,11 +268,12 @@ constexpr int kMergeItems = 8;
 // Merge path: thread t writes merged positions [t*items, t*items + items) of
 // the ordered union of a and b (ties: a first). Its start in a is the
 // largest i with i + j = d and a[i-1] <= b[j] ... found by binary search.
+template <int W>
 __global__ void __launch_bounds__(kTB) k_merge(const uint64_t* __restrict__ ak,
                                                const uint32_t* __restrict__ ac, uint64_t na,
                                                const uint64_t* __restrict__ bk,
                                                const uint32_t* __restrict__ bc, uint64_t nb,
-                                               int words, uint64_t* __restrict__ mk,
+                                               uint64_t* __restrict__ mk,
                                                uint32_t* __restrict__ mc) {
   const uint64_t total = na + nb;
   const uint64_t d = ((uint64_t)blockIdx.x * kTB + threadIdx.x) * kMergeItems;
@@ -259,7 +283,7 @@ __global__ void __launch_bounds__(kTB) k_merge(const uint64_t* __restrict__ ak,
   while (lo < hi) {
     const uint64_t i = (lo + hi + 1) >> 1;  // candidate: take i items of a
     // valid iff a[i-1] <= b[d-i] (a first on ties), i.e. not b[d-i] < a[i-1]
-    if (d - i >= nb || !(key_at(bk, d - i, words) < key_at(ak, i - 1, words))) lo = i;
+    if (d - i >= nb || !(key_at<W>(bk, d - i) < key_at<W>(ak, i - 1))) lo = i;
     else hi = i - 1;
   }
   uint64_t i = lo, j = d - lo;
@@ -267,13 +291,13 @@ __global__ void __launch_bounds__(kTB) k_merge(const uint64_t* __restrict__ ak,
     bool take_a;
     if (i >= na) take_a = false;
     else if (j >= nb) take_a = true;
-    else take_a = !(key_at(bk, j, words) < key_at(ak, i, words));
+    else take_a = !(key_at<W>(bk, j) < key_at<W>(ak, i));
     if (take_a) {
-      key_put(mk, d + t, words, key_at(ak, i, words));
+      key_put<W>(mk, d + t, key_at<W>(ak, i));
       mc[d + t] = ac[i];
       ++i;
     } else {
-      key_put(mk, d + t, words, key_at(bk, j, words));
+      key_put<W>(mk, d + t, key_at<W>(bk, j));
       mc[d + t] = bc[j];
       ++j;
     }
@@ -282,8 +306,8 @@ __global__ void __launch_bounds__(kTB) k_merge(const uint64_t* __restrict__ ak,
 
 // Dedup of the merged sequence: a key present in both inputs sits at two
 // neighbouring positions (a's first); the first keeps the summed count.
+template <int W>
 __global__ void __launch_bounds__(kTB) k_dedup_count(const uint64_t* __restrict__ mk, uint64_t n,
-                                                     int words,
                                                      unsigned long long* __restrict__ tsum) {
   __shared__ uint32_t s;
   if (threadIdx.x == 0) s = 0;
@@ -292,16 +316,16 @@ __global__ void __launch_bounds__(kTB) k_dedup_count(const uint64_t* __restrict_
   uint32_t c = 0;
   for (int j = 0; j < kPer; ++j) {
     const uint64_t i = base + (uint64_t)j * kTB + threadIdx.x;
-    c += (i < n && (i == 0 || key_at(mk, i, words) != key_at(mk, i - 1, words))) ? 1u : 0u;
+    c += (i < n && (i == 0 || key_at<W>(mk, i) != key_at<W>(mk, i - 1))) ? 1u : 0u;
   }
   atomicAdd(&s, c);
   __syncthreads();
   if (threadIdx.x == 0) tsum[blockIdx.x] = s;
 }
 
+template <int W>
 __global__ void __launch_bounds__(kTB) k_dedup_write(const uint64_t* __restrict__ mk,
                                                      const uint32_t* __restrict__ mc, uint64_t n,
-                                                     int words,
                                                      const unsigned long long* __restrict__ tsum,
                                                      uint64_t* __restrict__ out_keys,
                                                      uint32_t* __restrict__ out_counts,
@@ -312,10 +336,10 @@ __global__ void __launch_bounds__(kTB) k_dedup_write(const uint64_t* __restrict_
   for (int j = 0; j < kPer; ++j) {
     const uint64_t i = base + (uint64_t)j * kTB + threadIdx.x;
     bool keep = false;
-    unsigned __int128 key = 0;
+    typename KeyOf<W>::type key{};
     if (i < n) {
-      key = key_at(mk, i, words);
-      keep = i == 0 || key != key_at(mk, i - 1, words);
+      key = key_at<W>(mk, i);
+      keep = i == 0 || key != key_at<W>(mk, i - 1);
     }
     const unsigned long long m = __ballot(keep);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -328,10 +352,10 @@ __global__ void __launch_bounds__(kTB) k_dedup_write(const uint64_t* __restrict_
     }
     if (keep) {
       unsigned long long c = mc[i];
-      if (i + 1 < n && key_at(mk, i + 1, words) == key) c += mc[i + 1];
+      if (i + 1 < n && key_at<W>(mk, i + 1) == key) c += mc[i + 1];
       if (c > 0xFFFFFFFFull) atomicOr(overflow, 1u);
       const unsigned long long o = at + before + __popcll(m & ((1ull << lane) - 1));
-      key_put(out_keys, o, words, key);
+      key_put<W>(out_keys, o, key);
       out_counts[o] = (uint32_t)c;
     }
     at += row;
@@ -348,13 +372,13 @@ extern "C" int kc_merge_counts(const uint64_t* a_keys, const uint32_t* a_counts,
   kc::set_last_error("");
   if (!n_out) return bad("n_out is NULL");
   *n_out = 0;
-  if (k < 1 || k > 64) return bad("k must be in [1, 64]");
+  if (k < 1 || k > 128) return bad("k must be in [1, 128]");
   if ((na && (!a_keys || !a_counts)) || (nb && (!b_keys || !b_counts)))
     return bad("NULL input array");
   const uint64_t n = na + nb;
   if (n && (!out_keys || !out_counts)) return bad("NULL output array");
   if (n == 0) return KC_OK;
-  const int words = k > 32 ? 2 : 1;
+  const int words = k <= 32 ? 1 : (k <= 64 ? 2 : 4);
   const hipStream_t st = (hipStream_t)stream;
   const uint64_t nt = (n + kTile - 1) / kTile;
   void* d = nullptr;
@@ -368,12 +392,30 @@ extern "C" int kc_merge_counts(const uint64_t* a_keys, const uint32_t* a_counts,
     unsigned int* ovf = (unsigned int*)(tsum + nt + 1);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (unsigned long long*)ovf, (uint64_t)1);
     const uint64_t threads = (n + kMergeItems - 1) / kMergeItems;
-    hipLaunchKernelGGL(k_merge, dim3((unsigned)((threads + kTB - 1) / kTB)), dim3(kTB), 0, st,
-                       a_keys, a_counts, na, b_keys, b_counts, nb, words, mk, mc);
-    hipLaunchKernelGGL(k_dedup_count, dim3((unsigned)nt), dim3(kTB), 0, st, mk, n, words, tsum);
+    const dim3 gm((unsigned)((threads + kTB - 1) / kTB)), gt((unsigned)nt);
+    if (words == 4) {
+      hipLaunchKernelGGL(k_merge<4>, gm, dim3(kTB), 0, st, a_keys, a_counts, na, b_keys, b_counts,
+                         nb, mk, mc);
+      hipLaunchKernelGGL(k_dedup_count<4>, gt, dim3(kTB), 0, st, mk, n, tsum);
+    } else if (words == 2) {
+      hipLaunchKernelGGL(k_merge<2>, gm, dim3(kTB), 0, st, a_keys, a_counts, na, b_keys, b_counts,
+                         nb, mk, mc);
+      hipLaunchKernelGGL(k_dedup_count<2>, gt, dim3(kTB), 0, st, mk, n, tsum);
+    } else {
+      hipLaunchKernelGGL(k_merge<1>, gm, dim3(kTB), 0, st, a_keys, a_counts, na, b_keys, b_counts,
+                         nb, mk, mc);
+      hipLaunchKernelGGL(k_dedup_count<1>, gt, dim3(kTB), 0, st, mk, n, tsum);
+    }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tsum, nt);
-    hipLaunchKernelGGL(k_dedup_write, dim3((unsigned)nt), dim3(kTB), 0, st, mk, mc, n, words,
-                       tsum, out_keys, out_counts, ovf);
+    if (words == 4)
+      hipLaunchKernelGGL(k_dedup_write<4>, gt, dim3(kTB), 0, st, mk, mc, n, tsum, out_keys,
+                         out_counts, ovf);
+    else if (words == 2)
+      hipLaunchKernelGGL(k_dedup_write<2>, gt, dim3(kTB), 0, st, mk, mc, n, tsum, out_keys,
+                         out_counts, ovf);
+    else
+      hipLaunchKernelGGL(k_dedup_write<1>, gt, dim3(kTB), 0, st, mk, mc, n, tsum, out_keys,
+                         out_counts, ovf);
     chk(hipGetLastError(), "merge launch");
     uint64_t h[2] = {0, 0};
     chk(hipMemcpyAsync(&h[0], tsum + nt, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");

@@ -208,7 +208,7 @@ struct Call {
   uint64_t concat_leaves = 0;        // leaf slots the deferred concat covers
   // derived
   uint64_t N = 0, off0 = 0;
-  bool wide = false;
+  int words = 1;  // 64-bit words per key: 1, 2 or 4
   int keybits = 0, sb = 0, nb = 0, slots_log2 = 0;
   size_t ksz = 8;
   uint64_t C = 0, T = 0, H = 0;
@@ -302,16 +302,26 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
   std::vector<uint32_t> ord(R);
   for (uint32_t i = 0; i < R; ++i) ord[i] = i;
   std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return ridx[a] < ridx[b]; });
+  // key bits below a parent leaf's prefix (up to 256 bits for k <= 128)
+  struct Rel {
+    u128 lo = 0, hi = 0;
+    Rel shl(int n) const {  // n < 256
+      if (n == 0) return *this;
+      if (n >= 128) return Rel{0, lo << (n - 128)};
+      return Rel{lo << n, (hi << n) | (lo >> (128 - n))};
+    }
+    bool operator<(const Rel& o) const { return hi != o.hi ? hi < o.hi : lo < o.lo; }
+  };
   struct Part {
     uint64_t begin, end;
-    u128 rel;     // key bits below the parent leaf's prefix consumed so far
+    Rel rel;      // key bits below the parent leaf's prefix consumed so far
     int bits;     // key bits consumed in total (from the most significant end)
     int buf;      // buffer holding its records
     uint32_t root;
   };
   struct Done {
     uint32_t root;
-    u128 start;  // first key of its range, relative to the parent's prefix
+    Rel start;   // first key of its range, relative to the parent's prefix
     kc::Leaf leaf;
     uint32_t d;
   };
@@ -319,13 +329,13 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
   for (uint32_t r = 0; r < R; ++r) {
     const kc::Leaf& lf = rlv[ord[r]];
     if ((int)lf.bits >= q.keybits) fail(KC_E_INTERNAL, "single-key partition overflowed its table");
-    split.push_back(Part{lf.begin, lf.end, 0, (int)lf.bits, (int)lf.buf, r});  // root = rank r
+    split.push_back(Part{lf.begin, lf.end, Rel{}, (int)lf.bits, (int)lf.buf, r});  // root = rank r
     ++S.n_overflow;
   }
   std::vector<Done> done;
   void* bufs[2] = {c.bufA.p, c.bufB.p};
   constexpr int kRefineBits = 2;
-  const uint64_t tile = (uint64_t)kc::split_tile(q.wide);
+  const uint64_t tile = (uint64_t)kc::split_tile(q.words);
   int level = 0;
   while (!split.empty()) {
     ++level;
@@ -365,7 +375,7 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
       unsigned long long ni = it_src.size();
       upload_sync(&dst_state->n_items, &ni, 8, st);
       hipchk(kc::launch_fill_u64((unsigned long long*)c.subhist.p, hoff, 0, st), "fill launch");
-      hipchk(kc::launch_split_hist(q.wide, bufs[src], (kc::SplitItem*)c.items.p, dst_state,
+      hipchk(kc::launch_split_hist(q.words, bufs[src], (kc::SplitItem*)c.items.p, dst_state,
                                    it_src.size(), (kc::SplitBin*)c.bins.p,
                                    (unsigned long long*)c.subhist.p, st),
              "split histogram launch");
@@ -382,15 +392,17 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
         for (uint64_t j = 0; j < (1ull << sbn.nbits); ++j) {
           const uint64_t cnt = hsub[sbn.hist_off + j];
           hcur[sbn.hist_off + j] = r;
-          if (cnt)
-            next.push_back(Part{r, r + cnt, (b.rel << sbn.nbits) | (u128)j,
-                                b.bits + (int)sbn.nbits, 1 - b.buf, b.root});
+          if (cnt) {
+            Rel nr = b.rel.shl((int)sbn.nbits);
+            nr.lo |= (u128)j;
+            next.push_back(Part{r, r + cnt, nr, b.bits + (int)sbn.nbits, 1 - b.buf, b.root});
+          }
           r += cnt;
         }
         if (r != b.end) fail(KC_E_INTERNAL, "split histogram does not match partition size");
       }
       upload_sync(c.cursor2.p, hcur.data(), hoff * 8, st);
-      hipchk(kc::launch_split_scatter(q.wide, bufs[src], bufs[1 - src],
+      hipchk(kc::launch_split_scatter(q.words, bufs[src], bufs[1 - src],
                                       (kc::SplitItem*)c.items.p, dst_state, it_src.size(),
                                       (kc::SplitBin*)c.bins.p, (unsigned long long*)c.cursor2.p,
                                       st),
@@ -408,11 +420,11 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
     upload_sync(c.aleaves.p, al.data(), na * sizeof(kc::Leaf), st);
     unsigned long long nlu = na;
     upload_sync(&dst_state->n_leaves, &nlu, 8, st);
-    hipchk(kc::launch_leaf_small(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+    hipchk(kc::launch_leaf_small(q.words, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
                                  (uint32_t*)c.alarge.p, st, q.o.mode),
            "leaf count launch");
-    hipchk(kc::launch_leaf_large(q.wide, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+    hipchk(kc::launch_leaf_large(q.words, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
                                  q.slots_log2, (uint32_t*)c.alarge.p, st, q.o.mode),
            "leaf count launch");
@@ -428,7 +440,7 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
         ++S.n_overflow;
         split.push_back(b);
       } else {
-        done.push_back(Done{b.root, b.rel << (q.keybits - b.bits), al[i], hd[i]});
+        done.push_back(Done{b.root, b.rel.shl(q.keybits - b.bits), al[i], hd[i]});
         S.max_leaf_windows = std::max(S.max_leaf_windows, b.end - b.begin);
       }
     }
@@ -493,7 +505,7 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
   tm.mark(ST_OUT);
   q.concat_leaves = nl;
   if (q.oa) return;  // the caller allocates the output, then runs the concat
-  hipchk(kc::launch_concat(q.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+  hipchk(kc::launch_concat(q.words, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                            (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
                            (unsigned long long*)c.outoff.p, dst_state, nl, q.cap, q.out_keys,
                            q.out_counts, st),
@@ -507,7 +519,7 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
 // synchronization and no allocation happens here (buffers are prepared by
 // pipeline_prepare), so a run can be captured into a graph.
 struct Pipe {
-  bool wide = false;
+  int words = 1;  // 64-bit words per key: 1, 2 or 4
   int k = 0, keybits = 0, sb = 0, slots_log2 = 0;
   uint64_t byte_begin = 0, byte_end = 0;  // bytes scanned for windows
   uint64_t rec_bound = 0;                 // upper bound of the records (windows)
@@ -519,21 +531,22 @@ struct Pipe {
 };
 
 void pipe_bounds(Pipe& p) {
-  const uint64_t tile = (uint64_t)kc::split_tile(p.wide);
+  const uint64_t tile = (uint64_t)kc::split_tile(p.words);
   const uint64_t nb = 1ull << p.sb;
   p.max_items = p.rec_bound / tile + nb + 1;
   p.max_leaves = std::min<uint64_t>(nb << kc::kSplitMaxBits, 2 * p.rec_bound / p.T + 2 * nb) + 1;
 }
 
-// 64-base chunks of the packed stream (two chunks of padding).
-uint64_t packed_chunks(uint64_t n_bytes) { return (n_bytes + 63) / 64 + 2; }
+// 64-base chunks of the packed stream (five chunks of padding: the window
+// kernels of keys over 64 bases read five mask words from a window start).
+uint64_t packed_chunks(uint64_t n_bytes) { return (n_bytes + 63) / 64 + 5; }
 
 // The arena buffers a pipeline run needs: f(member, bytes, name) per buffer.
 // The one list both allocation (pipeline_prepare) and the memory estimates of
 // the server (scratch_growth) read.
 template <class F>
 void pipeline_needs(const Pipe& p, F&& f) {
-  const size_t ksz = p.wide ? 16 : 8;
+  const size_t ksz = 8 * p.words;
   const uint64_t nb = 1ull << p.sb;
   f(&Ctx::bufA, std::max<uint64_t>(p.rec_bound, 1) * ksz, "record buffer A");
   f(&Ctx::bufB, std::max<uint64_t>(p.rec_bound, 1) * ksz, "record buffer B");
@@ -582,24 +595,24 @@ struct PipeOut {
 void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, const PipeOut& out,
                       hipStream_t st) {
   hipchk(kc::launch_fill_u64((unsigned long long*)c.hist.p, 1ull << p.sb, 0, st), "fill launch");
-  hipchk(kc::launch_window_hist(p.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
+  hipchk(kc::launch_window_hist(p.words, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
                                 (uint64_t*)c.endm.p, p.byte_begin, p.byte_end, p.k, p.keybits,
                                 p.sb, p.batch, (unsigned long long*)c.hist.p, &dstate->W, st),
          "window histogram launch");
   tm.mark(ST_HIST);
   hipchk(kc::launch_plan_shards((unsigned long long*)c.hist.p, p.order, p.sb, p.keybits, p.T, p.H,
-                                kc::split_tile(p.wide), (unsigned long long*)c.sbegin.p,
+                                kc::split_tile(p.words), (unsigned long long*)c.sbegin.p,
                                 (unsigned long long*)c.cursor.p, (kc::SplitBin*)c.bins.p,
                                 (kc::SplitItem*)c.items.p, (unsigned long long*)c.itemoff.p,
                                 (unsigned long long*)c.subhist.p, p.max_leaves, p.max_items,
                                 dstate, st),
          "plan_shards launch");
-  hipchk(kc::launch_window_scatter(p.wide, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
+  hipchk(kc::launch_window_scatter(p.words, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
                                    (uint64_t*)c.endm.p, p.byte_begin, p.byte_end, p.k, p.keybits,
                                    p.sb, p.batch, (unsigned long long*)c.cursor.p, c.bufA.p, st),
          "owner scatter launch");
   tm.mark(ST_SCATTER);
-  hipchk(kc::launch_split_hist(p.wide, c.bufA.p, (kc::SplitItem*)c.items.p, dstate, p.max_items,
+  hipchk(kc::launch_split_hist(p.words, c.bufA.p, (kc::SplitItem*)c.items.p, dstate, p.max_items,
                                (kc::SplitBin*)c.bins.p, (unsigned long long*)c.subhist.p, st),
          "split histogram launch");
   tm.mark(ST_SPLIT_HIST);
@@ -607,17 +620,17 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
                                 (kc::SplitBin*)c.bins.p, p.sb, (unsigned long long*)c.subhist.p,
                                 (kc::Leaf*)c.leaves.p, (unsigned long long*)c.cursor2.p, st),
          "plan_leaves launch");
-  hipchk(kc::launch_split_scatter(p.wide, c.bufA.p, c.bufB.p, (kc::SplitItem*)c.items.p, dstate,
+  hipchk(kc::launch_split_scatter(p.words, c.bufA.p, c.bufB.p, (kc::SplitItem*)c.items.p, dstate,
                                   p.max_items, (kc::SplitBin*)c.bins.p,
                                   (unsigned long long*)c.cursor2.p, st),
          "split scatter launch");
   tm.mark(ST_SPLIT);
-  hipchk(kc::launch_leaf_small(p.wide, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+  hipchk(kc::launch_leaf_small(p.words, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
                                (uint32_t*)c.large.p, st, p.mode),
          "leaf count launch");
   tm.mark(ST_LEAF_SMALL);
-  hipchk(kc::launch_leaf_large(p.wide, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+  hipchk(kc::launch_leaf_large(p.words, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
                                p.slots_log2, (uint32_t*)c.large.p, st, p.mode),
          "leaf count launch");
@@ -628,13 +641,13 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
   tm.mark(ST_OUT);
   if (!out.concat) return;
   if (out.set)
-    hipchk(kc::launch_concat_batch(p.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+    hipchk(kc::launch_concat_batch(p.words, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                    (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
                                    (unsigned long long*)c.outoff.p, dstate, p.max_leaves, out.cap,
                                    p.k, out.keys, out.counts, out.set, st),
            "concat launch");
   else
-    hipchk(kc::launch_concat(p.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+    hipchk(kc::launch_concat(p.words, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                              (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
                              (unsigned long long*)c.outoff.p, dstate, p.max_leaves, out.cap,
                              out.keys, out.counts, st),
@@ -643,9 +656,9 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
 }
 
 // Leaf table size and leaf size targets from the options.
-void table_params(const kc_options& o, bool wide, int& slots_log2, uint64_t& C, uint64_t& T,
+void table_params(const kc_options& o, int words, int& slots_log2, uint64_t& C, uint64_t& T,
                   uint64_t& H) {
-  const int max_slots = kc::max_leaf_slots_log2(wide);
+  const int max_slots = kc::max_leaf_slots_log2(words);
   slots_log2 = o.table_slots_log2 > 0 ? std::min(std::max(o.table_slots_log2, 10), max_slots)
                                       : max_slots;
   C = 1ull << slots_log2;
@@ -668,16 +681,16 @@ int shard_bits_for(const kc_options& o, int P, uint64_t rec_bound, uint64_t T, i
 // The pipeline of a plain call over n_bytes bytes.
 Pipe plain_pipe(uint64_t n_bytes, int k, int P, const kc_options& o) {
   Pipe p;
-  p.wide = k > 32;
+  p.words = k <= 32 ? 1 : (k <= 64 ? 2 : 4);
   p.k = k;
   p.keybits = 2 * k;
   uint64_t C = 0;
-  table_params(o, p.wide, p.slots_log2, C, p.T, p.H);
+  table_params(o, p.words, p.slots_log2, C, p.T, p.H);
   p.sb = shard_bits_for(o, P, n_bytes, p.T, p.keybits);
   p.byte_begin = 0;
   p.byte_end = n_bytes;
   p.rec_bound = n_bytes;  // byte count: an upper bound of the window count
-  p.mode = o.mode;
+  p.mode = p.words == 4 ? 1 : o.mode;
   pipe_bounds(p);
   return p;
 }
@@ -701,7 +714,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   auto t_host0 = std::chrono::steady_clock::now();
   if (!n_out) fail(KC_E_INVAL, "n_out is NULL");
   *n_out = 0;
-  if (k < 1 || k > 64) fail(KC_E_INVAL, "k must be in [1, 64]");
+  if (k < 1 || k > 128) fail(KC_E_INVAL, "k must be in [1, 128]");
   if (P < 1) fail(KC_E_INVAL, "P must be >= 1");
   if (!offsets) fail(KC_E_INVAL, "offsets is NULL");
   if (n_reads && !reads) fail(KC_E_INVAL, "reads is NULL");
@@ -710,6 +723,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   std::memset(&q.o, 0, sizeof(q.o));
   if (opt) q.o = *opt;
   if (q.o.mode != 0 && q.o.mode != 1) fail(KC_E_INVAL, "mode must be 0 or 1");
+  if (k > 64) q.o.mode = 1;  // keys over 128 bits: sort-based leaves only
 
   Ctx& c = context();
   std::memset(&g_stats, 0, sizeof(g_stats));
@@ -744,10 +758,10 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
     return KC_OK;
   }
   const Pipe p0 = plain_pipe(q.N, k, P, q.o);
-  q.wide = p0.wide;
+  q.words = p0.words;
   q.keybits = p0.keybits;
-  q.ksz = q.wide ? 16 : 8;
-  table_params(q.o, q.wide, q.slots_log2, q.C, q.T, q.H);
+  q.ksz = 8 * q.words;
+  table_params(q.o, q.words, q.slots_log2, q.C, q.T, q.H);
   q.sb = p0.sb;
   q.nb = 1 << q.sb;
   Pipe p = p0;
@@ -779,11 +793,11 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   S.large_distinct = ds.large_distinct;
   if (ds.count_overflow) fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
   if (oa) {
-    const int r = oa->fn(oa->user, ds.D, q.wide ? 2 : 1, &out_keys, &out_counts);
+    const int r = oa->fn(oa->user, ds.D, q.words, &out_keys, &out_counts);
     if (r != KC_OK) fail(r, "output allocation of " + std::to_string(ds.D) + " pairs failed");
     cap = ds.D;
     tm.mark(ST_NONE);
-    hipchk(kc::launch_concat(q.wide, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+    hipchk(kc::launch_concat(q.words, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                              (kc::Leaf*)c.leaves.p, (uint32_t*)c.dcnt.p,
                              (unsigned long long*)c.outoff.p, dstate, q.concat_leaves, cap,
                              out_keys, out_counts, st),
@@ -799,7 +813,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
     hipchk(kc::launch_fill_u64((unsigned long long*)&dstate->check, sizeof(kc::CheckResult) / 8,
                                0, st),
            "fill launch");
-    hipchk(kc::launch_check(q.wide, out_keys, out_counts, ds.D, k, &dstate->check, st),
+    hipchk(kc::launch_check(q.words, out_keys, out_counts, ds.D, k, &dstate->check, st),
            "check launch");
     tm.mark(ST_CHECK);
     const kc::DevState d2 = read_state(c, st);
@@ -926,7 +940,7 @@ int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_byt
       });
       int slots_log2;
       uint64_t Cs, Tw, Hw;
-      table_params(b->o, true, slots_log2, Cs, Tw, Hw);  // the smaller (wide) leaf target
+      table_params(b->o, 2, slots_log2, Cs, Tw, Hw);  // the smaller (two-word) leaf target
       const uint64_t per_shard = (Tw << kc::kSplitMaxBits) / 2;
       size_t i = 0;
       while (i < sk.size()) {
@@ -971,9 +985,9 @@ int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_byt
     Pipe& p = C.pipe;
     p.k = C.k;
     p.keybits = 2 * C.k + C.set_bits;
-    p.wide = p.keybits > 64;
+    p.words = p.keybits > 64 ? 2 : 1;
     uint64_t Cslots;
-    table_params(b->o, p.wide, p.slots_log2, Cslots, p.T, p.H);
+    table_params(b->o, p.words, p.slots_log2, Cslots, p.T, p.H);
     p.rec_bound = std::max<uint64_t>(bytes, 1);
     p.sb = b->o.shard_bits > 0 ? std::min(b->o.shard_bits, kc::max_shard_bits())
                                : std::max(shard_bits_for(b->o, P, p.rec_bound, p.T, p.keybits),
@@ -1222,7 +1236,7 @@ int count_with_alloc(const uint8_t* reads, const uint64_t* offsets, uint64_t n_r
 
 namespace {
 uint64_t growth_of(const Ctx* c, uint64_t n_bytes, int k, int P, const kc_options* opt) {
-  if (n_bytes == 0 || k < 1 || k > 64 || P < 1) return 0;
+  if (n_bytes == 0 || k < 1 || k > 128 || P < 1) return 0;
   kc_options o;
   std::memset(&o, 0, sizeof(o));
   if (opt) o = *opt;
@@ -1332,7 +1346,7 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
 }
 
 uint64_t kc_max_outputs(const uint64_t* host_offsets, uint64_t n_reads, int k) {
-  if (!host_offsets || k < 1 || k > 64) return 0;
+  if (!host_offsets || k < 1 || k > 128) return 0;
   uint64_t w = 0;
   for (uint64_t i = 0; i < n_reads; ++i) {
     if (host_offsets[i + 1] < host_offsets[i]) return 0;

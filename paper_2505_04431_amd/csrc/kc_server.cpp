@@ -320,7 +320,7 @@ int kc_server_submit(kc_server* s, const uint8_t* reads, const uint64_t* offsets
   return server_guard([&]() -> int {
     if (!s || !job_id) return set_err(KC_E_INVAL, "server or job id pointer is NULL");
     *job_id = 0;
-    if (k < 1 || k > 64) return set_err(KC_E_INVAL, "k must be in [1, 64]");
+    if (k < 1 || k > 128) return set_err(KC_E_INVAL, "k must be in [1, 128]");
     if (P < 1) return set_err(KC_E_INVAL, "P must be >= 1");
     if (!offsets) return set_err(KC_E_INVAL, "offsets is NULL");
     if (n_reads && !reads) return set_err(KC_E_INVAL, "reads is NULL");
@@ -341,7 +341,7 @@ int kc_server_submit(kc_server* s, const uint8_t* reads, const uint64_t* offsets
     }
     if (offn < off0) return set_err(KC_E_INVAL, "offsets must be non-decreasing");
     const uint64_t n_bytes = offn - off0;
-    const uint64_t pair = k > 32 ? 20 : 12;
+    const uint64_t pair = 8 * (uint64_t)(k <= 32 ? 1 : k <= 64 ? 2 : 4) + 4;
     // the number of windows bounds the distinct keys; a hint replaces the bound
     const uint64_t bound = n_bytes * pair;
     const uint64_t est = distinct_hint ? std::min(bound, distinct_hint * pair) : bound;
@@ -438,7 +438,7 @@ int kc_server_result_copy(kc_server* s, uint64_t job_id, uint64_t* out_keys,
       keys = j->keys;
       counts = j->counts;
       n = j->n_out;
-      words = j->k > 32 ? 2 : 1;
+      words = j->k <= 32 ? 1 : (j->k <= 64 ? 2 : 4);
     }
     *n_out = n;
     if (n > out_capacity) return set_err(KC_E_CAPACITY, "output capacity too small");

@@ -205,6 +205,15 @@ def last_stats() -> dict:
     return d
 
 
+def key_words(k: int) -> int:
+    """64-bit words per key: 1 (k <= 32), 2 (k <= 64), 4 (k <= 128)."""
+    return 1 if k <= 32 else (2 if k <= 64 else 4)
+
+
+def _key_shape(n: int, words: int):
+    return (n, words) if words > 1 else (n,)
+
+
 def _check_tensor(t, what, dtypes):
     import torch
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
@@ -241,15 +250,16 @@ def count(reads, offsets, k: int, P: int = 1, opts: KcOptions | None = None, str
     """Count canonical k-mers of device reads.
 
     reads: uint8 CUDA tensor; offsets: int64 CUDA tensor of n_reads+1 offsets.
-    Returns (keys, counts): int64 tensors [D] (k <= 32) or [D, 2] as (lo, hi)
-    words (k > 32), and int32 counts [D] (bit patterns of uint64 / uint32).
+    Returns (keys, counts): int64 tensors [D] (k <= 32) or [D, w] with the w = 2
+    (k <= 64) or 4 (k <= 128) words of a key, least significant first, and
+    int32 counts [D] (bit patterns of uint64 / uint32).
     """
     import torch
     if capacity is None:
         capacity = max_outputs(offsets.cpu().numpy().view(np.uint64), k)
     capacity = max(1, int(capacity))
-    words = 2 if k > 32 else 1
-    keys = torch.empty((capacity, words) if words == 2 else (capacity,), dtype=torch.int64,
+    words = key_words(k)
+    keys = torch.empty(_key_shape(capacity, words), dtype=torch.int64,
                        device=reads.device)
     counts = torch.empty(capacity, dtype=torch.int32, device=reads.device)
     n = count_into(reads, offsets, k, P, keys, counts, capacity, opts, stream)
@@ -295,12 +305,12 @@ def merge_counts(a_keys, a_counts, b_keys, b_counts, k: int, stream=None):
     for t, nm in ((a_counts, "a_counts"), (b_counts, "b_counts")):
         _check_tensor(t, nm, (torch.int32, torch.uint32))
     na, nb = a_counts.numel(), b_counts.numel()
-    words = 2 if k > 32 else 1
+    words = key_words(k)
     if a_keys.numel() != na * words or b_keys.numel() != nb * words:
         raise ValueError("keys must hold %d word(s) per count" % words)
     dev = a_counts.device
     n = max(1, na + nb)
-    ok = torch.empty((n, 2) if words == 2 else (n,), dtype=torch.int64, device=dev)
+    ok = torch.empty(_key_shape(n, words), dtype=torch.int64, device=dev)
     oc = torch.empty(n, dtype=torch.int32, device=dev)
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
@@ -353,8 +363,8 @@ def count_chunked(host_reads, host_offsets, k: int, P: int = 1, chunk_bytes: int
     offs = np.ascontiguousarray(host_offsets, dtype=np.uint64)
     n_reads = offs.size - 1
     dev = torch.device("cuda", torch.cuda.current_device())
-    words = 2 if k > 32 else 1
-    keys = torch.empty((0, 2) if words == 2 else (0,), dtype=torch.int64, device=dev)
+    words = key_words(k)
+    keys = torch.empty(_key_shape(0, words), dtype=torch.int64, device=dev)
     counts = torch.empty(0, dtype=torch.int32, device=dev)
     r = 0
     while r < n_reads:
@@ -497,10 +507,9 @@ class Server:
         import torch
         self.wait(job)
         info = self.info(job)
-        n, words = int(info["distinct"]), (2 if info["k"] > 32 else 1)
+        n, words = int(info["distinct"]), key_words(info["k"])
         dev = torch.device("cuda", torch.cuda.current_device())
-        keys = torch.empty((max(n, 1), words) if words == 2 else (max(n, 1),), dtype=torch.int64,
-                           device=dev)
+        keys = torch.empty(_key_shape(max(n, 1), words), dtype=torch.int64, device=dev)
         counts = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         if stream is None:
             stream = torch.cuda.current_stream(dev).cuda_stream

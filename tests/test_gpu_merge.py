@@ -154,4 +154,4 @@ def test_merge_errors():
     with pytest.raises(kc.KcError):
         kc.merge_counts(ek, e, ek, e, 0)
     with pytest.raises(kc.KcError):
-        kc.merge_counts(ek, e, ek, e, 65)
+        kc.merge_counts(ek, e, ek, e, 129)
