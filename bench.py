@@ -381,6 +381,10 @@ def main() -> int:
     ap.add_argument("--fastq-steps", type=int, default=5,
                     help="calls of the FASTQ parser on the workload's reads as FASTQ text "
                          "(0: skip)")
+    ap.add_argument("--long-k", type=int, default=100,
+                    help="k of the long-key leg (65..128: four-word keys, sort-based leaves)")
+    ap.add_argument("--long-k-steps", type=int, default=3,
+                    help="calls of the long-key leg to time (0: skip)")
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="size of the plain copy kernel timed for the achievable HBM rate")
     args = ap.parse_args()
@@ -483,6 +487,32 @@ def main() -> int:
                      "note": "kc_options.mode = 1: each leaf's records sorted in LDS and "
                              "run-length accumulated instead of counted in a hash table"}
 
+    # keys of more than 64 bases on the same reads
+    long_k = None
+    if args.long_k_steps > 0:
+        kl = args.long_k
+        cap_l = kc.max_outputs(offs, kl)
+        keys_l = torch.empty((max(cap_l, 1), 4), dtype=torch.int64, device=dev)
+        cnts_l = torch.empty(max(cap_l, 1), dtype=torch.int32, device=dev)
+        ol = kc.options(timing=1)
+        kc.count_into(rt, ot, kl, P, keys_l, cnts_l, max(cap_l, 1), ol, stream.cuda_stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        leaf_l = 0.0
+        for _ in range(args.long_k_steps):
+            n_l = kc.count_into(rt, ot, kl, P, keys_l, cnts_l, max(cap_l, 1), ol,
+                                stream.cuda_stream)
+            leaf_l += kc.last_stats()["ms_stage"]["leaf_large"]
+        torch.cuda.synchronize()
+        ms_l = (time.perf_counter() - t1) * 1e3 / args.long_k_steps
+        st_l = kc.last_stats()
+        long_k = {"k": kl, "value": round(st_l["valid_windows"] / (ms_l / 1e3), 1),
+                  "unit": "k-mers/s", "ms_per_step": round(ms_l, 4),
+                  "leaf_ms": round(leaf_l / args.long_k_steps, 4),
+                  "valid_windows": st_l["valid_windows"], "distinct": n_l,
+                  "note": "256-bit keys (four words), counted by sorting each leaf in LDS"}
+        del keys_l, cnts_l
+
     # the same reads as FASTQ text on the device: parse, then count the parsed reads
     fastq = None
     if args.fastq_steps > 0:
@@ -561,6 +591,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "sort_mode": sort_mode,
         "fastq": fastq,
+        "long_k": long_k,
         "batched": batched,
         "served": served,
     }
