@@ -327,12 +327,17 @@ def served_leg(n_jobs: int, budget_gib: float, workers: int, load: float) -> dic
             arr.append(t)
             t += rng.expovariate(ld * capacity)
         infos = run_pass(arr)
+        slow.extend({"load": ld, "k": i["k"], "valid_windows": i["valid_windows"],
+                     "worker": i["worker"], "wait_ms": round(i["t_start_ms"] - i["t_submit_ms"], 3),
+                     "run_ms": round(i["t_end_ms"] - i["t_start_ms"], 3)}
+                    for i in sorted(infos, key=lambda i: i["t_start_ms"] - i["t_end_ms"])[:2])
         lat = sorted(i["t_end_ms"] - i["t_submit_ms"] for i in infos)
         wait = sorted(i["t_start_ms"] - i["t_submit_ms"] for i in infos)
         span = (max(i["t_end_ms"] for i in infos) - min(i["t_submit_ms"] for i in infos)) / 1e3
         W = sum(i["valid_windows"] for i in infos)
         return infos, lat, wait, span, W
 
+    slow = []  # the two longest-running jobs of each pass
     sweep = []
     for ld in (0.5, 0.9):  # the other arrival rates, beside the headline one
         _, lat_s, _, span_s, W_s = poisson_pass(ld)
@@ -352,7 +357,7 @@ def served_leg(n_jobs: int, budget_gib: float, workers: int, load: float) -> dic
         "load": load, "latency_p50_ms": pct(lat, 0.5), "latency_p99_ms": pct(lat, 0.99),
         "wait_p50_ms": pct(wait, 0.5), "wait_p99_ms": pct(wait, 0.99),
         "peak_bytes": st["bytes_peak"], "estimate_misses": st["estimate_misses"],
-        "gen_s": round(t_gen, 1), "load_sweep": sweep,
+        "gen_s": round(t_gen, 1), "load_sweep": sweep, "longest_jobs": slow,
         "note": "seeded sample of the 10,000 jobs (same distribution); inputs resident; Poisson "
                 "arrivals at load x capacity measured by a calibration pass; latency = "
                 "completion - submission",
@@ -487,32 +492,6 @@ def main() -> int:
                      "note": "kc_options.mode = 1: each leaf's records sorted in LDS and "
                              "run-length accumulated instead of counted in a hash table"}
 
-    # keys of more than 64 bases on the same reads
-    long_k = None
-    if args.long_k_steps > 0:
-        kl = args.long_k
-        cap_l = kc.max_outputs(offs, kl)
-        keys_l = torch.empty((max(cap_l, 1), 4), dtype=torch.int64, device=dev)
-        cnts_l = torch.empty(max(cap_l, 1), dtype=torch.int32, device=dev)
-        ol = kc.options(timing=1)
-        kc.count_into(rt, ot, kl, P, keys_l, cnts_l, max(cap_l, 1), ol, stream.cuda_stream)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        leaf_l = 0.0
-        for _ in range(args.long_k_steps):
-            n_l = kc.count_into(rt, ot, kl, P, keys_l, cnts_l, max(cap_l, 1), ol,
-                                stream.cuda_stream)
-            leaf_l += kc.last_stats()["ms_stage"]["leaf_large"]
-        torch.cuda.synchronize()
-        ms_l = (time.perf_counter() - t1) * 1e3 / args.long_k_steps
-        st_l = kc.last_stats()
-        long_k = {"k": kl, "value": round(st_l["valid_windows"] / (ms_l / 1e3), 1),
-                  "unit": "k-mers/s", "ms_per_step": round(ms_l, 4),
-                  "leaf_ms": round(leaf_l / args.long_k_steps, 4),
-                  "valid_windows": st_l["valid_windows"], "distinct": n_l,
-                  "note": "256-bit keys (four words), counted by sorting each leaf in LDS"}
-        del keys_l, cnts_l
-
     # the same reads as FASTQ text on the device: parse, then count the parsed reads
     fastq = None
     if args.fastq_steps > 0:
@@ -541,6 +520,52 @@ def main() -> int:
                          "qualities), then kc_count on its output"}
         del tt, pr, po
 
+    # the legs above leave this thread's scratch arena sized for their largest
+    # call (32-byte records for the long keys); the batched and served legs
+    # start from released device memory
+    kc.lib().kc_release_scratch()
+    torch.cuda.empty_cache()
+
+    batched = None
+    if args.batched_sets > 0:
+        batched = batched_leg(args.batched_sets, int(args.wave_gb * 1e9), not args.no_tune)
+
+    served = None
+    if args.served_jobs > 0:
+        kc.lib().kc_release_scratch()
+        torch.cuda.empty_cache()
+        served = served_leg(args.served_jobs, args.served_budget_gib, args.served_workers,
+                            args.served_load)
+
+    # keys of more than 64 bases on the same reads (last: its 32-byte records
+    # size this thread's scratch arena far above the other legs')
+    long_k = None
+    if args.long_k_steps > 0:
+        kl = args.long_k
+        cap_l = kc.max_outputs(offs, kl)
+        keys_l = torch.empty((max(cap_l, 1), 4), dtype=torch.int64, device=dev)
+        cnts_l = torch.empty(max(cap_l, 1), dtype=torch.int32, device=dev)
+        ol = kc.options(timing=1)
+        kc.count_into(rt, ot, kl, P, keys_l, cnts_l, max(cap_l, 1), ol, stream.cuda_stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        leaf_l = 0.0
+        for _ in range(args.long_k_steps):
+            n_l = kc.count_into(rt, ot, kl, P, keys_l, cnts_l, max(cap_l, 1), ol,
+                                stream.cuda_stream)
+            leaf_l += kc.last_stats()["ms_stage"]["leaf_large"]
+        torch.cuda.synchronize()
+        ms_l = (time.perf_counter() - t1) * 1e3 / args.long_k_steps
+        st_l = kc.last_stats()
+        long_k = {"k": kl, "value": round(st_l["valid_windows"] / (ms_l / 1e3), 1),
+                  "unit": "k-mers/s", "ms_per_step": round(ms_l, 4),
+                  "leaf_ms": round(leaf_l / args.long_k_steps, 4),
+                  "valid_windows": st_l["valid_windows"], "distinct": n_l,
+                  "note": "256-bit keys (four words), counted by sorting each leaf in LDS"}
+        del keys_l, cnts_l
+
+    # the CPU oracle runs after every GPU leg, so that its host allocations
+    # (several GB, 16 threads) do not overlap the served leg's host-side work
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -565,15 +590,6 @@ def main() -> int:
                "one_thread_value": round(w_1 / dt1, 1),
                "one_thread_sample": "first %d reads (%d valid windows)" % (n_1, w_1),
                "cpu_model": cpu_model()}
-
-    batched = None
-    if args.batched_sets > 0:
-        batched = batched_leg(args.batched_sets, int(args.wave_gb * 1e9), not args.no_tune)
-
-    served = None
-    if args.served_jobs > 0:
-        served = served_leg(args.served_jobs, args.served_budget_gib, args.served_workers,
-                            args.served_load)
 
     line = {
         "metric": "canonical k-mers counted/sec on 1 MI355X + % HBM roofline; batched vs plain",
