@@ -354,33 +354,91 @@ def parse_fastx(text, fmt: int = FASTX_AUTO, stream=None):
 
 def count_chunked(host_reads, host_offsets, k: int, P: int = 1, chunk_bytes: int = 1 << 30,
                   opts: KcOptions | None = None):
-    """Count reads held in host memory in pieces of about chunk_bytes: each
-    piece is copied to the device and counted, and the results are merged
-    (kc_merge_counts), so the input may exceed device memory (the result must
-    fit). host_reads: uint8 numpy array; host_offsets: uint64 numpy array of
-    n_reads + 1 offsets. Returns (keys, counts) on the current device."""
+    """Count reads held in host memory in pieces of about chunk_bytes, so the
+    input may exceed device memory (the result must fit): each piece's result
+    is merged into the running one (kc_merge_counts). Pieces are staged
+    through two pinned host buffers: while piece i is counted, piece i + 1 is
+    copied into pinned memory (a host thread) and on to the device (a side
+    stream). host_reads: uint8 numpy array, or a pinned uint8 CPU tensor
+    (then pieces are copied to the device straight from it, with no staging
+    copy); host_offsets: uint64 numpy array of n_reads + 1 offsets. Returns
+    (keys, counts) on the current device."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     offs = np.ascontiguousarray(host_offsets, dtype=np.uint64)
+    pinned_in = isinstance(host_reads, torch.Tensor) and host_reads.is_pinned()
+    reads = host_reads if pinned_in else np.asarray(host_reads, dtype=np.uint8)
     n_reads = offs.size - 1
     dev = torch.device("cuda", torch.cuda.current_device())
     words = key_words(k)
     keys = torch.empty(_key_shape(0, words), dtype=torch.int64, device=dev)
     counts = torch.empty(0, dtype=torch.int32, device=dev)
+    # pieces: reads [r, e), at least one read, then as many as fit in chunk_bytes
+    pieces = []
     r = 0
     while r < n_reads:
-        # reads [r, e): at least one read, then as many as fit in chunk_bytes
         limit = int(offs[r]) + max(1, int(chunk_bytes))
         e = int(np.searchsorted(offs, np.uint64(limit), side="right")) - 1
         e = min(n_reads, max(e, r + 1))
-        b0, b1 = int(offs[r]), int(offs[e])
-        rt = torch.from_numpy(np.ascontiguousarray(host_reads[b0:b1])).to(dev)
-        if rt.numel() == 0:
-            rt = torch.zeros(1, dtype=torch.uint8, device=dev)
-        ot = torch.from_numpy((offs[r:e + 1] - np.uint64(b0)).view(np.int64)).to(dev)
-        pk, pc = count(rt, ot, k, P, opts=opts)
-        del rt, ot
-        keys, counts = merge_counts(keys, counts, pk, pc, k) if counts.numel() else (pk, pc)
+        pieces.append((r, e))
         r = e
+    if not pieces:
+        return keys, counts
+    # output room of each piece: its windows of length k (from the host offsets)
+    lens = np.diff(offs.astype(np.int64))
+    wins = np.concatenate([[0], np.cumsum(np.maximum(lens - k + 1, 0))])
+    caps = [max(1, int(wins[e] - wins[r])) for r, e in pieces]
+    max_b = max(1, max(int(offs[e] - offs[r]) for r, e in pieces))
+    max_r = max(e - r for r, e in pieces)
+    pin_r = [torch.empty(1 if pinned_in else max_b, dtype=torch.uint8, pin_memory=True)
+             for _ in range(2)]
+    pin_o = [torch.empty(max_r + 1, dtype=torch.int64, pin_memory=True) for _ in range(2)]
+    dev_r = [torch.empty(max_b, dtype=torch.uint8, device=dev) for _ in range(2)]
+    dev_o = [torch.empty(max_r + 1, dtype=torch.int64, device=dev) for _ in range(2)]
+    copy_stream = torch.cuda.Stream(device=dev)
+    done = [torch.cuda.Event() for _ in range(2)]
+
+    sizes = [None] * len(pieces)
+
+    def stage(i):  # host thread: piece i into pinned buffer i % 2
+        s = i % 2
+        done[s].synchronize()  # the upload that last read this buffer has finished
+        r0, r1 = pieces[i]
+        b0, b1 = int(offs[r0]), int(offs[r1])
+        if not pinned_in:
+            np.copyto(pin_r[s].numpy()[:b1 - b0], reads[b0:b1])
+        pin_o[s].numpy()[:r1 - r0 + 1] = (offs[r0:r1 + 1] - np.uint64(b0)).view(np.int64)
+        sizes[i] = (b1 - b0, r1 - r0, b0)
+
+    def upload(i):  # side stream: pinned buffer i % 2 -> device buffer i % 2
+        s = i % 2
+        nb, nr, b0 = sizes[i]
+        src = reads[b0:b0 + nb] if pinned_in else pin_r[s][:nb]
+        with torch.cuda.stream(copy_stream):
+            dev_r[s][:nb].copy_(src, non_blocking=True)
+            dev_o[s][:nr + 1].copy_(pin_o[s][:nr + 1], non_blocking=True)
+            done[s].record(copy_stream)
+
+    # piece i + 1 travels to the device while piece i is counted; piece i + 2
+    # is staged into pinned memory meanwhile
+    compute = torch.cuda.current_stream(dev)
+    n = len(pieces)
+    with ThreadPoolExecutor(max_workers=1) as ex:
+        stage(0)
+        upload(0)
+        fut = ex.submit(stage, 1) if n > 1 else None
+        for i in range(n):
+            s = i % 2
+            if i + 1 < n:
+                fut.result()
+                upload(i + 1)  # its device buffer was last read by piece i - 1, counted
+            if i + 2 < n:
+                fut = ex.submit(stage, i + 2)
+            compute.wait_event(done[s])
+            nb, nr, _ = sizes[i]
+            pk, pc = count(dev_r[s][:max(nb, 1)], dev_o[s][:nr + 1], k, P, opts=opts,
+                           capacity=caps[i])
+            keys, counts = merge_counts(keys, counts, pk, pc, k) if counts.numel() else (pk, pc)
     return keys, counts
 
 

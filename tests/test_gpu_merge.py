@@ -138,6 +138,16 @@ def test_count_chunked(k, chunk_bytes):
                 "chunk %d" % chunk_bytes)
 
 
+def test_count_chunked_from_pinned_tensor():
+    import torch
+    c = synth.make_config(2, frac=0.03)
+    pinned = torch.from_numpy(c["reads"]).pin_memory()
+    for chunk in (1 << 19, 1 << 40):
+        keys, cnts = kc.count_chunked(pinned, c["offsets"], 31, P=8, chunk_bytes=chunk)
+        assert_same(_host(keys, cnts), oracle.count(c["reads"], c["offsets"], 31),
+                    "pinned chunk %d" % chunk)
+
+
 def test_count_chunked_one_read_per_piece():
     g = synth.genome(11, 5000, [])
     reads, offs = synth.reads(g, 40, 120, err_rate=0.01, n_rate=0.01, seed=5)
