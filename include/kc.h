@@ -269,6 +269,9 @@ void kc_pred_free(kc_predictor* pred);
  *   not overlap the inputs; *n_out receives the number of pairs. KC_E_OVERFLOW
  *   if a sum exceeds 2^32-1. Lets inputs larger than device memory be counted
  *   in pieces whose results are merged. Synchronous on stream.
+ * The temporaries of kc_merge_counts ((na + nb) * (8 * words + 4) bytes) and
+ * kc_filter_min_count sit in one device buffer per host thread that grows as
+ * needed and is kept between calls (kc_release_scratch frees it).
  * All return KC_OK, KC_E_INVAL, KC_E_NOMEM or KC_E_DEVICE (and as stated). */
 int kc_spectrum(const uint32_t* counts, uint64_t n, uint32_t max_count, uint64_t* host_hist,
                 void* stream);
@@ -317,7 +320,8 @@ uint64_t kc_max_outputs(const uint64_t* host_offsets, uint64_t n_reads, int k);
  * or KC_E_INVAL if out is NULL. */
 int kc_last_stats(kc_stats* out);
 
-/* Release this thread's scratch arena (device memory is freed). */
+/* Release this thread's scratch arena and the temporary buffer of
+ * kc_merge_counts / kc_filter_min_count (device memory is freed). */
 void kc_release_scratch(void);
 
 /* Static description of a status code. */

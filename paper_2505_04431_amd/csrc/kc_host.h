@@ -37,6 +37,9 @@ uint64_t scratch_bytes(uint64_t n_bytes, int k, int P, const kc_options* opt);
 // Device bytes held by the calling thread's arena on the current device.
 uint64_t arena_bytes();
 
+// Frees the calling thread's temporary buffer of the merge and the filter.
+void release_post_scratch();
+
 // Sets the message kc_last_error() returns on the calling thread.
 void set_last_error(const std::string& msg);
 

@@ -140,12 +140,58 @@ int bad(const char* msg) {
   return KC_E_INVAL;
 }
 
+// Temporary device memory of the merge and the filter: grow-only, one buffer
+// per host thread, kept between calls so that repeated calls (a result merged
+// piece by piece) do not map fresh memory each time. Every call is
+// synchronous, so a call on the same thread finds the buffer idle. Freed by
+// kc_release_scratch or when the thread ends.
+struct PostScratch {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~PostScratch() {
+    if (p) (void)hipFree(p);
+  }
+};
+thread_local PostScratch t_post;
+
+void* post_scratch(size_t bytes) {
+  if (t_post.p && t_post.cap >= bytes) return t_post.p;
+  if (t_post.p) {
+    (void)hipFree(t_post.p);
+    t_post.p = nullptr;
+    t_post.cap = 0;
+  }
+  size_t want = bytes + bytes / 4 + 256;
+  hipError_t e = hipMalloc(&t_post.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    want = bytes;
+    e = hipMalloc(&t_post.p, want);
+  }
+  if (e != hipSuccess) {
+    t_post.p = nullptr;
+    chk(e, "hipMalloc");
+  }
+  t_post.cap = want;
+  return t_post.p;
+}
+
 unsigned grid_of(uint64_t n, uint64_t per, unsigned cap) {
   const uint64_t g = (n + per - 1) / per;
   return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
 }  // namespace
+
+namespace kc {
+void release_post_scratch() {
+  if (t_post.p) {
+    (void)hipFree(t_post.p);
+    t_post.p = nullptr;
+    t_post.cap = 0;
+  }
+}
+}  // namespace kc
 
 extern "C" {
 
@@ -192,7 +238,7 @@ int kc_filter_min_count(const uint64_t* keys, const uint32_t* counts, uint64_t n
   const uint64_t nt = (n + kTile - 1) / kTile;
   void* d = nullptr;
   try {
-    chk(hipMallocAsync(&d, (size_t)(nt + 1) * 8, st), "hipMallocAsync");
+    d = post_scratch((size_t)(nt + 1) * 8);
     unsigned long long* tsum = (unsigned long long*)d;
     hipLaunchKernelGGL(k_keep_count, dim3((unsigned)nt), dim3(kTB), 0, st, counts, n, min_count,
                        tsum);
@@ -202,12 +248,9 @@ int kc_filter_min_count(const uint64_t* keys, const uint32_t* counts, uint64_t n
     chk(hipGetLastError(), "filter launch");
     uint64_t total = 0;
     chk(hipMemcpyAsync(&total, tsum + nt, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-    chk(hipFreeAsync(d, st), "hipFreeAsync");
-    d = nullptr;
     chk(hipStreamSynchronize(st), "hipStreamSynchronize");
     *n_out = total;
   } catch (const Fail& f) {
-    if (d) (void)hipFreeAsync(d, st);
     return f.code;
   }
   return KC_OK;
@@ -385,7 +428,7 @@ extern "C" int kc_merge_counts(const uint64_t* a_keys, const uint32_t* a_counts,
   try {
     // merged sequence, tile sums and the overflow flag in one allocation
     const size_t kb = n * 8 * (size_t)words, cb = n * 4, tb = (nt + 1) * 8;
-    chk(hipMallocAsync(&d, kb + cb + tb + 16, st), "hipMallocAsync");
+    d = post_scratch(kb + cb + tb + 16);
     uint64_t* mk = (uint64_t*)d;
     uint32_t* mc = (uint32_t*)((char*)d + kb);
     unsigned long long* tsum = (unsigned long long*)((char*)d + kb + cb + (8 - (cb & 7)) % 8);
@@ -420,8 +463,6 @@ extern "C" int kc_merge_counts(const uint64_t* a_keys, const uint32_t* a_counts,
     uint64_t h[2] = {0, 0};
     chk(hipMemcpyAsync(&h[0], tsum + nt, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
     chk(hipMemcpyAsync(&h[1], ovf, 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-    chk(hipFreeAsync(d, st), "hipFreeAsync");
-    d = nullptr;
     chk(hipStreamSynchronize(st), "hipStreamSynchronize");
     if ((uint32_t)h[1]) {
       kc::set_last_error("a merged count exceeds 2^32-1");
@@ -429,7 +470,6 @@ extern "C" int kc_merge_counts(const uint64_t* a_keys, const uint32_t* a_counts,
     }
     *n_out = h[0];
   } catch (const Fail& f) {
-    if (d) (void)hipFreeAsync(d, st);
     return f.code;
   }
   return KC_OK;

@@ -1365,6 +1365,7 @@ int kc_last_stats(kc_stats* out) {
 void kc_release_scratch(void) {
   try {
     g_ctx.clear();
+    kc::release_post_scratch();
   } catch (...) {
   }
 }
