@@ -308,6 +308,36 @@ __device__ __forceinline__ void key_put(uint64_t* keys, uint64_t i,
 
 constexpr int kMergeItems = 8;
 
+constexpr uint64_t kMergeTile = (uint64_t)kTB * kMergeItems;  // merged positions per block
+
+// Number of a's among the first d merged positions (a first on ties), by
+// binary search over i in [lo, hi]: the largest i with a[i-1] <= b[d-i].
+template <int W>
+__device__ __forceinline__ uint64_t merge_split(const uint64_t* __restrict__ ak, uint64_t na,
+                                                const uint64_t* __restrict__ bk, uint64_t nb,
+                                                uint64_t d, uint64_t lo, uint64_t hi) {
+  while (lo < hi) {
+    const uint64_t i = (lo + hi + 1) >> 1;  // candidate: take i items of a
+    if (d - i >= nb || !(key_at<W>(bk, d - i) < key_at<W>(ak, i - 1))) lo = i;
+    else hi = i - 1;
+  }
+  return lo;
+}
+
+// Split of every block boundary (part[q] for diagonal q * kMergeTile, q =
+// 0..nblocks), so that each thread of k_merge searches only its block's window.
+template <int W>
+__global__ void __launch_bounds__(kTB) k_merge_part(const uint64_t* __restrict__ ak, uint64_t na,
+                                                    const uint64_t* __restrict__ bk, uint64_t nb,
+                                                    uint64_t nblocks,
+                                                    unsigned long long* __restrict__ part) {
+  const uint64_t q = (uint64_t)blockIdx.x * kTB + threadIdx.x;
+  if (q > nblocks) return;
+  const uint64_t total = na + nb;
+  const uint64_t d = q * kMergeTile < total ? q * kMergeTile : total;
+  part[q] = merge_split<W>(ak, na, bk, nb, d, d > nb ? d - nb : 0, d < na ? d : na);
+}
+
 // Merge path: thread t writes merged positions [t*items, t*items + items) of
 // the ordered union of a and b (ties: a first). Its start in a is the
 // largest i with i + j = d and a[i-1] <= b[j] ... found by binary search.
@@ -317,19 +347,18 @@ __global__ void __launch_bounds__(kTB) k_merge(const uint64_t* __restrict__ ak,
                                                const uint64_t* __restrict__ bk,
                                                const uint32_t* __restrict__ bc, uint64_t nb,
                                                uint64_t* __restrict__ mk,
-                                               uint32_t* __restrict__ mc) {
+                                               uint32_t* __restrict__ mc,
+                                               const unsigned long long* __restrict__ part) {
   const uint64_t total = na + nb;
   const uint64_t d = ((uint64_t)blockIdx.x * kTB + threadIdx.x) * kMergeItems;
   if (d >= total) return;
-  // i in [max(0, d - nb), min(d, na)]: number of a's among the first d merged
+  // i in [max(0, d - nb), min(d, na)] and within this block's split range
+  const uint64_t p0 = part[blockIdx.x], p1 = part[blockIdx.x + 1];
   uint64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
-  while (lo < hi) {
-    const uint64_t i = (lo + hi + 1) >> 1;  // candidate: take i items of a
-    // valid iff a[i-1] <= b[d-i] (a first on ties), i.e. not b[d-i] < a[i-1]
-    if (d - i >= nb || !(key_at<W>(bk, d - i) < key_at<W>(ak, i - 1))) lo = i;
-    else hi = i - 1;
-  }
-  uint64_t i = lo, j = d - lo;
+  lo = lo > p0 ? lo : p0;
+  hi = hi < p1 ? hi : p1;
+  const uint64_t i0 = merge_split<W>(ak, na, bk, nb, d, lo, hi);
+  uint64_t i = i0, j = d - i0;
   for (int t = 0; t < kMergeItems && d + t < total; ++t) {
     bool take_a;
     if (i >= na) take_a = false;
@@ -428,25 +457,33 @@ extern "C" int kc_merge_counts(const uint64_t* a_keys, const uint32_t* a_counts,
   try {
     // merged sequence, tile sums and the overflow flag in one allocation
     const size_t kb = n * 8 * (size_t)words, cb = n * 4, tb = (nt + 1) * 8;
-    d = post_scratch(kb + cb + tb + 16);
+    const uint64_t nblk = (n + kMergeTile - 1) / kMergeTile;
+    // layout: merged keys, counts, (pad to 8), tile sums, flag (16 bytes), splits
+    d = post_scratch(kb + cb + 8 + tb + 16 + (nblk + 1) * 8);
     uint64_t* mk = (uint64_t*)d;
     uint32_t* mc = (uint32_t*)((char*)d + kb);
     unsigned long long* tsum = (unsigned long long*)((char*)d + kb + cb + (8 - (cb & 7)) % 8);
     unsigned int* ovf = (unsigned int*)(tsum + nt + 1);
+    unsigned long long* part = (unsigned long long*)(ovf + 4);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (unsigned long long*)ovf, (uint64_t)1);
-    const uint64_t threads = (n + kMergeItems - 1) / kMergeItems;
-    const dim3 gm((unsigned)((threads + kTB - 1) / kTB)), gt((unsigned)nt);
+    const dim3 gm((unsigned)nblk), gt((unsigned)nt), gp((unsigned)((nblk + kTB) / kTB));
     if (words == 4) {
+      hipLaunchKernelGGL(k_merge_part<4>, gp, dim3(kTB), 0, st, a_keys, na, b_keys, nb, nblk,
+                         part);
       hipLaunchKernelGGL(k_merge<4>, gm, dim3(kTB), 0, st, a_keys, a_counts, na, b_keys, b_counts,
-                         nb, mk, mc);
+                         nb, mk, mc, part);
       hipLaunchKernelGGL(k_dedup_count<4>, gt, dim3(kTB), 0, st, mk, n, tsum);
     } else if (words == 2) {
+      hipLaunchKernelGGL(k_merge_part<2>, gp, dim3(kTB), 0, st, a_keys, na, b_keys, nb, nblk,
+                         part);
       hipLaunchKernelGGL(k_merge<2>, gm, dim3(kTB), 0, st, a_keys, a_counts, na, b_keys, b_counts,
-                         nb, mk, mc);
+                         nb, mk, mc, part);
       hipLaunchKernelGGL(k_dedup_count<2>, gt, dim3(kTB), 0, st, mk, n, tsum);
     } else {
+      hipLaunchKernelGGL(k_merge_part<1>, gp, dim3(kTB), 0, st, a_keys, na, b_keys, nb, nblk,
+                         part);
       hipLaunchKernelGGL(k_merge<1>, gm, dim3(kTB), 0, st, a_keys, a_counts, na, b_keys, b_counts,
-                         nb, mk, mc);
+                         nb, mk, mc, part);
       hipLaunchKernelGGL(k_dedup_count<1>, gt, dim3(kTB), 0, st, mk, n, tsum);
     }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tsum, nt);
