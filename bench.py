@@ -451,7 +451,7 @@ def main() -> int:
     dom = max((n for n in avg if n in sb), key=lambda n: avg[n])
     achieved = sb[dom] / (avg[dom] / 1e3) / 1e9
     kernel_names = {"leaf_large": "k_leaf_count64<512, 4096, 4>" if k <= 32 else
-                    "k_leaf_count128<512, 2048, 4>"}
+                    "k_leaf_countw<u128, 512, 2048, 4>"}
     copy_gbs = copy_rate(torch, dev, args.copy_gib)
     ceil = kc.kc.measure_ceilings(4 << 30, stream.cuda_stream)
     t_h2d = h2d_ms(torch, dev, reads, offs)
@@ -587,7 +587,8 @@ def main() -> int:
                   "unit": "k-mers/s", "ms_per_step": round(ms_l, 4),
                   "leaf_ms": round(leaf_l / args.long_k_steps, 4),
                   "valid_windows": st_l["valid_windows"], "distinct": n_l,
-                  "note": "256-bit keys (four words), counted by sorting each leaf in LDS"}
+                  "note": "256-bit keys (four words); LDS tables whose slots are claimed "
+                          "through their 64-bit count word"}
         del keys_l, cnts_l
 
     # the CPU oracle runs after every GPU leg, so that its host allocations

@@ -70,7 +70,6 @@ typedef struct kc_options {
                           table, then a sort of its distinct keys; 1 = sort of its
                           records and run-length accumulation (Algorithm 1's Sort +
                           Accumulate, as each owner does in Algorithm 3). Same result.
-                          Keys of more than 64 bases are always counted by sorting.
                           The batched form takes 0 only (and k <= 32). */
   int reserved[5];
 } kc_options;

@@ -197,6 +197,12 @@ template <> struct Key<u256> {
   __device__ static uint32_t bits(const u256& x, int shift, int nbits) {
     return (uint32_t)(x >> shift) & ((1u << nbits) - 1u);
   }
+  __device__ static uint64_t hash(const u256& x) {
+    uint64_t h = fmix64((uint64_t)(x.hi >> 64) + 0x9E3779B97F4A7C15ull);
+    h = fmix64((uint64_t)x.hi ^ h);
+    h = fmix64((uint64_t)(x.lo >> 64) ^ h);
+    return fmix64((uint64_t)x.lo ^ h);
+  }
   // Bases [s/2, s/2 + k) of the little-endian base stream in p[0..4] (base j
   // of the window at bits 2j), s even, 0 <= s <= 62.
   __device__ static u256 window(const uint64_t (&p)[5], int s, int k) {
@@ -1302,8 +1308,8 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
 //   claimed through its 64-bit count word: 0 = empty, LOCK = being written;
 //   the claimer writes the key and then publishes the count; others seeing
 //   LOCK retry the same slot.
-template <int TB, int CMAX, int R, bool HI>
-__global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u128* bufB,
+template <typename K, int TB, int CMAX, int R, bool HI>
+__global__ void __launch_bounds__(TB) k_leaf_countw(int keybits, K* bufA, K* bufB,
                                                       uint32_t* __restrict__ tmp_cnt,
                                                       const Leaf* __restrict__ leaves,
                                                       DevState* __restrict__ st,
@@ -1311,8 +1317,9 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
                                                       int slots_log2,
                                                       const uint32_t* __restrict__ list,
                                                       uint64_t small_max) {
+  static_assert(!HI || std::is_same<K, u128>::value, "high-word claims need 128-bit keys");
   typedef typename std::conditional<HI, uint32_t, unsigned long long>::type C;
-  __shared__ u128 tk[CMAX];
+  __shared__ K tk[CMAX];
   __shared__ C tc[CMAX];
   __shared__ uint32_t aux[CMAX];
   __shared__ uint32_t wsum[TB / 64];
@@ -1334,15 +1341,18 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
       continue;
     }
     if (!list && n > small_max) continue;
-    const u128* src = lf.buf ? bufB : bufA;
-    u128* dst = lf.buf ? bufA : bufB;
+    const K* src = lf.buf ? bufB : bufA;
+    K* dst = lf.buf ? bufA : bufB;
     const uint32_t Cfull = leaf_slots<TB, CMAX>(n, cmax_rt);
-    uint32_t Cn = leaf_slots<TB, CMAX>(n / 2, cmax_rt);
+    // keys of more than 64 bases are mostly distinct: their first table is the
+    // full one (a half table would fill to its limit, with long probe runs,
+    // before the retry)
+    uint32_t Cn = sizeof(K) > 16 ? Cfull : leaf_slots<TB, CMAX>(n / 2, cmax_rt);
     for (;;) {
     const uint32_t cmask = Cn - 1;
     for (uint32_t i = threadIdx.x; i < Cn; i += TB) {
       tc[i] = 0;
-      if (HI) reinterpret_cast<unsigned long long*>(&tk[i])[1] = ~0ull;
+      if constexpr (HI) reinterpret_cast<unsigned long long*>(&tk[i])[1] = ~0ull;
     }
     if (threadIdx.x == 0) {
       s_nd = 0;
@@ -1354,22 +1364,22 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
     const bool track = n >= limit;  // fewer records than the limit cannot overflow
     for (uint64_t base = lf.begin; base < lf.end; base += (uint64_t)TB * R) {
       if (ovf_get(&s_ovf)) break;
-      u128 kb[R];
+      K kb[R];
       bool kv[R];
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const uint64_t r = base + (uint64_t)j * TB + threadIdx.x;
         kv[j] = r < lf.end;
-        kb[j] = kv[j] ? src[r] : (u128)0;
+        kb[j] = kv[j] ? src[r] : (K)0;
       }
 #pragma unroll
       for (int j = 0; j < R; ++j) {
       if (!kv[j]) continue;
-      const u128 key = kb[j];
-      uint32_t pos = (uint32_t)Key<u128>::hash(key) & cmask;
+      const K key = kb[j];
+      uint32_t pos = (uint32_t)Key<K>::hash(key) & cmask;
       uint32_t probe = 0, spins = 0;
       bool done = false;
-      if (HI) {
+      if constexpr (HI) {
         const unsigned long long khi = (unsigned long long)(key >> 64);
         const unsigned long long klo = (unsigned long long)key;
         bool todo = true;
@@ -1450,7 +1460,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
       __syncthreads();
       continue;
     }
-    if (HI) {
+    if constexpr (HI) {
       if (n > 0xFFFFFFFFull) {
         // 32-bit counts may have wrapped: they then sum to less than the records
         if (threadIdx.x == 0) s_sum = 0;
@@ -1465,7 +1475,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count128(int keybits, u128* bufA, u
       for (uint32_t i = threadIdx.x; i < Cn; i += TB)
         if ((unsigned long long)tc[i] > 0xFFFFFFFFull) s_cov = 1;
     }
-    const uint32_t d = leaf_sort_write<u128, C, TB, CMAX / TB>(
+    const uint32_t d = leaf_sort_write<K, C, TB, CMAX / TB>(
         tk, tc, aux, wsum, &s_max, Cn, keybits, (int)lf.bits, dst, tmp_cnt, lf.begin,
         HI ? (bool (*)(C))occ32 : (bool (*)(C))occ64);
     if (threadIdx.x == 0) {
@@ -1804,6 +1814,7 @@ constexpr int kSplitR = 8;
 constexpr int kLeafTB = 512;
 constexpr int kLeafCmax64 = 4096;
 constexpr int kLeafCmax128 = 2048;
+constexpr int kLeafCmax256 = 2048;  // 44 bytes a slot: key, 64-bit count, sort aux
 constexpr unsigned kPersistentGrid = 1024;  // blocks of the persistent kernels
 constexpr int kSmallCmax64 = 1024;  // one-wave leaf kernel: slots of its private table
 constexpr int kSmallCmax128 = 512;
@@ -1980,13 +1991,12 @@ uint64_t small_leaf_max(int words) {
 hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode) {
-  if (words == 4 && mode != 1) return hipErrorInvalidValue;
   const bool wide = words == 2;
   const uint64_t small_max = mode == 1 ? 0 : small_leaf_max(words);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &st->n_large, (uint64_t)1, 0ull);
   hipLaunchKernelGGL(k_classify_leaves, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s,
                      leaves, st, small_max, large_list);
-  if (mode == 1) {  // sort-based: every non-empty leaf is in the list
+  if (mode == 1 || words == 4) {  // every non-empty leaf is in the list
     hipLaunchKernelGGL(k_empty_leaves, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s,
                        leaves, st, d_out);
     return hipGetLastError();
@@ -1994,11 +2004,11 @@ hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uin
   const unsigned gsmall = persistent(max_leaves, kSmallGrid);
   if (wide)
     if (keybits <= 126)
-      hipLaunchKernelGGL((k_leaf_count128<64, kSmallCmax128, 8, true>), dim3(gsmall), dim3(64), 0,
+      hipLaunchKernelGGL((k_leaf_countw<u128, 64, kSmallCmax128, 8, true>), dim3(gsmall), dim3(64), 0,
                          s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
                          __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max);
     else
-      hipLaunchKernelGGL((k_leaf_count128<64, kSmallCmax128, 8, false>), dim3(gsmall), dim3(64), 0,
+      hipLaunchKernelGGL((k_leaf_countw<u128, 64, kSmallCmax128, 8, false>), dim3(gsmall), dim3(64), 0,
                          s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
                          __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max);
   else
@@ -2012,7 +2022,6 @@ hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uin
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
                              hipStream_t s, int mode) {
-  if (words == 4 && mode != 1) return hipErrorInvalidValue;
   const bool wide = words == 2;
   const uint64_t small_max = small_leaf_max(words);
   const unsigned glarge = persistent(max_leaves, kPersistentGrid);
@@ -2031,13 +2040,17 @@ hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uin
                          leaves, st, d_out, large_list);
     return hipGetLastError();
   }
-  if (wide)
+  if (words == 4)
+    hipLaunchKernelGGL((k_leaf_countw<u256, kLeafTB, kLeafCmax256, 4, false>), dim3(glarge),
+                       dim3(kLeafTB), 0, s, keybits, (u256*)bufA, (u256*)bufB, tmp_cnt, leaves, st,
+                       d_out, slots_log2, large_list, small_max);
+  else if (wide)
     if (keybits <= 126)
-      hipLaunchKernelGGL((k_leaf_count128<kLeafTB, kLeafCmax128, 4, true>), dim3(glarge),
+      hipLaunchKernelGGL((k_leaf_countw<u128, kLeafTB, kLeafCmax128, 4, true>), dim3(glarge),
                          dim3(kLeafTB), 0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves,
                          st, d_out, slots_log2, large_list, small_max);
     else
-      hipLaunchKernelGGL((k_leaf_count128<kLeafTB, kLeafCmax128, 4, false>), dim3(glarge),
+      hipLaunchKernelGGL((k_leaf_countw<u128, kLeafTB, kLeafCmax128, 4, false>), dim3(glarge),
                          dim3(kLeafTB), 0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves,
                          st, d_out, slots_log2, large_list, small_max);
   else

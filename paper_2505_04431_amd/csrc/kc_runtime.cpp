@@ -690,7 +690,7 @@ Pipe plain_pipe(uint64_t n_bytes, int k, int P, const kc_options& o) {
   p.byte_begin = 0;
   p.byte_end = n_bytes;
   p.rec_bound = n_bytes;  // byte count: an upper bound of the window count
-  p.mode = p.words == 4 ? 1 : o.mode;
+  p.mode = o.mode;
   pipe_bounds(p);
   return p;
 }
@@ -723,7 +723,6 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   std::memset(&q.o, 0, sizeof(q.o));
   if (opt) q.o = *opt;
   if (q.o.mode != 0 && q.o.mode != 1) fail(KC_E_INVAL, "mode must be 0 or 1");
-  if (k > 64) q.o.mode = 1;  // keys over 128 bits: sort-based leaves only
 
   Ctx& c = context();
   std::memset(&g_stats, 0, sizeof(g_stats));
