@@ -1347,7 +1347,7 @@ __global__ void __launch_bounds__(TB) k_leaf_countw(int keybits, K* bufA, K* buf
     // keys of more than 64 bases are mostly distinct: their first table is the
     // full one (a half table would fill to its limit, with long probe runs,
     // before the retry)
-    uint32_t Cn = sizeof(K) > 16 ? Cfull : leaf_slots<TB, CMAX>(n / 2, cmax_rt);
+    uint32_t Cn = sizeof(K) >= 16 ? Cfull : leaf_slots<TB, CMAX>(n / 2, cmax_rt);
     for (;;) {
     const uint32_t cmask = Cn - 1;
     for (uint32_t i = threadIdx.x; i < Cn; i += TB) {
