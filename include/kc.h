@@ -110,7 +110,11 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
 
 /* As kc_count with an explicit output capacity (in keys), options (NULL =
  * automatic) and a HIP stream (hipStream_t passed as void*, NULL = default).
- * If more than out_capacity keys result, returns KC_E_CAPACITY with *n_out set. */
+ * If more than out_capacity keys result, returns KC_E_CAPACITY with *n_out set.
+ * Returns once *n_out is known; the copy into the outputs may still be queued
+ * on the stream. Calls of one host thread share its scratch arena: a call on
+ * another stream than the thread's previous call first waits (on the device)
+ * for that call's work. */
 int kc_count_ex(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
                 uint64_t* out_keys, uint32_t* out_counts, uint64_t out_capacity,
                 uint64_t* n_out, const kc_options* opt, void* stream);
@@ -202,6 +206,8 @@ typedef struct kc_server_stats {
   uint64_t estimate_misses;        /* results larger than their reservation */
   uint64_t result_bytes_reserved;  /* sum over finished jobs */
   uint64_t result_bytes_actual;
+  uint64_t arena_growths;          /* jobs after which their worker's scratch arena grew */
+  uint64_t scratch_releases;       /* times an idle worker gave its arena back to fit a job */
   double latency_p50_ms, latency_p99_ms; /* completion - submission, completed jobs */
   double wait_p50_ms, wait_p99_ms;       /* start - submission */
   double busy_ms;                        /* first start to last completion */
@@ -320,7 +326,10 @@ uint64_t kc_max_outputs(const uint64_t* host_offsets, uint64_t n_reads, int k);
 int kc_last_stats(kc_stats* out);
 
 /* Release this thread's scratch arena and the temporary buffer of
- * kc_merge_counts / kc_filter_min_count (device memory is freed). */
+ * kc_merge_counts / kc_filter_min_count, and return the idle blocks of the
+ * library's device memory pool (the arenas of kc_count grow stream-ordered
+ * from that pool, which keeps freed blocks for reuse instead of handing them
+ * back to the driver at once) to the device. */
 void kc_release_scratch(void);
 
 /* Static description of a status code. */

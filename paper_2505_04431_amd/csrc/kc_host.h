@@ -40,6 +40,15 @@ uint64_t arena_bytes();
 // Frees the calling thread's temporary buffer of the merge and the filter.
 void release_post_scratch();
 
+// The library's stream-ordered memory pool of a device (created on first
+// use): the count arenas and the server's results come from it. It keeps the
+// blocks freed into it (no release threshold), so growing an arena or
+// dropping a result while other streams run never hands memory back to the
+// driver; trim_device_pool returns the idle blocks (kc_release_scratch and
+// server teardown call it).
+hipError_t device_pool(int device, hipMemPool_t* pool);
+void trim_device_pool(int device);
+
 // Sets the message kc_last_error() returns on the calling thread.
 void set_last_error(const std::string& msg);
 

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,7 +28,14 @@ thread_local kc_stats g_stats;
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool pooled = false;  // from the library's device pool (freed stream-ordered)
 };
+
+// Frees an idle buffer.
+void drop(DevBuf& b) {
+  if (b.p) (void)(b.pooled ? hipFreeAsync(b.p, nullptr) : hipFree(b.p));
+  b = DevBuf{};
+}
 
 struct Ctx {
   int device = -1;
@@ -42,6 +50,12 @@ struct Ctx {
   size_t host_cap = 0;
   hipEvent_t ev[32] = {};
   bool ev_ok = false;
+  // The last call's work on its stream: a call may return with kernels still
+  // reading these buffers (the concat into caller-owned outputs), so a call on
+  // another stream first waits for it.
+  hipEvent_t done = nullptr;
+  hipStream_t done_st = nullptr;
+  bool done_set = false;
 
   ~Ctx() {
     int prev = -1;
@@ -51,11 +65,13 @@ struct Ctx {
                      &leaves,  &dcnt,    &outoff, &state,   &large,  &bsum,    &itemoff,
                      &rlist,   &rleaves, &rcount, &aleaves, &adcnt,  &alarge,  &rparts,
                      &rcnt,    &leaves2, &dcnt2};
-    for (DevBuf* b : all)
-      if (b->p) (void)hipFree(b->p);
+    // the last call's kernels may still read the buffers
+    if (done_set) (void)hipEventSynchronize(done);
+    for (DevBuf* b : all) drop(*b);
     if (host) (void)hipHostFree(host);
     if (ev_ok)
       for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
+    if (done) (void)hipEventDestroy(done);
     if (prev >= 0) (void)hipSetDevice(prev);
   }
 };
@@ -84,13 +100,18 @@ size_t alloc_size(size_t bytes) {
   return bytes + bytes / 8;
 }
 
+// Synchronous growth (plans, whose buffers are set up before any launch).
 void ensure(DevBuf& b, size_t bytes, const char* name) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return;
   if (b.p) {
-    hipchk(hipFree(b.p), "hipFree");
-    b.p = nullptr;
-    b.cap = 0;
+    if (b.pooled) {
+      hipchk(hipFreeAsync(b.p, nullptr), "hipFreeAsync");
+      hipchk(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
+    } else {
+      hipchk(hipFree(b.p), "hipFree");
+    }
+    b = DevBuf{};
   }
   size_t want = alloc_size(bytes);
   hipError_t e = hipMalloc(&b.p, want);
@@ -106,6 +127,44 @@ void ensure(DevBuf& b, size_t bytes, const char* name) {
                          name + " failed");
   }
   b.cap = want;
+}
+
+// Stream-ordered growth of a count buffer: the old block goes back to the
+// library pool behind the work queued on st and the new one comes from it, so
+// growth neither waits for the device nor frees memory to the driver.
+void grow(DevBuf& b, size_t bytes, const char* name, hipStream_t st) {
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return;
+  int dev = 0;
+  hipchk(hipGetDevice(&dev), "hipGetDevice");
+  hipMemPool_t pool = nullptr;
+  hipchk(kc::device_pool(dev, &pool), "device memory pool");
+  if (b.p) {
+    hipchk(b.pooled ? hipFreeAsync(b.p, st) : hipFree(b.p), "free");
+    b = DevBuf{};
+  }
+  size_t want = alloc_size(bytes);
+  hipError_t e = hipMallocFromPoolAsync(&b.p, want, pool, st);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    want = bytes;
+    e = hipMallocFromPoolAsync(&b.p, want, pool, st);
+  }
+  if (e != hipSuccess) {
+    // idle blocks the pool keeps may be what is missing: return them, retry
+    (void)hipGetLastError();
+    hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+    (void)hipMemPoolTrimTo(pool, 0);
+    e = hipMallocFromPoolAsync(&b.p, want, pool, st);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b = DevBuf{};
+    fail(KC_E_NOMEM, std::string("device allocation of ") + std::to_string(bytes) + " bytes for " +
+                         name + " failed");
+  }
+  b.cap = want;
+  b.pooled = true;
 }
 
 void* host_stage(Ctx& c, size_t bytes) {
@@ -131,6 +190,28 @@ Ctx& context() {
   }
   return *slot;
 }
+
+// Orders a call on `st` after the previous call on this thread's context (when
+// that one ran on another stream) and, on every exit, marks the call's end.
+struct CtxUse {
+  Ctx& c;
+  hipStream_t st;
+  CtxUse(Ctx& ctx, hipStream_t s) : c(ctx), st(s) {
+    if (!c.done) hipchk(hipEventCreateWithFlags(&c.done, hipEventDisableTiming), "hipEventCreate");
+    if (c.done_set && c.done_st != st) hipchk(hipStreamWaitEvent(st, c.done, 0), "hipStreamWaitEvent");
+  }
+  ~CtxUse() {
+    if (hipEventRecord(c.done, st) == hipSuccess) {
+      c.done_st = st;
+      c.done_set = true;
+    } else {
+      // without the mark, wait for everything before the context is reused
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(st);
+      c.done_set = false;
+    }
+  }
+};
 
 uint64_t host_mix(uint64_t h) {  // owner assignment of shards (MurmurHash3 finalizer)
   h ^= h >> 33;
@@ -273,9 +354,9 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
   const hipStream_t st = q.st;
   kc::DevState* dst_state = (kc::DevState*)c.state.p;
   // the overflowed leaves only (the list of all leaves stays on the device)
-  ensure(c.rlist, nl0 * 4, "overflowed leaf list");
-  ensure(c.rleaves, nl0 * sizeof(kc::Leaf), "overflowed leaves");
-  ensure(c.rcount, 8, "overflow count");
+  grow(c.rlist, nl0 * 4, "overflowed leaf list", st);
+  grow(c.rleaves, nl0 * sizeof(kc::Leaf), "overflowed leaves", st);
+  grow(c.rcount, 8, "overflow count", st);
   hipchk(kc::launch_list_overflowed((uint32_t*)c.dcnt.p, nl0, (kc::Leaf*)c.leaves.p,
                                     (uint32_t*)c.rlist.p, (kc::Leaf*)c.rleaves.p,
                                     (unsigned long long*)c.rcount.p, st),
@@ -366,10 +447,10 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
       for (const kc::SplitItem& it : items)
         if (split[it.bin].buf == src) it_src.push_back(it);
       if (it_src.empty()) continue;
-      ensure(c.bins, ns * sizeof(kc::SplitBin), "split bins");
-      ensure(c.items, it_src.size() * sizeof(kc::SplitItem), "split items");
-      ensure(c.subhist, hoff * 8, "sub-bin histogram");
-      ensure(c.cursor2, hoff * 8, "sub-bin cursors");
+      grow(c.bins, ns * sizeof(kc::SplitBin), "split bins", st);
+      grow(c.items, it_src.size() * sizeof(kc::SplitItem), "split items", st);
+      grow(c.subhist, hoff * 8, "sub-bin histogram", st);
+      grow(c.cursor2, hoff * 8, "sub-bin cursors", st);
       upload_sync(c.items.p, it_src.data(), it_src.size() * sizeof(kc::SplitItem), st);
       upload_sync(c.bins.p, sbins.data(), ns * sizeof(kc::SplitBin), st);
       unsigned long long ni = it_src.size();
@@ -414,9 +495,9 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
     std::vector<kc::Leaf> al(na);
     for (size_t i = 0; i < na; ++i)
       al[i] = kc::Leaf{next[i].begin, next[i].end, (uint32_t)next[i].buf, (uint32_t)next[i].bits};
-    ensure(c.aleaves, na * sizeof(kc::Leaf), "part table");
-    ensure(c.adcnt, na * 4, "part counts");
-    ensure(c.alarge, na * 4, "large-part list");
+    grow(c.aleaves, na * sizeof(kc::Leaf), "part table", st);
+    grow(c.adcnt, na * 4, "part counts", st);
+    grow(c.alarge, na * 4, "large-part list", st);
     upload_sync(c.aleaves.p, al.data(), na * sizeof(kc::Leaf), st);
     unsigned long long nlu = na;
     upload_sync(&dst_state->n_leaves, &nlu, 8, st);
@@ -471,17 +552,17 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
     hpd[i] = done[i].d;
     if (hnp[done[i].root]++ == 0) hbeg[done[i].root] = (uint32_t)i;
   }
-  ensure(c.rparts, bytes, "refined parts");
+  grow(c.rparts, bytes, "refined parts", st);
   upload_sync(c.rparts.p, hb.data(), bytes, st);
   const char* dp = (const char*)c.rparts.p;
   const uint64_t nl = nl0 - R + P;
-  ensure(c.rcnt, nl0 * 4, "splice counts");
+  grow(c.rcnt, nl0 * 4, "splice counts", st);
   // the spliced list is built beside the old one and the two are swapped;
   // both keep the larger capacity so that the next call does not reallocate
-  ensure(c.leaves2, std::max(nl, keep_leaves) * sizeof(kc::Leaf), "leaf table");
-  ensure(c.dcnt2, std::max(nl, keep_leaves) * 4, "leaf counts");
-  ensure(c.bsum, kc::scan_blocks(std::max(nl0, nl)) * 8, "scan block sums");
-  ensure(c.outoff, std::max(nl0, nl) * 8, "output offsets");
+  grow(c.leaves2, std::max(nl, keep_leaves) * sizeof(kc::Leaf), "leaf table", st);
+  grow(c.dcnt2, std::max(nl, keep_leaves) * 4, "leaf counts", st);
+  grow(c.bsum, kc::scan_blocks(std::max(nl0, nl)) * 8, "scan block sums", st);
+  grow(c.outoff, std::max(nl0, nl) * 8, "output offsets", st);
   unsigned long long n0 = nl0;
   upload_sync(&dst_state->n_leaves, &n0, 8, st);
   hipchk(kc::launch_splice((const kc::Leaf*)c.leaves.p, (const uint32_t*)c.dcnt.p, nl0,
@@ -698,7 +779,7 @@ Pipe plain_pipe(uint64_t n_bytes, int k, int P, const kc_options& o) {
 // Owner-major shard order on the device, cached in the context per (P, sb).
 const int* device_order(Ctx& c, const Call& q, kc_stats& S, hipStream_t st) {
   if (c.order_P != q.P || c.order_sb != q.sb) {
-    ensure(c.order, (size_t)q.nb * 4, "owner order");
+    grow(c.order, (size_t)q.nb * 4, "owner order", st);
     const std::vector<int>& order = owner_order(c, q, S, nullptr);
     c.order_host.assign(order.begin(), order.end());
     upload_sync(c.order.p, c.order_host.data(), (size_t)q.nb * 4, st);
@@ -725,13 +806,14 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   if (q.o.mode != 0 && q.o.mode != 1) fail(KC_E_INVAL, "mode must be 0 or 1");
 
   Ctx& c = context();
+  const CtxUse use(c, st);
   std::memset(&g_stats, 0, sizeof(g_stats));
   kc_stats S;
   std::memset(&S, 0, sizeof(S));
   Timer tm(c, st, q.o.timing != 0);
 
   // ---- offsets: first/last, monotonicity (host sync 1 of 2)
-  ensure(c.state, sizeof(kc::DevState), "device state");
+  grow(c.state, sizeof(kc::DevState), "device state", st);
   hipchk(kc::launch_fill_u64((unsigned long long*)c.state.p, sizeof(kc::DevState) / 8, 0, st),
          "fill launch");
   if (n_reads) {
@@ -765,7 +847,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   q.nb = 1 << q.sb;
   Pipe p = p0;
   const uint64_t nchunks = packed_chunks(q.N);
-  plain_needs(p, [&](DevBuf Ctx::*m, size_t bytes, const char* name) { ensure(c.*m, bytes, name); });
+  plain_needs(p, [&](DevBuf Ctx::*m, size_t bytes, const char* name) { grow(c.*m, bytes, name, st); });
   p.order = device_order(c, q, S, st);
   kc::DevState* dstate = (kc::DevState*)c.state.p;
 
@@ -837,11 +919,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   return KC_OK;
 }
 
-void free_buf(DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
-  b.p = nullptr;
-  b.cap = 0;
-}
+void free_buf(DevBuf& b) { drop(b); }
 
 }  // namespace
 
@@ -1222,6 +1300,55 @@ int guarded(F f) {
 
 namespace kc {
 
+namespace {
+std::mutex g_pool_m;
+std::map<int, hipMemPool_t> g_pools;
+}  // namespace
+
+hipError_t device_pool(int device, hipMemPool_t* pool) {
+  std::lock_guard<std::mutex> lk(g_pool_m);
+  auto it = g_pools.find(device);
+  if (it != g_pools.end()) {
+    *pool = it->second;
+    return hipSuccess;
+  }
+  hipMemPoolProps props;
+  std::memset(&props, 0, sizeof(props));
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = device;
+  hipMemPool_t p = nullptr;
+  hipError_t e = hipMemPoolCreate(&p, &props);
+  if (e != hipSuccess) return e;
+  uint64_t keep = ~0ull;  // never hand idle blocks back on a synchronization
+  e = hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+  // a block freed on one stream is not reused on another before its free has
+  // completed (no waits inserted between the server's streams)
+  int no = 0;
+  if (e == hipSuccess) e = hipMemPoolSetAttribute(p, hipMemPoolReuseAllowInternalDependencies, &no);
+  if (e != hipSuccess) {
+    (void)hipMemPoolDestroy(p);
+    return e;
+  }
+  g_pools[device] = p;
+  *pool = p;
+  return hipSuccess;
+}
+
+void trim_device_pool(int device) {
+  hipMemPool_t p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_m);
+    auto it = g_pools.find(device);
+    if (it == g_pools.end()) return;
+    p = it->second;
+  }
+  // blocks freed on the null stream (released arenas) become idle first
+  (void)hipStreamSynchronize(nullptr);
+  (void)hipMemPoolTrimTo(p, 0);
+}
+
 int count_with_alloc(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k,
                      int P, const kc_options* opt, hipStream_t st, const OutAlloc& oa,
                      uint64_t* n_out, kc_stats* stats, std::string* err) {
@@ -1365,6 +1492,8 @@ void kc_release_scratch(void) {
   try {
     g_ctx.clear();
     kc::release_post_scratch();
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) kc::trim_device_pool(dev);
   } catch (...) {
   }
 }

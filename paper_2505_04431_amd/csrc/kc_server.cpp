@@ -8,6 +8,10 @@
 // different sizes run side by side on the device and a finished job's slot is
 // refilled at once. Results are allocated at their exact size once the
 // number of distinct keys is known and stay on the device until released.
+// Results and arena growth come from the library's stream-ordered pool, which
+// keeps what is freed into it: a device free waits for every stream of the
+// device, so handing memory back to the driver while jobs run stalls all
+// workers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,6 +59,7 @@ struct Job {
 struct JobAlloc {
   Job* job;
   hipStream_t st;
+  hipMemPool_t pool;
 };
 
 int alloc_result(void* user, uint64_t distinct, int key_words, uint64_t** keys, uint32_t** counts) {
@@ -64,14 +69,23 @@ int alloc_result(void* user, uint64_t distinct, int key_words, uint64_t** keys, 
   if (distinct == 0) return KC_OK;
   void* pk = nullptr;
   void* pc = nullptr;
-  if (hipMallocAsync(&pk, distinct * 8 * (uint64_t)key_words, a->st) != hipSuccess) {
-    (void)hipGetLastError();
-    return KC_E_NOMEM;
-  }
-  if (hipMallocAsync(&pc, distinct * 4, a->st) != hipSuccess) {
-    (void)hipGetLastError();
-    (void)hipFreeAsync(pk, a->st);
-    return KC_E_NOMEM;
+  // from the library pool, which keeps released results for later ones; when
+  // the device is short, the pool's idle blocks are returned and it is tried
+  // once more
+  const uint64_t kbytes = distinct * 8 * (uint64_t)key_words;
+  for (int attempt = 0;; ++attempt) {
+    if (hipMallocFromPoolAsync(&pk, kbytes, a->pool, a->st) == hipSuccess) {
+      if (hipMallocFromPoolAsync(&pc, distinct * 4, a->pool, a->st) == hipSuccess) break;
+      (void)hipGetLastError();
+      (void)hipFreeAsync(pk, a->st);
+      pk = nullptr;
+    } else {
+      (void)hipGetLastError();
+    }
+    if (attempt == 1) return KC_E_NOMEM;
+    int dev = 0;
+    (void)hipStreamSynchronize(a->st);
+    if (hipGetDevice(&dev) == hipSuccess) kc::trim_device_pool(dev);
   }
   a->job->keys = (uint64_t*)pk;
   a->job->counts = (uint32_t*)pc;
@@ -112,13 +126,14 @@ struct kc_server {
   uint64_t next_id = 1;
   bool stop = false;
   uint64_t submitted = 0, completed = 0, failed = 0, running = 0, windows = 0;
-  uint64_t est_misses = 0, reserved_total = 0, actual_total = 0;
+  uint64_t est_misses = 0, reserved_total = 0, actual_total = 0, growths = 0, releases = 0;
   bool any_start = false;
   Clock::time_point first_start, last_end;
   std::vector<double> lat_ms, wait_ms;
 
   std::mutex submit_m;  // the control stream and its pinned staging
   hipStream_t ctl = nullptr;
+  hipMemPool_t pool = nullptr;  // results and worker arenas
   uint64_t* pinned = nullptr;
   std::vector<hipStream_t> streams;
   std::vector<std::thread> threads;
@@ -165,6 +180,7 @@ void kc_server::worker_main(int w) {
           lk.lock();
           ledger.sub(arena[w]);
           arena[w] = 0;
+          ++releases;
           cv_work.notify_all();
           continue;
         }
@@ -172,7 +188,7 @@ void kc_server::worker_main(int w) {
       }
       if (!job) return;
     }
-    JobAlloc a{job, st};
+    JobAlloc a{job, st, pool};
     kc::OutAlloc oa{alloc_result, &a};
     kc_stats S;
     std::memset(&S, 0, sizeof(S));
@@ -201,6 +217,7 @@ void kc_server::worker_main(int w) {
 void kc_server::finish_locked(Job* j, int w, uint64_t new_arena) {
   ledger.sub(j->reserved);
   j->reserved = 0;
+  if (new_arena > arena[w]) ++growths;
   if (new_arena >= arena[w])
     ledger.add(new_arena - arena[w]);
   else
@@ -270,6 +287,8 @@ void destroy_server(kc_server* s) {
     if (st) (void)hipStreamDestroy(st);
   if (s->ctl) (void)hipStreamDestroy(s->ctl);
   if (s->pinned) (void)hipHostFree(s->pinned);
+  // the results and the workers' arenas (freed as their threads ended)
+  if (s->pool) kc::trim_device_pool(s->device);
   delete s;
 }
 
@@ -292,6 +311,10 @@ int kc_server_create(uint64_t hbm_budget_bytes, int n_workers, const kc_options*
     s->n_workers = n_workers;
     s->t0 = Clock::now();
     s->arena.assign(n_workers, 0);
+    if (kc::device_pool(s->device, &s->pool) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(KC_E_DEVICE, "device memory pool creation failed");
+    }
     if (hipStreamCreateWithFlags(&s->ctl, hipStreamNonBlocking) != hipSuccess ||
         hipHostMalloc((void**)&s->pinned, 64, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
@@ -521,6 +544,8 @@ int kc_server_stats(kc_server* s, kc_serve_stats* out) {
     out->estimate_misses = s->est_misses;
     out->result_bytes_reserved = s->reserved_total;
     out->result_bytes_actual = s->actual_total;
+    out->arena_growths = s->growths;
+    out->scratch_releases = s->releases;
     out->latency_p50_ms = percentile(s->lat_ms, 0.50);
     out->latency_p99_ms = percentile(s->lat_ms, 0.99);
     out->wait_p50_ms = percentile(s->wait_ms, 0.50);

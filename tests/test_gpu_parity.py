@@ -233,3 +233,37 @@ def test_sort_mode_single_key_leaves_and_full_size():
                 oracle.count(c["reads"], c["offsets"], 31), "config 2, mode 1")
     st = kc.last_stats()
     assert st["distinct"] > 0
+
+
+def test_calls_on_two_streams_in_a_row():
+    """A call returns with its last kernels (the copy into the outputs) still
+    queued on its stream; the next call of the same thread on another stream
+    reuses the thread's device buffers and must not overwrite them early."""
+    import torch
+    import paper_2505_04431_amd as kc
+    a = synth.make_config(2, frac=0.15)
+    g = synth.genome(5, 300_000, [(2000, 8, 0.02)])
+    br, bo = synth.reads(g, 60_000, 150, err_rate=0.01, seed=6)
+    ra, oa = to_device(a["reads"], a["offsets"])
+    rb, ob = to_device(br, bo)
+    want_a = oracle.count(a["reads"], a["offsets"], 31)
+    want_b = oracle.count(br, bo, 31)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            ka, ca = kc.count(ra, oa, 31, P=16)
+        with torch.cuda.stream(s2):
+            kb, cb = kc.count(rb, ob, 31, P=16)
+        torch.cuda.synchronize()
+        assert_same((ka.cpu().numpy().view(np.uint64), ca.cpu().numpy().view(np.uint32)), want_a,
+                    "first call, stream 1")
+        assert_same((kb.cpu().numpy().view(np.uint64), cb.cpu().numpy().view(np.uint32)), want_b,
+                    "second call, stream 2")
+    # the arena handed back (its blocks returned to the device) and grown again
+    kc.lib().kc_release_scratch()
+    with torch.cuda.stream(s2):
+        ka, ca = kc.count(ra, oa, 31, P=16)
+    torch.cuda.synchronize()
+    assert_same((ka.cpu().numpy().view(np.uint64), ca.cpu().numpy().view(np.uint32)), want_a,
+                "after release")
