@@ -44,8 +44,8 @@ void release_post_scratch();
 // use): the count arenas and the server's results come from it. It keeps the
 // blocks freed into it (no release threshold), so growing an arena or
 // dropping a result while other streams run never hands memory back to the
-// driver; trim_device_pool returns the idle blocks (kc_release_scratch and
-// server teardown call it).
+// driver; trim_device_pool frees the arenas of threads that have ended and
+// returns the idle blocks (kc_release_scratch and server teardown call it).
 hipError_t device_pool(int device, hipMemPool_t* pool);
 void trim_device_pool(int device);
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -76,7 +77,37 @@ struct Ctx {
   }
 };
 
-thread_local std::map<int, std::unique_ptr<Ctx>> g_ctx;
+using CtxMap = std::map<int, std::unique_ptr<Ctx>>;
+
+// Contexts of threads that have ended. A thread-local destructor must not call
+// HIP (the runtime's and a profiler's per-thread state may be gone by then),
+// so an ending thread only hands its contexts over; they are freed by the next
+// count on any thread, kc_release_scratch or a server's teardown. Never
+// destroyed: at process exit the device memory goes with the process.
+std::mutex g_orphan_m;
+std::vector<std::unique_ptr<Ctx>>* const g_orphans = new std::vector<std::unique_ptr<Ctx>>();
+std::atomic<bool> g_have_orphans{false};  // a hint read without the lock
+
+struct ThreadCtx {
+  CtxMap m;
+  ~ThreadCtx() {
+    std::lock_guard<std::mutex> lk(g_orphan_m);
+    for (auto& kv : m)
+      if (kv.second) g_orphans->push_back(std::move(kv.second));
+    g_have_orphans.store(!g_orphans->empty(), std::memory_order_relaxed);
+  }
+};
+thread_local ThreadCtx g_ctx;
+
+// Frees the contexts of ended threads (after their last work has finished).
+void free_orphans() {
+  std::vector<std::unique_ptr<Ctx>> v;
+  {
+    std::lock_guard<std::mutex> lk(g_orphan_m);
+    v.swap(*g_orphans);
+    g_have_orphans.store(false, std::memory_order_relaxed);
+  }
+}
 
 struct Fail {
   int code;
@@ -183,7 +214,7 @@ void* host_stage(Ctx& c, size_t bytes) {
 Ctx& context() {
   int dev = 0;
   hipchk(hipGetDevice(&dev), "hipGetDevice");
-  auto& slot = g_ctx[dev];
+  auto& slot = g_ctx.m[dev];
   if (!slot) {
     slot.reset(new Ctx());
     slot->device = dev;
@@ -805,6 +836,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   if (opt) q.o = *opt;
   if (q.o.mode != 0 && q.o.mode != 1) fail(KC_E_INVAL, "mode must be 0 or 1");
 
+  if (g_have_orphans.load(std::memory_order_relaxed)) free_orphans();
   Ctx& c = context();
   const CtxUse use(c, st);
   std::memset(&g_stats, 0, sizeof(g_stats));
@@ -1337,6 +1369,7 @@ hipError_t device_pool(int device, hipMemPool_t* pool) {
 }
 
 void trim_device_pool(int device) {
+  free_orphans();  // arenas of ended threads (a server's workers) first
   hipMemPool_t p = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_pool_m);
@@ -1380,8 +1413,8 @@ uint64_t scratch_growth(uint64_t n_bytes, int k, int P, const kc_options* opt) {
   try {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return growth_of(nullptr, n_bytes, k, P, opt);
-    auto it = g_ctx.find(dev);
-    return growth_of(it == g_ctx.end() ? nullptr : it->second.get(), n_bytes, k, P, opt);
+    auto it = g_ctx.m.find(dev);
+    return growth_of(it == g_ctx.m.end() ? nullptr : it->second.get(), n_bytes, k, P, opt);
   } catch (...) {
     return growth_of(nullptr, n_bytes, k, P, opt);
   }
@@ -1396,8 +1429,8 @@ uint64_t scratch_bytes(uint64_t n_bytes, int k, int P, const kc_options* opt) {
 uint64_t arena_bytes() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
-  auto it = g_ctx.find(dev);
-  if (it == g_ctx.end() || !it->second) return 0;
+  auto it = g_ctx.m.find(dev);
+  if (it == g_ctx.m.end() || !it->second) return 0;
   const Ctx& c = *it->second;
   const DevBuf* all[] = {&c.packed,  &c.inv,     &c.endm,   &c.bufA,    &c.bufB,   &c.tmpcnt,
                          &c.hist,    &c.sbegin,  &c.cursor, &c.cursor2, &c.order,  &c.items,
@@ -1490,7 +1523,8 @@ int kc_last_stats(kc_stats* out) {
 
 void kc_release_scratch(void) {
   try {
-    g_ctx.clear();
+    g_ctx.m.clear();
+    free_orphans();
     kc::release_post_scratch();
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) kc::trim_device_pool(dev);

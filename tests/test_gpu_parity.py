@@ -267,3 +267,32 @@ def test_calls_on_two_streams_in_a_row():
     torch.cuda.synchronize()
     assert_same((ka.cpu().numpy().view(np.uint64), ca.cpu().numpy().view(np.uint32)), want_a,
                 "after release")
+
+
+def test_arena_of_an_ended_thread():
+    """A thread that counted and ended leaves its arena behind; the next count
+    (on another thread) frees it and its own result is unaffected."""
+    import threading
+    import torch
+    import paper_2505_04431_amd as kc
+    g = synth.genome(9, 200_000, [(1500, 6, 0.02)])
+    r, o = synth.reads(g, 40_000, 150, err_rate=0.01, seed=2)
+    rt, ot = to_device(r, o)
+    want = oracle.count(r, o, 55)
+    got = {}
+
+    def worker():
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            k1, c1 = kc.count(rt, ot, 55, P=8)
+        s.synchronize()
+        got["t"] = (k1.cpu().numpy().view(np.uint64), c1.cpu().numpy().view(np.uint32))
+
+    for _ in range(2):
+        th = threading.Thread(target=worker)
+        th.start()
+        th.join()
+        assert_same(got["t"], want, "ended thread")
+        k2, c2 = kc.count(rt, ot, 55, P=8)
+        assert_same((k2.cpu().numpy().view(np.uint64), c2.cpu().numpy().view(np.uint32)), want,
+                    "after the thread ended")
