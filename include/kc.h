@@ -112,9 +112,9 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
  * automatic) and a HIP stream (hipStream_t passed as void*, NULL = default).
  * If more than out_capacity keys result, returns KC_E_CAPACITY with *n_out set.
  * Returns once *n_out is known; the copy into the outputs may still be queued
- * on the stream. Calls of one host thread share its scratch arena: a call on
- * another stream than the thread's previous call first waits (on the device)
- * for that call's work. */
+ * on the stream. Calls of one host thread share its scratch arena: each call
+ * first waits (on the device, in stream order) for the thread's previous
+ * call's work, whatever stream that ran on. */
 int kc_count_ex(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
                 uint64_t* out_keys, uint32_t* out_counts, uint64_t out_capacity,
                 uint64_t* n_out, const kc_options* opt, void* stream);

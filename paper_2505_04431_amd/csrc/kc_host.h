@@ -49,6 +49,10 @@ void release_post_scratch();
 hipError_t device_pool(int device, hipMemPool_t* pool);
 void trim_device_pool(int device);
 
+// Returns the calling thread's count arenas to the pool without trimming it
+// (a server worker making room under its budget while others run).
+void release_thread_arena();
+
 // Sets the message kc_last_error() returns on the calling thread.
 void set_last_error(const std::string& msg);
 

@@ -55,7 +55,6 @@ struct Ctx {
   // reading these buffers (the concat into caller-owned outputs), so a call on
   // another stream first waits for it.
   hipEvent_t done = nullptr;
-  hipStream_t done_st = nullptr;
   bool done_set = false;
 
   ~Ctx() {
@@ -170,11 +169,13 @@ void grow(DevBuf& b, size_t bytes, const char* name, hipStream_t st) {
   hipchk(hipGetDevice(&dev), "hipGetDevice");
   hipMemPool_t pool = nullptr;
   hipchk(kc::device_pool(dev, &pool), "device memory pool");
+  // a buffer that grows again grows by half at least: fewer growths, each of
+  // which may map fresh memory, while a server's arenas reach their sizes
+  size_t want = std::max(alloc_size(bytes), b.cap + b.cap / 2);
   if (b.p) {
     hipchk(b.pooled ? hipFreeAsync(b.p, st) : hipFree(b.p), "free");
     b = DevBuf{};
   }
-  size_t want = alloc_size(bytes);
   hipError_t e = hipMallocFromPoolAsync(&b.p, want, pool, st);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -222,18 +223,18 @@ Ctx& context() {
   return *slot;
 }
 
-// Orders a call on `st` after the previous call on this thread's context (when
-// that one ran on another stream) and, on every exit, marks the call's end.
+// Orders a call on `st` after the previous call on this thread's context and,
+// on every exit, marks the call's end. The wait is made even when the stream
+// handle is the same: a destroyed stream's handle may come back for a new one.
 struct CtxUse {
   Ctx& c;
   hipStream_t st;
   CtxUse(Ctx& ctx, hipStream_t s) : c(ctx), st(s) {
     if (!c.done) hipchk(hipEventCreateWithFlags(&c.done, hipEventDisableTiming), "hipEventCreate");
-    if (c.done_set && c.done_st != st) hipchk(hipStreamWaitEvent(st, c.done, 0), "hipStreamWaitEvent");
+    if (c.done_set) hipchk(hipStreamWaitEvent(st, c.done, 0), "hipStreamWaitEvent");
   }
   ~CtxUse() {
     if (hipEventRecord(c.done, st) == hipSuccess) {
-      c.done_st = st;
       c.done_set = true;
     } else {
       // without the mark, wait for everything before the context is reused
@@ -1368,6 +1369,8 @@ hipError_t device_pool(int device, hipMemPool_t* pool) {
   return hipSuccess;
 }
 
+void release_thread_arena() { g_ctx.m.clear(); }
+
 void trim_device_pool(int device) {
   free_orphans();  // arenas of ended threads (a server's workers) first
   hipMemPool_t p = nullptr;
@@ -1403,7 +1406,8 @@ uint64_t growth_of(const Ctx* c, uint64_t n_bytes, int k, int P, const kc_option
   uint64_t g = 0;
   plain_needs(p, [&](DevBuf Ctx::*m, size_t bytes, const char*) {
     const size_t have = c ? (c->*m).cap : 0;
-    if (have < std::max<size_t>(bytes, 1)) g += alloc_size(bytes) - have;
+    // as grow() allocates: a buffer that grows again takes half its size more at least
+    if (have < std::max<size_t>(bytes, 1)) g += std::max(alloc_size(bytes), have + have / 2) - have;
   });
   return g;
 }

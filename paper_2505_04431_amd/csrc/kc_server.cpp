@@ -174,9 +174,11 @@ void kc_server::worker_main(int w) {
         }
         if (!queue.empty() && arena[w] > 0 && running == 0) {
           // nothing fits while every worker is idle: give this worker's
-          // scratch back so that the jobs' own needs can fit
+          // scratch back so that the jobs' own needs can fit. Its blocks stay
+          // in the library pool for the next allocations (handing them to the
+          // driver would make every stream of the device wait)
           lk.unlock();
-          kc_release_scratch();
+          kc::release_thread_arena();
           lk.lock();
           ledger.sub(arena[w]);
           arena[w] = 0;
