@@ -296,3 +296,17 @@ def test_arena_of_an_ended_thread():
         k2, c2 = kc.count(rt, ot, 55, P=8)
         assert_same((k2.cpu().numpy().view(np.uint64), c2.cpu().numpy().view(np.uint32)), want,
                     "after the thread ended")
+
+
+def test_arena_regrowth_sizes():
+    """Inputs of rising and falling sizes on one thread: the arena grows
+    stream-ordered from the device pool (by half its size at least), is kept
+    when a smaller input follows, and is rebuilt after a release."""
+    import paper_2505_04431_amd as kc
+    g = synth.genome(13, 400_000, [(2000, 5, 0.02)])
+    for i, n in enumerate((300, 4_000, 1_500, 30_000, 90_000, 20_000, 60_000)):
+        r, o = synth.reads(g, n, 150, err_rate=0.01, seed=100 + n)
+        k = 31 if i % 2 == 0 else 55
+        assert_same(gpu_count(r, o, k, P=8), oracle.count(r, o, k), "n=%d k=%d" % (n, k))
+        if i == 4:
+            kc.lib().kc_release_scratch()
