@@ -51,9 +51,9 @@ struct Ctx {
   size_t host_cap = 0;
   hipEvent_t ev[32] = {};
   bool ev_ok = false;
-  // The last call's work on its stream: a call may return with kernels still
-  // reading these buffers (the concat into caller-owned outputs), so a call on
-  // another stream first waits for it.
+  // The end of the last call's work: a call may return with kernels still
+  // reading these buffers (the concat into caller-owned outputs), so the next
+  // call, on whatever stream, first waits for it.
   hipEvent_t done = nullptr;
   bool done_set = false;
 
