@@ -275,7 +275,8 @@ void kc_pred_free(kc_predictor* pred);
  *   if a sum exceeds 2^32-1. Lets inputs larger than device memory be counted
  *   in pieces whose results are merged. Synchronous on stream.
  * The temporaries of kc_merge_counts ((na + nb) * (8 * words + 4) bytes) and
- * kc_filter_min_count sit in one device buffer per host thread that grows as
+ * kc_filter_min_count sit in one device buffer per host thread, part of the
+ * thread's scratch arena: it grows stream-ordered from the library pool as
  * needed and is kept between calls (kc_release_scratch frees it).
  * All return KC_OK, KC_E_INVAL, KC_E_NOMEM or KC_E_DEVICE (and as stated). */
 int kc_spectrum(const uint32_t* counts, uint64_t n, uint32_t max_count, uint64_t* host_hist,

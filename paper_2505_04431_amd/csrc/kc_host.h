@@ -37,8 +37,12 @@ uint64_t scratch_bytes(uint64_t n_bytes, int k, int P, const kc_options* opt);
 // Device bytes held by the calling thread's arena on the current device.
 uint64_t arena_bytes();
 
-// Frees the calling thread's temporary buffer of the merge and the filter.
-void release_post_scratch();
+// Device temporaries of the merge and the filter: a buffer of the calling
+// thread's context on the current device, grown stream-ordered on st from the
+// library pool and kept between calls (the callers are synchronous, so the
+// buffer is idle when a call starts). Returns nullptr on failure, with the
+// error message in *err and its status in *code.
+void* thread_scratch(size_t bytes, hipStream_t st, std::string* err, int* code) noexcept;
 
 // The library's stream-ordered memory pool of a device (created on first
 // use): the count arenas and the server's results come from it. It keeps the

@@ -140,40 +140,17 @@ int bad(const char* msg) {
   return KC_E_INVAL;
 }
 
-// Temporary device memory of the merge and the filter: grow-only, one buffer
-// per host thread, kept between calls so that repeated calls (a result merged
-// piece by piece) do not map fresh memory each time. Every call is
-// synchronous, so a call on the same thread finds the buffer idle. Freed by
-// kc_release_scratch or when the thread ends.
-struct PostScratch {
-  void* p = nullptr;
-  size_t cap = 0;
-  ~PostScratch() {
-    if (p) (void)hipFree(p);
+// Temporary device memory of the merge and the filter: the calling thread's
+// buffer, kept between calls (kc_release_scratch frees it).
+void* post_scratch(size_t bytes, hipStream_t st) {
+  std::string err;
+  int code = KC_E_NOMEM;
+  void* p = kc::thread_scratch(bytes, st, &err, &code);
+  if (!p) {
+    kc::set_last_error(err);
+    throw Fail{code};
   }
-};
-thread_local PostScratch t_post;
-
-void* post_scratch(size_t bytes) {
-  if (t_post.p && t_post.cap >= bytes) return t_post.p;
-  if (t_post.p) {
-    (void)hipFree(t_post.p);
-    t_post.p = nullptr;
-    t_post.cap = 0;
-  }
-  size_t want = bytes + bytes / 4 + 256;
-  hipError_t e = hipMalloc(&t_post.p, want);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    want = bytes;
-    e = hipMalloc(&t_post.p, want);
-  }
-  if (e != hipSuccess) {
-    t_post.p = nullptr;
-    chk(e, "hipMalloc");
-  }
-  t_post.cap = want;
-  return t_post.p;
+  return p;
 }
 
 unsigned grid_of(uint64_t n, uint64_t per, unsigned cap) {
@@ -183,15 +160,6 @@ unsigned grid_of(uint64_t n, uint64_t per, unsigned cap) {
 
 }  // namespace
 
-namespace kc {
-void release_post_scratch() {
-  if (t_post.p) {
-    (void)hipFree(t_post.p);
-    t_post.p = nullptr;
-    t_post.cap = 0;
-  }
-}
-}  // namespace kc
 
 extern "C" {
 
@@ -238,7 +206,7 @@ int kc_filter_min_count(const uint64_t* keys, const uint32_t* counts, uint64_t n
   const uint64_t nt = (n + kTile - 1) / kTile;
   void* d = nullptr;
   try {
-    d = post_scratch((size_t)(nt + 1) * 8);
+    d = post_scratch((size_t)(nt + 1) * 8, st);
     unsigned long long* tsum = (unsigned long long*)d;
     hipLaunchKernelGGL(k_keep_count, dim3((unsigned)nt), dim3(kTB), 0, st, counts, n, min_count,
                        tsum);
@@ -459,7 +427,7 @@ extern "C" int kc_merge_counts(const uint64_t* a_keys, const uint32_t* a_counts,
     const size_t kb = n * 8 * (size_t)words, cb = n * 4, tb = (nt + 1) * 8;
     const uint64_t nblk = (n + kMergeTile - 1) / kMergeTile;
     // layout: merged keys, counts, (pad to 8), tile sums, flag (16 bytes), splits
-    d = post_scratch(kb + cb + 8 + tb + 16 + (nblk + 1) * 8);
+    d = post_scratch(kb + cb + 8 + tb + 16 + (nblk + 1) * 8, st);
     uint64_t* mk = (uint64_t*)d;
     uint32_t* mc = (uint32_t*)((char*)d + kb);
     unsigned long long* tsum = (unsigned long long*)((char*)d + kb + cb + (8 - (cb & 7)) % 8);

@@ -45,6 +45,7 @@ struct Ctx {
   DevBuf large, bsum, itemoff;
   // overflow refinement: overflowed leaves, part attempts, the spliced list
   DevBuf rlist, rleaves, rcount, aleaves, adcnt, alarge, rparts, rcnt, leaves2, dcnt2;
+  DevBuf post;  // temporaries of kc_merge_counts / kc_filter_min_count
   std::vector<int> order_host;
   int order_P = -1, order_sb = -1;
   void* host = nullptr;  // pinned staging for small device<->host copies
@@ -64,7 +65,7 @@ struct Ctx {
                      &sbegin,  &cursor,  &cursor2, &order,  &items,  &bins,    &subhist,
                      &leaves,  &dcnt,    &outoff, &state,   &large,  &bsum,    &itemoff,
                      &rlist,   &rleaves, &rcount, &aleaves, &adcnt,  &alarge,  &rparts,
-                     &rcnt,    &leaves2, &dcnt2};
+                     &rcnt,    &leaves2, &dcnt2,  &post};
     // the last call's kernels may still read the buffers
     if (done_set) (void)hipEventSynchronize(done);
     for (DevBuf* b : all) drop(*b);
@@ -1375,6 +1376,21 @@ hipError_t device_pool(int device, hipMemPool_t* pool) {
 
 void release_thread_arena() { g_ctx.m.clear(); }
 
+void* thread_scratch(size_t bytes, hipStream_t st, std::string* err, int* code) noexcept {
+  try {
+    Ctx& c = context();
+    grow(c.post, bytes, "merge and filter temporaries", st);
+    return c.post.p;
+  } catch (const Fail& f) {
+    if (err) *err = g_err;
+    if (code) *code = f.code;
+  } catch (...) {
+    if (err) *err = "merge and filter temporaries: allocation failed";
+    if (code) *code = KC_E_NOMEM;
+  }
+  return nullptr;
+}
+
 void trim_device_pool(int device) {
   free_orphans();  // arenas of ended threads (a server's workers) first
   hipMemPool_t p = nullptr;
@@ -1533,7 +1549,6 @@ void kc_release_scratch(void) {
   try {
     g_ctx.m.clear();
     free_orphans();
-    kc::release_post_scratch();
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) kc::trim_device_pool(dev);
   } catch (...) {
