@@ -353,6 +353,36 @@ def parse_fastx(text, fmt: int = FASTX_AUTO, stream=None):
         return reads[:nbase.value], offs[:nr.value + 1], fo.value
 
 
+_chunk_local = threading.local()
+
+
+def _chunk_staging(dev, pin_bytes: int, n_offs: int, dev_bytes: int) -> dict:
+    """The calling thread's staging for count_chunked on dev: two pinned and two
+    device buffers for reads and offsets, a side stream and two events, kept
+    between calls and grown when a call needs more (a pinned allocation costs
+    milliseconds)."""
+    import torch
+    cache = getattr(_chunk_local, "staging", None)
+    if cache is None:
+        cache = _chunk_local.staging = {}
+    st = cache.get(dev.index)
+    if st is None:
+        st = cache[dev.index] = {"stream": torch.cuda.Stream(device=dev),
+                                 "done": [torch.cuda.Event() for _ in range(2)],
+                                 "pin_r": None, "pin_o": None, "dev_r": None, "dev_o": None}
+    for e in st["done"]:
+        e.synchronize()  # no copy of an earlier call still reads these buffers
+    if st["pin_r"] is None or st["pin_r"][0].numel() < pin_bytes:
+        st["pin_r"] = [torch.empty(pin_bytes, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+    if st["pin_o"] is None or st["pin_o"][0].numel() < n_offs:
+        st["pin_o"] = [torch.empty(n_offs, dtype=torch.int64, pin_memory=True) for _ in range(2)]
+    if st["dev_r"] is None or st["dev_r"][0].numel() < dev_bytes:
+        st["dev_r"] = [torch.empty(dev_bytes, dtype=torch.uint8, device=dev) for _ in range(2)]
+    if st["dev_o"] is None or st["dev_o"][0].numel() < n_offs:
+        st["dev_o"] = [torch.empty(n_offs, dtype=torch.int64, device=dev) for _ in range(2)]
+    return st
+
+
 def count_chunked(host_reads, host_offsets, k: int, P: int = 1, chunk_bytes: int = 1 << 30,
                   opts: KcOptions | None = None):
     """Count reads held in host memory in pieces of about chunk_bytes, so the
@@ -385,19 +415,15 @@ def count_chunked(host_reads, host_offsets, k: int, P: int = 1, chunk_bytes: int
         r = e
     if not pieces:
         return keys, counts
-    # output room of each piece: its windows of length k (from the host offsets)
-    lens = np.diff(offs.astype(np.int64))
-    wins = np.concatenate([[0], np.cumsum(np.maximum(lens - k + 1, 0))])
-    caps = [max(1, int(wins[e] - wins[r])) for r, e in pieces]
+    # output room of each piece: its windows of length k (kc_max_outputs over
+    # the piece's host offsets)
+    lib_ = lib()
+    caps = [max(1, int(lib_.kc_max_outputs(offs[r:].ctypes.data, e - r, k))) for r, e in pieces]
     max_b = max(1, max(int(offs[e] - offs[r]) for r, e in pieces))
     max_r = max(e - r for r, e in pieces)
-    pin_r = [torch.empty(1 if pinned_in else max_b, dtype=torch.uint8, pin_memory=True)
-             for _ in range(2)]
-    pin_o = [torch.empty(max_r + 1, dtype=torch.int64, pin_memory=True) for _ in range(2)]
-    dev_r = [torch.empty(max_b, dtype=torch.uint8, device=dev) for _ in range(2)]
-    dev_o = [torch.empty(max_r + 1, dtype=torch.int64, device=dev) for _ in range(2)]
-    copy_stream = torch.cuda.Stream(device=dev)
-    done = [torch.cuda.Event() for _ in range(2)]
+    st_ = _chunk_staging(dev, 1 if pinned_in else max_b, max_r + 1, max_b)
+    pin_r, pin_o, dev_r, dev_o = st_["pin_r"], st_["pin_o"], st_["dev_r"], st_["dev_o"]
+    copy_stream, done = st_["stream"], st_["done"]
 
     sizes = [None] * len(pieces)
 
