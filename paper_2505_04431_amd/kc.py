@@ -257,7 +257,9 @@ def count(reads, offsets, k: int, P: int = 1, opts: KcOptions | None = None, str
     """
     import torch
     if capacity is None:
-        capacity = max_outputs(offsets.cpu().numpy().view(np.uint64), k)
+        # every window starts at its own byte of reads: no copy of the offsets
+        # to the host (kc_max_outputs would need one) for a tighter bound
+        capacity = reads.numel()
     capacity = max(1, int(capacity))
     words = key_words(k)
     keys = torch.empty(_key_shape(capacity, words), dtype=torch.int64,
