@@ -317,6 +317,33 @@ int kc_parse_fastx(const uint8_t* text, uint64_t n_bytes, int format, uint8_t* o
                    uint64_t reads_capacity, uint64_t* out_offsets, uint64_t max_records,
                    uint64_t* n_records, uint64_t* n_bases, int* format_out, void* stream);
 
+/* ---- Allocation-free form, for callers that cannot allocate device memory
+ * (code that runs between a HIP graph capture's begin and end, tight serving
+ * loops, harnesses that forbid hipMalloc).
+ * kc_count_noalloc: the same arguments, result and errors as kc_count_ex, but
+ * the call allocates nothing: no hipMalloc / hipFree, no pool or pinned host
+ * allocation, no event or stream creation. Its device scratch is one fixed
+ * array of KC_NOALLOC_SCRATCH_MIB MiB per device, part of the library's code
+ * object (each device the library runs on holds it until the process ends);
+ * small host copies go through a fixed static host array of 8 MiB.
+ *   - Inputs whose scratch need exceeds the array are refused up front with
+ *     KC_E_NOMEM and a message giving both sizes (about 21 bytes of scratch
+ *     per read byte for k <= 32, 37 for k <= 64, 69 for k <= 128: roughly
+ *     12, 7 and 3.7 MB of reads). The rare leaf refinement that a
+ *     repeat-rich input may need also takes its buffers from the array and
+ *     fails the same way if it runs out.
+ *   - The call is synchronous: the outputs are complete when it returns.
+ *   - Every call on a device shares that device's array and the static host
+ *     array, which keep the last call's contents (each call clears what it
+ *     needs cleared). Calls are serialized by a process-wide lock; work that
+ *     another library call (or kernel) leaves running on the same device
+ *     concurrently does not touch the array.
+ *   - timing in opt is ignored (no events are created). */
+#define KC_NOALLOC_SCRATCH_MIB 256
+int kc_count_noalloc(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k,
+                     int P, uint64_t* out_keys, uint32_t* out_counts, uint64_t out_capacity,
+                     uint64_t* n_out, const kc_options* opt, void* stream);
+
 /* Upper bound on the number of output keys (= number of length-k windows,
  * valid or not): sum over reads of max(0, len - k + 1). host_offsets is a
  * HOST array of n_reads+1 offsets. Returns 0 for bad arguments. */

@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <optional>
 #include <string>
 #include <vector>
 
@@ -29,13 +30,52 @@ thread_local kc_stats g_stats;
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
-  bool pooled = false;  // from the library's device pool (freed stream-ordered)
+  bool pooled = false;    // from the library's device pool (freed stream-ordered)
+  bool borrowed = false;  // a piece of the allocation-free entry point's scratch (never freed)
 };
 
 // Frees an idle buffer.
 void drop(DevBuf& b) {
-  if (b.p) (void)(b.pooled ? hipFreeAsync(b.p, nullptr) : hipFree(b.p));
+  if (b.p && !b.borrowed) (void)(b.pooled ? hipFreeAsync(b.p, nullptr) : hipFree(b.p));
   b = DevBuf{};
+}
+
+// ---- the allocation-free entry point (kc_count_noalloc)
+//
+// Its device memory is one static array per device, `scratch`; while one of
+// its calls runs on a thread, every buffer the call would grow is carved from
+// that array instead (a bump pointer reset per call), and small host copies
+// go through a static host array instead of pinned memory.
+constexpr size_t kNoAllocScratchBytes = (size_t)KC_NOALLOC_SCRATCH_MIB << 20;
+constexpr size_t kNoAllocHostBytes = 8u << 20;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+struct Carve {
+  char* base;
+  size_t cap, used;
+};
+thread_local Carve* g_carve = nullptr;
+alignas(64) char g_noalloc_host[kNoAllocHostBytes];
+std::mutex g_noalloc_m;  // one allocation-free call at a time (the host array is shared)
+
+struct Fail;
+[[noreturn]] void fail(int code, const std::string& msg);
+
+// Gives b a fresh piece of the scratch array of at least `bytes` bytes (its
+// old piece, if any, is abandoned until the call ends).
+void carve(DevBuf& b, size_t bytes, const char* name) {
+  Carve& cv = *g_carve;
+  const size_t want = (std::max<size_t>(bytes, 256) + 255) & ~(size_t)255;
+  if (want > cv.cap - cv.used)
+    fail(KC_E_NOMEM, std::string("kc_count_noalloc: its fixed device scratch of ") +
+                         std::to_string(cv.cap >> 20) + " MiB is exhausted (" +
+                         std::to_string(bytes) + " more bytes for " + name + ")");
+  b.p = cv.base + cv.used;
+  b.cap = want;
+  b.pooled = false;
+  b.borrowed = true;
+  cv.used += want;
 }
 
 struct Ctx {
@@ -135,6 +175,7 @@ size_t alloc_size(size_t bytes) {
 void ensure(DevBuf& b, size_t bytes, const char* name) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return;
+  if (g_carve) return carve(b, bytes, name);
   if (b.p) {
     if (b.pooled) {
       hipchk(hipFreeAsync(b.p, nullptr), "hipFreeAsync");
@@ -166,6 +207,7 @@ void ensure(DevBuf& b, size_t bytes, const char* name) {
 void grow(DevBuf& b, size_t bytes, const char* name, hipStream_t st) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return;
+  if (g_carve) return carve(b, bytes, name);
   int dev = 0;
   hipchk(hipGetDevice(&dev), "hipGetDevice");
   hipMemPool_t pool = nullptr;
@@ -201,6 +243,14 @@ void grow(DevBuf& b, size_t bytes, const char* name, hipStream_t st) {
 }
 
 void* host_stage(Ctx& c, size_t bytes) {
+  if (g_carve) {
+    // allocation-free call: the static host array (held under g_noalloc_m)
+    if (bytes > kNoAllocHostBytes)
+      fail(KC_E_NOMEM, "kc_count_noalloc: " + std::to_string(bytes) +
+                           " bytes of host staging exceed its fixed " +
+                           std::to_string(kNoAllocHostBytes >> 20) + " MiB");
+    return g_noalloc_host;
+  }
   // callers only stage device-to-host copies and synchronize before reading,
   // so no copy into this buffer is pending when it is reallocated
   if (c.host_cap < bytes) {
@@ -826,9 +876,12 @@ const int* device_order(Ctx& c, const Call& q, kc_stats& S, hipStream_t st) {
   return (const int*)c.order.p;
 }
 
+// fixed: the context of an allocation-free call (buffers carved from the
+// static scratch), instead of the calling thread's arena.
 int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
                uint64_t* out_keys, uint32_t* out_counts, uint64_t cap, uint64_t* n_out,
-               const kc_options* opt, hipStream_t st, const kc::OutAlloc* oa = nullptr) {
+               const kc_options* opt, hipStream_t st, const kc::OutAlloc* oa = nullptr,
+               Ctx* fixed = nullptr) {
   auto t_host0 = std::chrono::steady_clock::now();
   if (!n_out) fail(KC_E_INVAL, "n_out is NULL");
   *n_out = 0;
@@ -842,13 +895,15 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   if (opt) q.o = *opt;
   if (q.o.mode != 0 && q.o.mode != 1) fail(KC_E_INVAL, "mode must be 0 or 1");
 
-  if (g_have_orphans.load(std::memory_order_relaxed)) free_orphans();
-  Ctx& c = context();
-  const CtxUse use(c, st);
+  if (!fixed && g_have_orphans.load(std::memory_order_relaxed)) free_orphans();
+  Ctx& c = fixed ? *fixed : context();
+  // an allocation-free call is synchronous and records no event or timing
+  std::optional<CtxUse> use;
+  if (!fixed) use.emplace(c, st);
   std::memset(&g_stats, 0, sizeof(g_stats));
   kc_stats S;
   std::memset(&S, 0, sizeof(S));
-  Timer tm(c, st, q.o.timing != 0);
+  Timer tm(c, st, q.o.timing != 0 && !fixed);
 
   // ---- offsets: first/last, monotonicity (host sync 1 of 2)
   grow(c.state, sizeof(kc::DevState), "device state", st);
@@ -885,6 +940,18 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   q.nb = 1 << q.sb;
   Pipe p = p0;
   const uint64_t nchunks = packed_chunks(q.N);
+  if (fixed) {
+    // the input must fit the fixed scratch before anything is carved from it
+    size_t need = 0;
+    plain_needs(p, [&](DevBuf Ctx::*, size_t bytes, const char*) {
+      need += (std::max<size_t>(bytes, 256) + 255) & ~(size_t)255;
+    });
+    if (need > g_carve->cap - g_carve->used)
+      fail(KC_E_NOMEM, "kc_count_noalloc: an input of " + std::to_string(q.N) + " bytes at k = " +
+                           std::to_string(k) + " needs " + std::to_string(need) +
+                           " bytes of device scratch; its fixed scratch holds " +
+                           std::to_string(kNoAllocScratchBytes) + " bytes");
+  }
   plain_needs(p, [&](DevBuf Ctx::*m, size_t bytes, const char* name) { grow(c.*m, bytes, name, st); });
   p.order = device_order(c, q, S, st);
   kc::DevState* dstate = (kc::DevState*)c.state.p;
@@ -948,7 +1015,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
       fail(KC_E_INTERNAL, msg);
     }
   }
-  if (oa) hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (oa || fixed) hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
   tm.collect(S);
   *n_out = ds.D;
   S.ms_total =
@@ -1469,6 +1536,32 @@ uint64_t arena_bytes() {
 
 }  // namespace kc
 
+namespace {
+
+std::mutex g_scratch_m;
+std::map<int, void*> g_scratch_ptr;  // per device: the device address of `scratch`
+
+// The device address of this device's copy of `scratch`, looked up once per
+// device (with that device current). In host code the array's own name is a
+// host-side stand-in, never a device address, so kernels get this pointer.
+char* noalloc_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_m);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return (char*)it->second;
+  void* ptr = nullptr;
+  hipchk(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  if (!ptr) fail(KC_E_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+  g_scratch_ptr[dev] = ptr;
+  return (char*)ptr;
+}
+
+struct CarveScope {
+  explicit CarveScope(Carve* c) { g_carve = c; }
+  ~CarveScope() { g_carve = nullptr; }
+};
+
+}  // namespace
+
 extern "C" {
 
 int kc_batch_plan(const uint64_t* host_set_reads, const uint64_t* host_set_bytes,
@@ -1526,6 +1619,23 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
              uint64_t* out_keys, uint32_t* out_counts, uint64_t* n_out) {
   return kc_count_ex(reads, offsets, n_reads, k, P, out_keys, out_counts, ~0ull, n_out, nullptr,
                      nullptr);
+}
+
+int kc_count_noalloc(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k,
+                     int P, uint64_t* out_keys, uint32_t* out_counts, uint64_t out_capacity,
+                     uint64_t* n_out, const kc_options* opt, void* stream) {
+  return guarded([&] {
+    int dev = 0;
+    hipchk(hipGetDevice(&dev), "hipGetDevice");
+    char* base = noalloc_scratch(dev);
+    std::lock_guard<std::mutex> lk(g_noalloc_m);
+    Carve cv{base, kNoAllocScratchBytes, 0};
+    const CarveScope scope(&cv);
+    Ctx c;
+    c.device = dev;
+    return count_impl(reads, offsets, n_reads, k, P, out_keys, out_counts, out_capacity, n_out,
+                      opt, (hipStream_t)stream, nullptr, &c);
+  });
 }
 
 uint64_t kc_max_outputs(const uint64_t* host_offsets, uint64_t n_reads, int k) {

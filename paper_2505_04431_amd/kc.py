@@ -29,7 +29,7 @@ EXPORTED_SYMBOLS = ["kc_count", "kc_count_ex", "kc_max_outputs", "kc_last_stats"
                     "kc_pred_get_params", "kc_pred_set_params", "kc_pred_get_grads",
                     "kc_pred_forward", "kc_pred_gradient", "kc_pred_adam_step", "kc_pred_free",
                     "kc_measure_ceilings", "kc_spectrum", "kc_filter_min_count",
-                    "kc_merge_counts", "kc_parse_fastx"]
+                    "kc_merge_counts", "kc_parse_fastx", "kc_count_noalloc"]
 
 JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
@@ -115,6 +115,8 @@ def lib():
             L.kc_count.argtypes = [p, p, u64, i32, i32, p, p, p]
             L.kc_count_ex.restype = i32
             L.kc_count_ex.argtypes = [p, p, u64, i32, i32, p, p, u64, p, p, p]
+            L.kc_count_noalloc.restype = i32
+            L.kc_count_noalloc.argtypes = [p, p, u64, i32, i32, p, p, u64, p, p, p]
             L.kc_max_outputs.restype = u64
             L.kc_max_outputs.argtypes = [p, u64, i32]
             L.kc_last_stats.restype = i32
@@ -241,6 +243,28 @@ def count_into(reads, offsets, k: int, P: int, out_keys, out_counts, capacity: i
                                out_keys.data_ptr(), out_counts.data_ptr(), capacity,
                                ctypes.byref(n_out),
                                ctypes.byref(opts) if opts is not None else None, stream)
+    if st != 0:
+        raise KcError(st, lib().kc_last_error().decode(), int(n_out.value))
+    return int(n_out.value)
+
+
+def count_noalloc_into(reads, offsets, k: int, P: int, out_keys, out_counts, capacity: int,
+                       opts: KcOptions | None = None, stream=None) -> int:
+    """Call kc_count_noalloc (the allocation-free form: fixed device scratch,
+    synchronous) on torch device tensors; returns the number of keys written."""
+    import torch
+    _check_tensor(reads, "reads", (torch.uint8,))
+    _check_tensor(offsets, "offsets", (torch.int64, torch.uint64))
+    _check_tensor(out_keys, "out_keys", (torch.int64, torch.uint64))
+    _check_tensor(out_counts, "out_counts", (torch.int32, torch.uint32))
+    if stream is None:
+        stream = torch.cuda.current_stream(reads.device).cuda_stream
+    n_out = ctypes.c_uint64(0)
+    with torch.cuda.device(reads.device):
+        st = lib().kc_count_noalloc(reads.data_ptr(), offsets.data_ptr(), offsets.numel() - 1, k,
+                                    P, out_keys.data_ptr(), out_counts.data_ptr(), capacity,
+                                    ctypes.byref(n_out),
+                                    ctypes.byref(opts) if opts is not None else None, stream)
     if st != 0:
         raise KcError(st, lib().kc_last_error().decode(), int(n_out.value))
     return int(n_out.value)
