@@ -120,30 +120,65 @@ int kc_count_ex(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads,
                 uint64_t* n_out, const kc_options* opt, void* stream);
 
 /* ---- Batched form: many independent read sets counted together.
+ * (Each set's result is the k-mer histogram of Section II of its reads alone;
+ * a memory wave plays the part of the batches of size b in which the BSP
+ * algorithm of Section III-B counts, bounding the memory one pass holds.)
  * The sets are consecutive in one read stream: set s holds host_set_reads[s]
  * reads and host_set_bytes[s] bytes, and has its own k (1..32). A set's
- * result is exactly what kc_count gives for its reads alone. All sets are
- * counted in one pass per distinct k with keys (set id << 2k) | k-mer, so the
- * counts of different sets never mix; the passes and the final placement of
- * each set's pairs are recorded once into a HIP graph and replayed.
+ * result is exactly what kc_count gives for its reads alone.
+ *
+ * Memory waves: the plan cuts the sets, in order, into waves of consecutive
+ * sets such that the device memory a wave needs (packed input, per-class
+ * pipeline buffers, class outputs, tables) stays within hbm_budget bytes
+ * (0 = no budget: one wave). The plan holds the memory of its largest wave
+ * only: waves run one after the other on the same buffers. Inside a wave the
+ * sets of one k are counted together in one pipeline pass per class with keys
+ * (set id << 2k) | k-mer, so the counts of different sets never mix; a
+ * wave's passes and the final placement of each set's pairs are recorded once
+ * into a HIP graph and replayed.
  *
  * kc_batch_plan: host arrays of n_sets entries; P as in kc_count; opt may be
- *   NULL. Allocates device memory for the batch; *plan receives the handle.
- * kc_batch_run: reads/offsets are device arrays laid out as planned
- *   (offsets has sum(host_set_reads)+1 entries); out_keys/out_counts device
- *   arrays of out_capacity entries (one uint64 key each); host_out_set_offsets
- *   a host array of n_sets+1 entries receiving where each set's pairs start.
- *   Returns KC_E_INVAL if the inputs do not match the plan, KC_E_CAPACITY (with
- *   *n_out set) if the outputs are too small. The graph is recorded on the
- *   first run and recorded again when a pointer or the capacity changes.
- *   Runs with one plan must not overlap; the plan keeps its scratch memory.
- * kc_batch_max_outputs: an upper bound of the pairs of the batch.
+ *   NULL. Allocates the device memory of the batch; *plan receives the handle.
+ *   KC_E_NOMEM if a single set needs more than hbm_budget.
+ * kc_batch_waves / kc_batch_wave_info: the waves and, for each, its sets,
+ *   reads and bytes (their ranges in the whole stream) and planned device bytes.
+ * kc_batch_run_wave: counts one wave from ITS OWN inputs: reads/offsets are
+ *   device arrays holding only the wave's reads (offsets has n_reads + 1
+ *   entries, offsets[0] may be nonzero), so a caller can prepare wave w + 1
+ *   while wave w counts. out_keys/out_counts: out_capacity entries (one uint64
+ *   key each); host_out_set_offsets: a host array of n_sets + 1 entries of the
+ *   wave receiving where each of its sets' pairs start.
+ * kc_batch_run: all waves in turn on the inputs of the whole batch (offsets
+ *   has sum(host_set_reads) + 1 entries); the sets' pairs follow each other in
+ *   set order; host_out_set_offsets receives n_sets + 1 entries.
+ * Both runs return KC_E_INVAL if the inputs do not match the plan, and
+ *   KC_E_CAPACITY (with *n_out set to the pairs needed) if the outputs are too
+ *   small. A wave's graph is recorded on its first run and recorded again when
+ *   a pointer or the capacity changes. Runs with one plan must not overlap.
+ *   When a class has a leaf its device-planned split cannot count, that
+ *   wave's sets are counted one by one with kc_count's path instead (same
+ *   result).
+ * kc_batch_max_outputs: an upper bound of the pairs of the whole batch.
  * kc_batch_stats: totals of the last run (windows, distinct, leaves, times).
  * kc_batch_free: releases the plan. */
 typedef struct kc_batch kc_batch;
+typedef struct kc_batch_wave {
+  uint32_t first_set, n_sets;
+  uint64_t first_read, n_reads;
+  uint64_t first_byte, n_bytes;
+  uint64_t device_bytes;  /* planned device bytes of the wave */
+  uint32_t n_classes;     /* pipeline passes in its graph */
+  uint32_t pad;
+} kc_batch_wave;
 int kc_batch_plan(const uint64_t* host_set_reads, const uint64_t* host_set_bytes,
-                  const int* host_ks, uint32_t n_sets, int P, const kc_options* opt,
-                  kc_batch** plan);
+                  const int* host_ks, uint32_t n_sets, int P, uint64_t hbm_budget,
+                  const kc_options* opt, kc_batch** plan);
+uint32_t kc_batch_waves(const kc_batch* plan);
+int kc_batch_wave_info(const kc_batch* plan, uint32_t wave, kc_batch_wave* out);
+int kc_batch_run_wave(kc_batch* plan, uint32_t wave, const uint8_t* reads,
+                      const uint64_t* offsets, uint64_t* out_keys, uint32_t* out_counts,
+                      uint64_t out_capacity, uint64_t* host_out_set_offsets, uint64_t* n_out,
+                      void* stream);
 int kc_batch_run(kc_batch* plan, const uint8_t* reads, const uint64_t* offsets,
                  uint64_t* out_keys, uint32_t* out_counts, uint64_t out_capacity,
                  uint64_t* host_out_set_offsets, uint64_t* n_out, void* stream);
@@ -174,7 +209,12 @@ void kc_batch_free(kc_batch* plan);
  *   miss is counted in kc_server_stats). Returns KC_E_NOMEM at once if the
  *   job alone needs more than the budget; *job_id receives the job's id.
  * kc_server_poll / kc_server_wait: the job's state (KC_JOB_*); wait blocks
- *   until it is DONE or FAILED.
+ *   until it is DONE or FAILED. Results the client has not released stay
+ *   charged to the budget: if they leave too little for every queued job
+ *   while nothing runs and every worker has given its scratch back, no queued
+ *   job can ever start, and kc_server_wait on a queued job returns
+ *   KC_E_NOMEM at once (the job stays queued; release results and wait
+ *   again) instead of blocking.
  * kc_server_result: device pointers to the sorted keys (1, 2 or 4 words each, as
  *   in kc_count) and counts, and their number. A FAILED job returns its status
  *   (message in kc_last_error).

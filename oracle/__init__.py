@@ -4,16 +4,20 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The product library never imports,
 links or calls it.
 
-Two independent implementations of the k-mer histogram (Section II) are here:
+What is here, each written from the definition of the k-mer histogram
+(Section II; Algorithm 1 counts it serially by sorting):
 
-* ``liboracle.so`` (``kc_oracle.cpp``): the serial sort-based counter of
-  Algorithm 1 ("Serial Algorithm": GetFirstKmer, rolling update, Sort,
-  Accumulate) extended with the 2k-bit mask, the rolling reverse complement
-  and the canonical form min(kmer, rc); plus an unordered_map cross-check and a
-  selected-keys counter for inputs too large to count in full.
+* ``liboracle.so`` (``kc_oracle.cpp``): every valid window's forward and
+  reverse-complement values decoded from its own bytes, the smaller kept,
+  keys sorted and tallied; a std::map tally as a cross-check; a tally of
+  chosen keys and a tally restricted to a range of top key bits, for inputs
+  too large to tally at once.
+* ``post.py``: the uses of a result (spectrum, minimum-count filter, merge of
+  two results) as plain numpy / dict code.
 * ``brute.py``: pure-Python string brute force for tiny inputs.
+* ``fastx.py``: FASTQ / FASTA parsing by the formats' definitions.
 
-Neither shares code with the GPU path. Parity pins: see tests/test_oracle_*.py.
+None shares code with the GPU path. Parity pins: tests/test_oracle_*.py.
 """
 from __future__ import annotations
 
@@ -53,6 +57,8 @@ def lib():
             L.oracle_count_sort.argtypes = [p, p, u64, i32, i32, p, p, u64, p]
             L.oracle_count_map.restype = i32
             L.oracle_count_map.argtypes = [p, p, u64, i32, p, p, u64, p]
+            L.oracle_count_range.restype = i32
+            L.oracle_count_range.argtypes = [p, p, u64, i32, i32, i32, u64, u64, p, p, u64, p]
             L.oracle_count_selected.restype = i32
             L.oracle_count_selected.argtypes = [p, p, u64, i32, i32, p, u64, p]
             _lib = L
@@ -113,6 +119,29 @@ def count(reads, offsets, k: int, threads: int | None = None, method: str = "sor
         raise ValueError(method)
     if rc != 0:
         raise RuntimeError("oracle error %d" % rc)
+    d = int(n_out[0])
+    keys = keys[:d * words].copy()
+    return (keys.reshape(d, words) if words > 1 else keys), cnt[:d].copy()
+
+
+def count_range(reads, offsets, k: int, bits: int, lo: int, hi: int,
+                threads: int | None = None, capacity: int | None = None):
+    """The histogram restricted to keys whose top `bits` bits (of the 2k-bit
+    key) lie in [lo, hi); same layout as count(). capacity bounds the pairs
+    of the slice (default: every window)."""
+    reads, offsets = _prep(reads, offsets)
+    n = offsets.size - 1
+    words = key_words(k)
+    cap = max(1, capacity if capacity is not None else max_windows(offsets, k))
+    keys = np.empty(cap * words, dtype=np.uint64)
+    cnt = np.empty(cap, dtype=np.uint32)
+    n_out = np.zeros(1, dtype=np.uint64)
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    rc = lib().oracle_count_range(_p(reads), _p(offsets), n, k, threads, bits, lo, hi, _p(keys),
+                                  _p(cnt), cap, _p(n_out))
+    if rc != 0:
+        raise RuntimeError("oracle error %d (n_out %d)" % (rc, int(n_out[0])))
     d = int(n_out[0])
     keys = keys[:d * words].copy()
     return (keys.reshape(d, words) if words > 1 else keys), cnt[:d].copy()

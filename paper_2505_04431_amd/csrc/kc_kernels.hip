@@ -549,7 +549,8 @@ __device__ __forceinline__ uint32_t window_keys(const uint64_t* __restrict__ pac
     while (set + 1 < bs.n_sets && g + i >= bs.set_byte_off[set + 1]) ++set;
     const uint32_t loc = bs.set_local[set];
     if (loc == kNoSet) vm &= ~(1u << i);
-    else key[i] = ((K)loc << (2 * k)) | (K)c[i];
+    // (a class of one k = 32 set has no set-id bits: no shift by the key width)
+    else key[i] = (2 * k < (int)(8 * sizeof(K)) ? ((K)loc << (2 * k)) : (K)0) | (K)c[i];
   }
   return vm;
   }
@@ -1654,7 +1655,8 @@ __global__ void __launch_bounds__(256) k_concat_batch(
   const unsigned long long n_leaves = st->n_leaves;
   const unsigned lane = threadIdx.x & 63;
   const unsigned long long nw = (unsigned long long)gridDim.x * 4;
-  const K kmask = ((K)1 << (2 * k)) - 1;
+  const bool has_set_bits = 2 * k < (int)(8 * sizeof(K));
+  const K kmask = has_set_bits ? ((K)1 << (2 * k)) - 1 : ~(K)0;
   for (unsigned long long l = (unsigned long long)blockIdx.x * 4 + (threadIdx.x >> 6); l < n_leaves;
        l += nw) {
     const uint32_t n = d[l];
@@ -1667,7 +1669,7 @@ __global__ void __launch_bounds__(256) k_concat_batch(
       if (o >= cap) break;
       const K key = src[lf.begin + i];
       out_keys[o] = (uint64_t)(key & kmask);
-      out_set[o] = (uint32_t)(key >> (2 * k));
+      out_set[o] = has_set_bits ? (uint32_t)(key >> (2 * k)) : 0u;
       out_counts[o] = tmp_cnt[lf.begin + i];
     }
   }

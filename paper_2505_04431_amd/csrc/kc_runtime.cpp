@@ -1028,47 +1028,63 @@ void free_buf(DevBuf& b) { drop(b); }
 
 }  // namespace
 
-// A planned batch of read sets (opaque in the C ABI).
+// A planned batch of read sets (opaque in the C ABI): the sets are cut into
+// memory waves of consecutive sets, each counted by one recorded graph.
 struct kc_batch {
   int device = 0;
   uint32_t n_sets = 0;
   int P = 1;
   kc_options o{};
+  uint64_t hbm_budget = 0;
   uint64_t n_reads = 0, N = 0;
-  std::vector<unsigned long long> set_first_read, set_byte_off;  // n_sets + 1 each
+  std::vector<unsigned long long> set_first_read, set_byte_off;  // whole batch, n_sets + 1 each
   std::vector<int> ks;
   struct Class {
     int k = 0, set_bits = 0;
-    std::vector<uint32_t> sets;
+    std::vector<uint32_t> sets;  // wave-local set indices
     Pipe pipe;
     uint64_t out_base = 0, out_cap = 0, start_base = 0;
     DevBuf order, set_local;
     kc::BatchSets bs{};
   };
-  std::vector<Class> cls;
-  Ctx ctx;
-  DevBuf set_first_read_dev, set_byte_off_dev, set_class_dev, set_local_dev, starts,
-      start_base_dev, class_base_dev, cls_keys, cls_counts, cls_set, set_off, states, flag;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  struct Wave {
+    uint32_t s0 = 0, ns = 0;      // sets [s0, s0 + ns)
+    uint64_t r0 = 0, nr = 0;      // their reads
+    uint64_t b0 = 0, nbytes = 0;  // their bytes
+    uint64_t need = 0;            // device bytes planned for the wave
+    std::vector<unsigned long long> first_read, byte_off;  // wave-relative, ns + 1 each
+    std::vector<Class> cls;
+    uint64_t out_total = 0, starts_total = 0;
+    DevBuf first_read_dev, byte_off_dev, set_class_dev, set_local_dev, starts, start_base_dev,
+        class_base_dev, states;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* key[5] = {};
+    uint64_t key_cap = 0, key_off0 = 0;
+    kc_stats stats{};
+  };
+  std::vector<Wave> waves;
+  Ctx ctx;  // pipeline buffers, shared by the waves (sized for the largest)
+  DevBuf cls_keys, cls_counts, cls_set, set_off, flag;
   hipStream_t cap_stream = nullptr;
-  const void* key[5] = {};
-  uint64_t key_cap = 0, key_off0 = 0;
   kc_stats stats{};
 
   ~kc_batch() {
     int prev = -1;
     if (hipGetDevice(&prev) == hipSuccess) (void)hipSetDevice(device);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    for (Class& c : cls) {
-      free_buf(c.order);
-      free_buf(c.set_local);
+    for (Wave& w : waves) {
+      if (w.exec) (void)hipGraphExecDestroy(w.exec);
+      if (w.graph) (void)hipGraphDestroy(w.graph);
+      for (Class& c : w.cls) {
+        free_buf(c.order);
+        free_buf(c.set_local);
+      }
+      DevBuf* wb[] = {&w.first_read_dev, &w.byte_off_dev, &w.set_class_dev, &w.set_local_dev,
+                      &w.starts,        &w.start_base_dev, &w.class_base_dev, &w.states};
+      for (DevBuf* b : wb) free_buf(*b);
     }
-    DevBuf* all[] = {&set_first_read_dev, &set_byte_off_dev, &set_class_dev, &set_local_dev,
-                     &starts, &start_base_dev, &class_base_dev, &cls_keys, &cls_counts, &cls_set,
-                     &set_off, &states, &flag};
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    DevBuf* all[] = {&cls_keys, &cls_counts, &cls_set, &set_off, &flag};
     for (DevBuf* b : all) free_buf(*b);
     if (prev >= 0) (void)hipSetDevice(prev);
   }
@@ -1076,9 +1092,79 @@ struct kc_batch {
 
 namespace {
 
+// Device bytes of one batch pipeline over `bytes` bytes of sets of one k with
+// up to `n_sets` sets in a class (keys widen to two words when the set id
+// bits and 2k pass 64 bits).
+uint64_t class_pipe_bytes(uint64_t bytes, int k, uint64_t n_sets, const kc_options& o) {
+  if (bytes == 0) return 0;
+  Pipe p;
+  p.k = k;
+  p.keybits = 2 * k + ceil_log2(std::max<uint64_t>(n_sets, 1));
+  p.words = p.keybits > 64 ? 2 : 1;
+  uint64_t C;
+  table_params(o, p.words, p.slots_log2, C, p.T, p.H);
+  p.sb = kc::max_shard_bits();
+  p.rec_bound = bytes;
+  pipe_bounds(p);
+  uint64_t t = 0;
+  pipeline_needs(p, [&](DevBuf Ctx::*, size_t b, const char*) { t += alloc_size(b); });
+  return t;
+}
+
+// Device bytes a wave holds: packed input, class outputs (key, count, set id
+// per byte of input at most), the largest class pipeline, per-set tables.
+uint64_t wave_bytes(uint64_t bytes, const std::map<int, std::pair<uint64_t, uint64_t>>& by_k,
+                    uint64_t n_sets, const kc_options& o) {
+  uint64_t pipe = 0;
+  for (const auto& kv : by_k)
+    pipe = std::max(pipe, class_pipe_bytes(kv.second.first, kv.first, kv.second.second, o));
+  return packed_chunks(bytes) * 32 + alloc_size(bytes * 16) + pipe + n_sets * 96 + (1 << 20);
+}
+
+// Classes of a wave: sets of one k counted together with keys (set id << 2k)
+// | k-mer. Every set of a class gets the same share of the first-level shards,
+// so a class holds at most as many sets as its largest set can afford: the
+// sets of each k are taken largest first, and a class is closed once
+// 2^set_bits sets are in it, set_bits being the most that still leaves the
+// largest set enough shards for leaves of the target size (at half of full
+// use).
+void form_classes(kc_batch* b, kc_batch::Wave& w, const uint64_t* set_bytes) {
+  std::vector<int> kv;
+  for (uint32_t s = 0; s < w.ns; ++s) kv.push_back(b->ks[w.s0 + s]);
+  std::sort(kv.begin(), kv.end());
+  kv.erase(std::unique(kv.begin(), kv.end()), kv.end());
+  for (int k : kv) {
+    std::vector<uint32_t> sk;
+    for (uint32_t s = 0; s < w.ns; ++s)
+      if (b->ks[w.s0 + s] == k) sk.push_back(s);
+    std::stable_sort(sk.begin(), sk.end(), [&](uint32_t x, uint32_t y) {
+      return set_bytes[w.s0 + x] > set_bytes[w.s0 + y];
+    });
+    int slots_log2;
+    uint64_t Cs, Tw, Hw;
+    table_params(b->o, 2, slots_log2, Cs, Tw, Hw);  // the smaller (two-word) leaf target
+    const uint64_t per_shard = (Tw << kc::kSplitMaxBits) / 2;
+    size_t i = 0;
+    while (i < sk.size()) {
+      const uint64_t wb = std::max<uint64_t>(set_bytes[w.s0 + sk[i]], 1);
+      int need = 0;  // shard bits the largest set needs
+      while (need < kc::kMaxShardBits && ((uint64_t)per_shard << need) < wb) ++need;
+      int sbits = std::max(0, kc::kMaxShardBits - need);
+      sbits = std::min(sbits, 128 - 2 * k);
+      const size_t take = std::min(sk.size() - i, (size_t)1 << sbits);
+      kc_batch::Class C;
+      C.k = k;
+      C.sets.assign(sk.begin() + i, sk.begin() + i + take);
+      std::sort(C.sets.begin(), C.sets.end());  // set order inside a class
+      w.cls.push_back(std::move(C));
+      i += take;
+    }
+  }
+}
+
 int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_bytes,
-                    const int* host_ks, uint32_t n_sets, int P, const kc_options* opt,
-                    kc_batch** out) {
+                    const int* host_ks, uint32_t n_sets, int P, uint64_t hbm_budget,
+                    const kc_options* opt, kc_batch** out) {
   if (!out) fail(KC_E_INVAL, "plan pointer is NULL");
   *out = nullptr;
   if (!host_set_reads || !host_set_bytes || !host_ks || n_sets == 0)
@@ -1088,6 +1174,7 @@ int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_byt
   hipchk(hipGetDevice(&b->device), "hipGetDevice");
   b->n_sets = n_sets;
   b->P = P;
+  b->hbm_budget = hbm_budget;
   std::memset(&b->o, 0, sizeof(b->o));
   if (opt) b->o = *opt;
   if (b->o.mode != 0) fail(KC_E_INVAL, "mode must be 0 for a batch");
@@ -1101,161 +1188,318 @@ int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_byt
   }
   b->n_reads = b->set_first_read[n_sets];
   b->N = b->set_byte_off[n_sets];
-  // Classes: sets of one k counted together with keys (set id << 2k) | k-mer.
-  // Every set of a class gets the same share of the first-level shards, so a
-  // class holds at most as many sets as its largest set can afford: the sets
-  // of each k are taken largest first, and a class is closed once 2^set_bits
-  // sets are in it, set_bits being the most that still leaves the largest set
-  // enough shards for leaves of the target size (at half of full use).
-  std::vector<std::vector<uint32_t>> groups;
-  std::vector<int> group_k;
+
+  // Memory waves: consecutive sets, as many as keep the wave's device bytes
+  // within the budget (0 = no budget: one wave).
   {
-    std::vector<int> kv(b->ks);
-    std::sort(kv.begin(), kv.end());
-    kv.erase(std::unique(kv.begin(), kv.end()), kv.end());
-    for (int k : kv) {
-      std::vector<uint32_t> sk;
-      for (uint32_t s = 0; s < n_sets; ++s)
-        if (b->ks[s] == k) sk.push_back(s);
-      std::stable_sort(sk.begin(), sk.end(), [&](uint32_t x, uint32_t y) {
-        return host_set_bytes[x] > host_set_bytes[y];
-      });
-      int slots_log2;
-      uint64_t Cs, Tw, Hw;
-      table_params(b->o, 2, slots_log2, Cs, Tw, Hw);  // the smaller (two-word) leaf target
-      const uint64_t per_shard = (Tw << kc::kSplitMaxBits) / 2;
-      size_t i = 0;
-      while (i < sk.size()) {
-        const uint64_t w = std::max<uint64_t>(host_set_bytes[sk[i]], 1);
-        int need = 0;  // shard bits the largest set needs
-        while (need < kc::kMaxShardBits && ((uint64_t)per_shard << need) < w) ++need;
-        int sbits = std::max(0, kc::kMaxShardBits - need);
-        sbits = std::min(sbits, 128 - 2 * k);
-        const size_t take = std::min(sk.size() - i, (size_t)1 << sbits);
-        std::vector<uint32_t> g(sk.begin() + i, sk.begin() + i + take);
-        std::sort(g.begin(), g.end());  // set order inside a class
-        groups.push_back(g);
-        group_k.push_back(k);
-        i += take;
+    uint32_t s0 = 0;
+    uint64_t bytes = 0;
+    std::map<int, std::pair<uint64_t, uint64_t>> by_k;  // k -> (bytes, sets)
+    uint64_t need = 0;
+    auto close = [&](uint32_t s1) {
+      kc_batch::Wave w;
+      w.s0 = s0;
+      w.ns = s1 - s0;
+      w.need = need;
+      b->waves.push_back(std::move(w));
+      s0 = s1;
+      bytes = 0;
+      by_k.clear();
+      need = 0;
+    };
+    for (uint32_t s = 0; s < n_sets; ++s) {
+      auto trial = by_k;
+      trial[b->ks[s]].first += host_set_bytes[s];
+      trial[b->ks[s]].second += 1;
+      const uint64_t nt = wave_bytes(bytes + host_set_bytes[s], trial, s - s0 + 1, b->o);
+      if (hbm_budget && nt > hbm_budget && s > s0) {
+        close(s);
+        trial.clear();
+        trial[b->ks[s]] = {host_set_bytes[s], 1};
       }
+      by_k = std::move(trial);
+      bytes += host_set_bytes[s];
+      need = wave_bytes(bytes, by_k, s - s0 + 1, b->o);
+      if (hbm_budget && need > hbm_budget)
+        fail(KC_E_NOMEM, "set " + std::to_string(s) + " alone needs " + std::to_string(need) +
+                             " device bytes, more than the batch budget of " +
+                             std::to_string(hbm_budget));
     }
+    close(n_sets);
   }
-  std::vector<uint32_t> set_class(n_sets), set_local(n_sets);
-  uint64_t out_base = 0, start_base = 0;
+
   Ctx& c = b->ctx;
   c.device = b->device;
-  const uint64_t nchunks = (b->N + 63) / 64 + 2;
+  hipStream_t st = nullptr;
+  uint64_t max_bytes = 0, max_out = 0, max_ns = 0;
+  for (kc_batch::Wave& w : b->waves) {
+    w.r0 = b->set_first_read[w.s0];
+    w.nr = b->set_first_read[w.s0 + w.ns] - w.r0;
+    w.b0 = b->set_byte_off[w.s0];
+    w.nbytes = b->set_byte_off[w.s0 + w.ns] - w.b0;
+    w.first_read.assign(w.ns + 1, 0);
+    w.byte_off.assign(w.ns + 1, 0);
+    for (uint32_t s = 0; s <= w.ns; ++s) {
+      w.first_read[s] = b->set_first_read[w.s0 + s] - w.r0;
+      w.byte_off[s] = b->set_byte_off[w.s0 + s] - w.b0;
+    }
+    form_classes(b.get(), w, host_set_bytes);
+    std::vector<uint32_t> set_class(w.ns), set_local(w.ns);
+    uint64_t out_base = 0, start_base = 0;
+    std::vector<unsigned long long> sbase(w.cls.size()), cbase(w.cls.size());
+    kc_stats dummy;
+    std::memset(&dummy, 0, sizeof(dummy));
+    for (size_t ci = 0; ci < w.cls.size(); ++ci) {
+      kc_batch::Class& C = w.cls[ci];
+      uint64_t bytes = 0, lo = ~0ull, hi = 0;
+      for (size_t j = 0; j < C.sets.size(); ++j) {
+        const uint32_t s = C.sets[j];
+        set_class[s] = (uint32_t)ci;
+        set_local[s] = (uint32_t)j;
+        bytes += host_set_bytes[w.s0 + s];
+        lo = std::min<uint64_t>(lo, w.byte_off[s]);
+        hi = std::max<uint64_t>(hi, w.byte_off[s + 1]);
+      }
+      C.set_bits = ceil_log2(C.sets.size());
+      Pipe& p = C.pipe;
+      p.k = C.k;
+      p.keybits = 2 * C.k + C.set_bits;
+      p.words = p.keybits > 64 ? 2 : 1;
+      uint64_t Cslots;
+      table_params(b->o, p.words, p.slots_log2, Cslots, p.T, p.H);
+      p.rec_bound = std::max<uint64_t>(bytes, 1);
+      p.sb = b->o.shard_bits > 0 ? std::min(b->o.shard_bits, kc::max_shard_bits())
+                                 : std::max(shard_bits_for(b->o, P, p.rec_bound, p.T, p.keybits),
+                                            std::min(kc::max_shard_bits(), C.set_bits + 3));
+      p.sb = std::max(1, std::min(p.sb, p.keybits));
+      p.byte_begin = lo & ~31ull;
+      p.byte_end = hi;
+      pipe_bounds(p);
+      pipeline_prepare(c, p);
+      C.out_base = out_base;
+      C.out_cap = p.rec_bound;
+      out_base += C.out_cap;
+      C.start_base = start_base;
+      start_base += C.sets.size() + 1;
+      sbase[ci] = C.start_base;
+      cbase[ci] = C.out_base;
+      // owner order of the class's shards and its set ids
+      std::vector<uint32_t> loc(w.ns, kc::kNoSet);
+      for (size_t j = 0; j < C.sets.size(); ++j) loc[C.sets[j]] = (uint32_t)j;
+      ensure(C.set_local, w.ns * 4, "batch tables");
+      upload_sync(C.set_local.p, loc.data(), w.ns * 4, st);
+      Call q{};
+      q.P = P;
+      q.sb = p.sb;
+      q.nb = 1 << p.sb;
+      const std::vector<int>& order = owner_order(c, q, dummy, nullptr);
+      ensure(C.order, (size_t)q.nb * 4, "owner order");
+      upload_sync(C.order.p, order.data(), (size_t)q.nb * 4, st);
+      p.order = (const int*)C.order.p;
+    }
+    w.out_total = out_base;
+    w.starts_total = start_base;
+    ensure(w.first_read_dev, (w.ns + 1) * 8, "batch tables");
+    ensure(w.byte_off_dev, (w.ns + 1) * 8, "batch tables");
+    ensure(w.set_class_dev, w.ns * 4, "batch tables");
+    ensure(w.set_local_dev, w.ns * 4, "batch tables");
+    ensure(w.starts, start_base * 8, "set bounds");
+    ensure(w.start_base_dev, w.cls.size() * 8, "batch tables");
+    ensure(w.class_base_dev, w.cls.size() * 8, "batch tables");
+    ensure(w.states, w.cls.size() * sizeof(kc::DevState), "device states");
+    upload_sync(w.first_read_dev.p, w.first_read.data(), (w.ns + 1) * 8, st);
+    upload_sync(w.byte_off_dev.p, w.byte_off.data(), (w.ns + 1) * 8, st);
+    upload_sync(w.set_class_dev.p, set_class.data(), w.ns * 4, st);
+    upload_sync(w.set_local_dev.p, set_local.data(), w.ns * 4, st);
+    upload_sync(w.start_base_dev.p, sbase.data(), w.cls.size() * 8, st);
+    upload_sync(w.class_base_dev.p, cbase.data(), w.cls.size() * 8, st);
+    for (kc_batch::Class& C : w.cls) {
+      C.bs = kc::BatchSets{(const unsigned long long*)w.byte_off_dev.p,
+                           (const uint32_t*)C.set_local.p, w.ns};
+      C.pipe.batch = &C.bs;
+    }
+    max_bytes = std::max(max_bytes, w.nbytes);
+    max_out = std::max(max_out, w.out_total);
+    max_ns = std::max<uint64_t>(max_ns, w.ns);
+  }
+  const uint64_t nchunks = packed_chunks(max_bytes);
   ensure(c.packed, nchunks * 16, "packed bases");
   ensure(c.inv, nchunks * 8, "invalid mask");
   ensure(c.endm, nchunks * 8, "end mask");
-  std::vector<int> kv(groups.size());
-  b->cls.resize(groups.size());
-  for (size_t ci = 0; ci < groups.size(); ++ci) {
-    kc_batch::Class& C = b->cls[ci];
-    C.k = group_k[ci];
-    kv[ci] = C.k;
-    uint64_t bytes = 0, lo = ~0ull, hi = 0;
-    for (uint32_t s : groups[ci]) {
-      set_class[s] = (uint32_t)ci;
-      set_local[s] = (uint32_t)C.sets.size();
-      C.sets.push_back(s);
-      bytes += host_set_bytes[s];
-      lo = std::min<uint64_t>(lo, b->set_byte_off[s]);
-      hi = std::max<uint64_t>(hi, b->set_byte_off[s + 1]);
-    }
-    C.set_bits = ceil_log2(C.sets.size());
-    Pipe& p = C.pipe;
-    p.k = C.k;
-    p.keybits = 2 * C.k + C.set_bits;
-    p.words = p.keybits > 64 ? 2 : 1;
-    uint64_t Cslots;
-    table_params(b->o, p.words, p.slots_log2, Cslots, p.T, p.H);
-    p.rec_bound = std::max<uint64_t>(bytes, 1);
-    p.sb = b->o.shard_bits > 0 ? std::min(b->o.shard_bits, kc::max_shard_bits())
-                               : std::max(shard_bits_for(b->o, P, p.rec_bound, p.T, p.keybits),
-                                          std::min(kc::max_shard_bits(), C.set_bits + 3));
-    p.sb = std::max(1, std::min(p.sb, p.keybits));
-    p.byte_begin = lo & ~31ull;
-    p.byte_end = hi;
-    pipe_bounds(p);
-    pipeline_prepare(c, p);
-    C.out_base = out_base;
-    C.out_cap = p.rec_bound;
-    out_base += C.out_cap;
-    C.start_base = start_base;
-    start_base += C.sets.size() + 1;
-  }
-  // device tables
-  ensure(b->set_first_read_dev, (n_sets + 1) * 8, "batch tables");
-  ensure(b->set_byte_off_dev, (n_sets + 1) * 8, "batch tables");
-  ensure(b->set_class_dev, n_sets * 4, "batch tables");
-  ensure(b->set_local_dev, n_sets * 4, "batch tables");
-  ensure(b->starts, start_base * 8, "set bounds");
-  ensure(b->start_base_dev, kv.size() * 8, "batch tables");
-  ensure(b->class_base_dev, kv.size() * 8, "batch tables");
-  ensure(b->cls_keys, out_base * 8, "class outputs");
-  ensure(b->cls_counts, out_base * 4, "class outputs");
-  ensure(b->cls_set, out_base * 4, "class outputs");
-  ensure(b->set_off, (n_sets + 1) * 8, "set offsets");
-  ensure(b->states, kv.size() * sizeof(kc::DevState), "device states");
+  ensure(c.state, sizeof(kc::DevState), "device state");
+  ensure(b->cls_keys, max_out * 8, "class outputs");
+  ensure(b->cls_counts, max_out * 4, "class outputs");
+  ensure(b->cls_set, max_out * 4, "class outputs");
+  ensure(b->set_off, (max_ns + 1) * 8, "set offsets");
   ensure(b->flag, 64, "flags");
-  hipStream_t st = nullptr;
-  upload_sync(b->set_first_read_dev.p, b->set_first_read.data(), (n_sets + 1) * 8, st);
-  upload_sync(b->set_byte_off_dev.p, b->set_byte_off.data(), (n_sets + 1) * 8, st);
-  upload_sync(b->set_class_dev.p, set_class.data(), n_sets * 4, st);
-  upload_sync(b->set_local_dev.p, set_local.data(), n_sets * 4, st);
-  std::vector<unsigned long long> sbase(kv.size()), cbase(kv.size());
-  kc_stats dummy;
-  std::memset(&dummy, 0, sizeof(dummy));
-  for (size_t ci = 0; ci < kv.size(); ++ci) {
-    kc_batch::Class& C = b->cls[ci];
-    sbase[ci] = C.start_base;
-    cbase[ci] = C.out_base;
-    std::vector<uint32_t> loc(n_sets, kc::kNoSet);
-    for (size_t j = 0; j < C.sets.size(); ++j) loc[C.sets[j]] = (uint32_t)j;
-    ensure(C.set_local, n_sets * 4, "batch tables");
-    upload_sync(C.set_local.p, loc.data(), n_sets * 4, st);
-    Call q{};
-    q.P = P;
-    q.sb = C.pipe.sb;
-    q.nb = 1 << C.pipe.sb;
-    const std::vector<int>& order = owner_order(c, q, dummy, nullptr);
-    ensure(C.order, (size_t)q.nb * 4, "owner order");
-    upload_sync(C.order.p, order.data(), (size_t)q.nb * 4, st);
-    C.pipe.order = (const int*)C.order.p;
-    C.bs = kc::BatchSets{(const unsigned long long*)b->set_byte_off_dev.p,
-                         (const uint32_t*)C.set_local.p, n_sets};
-    C.pipe.batch = &C.bs;
-  }
-  upload_sync(b->start_base_dev.p, sbase.data(), kv.size() * 8, st);
-  upload_sync(b->class_base_dev.p, cbase.data(), kv.size() * 8, st);
   *out = b.release();
   return KC_OK;
 }
 
-// Per-set plain counts of a whole batch (used when a class overflowed).
-void batch_by_sets(kc_batch* b, const uint8_t* reads, const uint64_t* offsets, uint64_t* out_keys,
-                   uint32_t* out_counts, uint64_t cap, uint64_t* set_off, uint64_t* n_out,
-                   hipStream_t st) {
+// Per-set plain counts of the sets of a wave (used when a class overflowed);
+// set_off receives w.ns + 1 wave-relative offsets.
+void wave_by_sets(kc_batch* b, const kc_batch::Wave& w, const uint8_t* reads,
+                  const uint64_t* offsets, uint64_t* out_keys, uint32_t* out_counts, uint64_t cap,
+                  uint64_t* set_off, uint64_t* n_out, hipStream_t st) {
   uint64_t o = 0;
-  for (uint32_t s = 0; s < b->n_sets; ++s) {
+  bool short_cap = false;
+  for (uint32_t s = 0; s < w.ns; ++s) {
     set_off[s] = o;
     uint64_t n = 0;
-    const uint64_t r0 = b->set_first_read[s], r1 = b->set_first_read[s + 1];
-    const int rc = count_impl(reads, offsets + r0, r1 - r0, b->ks[s], b->P, out_keys + o,
-                              out_counts + o, o <= cap ? cap - o : 0, &n, &b->o, st);
+    const uint64_t r0 = w.first_read[s], r1 = w.first_read[s + 1];
+    const int rc = count_impl(reads, offsets + r0, r1 - r0, b->ks[w.s0 + s], b->P,
+                              short_cap ? nullptr : out_keys + o,
+                              short_cap ? nullptr : out_counts + o,
+                              short_cap || o > cap ? 0 : cap - o, &n, &b->o, st);
     if (rc == KC_E_CAPACITY) {
       // keep counting the sizes so that the caller learns the total needed
       o += n;
-      cap = 0;
+      short_cap = true;
       continue;
     }
     if (rc != KC_OK) throw Fail{rc};
     o += n;
   }
-  set_off[b->n_sets] = o;
+  set_off[w.ns] = o;
   *n_out = o;
-  if (cap == 0 && o > 0) fail(KC_E_CAPACITY, "output capacity too small for the batch");
+}
+
+// Runs wave wi on its own reads (offsets: its w.nr + 1 read offsets), writes
+// its pairs to out (cap entries) and w.ns + 1 wave-relative set offsets.
+// Returns the number of pairs; pairs past cap are not written.
+uint64_t run_wave(kc_batch* b, uint32_t wi, const uint8_t* reads, const uint64_t* offsets,
+                  uint64_t* out_keys, uint32_t* out_counts, uint64_t cap, uint64_t* host_set_off,
+                  hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  kc_batch::Wave& w = b->waves[wi];
+  Ctx& c = b->ctx;
+  // inputs must have the layout the plan describes
+  hipchk(kc::launch_fill_u64((unsigned long long*)b->flag.p, 8, 0, st), "fill launch");
+  if (w.nr) {
+    hipLaunchKernelGGL(k_offsets_ok, dim3((unsigned)((w.nr + 255) / 256)), dim3(256), 0, st,
+                       offsets, w.nr, (unsigned int*)b->flag.p);
+    hipchk(hipGetLastError(), "offsets check launch");
+  }
+  hipLaunchKernelGGL(k_batch_layout_ok, dim3((w.ns + 256) / 256), dim3(256), 0, st, offsets,
+                     (const unsigned long long*)w.first_read_dev.p,
+                     (const unsigned long long*)w.byte_off_dev.p, w.ns, (unsigned int*)b->flag.p);
+  hipchk(hipGetLastError(), "layout check launch");
+  uint64_t* h = (uint64_t*)host_stage(c, 64);
+  hipchk(hipMemcpyAsync(h, offsets, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  hipchk(hipMemcpyAsync(h + 1, b->flag.p, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+  const uint64_t off0 = h[0];
+  if (h[1] != 0) fail(KC_E_INVAL, "reads and offsets do not match the batch plan");
+  const void* key[5] = {reads, offsets, out_keys, out_counts, nullptr};
+  const bool same = std::equal(key, key + 5, w.key) && w.key_cap == cap && w.key_off0 == off0;
+  if (!w.exec || !same) {
+    if (w.exec) (void)hipGraphExecDestroy(w.exec);
+    if (w.graph) (void)hipGraphDestroy(w.graph);
+    w.exec = nullptr;
+    w.graph = nullptr;
+    if (!b->cap_stream)
+      hipchk(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    hipStream_t cs = b->cap_stream;
+    hipchk(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+      Timer off(c, cs, false);
+      const size_t nst = w.cls.size();
+      hipchk(kc::launch_fill_u64((unsigned long long*)w.states.p, nst * sizeof(kc::DevState) / 8,
+                                 0, cs),
+             "fill launch");
+      const uint64_t nchunks = packed_chunks(w.nbytes);
+      hipchk(kc::launch_pack(reads + off0, w.nbytes, offsets, w.nr, off0, (uint64_t*)c.packed.p,
+                             (uint64_t*)c.inv.p, (uint64_t*)c.endm.p, nchunks, cs),
+             "pack launch");
+      for (size_t ci = 0; ci < nst; ++ci) {
+        kc_batch::Class& C = w.cls[ci];
+        kc::DevState* ds = (kc::DevState*)w.states.p + ci;
+        PipeOut po{(uint64_t*)b->cls_keys.p + C.out_base, (uint32_t*)b->cls_counts.p + C.out_base,
+                   (uint32_t*)b->cls_set.p + C.out_base, C.out_cap};
+        enqueue_pipeline(c, C.pipe, ds, off, po, cs);
+        hipchk(kc::launch_set_bounds(po.set, ds, C.out_cap, (uint32_t)C.sets.size(),
+                                     (unsigned long long*)w.starts.p + C.start_base, cs),
+               "set bounds launch");
+      }
+      hipchk(kc::launch_batch_offsets((const uint32_t*)w.set_class_dev.p,
+                                      (const uint32_t*)w.set_local_dev.p,
+                                      (const unsigned long long*)w.starts.p,
+                                      (const unsigned long long*)w.start_base_dev.p, w.ns,
+                                      (unsigned long long*)b->set_off.p, cs),
+             "batch offsets launch");
+      hipchk(kc::launch_batch_gather(
+                 (const uint32_t*)w.set_class_dev.p, (const uint32_t*)w.set_local_dev.p,
+                 (const unsigned long long*)w.starts.p,
+                 (const unsigned long long*)w.start_base_dev.p,
+                 (const unsigned long long*)w.class_base_dev.p, (const uint64_t*)b->cls_keys.p,
+                 (const uint32_t*)b->cls_counts.p, (const unsigned long long*)b->set_off.p, w.ns,
+                 cap, out_keys, out_counts, cs),
+             "batch gather launch");
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    hipchk(hipStreamEndCapture(cs, &w.graph), "hipStreamEndCapture");
+    hipchk(hipGraphInstantiate(&w.exec, w.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    std::copy(key, key + 5, w.key);
+    w.key_cap = cap;
+    w.key_off0 = off0;
+  }
+  hipchk(hipGraphLaunch(w.exec, st), "hipGraphLaunch");
+  const size_t nst = w.cls.size();
+  const size_t bytes = nst * sizeof(kc::DevState) + (w.ns + 1) * 8;
+  char* hs = (char*)host_stage(c, bytes);
+  hipchk(hipMemcpyAsync(hs, w.states.p, nst * sizeof(kc::DevState), hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync");
+  hipchk(hipMemcpyAsync(hs + nst * sizeof(kc::DevState), b->set_off.p, (w.ns + 1) * 8,
+                        hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync");
+  hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+  std::memset(&w.stats, 0, sizeof(w.stats));
+  bool overflow = false;
+  for (size_t ci = 0; ci < nst; ++ci) {
+    kc::DevState ds;
+    std::memcpy(&ds, hs + ci * sizeof(kc::DevState), sizeof(ds));
+    if (ds.count_overflow) fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
+    overflow |= ds.overflow != 0;
+    w.stats.valid_windows += ds.W;
+    w.stats.distinct += ds.D;
+    w.stats.n_leaves += ds.n_leaves;
+    w.stats.large_records += ds.large_records;
+    w.stats.large_distinct += ds.large_distinct;
+  }
+  w.stats.n_bases = w.nbytes;
+  std::memcpy(host_set_off, hs + nst * sizeof(kc::DevState), (w.ns + 1) * 8);
+  uint64_t D = host_set_off[w.ns];
+  if (overflow) {
+    // a class had a leaf too large for the device-planned split: count the
+    // wave's sets one by one
+    ++w.stats.n_overflow;
+    wave_by_sets(b, w, reads, offsets, out_keys, out_counts, cap, host_set_off, &D, st);
+    w.stats.distinct = D;
+  }
+  w.stats.ms_total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return D;
+}
+
+int batch_run_wave_impl(kc_batch* b, uint32_t wi, const uint8_t* reads, const uint64_t* offsets,
+                        uint64_t* out_keys, uint32_t* out_counts, uint64_t cap,
+                        uint64_t* host_set_off, uint64_t* n_out, hipStream_t st) {
+  if (!b || !n_out || !host_set_off) fail(KC_E_INVAL, "NULL argument");
+  *n_out = 0;
+  if (wi >= b->waves.size()) fail(KC_E_INVAL, "wave index out of range");
+  if (!reads || !offsets) fail(KC_E_INVAL, "NULL input pointer");
+  if (cap && (!out_keys || !out_counts)) fail(KC_E_INVAL, "output pointer is NULL");
+  const uint64_t D = run_wave(b, wi, reads, offsets, out_keys, out_counts, cap, host_set_off, st);
+  b->stats = b->waves[wi].stats;
+  *n_out = D;
+  if (D > cap)
+    fail(KC_E_CAPACITY, "output capacity " + std::to_string(cap) + " < " + std::to_string(D) +
+                            " pairs in the wave");
+  return KC_OK;
 }
 
 int batch_run_impl(kc_batch* b, const uint8_t* reads, const uint64_t* offsets, uint64_t* out_keys,
@@ -1266,122 +1510,35 @@ int batch_run_impl(kc_batch* b, const uint8_t* reads, const uint64_t* offsets, u
   *n_out = 0;
   if (!reads || !offsets) fail(KC_E_INVAL, "NULL input pointer");
   if (cap && (!out_keys || !out_counts)) fail(KC_E_INVAL, "output pointer is NULL");
-  Ctx& c = b->ctx;
-  // inputs must have the layout the plan describes
-  ensure(c.state, sizeof(kc::DevState), "device state");
-  hipchk(kc::launch_fill_u64((unsigned long long*)b->flag.p, 8, 0, st), "fill launch");
-  if (b->n_reads) {
-    hipLaunchKernelGGL(k_offsets_ok, dim3((unsigned)((b->n_reads + 255) / 256)), dim3(256), 0, st,
-                       offsets, b->n_reads, (unsigned int*)b->flag.p);
-    hipchk(hipGetLastError(), "offsets check launch");
-  }
-  hipLaunchKernelGGL(k_batch_layout_ok, dim3((b->n_sets + 256) / 256), dim3(256), 0, st, offsets,
-                     (const unsigned long long*)b->set_first_read_dev.p,
-                     (const unsigned long long*)b->set_byte_off_dev.p, b->n_sets,
-                     (unsigned int*)b->flag.p);
-  hipchk(hipGetLastError(), "layout check launch");
-  uint64_t* h = (uint64_t*)host_stage(c, 64);
-  hipchk(hipMemcpyAsync(h, offsets, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-  hipchk(hipMemcpyAsync(h + 1, b->flag.p, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-  hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-  const uint64_t off0 = h[0];
-  if (h[1] != 0) fail(KC_E_INVAL, "reads and offsets do not match the batch plan");
-  const void* key[5] = {reads, offsets, out_keys, out_counts, nullptr};
-  const bool same = std::equal(key, key + 5, b->key) && b->key_cap == cap && b->key_off0 == off0;
-  if (!b->exec || !same) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
-    if (!b->cap_stream) hipchk(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking),
-                               "hipStreamCreate");
-    hipStream_t cs = b->cap_stream;
-    hipchk(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    try {
-      Timer off(c, cs, false);
-      const size_t nst = b->cls.size();
-      hipchk(kc::launch_fill_u64((unsigned long long*)b->states.p,
-                                 nst * sizeof(kc::DevState) / 8, 0, cs),
-             "fill launch");
-      const uint64_t nchunks = (b->N + 63) / 64 + 2;
-      hipchk(kc::launch_pack(reads + off0, b->N, offsets, b->n_reads, off0, (uint64_t*)c.packed.p,
-                             (uint64_t*)c.inv.p, (uint64_t*)c.endm.p, nchunks, cs),
-             "pack launch");
-      for (size_t ci = 0; ci < nst; ++ci) {
-        kc_batch::Class& C = b->cls[ci];
-        kc::DevState* ds = (kc::DevState*)b->states.p + ci;
-        PipeOut po{(uint64_t*)b->cls_keys.p + C.out_base, (uint32_t*)b->cls_counts.p + C.out_base,
-                   (uint32_t*)b->cls_set.p + C.out_base, C.out_cap};
-        enqueue_pipeline(c, C.pipe, ds, off, po, cs);
-        hipchk(kc::launch_set_bounds(po.set, ds, C.out_cap, (uint32_t)C.sets.size(),
-                                     (unsigned long long*)b->starts.p + C.start_base, cs),
-               "set bounds launch");
-      }
-      hipchk(kc::launch_batch_offsets((const uint32_t*)b->set_class_dev.p,
-                                      (const uint32_t*)b->set_local_dev.p,
-                                      (const unsigned long long*)b->starts.p,
-                                      (const unsigned long long*)b->start_base_dev.p, b->n_sets,
-                                      (unsigned long long*)b->set_off.p, cs),
-             "batch offsets launch");
-      hipchk(kc::launch_batch_gather(
-                 (const uint32_t*)b->set_class_dev.p, (const uint32_t*)b->set_local_dev.p,
-                 (const unsigned long long*)b->starts.p,
-                 (const unsigned long long*)b->start_base_dev.p,
-                 (const unsigned long long*)b->class_base_dev.p, (const uint64_t*)b->cls_keys.p,
-                 (const uint32_t*)b->cls_counts.p, (const unsigned long long*)b->set_off.p,
-                 b->n_sets, cap, out_keys, out_counts, cs),
-             "batch gather launch");
-    } catch (...) {
-      hipGraph_t g = nullptr;
-      (void)hipStreamEndCapture(cs, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    hipchk(hipStreamEndCapture(cs, &b->graph), "hipStreamEndCapture");
-    hipchk(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-    std::copy(key, key + 5, b->key);
-    b->key_cap = cap;
-    b->key_off0 = off0;
-  }
-  hipchk(hipGraphLaunch(b->exec, st), "hipGraphLaunch");
-  const size_t nst = b->cls.size();
-  const size_t bytes = nst * sizeof(kc::DevState) + (b->n_sets + 1) * 8;
-  char* hs = (char*)host_stage(c, bytes);
-  hipchk(hipMemcpyAsync(hs, b->states.p, nst * sizeof(kc::DevState), hipMemcpyDeviceToHost, st),
-         "hipMemcpyAsync");
-  hipchk(hipMemcpyAsync(hs + nst * sizeof(kc::DevState), b->set_off.p, (b->n_sets + 1) * 8,
-                        hipMemcpyDeviceToHost, st),
-         "hipMemcpyAsync");
-  hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
   std::memset(&b->stats, 0, sizeof(b->stats));
-  bool overflow = false;
-  for (size_t ci = 0; ci < nst; ++ci) {
-    kc::DevState ds;
-    std::memcpy(&ds, hs + ci * sizeof(kc::DevState), sizeof(ds));
-    if (ds.count_overflow) fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
-    overflow |= ds.overflow != 0;
-    b->stats.valid_windows += ds.W;
-    b->stats.distinct += ds.D;
-    b->stats.n_leaves += ds.n_leaves;
-    b->stats.large_records += ds.large_records;
-    b->stats.large_distinct += ds.large_distinct;
+  uint64_t base = 0;
+  bool short_cap = false;
+  std::vector<uint64_t> so;
+  for (uint32_t wi = 0; wi < b->waves.size(); ++wi) {
+    const kc_batch::Wave& w = b->waves[wi];
+    so.assign(w.ns + 1, 0);
+    // once the output is too small, the remaining waves only count their pairs
+    const uint64_t room = short_cap || base > cap ? 0 : cap - base;
+    const uint64_t D = run_wave(b, wi, reads, offsets + w.r0, room ? out_keys + base : nullptr,
+                                room ? out_counts + base : nullptr, room, so.data(), st);
+    if (D > room) short_cap = true;
+    for (uint32_t s = 0; s <= w.ns; ++s) host_set_off[w.s0 + s] = base + so[s];
+    base += D;
+    const kc_stats& ws = w.stats;
+    b->stats.n_bases += ws.n_bases;
+    b->stats.valid_windows += ws.valid_windows;
+    b->stats.distinct += ws.distinct;
+    b->stats.n_leaves += ws.n_leaves;
+    b->stats.n_overflow += ws.n_overflow;
+    b->stats.large_records += ws.large_records;
+    b->stats.large_distinct += ws.large_distinct;
   }
-  b->stats.n_bases = b->N;
-  std::memcpy(host_set_off, hs + nst * sizeof(kc::DevState), (b->n_sets + 1) * 8);
-  if (overflow) {
-    // a class had a leaf too large for the device-planned split: count set by set
-    ++b->stats.n_overflow;
-    batch_by_sets(b, reads, offsets, out_keys, out_counts, cap, host_set_off, n_out, st);
-  }
-  const uint64_t D = host_set_off[b->n_sets];
-  if (D > cap) {
-    *n_out = D;
-    fail(KC_E_CAPACITY, "output capacity " + std::to_string(cap) + " < " + std::to_string(D) +
-                            " pairs in the batch");
-  }
-  *n_out = D;
+  *n_out = base;
   b->stats.ms_total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (base > cap)
+    fail(KC_E_CAPACITY, "output capacity " + std::to_string(cap) + " < " + std::to_string(base) +
+                            " pairs in the batch");
   return KC_OK;
 }
 
@@ -1565,10 +1722,37 @@ struct CarveScope {
 extern "C" {
 
 int kc_batch_plan(const uint64_t* host_set_reads, const uint64_t* host_set_bytes,
-                  const int* host_ks, uint32_t n_sets, int P, const kc_options* opt,
-                  kc_batch** plan) {
+                  const int* host_ks, uint32_t n_sets, int P, uint64_t hbm_budget,
+                  const kc_options* opt, kc_batch** plan) {
   return guarded([&] {
-    return batch_plan_impl(host_set_reads, host_set_bytes, host_ks, n_sets, P, opt, plan);
+    return batch_plan_impl(host_set_reads, host_set_bytes, host_ks, n_sets, P, hbm_budget, opt,
+                           plan);
+  });
+}
+
+uint32_t kc_batch_waves(const kc_batch* plan) { return plan ? (uint32_t)plan->waves.size() : 0; }
+
+int kc_batch_wave_info(const kc_batch* plan, uint32_t wave, kc_batch_wave* out) {
+  if (!plan || !out || wave >= plan->waves.size()) return KC_E_INVAL;
+  const kc_batch::Wave& w = plan->waves[wave];
+  out->first_set = w.s0;
+  out->n_sets = w.ns;
+  out->first_read = w.r0;
+  out->n_reads = w.nr;
+  out->first_byte = w.b0;
+  out->n_bytes = w.nbytes;
+  out->device_bytes = w.need;
+  out->n_classes = (uint32_t)w.cls.size();
+  return KC_OK;
+}
+
+int kc_batch_run_wave(kc_batch* plan, uint32_t wave, const uint8_t* reads,
+                      const uint64_t* offsets, uint64_t* out_keys, uint32_t* out_counts,
+                      uint64_t out_capacity, uint64_t* host_out_set_offsets, uint64_t* n_out,
+                      void* stream) {
+  return guarded([&] {
+    return batch_run_wave_impl(plan, wave, reads, offsets, out_keys, out_counts, out_capacity,
+                               host_out_set_offsets, n_out, (hipStream_t)stream);
   });
 }
 

@@ -33,19 +33,37 @@ struct Ledger {
 
 // The queued job to start next, or -1: the first job in arrival order whose
 // need (bytes it would add to the ledger when started now) fits in
-// free_bytes. Jobs passed over are marked bypassed; a job passed over
-// max_bypass times blocks all later jobs until it fits itself, so a large
-// job waits at most max_bypass starts before memory is kept for it.
+// free_bytes. A job passed over max_bypass times blocks all later jobs until
+// it fits itself, so a large job waits at most max_bypass starts before memory
+// is kept for it. peek_job only looks; pick_job also marks the jobs passed
+// over as bypassed.
 template <class Need>
-long pick_job(std::deque<QueuedJob>& q, uint64_t free_bytes, uint32_t max_bypass, Need&& need) {
+long peek_job(const std::deque<QueuedJob>& q, uint64_t free_bytes, uint32_t max_bypass,
+              Need&& need) {
   for (size_t i = 0; i < q.size(); ++i) {
-    if (need(q[i]) <= free_bytes) {
-      for (size_t j = 0; j < i; ++j) ++q[j].bypassed;
-      return (long)i;
-    }
+    if (need(q[i]) <= free_bytes) return (long)i;
     if (q[i].bypassed >= max_bypass) return -1;
   }
   return -1;
+}
+
+template <class Need>
+long pick_job(std::deque<QueuedJob>& q, uint64_t free_bytes, uint32_t max_bypass, Need&& need) {
+  const long i = peek_job(q, free_bytes, max_bypass, need);
+  for (long j = 0; j < i; ++j) ++q[(size_t)j].bypassed;
+  return i;
+}
+
+// True when no queued job can start until the client releases results it
+// holds: nothing is running, every worker has given its scratch back, and
+// still no queued job is admitted (what the budget has left after the held
+// results is too small). A wait on a queued job then reports KC_E_NOMEM
+// instead of blocking for ever.
+template <class Need>
+bool stalled_on_results(const std::deque<QueuedJob>& q, uint64_t free_bytes, uint32_t max_bypass,
+                        uint64_t running, uint64_t arena_total, Need&& need) {
+  return !q.empty() && running == 0 && arena_total == 0 &&
+         peek_job(q, free_bytes, max_bypass, need) < 0;
 }
 
 }  // namespace kc

@@ -140,6 +140,15 @@ struct kc_server {
 
   void worker_main(int w);
   void finish_locked(Job* j, int w, uint64_t new_arena);
+  bool stalled_locked() const {
+    uint64_t held = 0;
+    for (uint64_t a : arena) held += a;
+    return kc::stalled_on_results(queue, ledger.free_bytes(), max_bypass, running, held,
+                                  [&](const kc::QueuedJob& q) {
+                                    return kc::scratch_bytes(q.n_bytes, q.k, q.P, &opt) +
+                                           q.result_est;
+                                  });
+  }
 };
 
 void kc_server::worker_main(int w) {
@@ -184,6 +193,7 @@ void kc_server::worker_main(int w) {
           arena[w] = 0;
           ++releases;
           cv_work.notify_all();
+          cv_done.notify_all();  // a waiter may now find the queue stalled on held results
           continue;
         }
         cv_work.wait(lk);
@@ -420,7 +430,17 @@ int kc_server_wait(kc_server* s, uint64_t job_id, int* state) {
     auto it = s->jobs.find(job_id);
     if (it == s->jobs.end()) return set_err(KC_E_INVAL, "unknown job id");
     Job* j = it->second.get();
-    s->cv_done.wait(lk, [&] { return j->state == KC_JOB_DONE || j->state == KC_JOB_FAILED; });
+    while (j->state != KC_JOB_DONE && j->state != KC_JOB_FAILED) {
+      if (j->state == KC_JOB_QUEUED && s->stalled_locked()) {
+        if (state) *state = j->state;
+        return set_err(KC_E_NOMEM,
+                       "job " + std::to_string(job_id) + " cannot start: results held on the "
+                       "device (" + std::to_string(s->ledger.in_use) + " of the " +
+                       std::to_string(s->ledger.budget) + " budget bytes) leave too little for "
+                       "the queued jobs; release results, then wait again");
+      }
+      s->cv_done.wait(lk);
+    }
     if (state) *state = j->state;
     return KC_OK;
   });

@@ -29,7 +29,8 @@ EXPORTED_SYMBOLS = ["kc_count", "kc_count_ex", "kc_max_outputs", "kc_last_stats"
                     "kc_pred_get_params", "kc_pred_set_params", "kc_pred_get_grads",
                     "kc_pred_forward", "kc_pred_gradient", "kc_pred_adam_step", "kc_pred_free",
                     "kc_measure_ceilings", "kc_spectrum", "kc_filter_min_count",
-                    "kc_merge_counts", "kc_parse_fastx", "kc_count_noalloc"]
+                    "kc_merge_counts", "kc_parse_fastx", "kc_count_noalloc", "kc_batch_waves",
+                    "kc_batch_wave_info", "kc_batch_run_wave"]
 
 JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
@@ -68,6 +69,14 @@ class KcServeStats(ctypes.Structure):
                  "scratch_releases")] + \
                [(n, ctypes.c_double) for n in
                 ("latency_p50_ms", "latency_p99_ms", "wait_p50_ms", "wait_p99_ms", "busy_ms")]
+
+
+class KcBatchWave(ctypes.Structure):
+    _fields_ = [("first_set", ctypes.c_uint32), ("n_sets", ctypes.c_uint32),
+                ("first_read", ctypes.c_uint64), ("n_reads", ctypes.c_uint64),
+                ("first_byte", ctypes.c_uint64), ("n_bytes", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64), ("n_classes", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
 
 
 class KcCeilings(ctypes.Structure):
@@ -130,7 +139,13 @@ def lib():
             L.kc_version.restype = ctypes.c_char_p
             L.kc_version.argtypes = []
             L.kc_batch_plan.restype = i32
-            L.kc_batch_plan.argtypes = [p, p, p, ctypes.c_uint32, i32, p, p]
+            L.kc_batch_plan.argtypes = [p, p, p, ctypes.c_uint32, i32, u64, p, p]
+            L.kc_batch_waves.restype = ctypes.c_uint32
+            L.kc_batch_waves.argtypes = [p]
+            L.kc_batch_wave_info.restype = i32
+            L.kc_batch_wave_info.argtypes = [p, ctypes.c_uint32, p]
+            L.kc_batch_run_wave.restype = i32
+            L.kc_batch_run_wave.argtypes = [p, ctypes.c_uint32, p, p, p, p, u64, p, p, p]
             L.kc_batch_run.restype = i32
             L.kc_batch_run.argtypes = [p, p, p, p, p, u64, p, p, p]
             L.kc_batch_max_outputs.restype = u64
@@ -502,28 +517,39 @@ def _stats_dict(s: KcStats) -> dict:
 
 
 class BatchPlan:
-    """A planned batch of read sets (kc_batch_plan / kc_batch_run).
+    """A planned batch of read sets (kc_batch_plan / kc_batch_run / kc_batch_run_wave).
 
     set_reads, set_bytes, ks: per set (host sequences). The reads of all sets
-    are consecutive in one stream; set s has its own k (1..32).
+    are consecutive in one stream; set s has its own k (1..32). hbm_budget:
+    device bytes a memory wave may hold (0: one wave for all sets).
     """
 
-    def __init__(self, set_reads, set_bytes, ks, P: int = 1, opts: KcOptions | None = None):
+    def __init__(self, set_reads, set_bytes, ks, P: int = 1, opts: KcOptions | None = None,
+                 hbm_budget: int = 0):
         self.set_reads = np.ascontiguousarray(set_reads, dtype=np.uint64)
         self.set_bytes = np.ascontiguousarray(set_bytes, dtype=np.uint64)
         self.ks = np.ascontiguousarray(ks, dtype=np.int32)
         self.n_sets = int(self.ks.size)
         self._h = ctypes.c_void_p()
         st = lib().kc_batch_plan(self.set_reads.ctypes.data, self.set_bytes.ctypes.data,
-                                 self.ks.ctypes.data, self.n_sets, P,
+                                 self.ks.ctypes.data, self.n_sets, P, int(hbm_budget),
                                  ctypes.byref(opts) if opts is not None else None,
                                  ctypes.byref(self._h))
         if st != 0:
             raise KcError(st, lib().kc_last_error().decode())
         self.max_outputs = int(lib().kc_batch_max_outputs(self._h))
+        self.waves = [self.wave_info(w) for w in range(int(lib().kc_batch_waves(self._h)))]
+
+    def wave_info(self, w: int) -> dict:
+        info = KcBatchWave()
+        st = lib().kc_batch_wave_info(self._h, w, ctypes.byref(info))
+        if st != 0:
+            raise KcError(st, "wave %d" % w)
+        return {n: getattr(info, n) for n, _ in KcBatchWave._fields_ if n != "pad"}
 
     def run_into(self, reads, offsets, out_keys, out_counts, capacity: int, stream=None):
-        """Run on device tensors; returns (n_pairs, set_offsets as a numpy uint64 array)."""
+        """Run every wave on device tensors of the whole batch; returns
+        (n_pairs, set_offsets as a numpy uint64 array of n_sets + 1)."""
         import torch
         _check_tensor(reads, "reads", (torch.uint8,))
         _check_tensor(offsets, "offsets", (torch.int64, torch.uint64))
@@ -535,6 +561,25 @@ class BatchPlan:
             st = lib().kc_batch_run(self._h, reads.data_ptr(), offsets.data_ptr(),
                                     out_keys.data_ptr(), out_counts.data_ptr(), capacity,
                                     set_off.ctypes.data, ctypes.byref(n_out), stream)
+        if st != 0:
+            raise KcError(st, lib().kc_last_error().decode(), int(n_out.value))
+        return int(n_out.value), set_off
+
+    def run_wave_into(self, w: int, reads, offsets, out_keys, out_counts, capacity: int,
+                      stream=None):
+        """Run wave w on device tensors holding only that wave's reads and
+        their offsets; returns (n_pairs, the wave's n_sets + 1 set offsets)."""
+        import torch
+        _check_tensor(reads, "reads", (torch.uint8,))
+        _check_tensor(offsets, "offsets", (torch.int64, torch.uint64))
+        if stream is None:
+            stream = torch.cuda.current_stream(reads.device).cuda_stream
+        set_off = np.zeros(self.waves[w]["n_sets"] + 1, dtype=np.uint64)
+        n_out = ctypes.c_uint64(0)
+        with torch.cuda.device(reads.device):
+            st = lib().kc_batch_run_wave(self._h, w, reads.data_ptr(), offsets.data_ptr(),
+                                         out_keys.data_ptr(), out_counts.data_ptr(), capacity,
+                                         set_off.ctypes.data, ctypes.byref(n_out), stream)
         if st != 0:
             raise KcError(st, lib().kc_last_error().decode(), int(n_out.value))
         return int(n_out.value), set_off

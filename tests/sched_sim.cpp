@@ -6,7 +6,11 @@
 // and prints one line per job: id start end worker, then "peak <bytes>".
 // A worker keeps its scratch (grows to the largest job it ran) and gives it
 // back only when every worker is idle and no queued job fits, as the server
-// does; a result is held from the job's end until end + hold.
+// does; a result is held from the job's end until end + hold. A negative hold
+// models a client that waits for the jobs in submission order and releases
+// each result once it has waited for it: when the server reports that the
+// queue is stalled on held results (kc_server_wait's KC_E_NOMEM), that client
+// releases every result it holds. The last line is "stalls <reports>".
 #include <cstdio>
 #include <deque>
 #include <map>
@@ -42,6 +46,9 @@ int main() {
   std::multimap<double, int> ends, releases;  // time -> job
   size_t next_arrival = 0;
   int done = 0;
+  int consumed = 0;  // in-order client: jobs [0, consumed) waited for and released
+  int stalls = 0;
+  std::vector<int> held;  // finished jobs with negative hold, not yet released
   double now = 0;
   uint64_t reserved_running[64] = {};
   while (done < n) {
@@ -50,9 +57,22 @@ int main() {
     if (next_arrival < jobs.size()) t = jobs[next_arrival].arrival;
     if (!ends.empty()) t = std::min(t, ends.begin()->first);
     if (!releases.empty()) t = std::min(t, releases.begin()->first);
-    if (t == 1e300) {  // nothing pending but queued jobs: they can never start
-      std::printf("stuck %zu\n", q.size());
-      return 1;
+    if (t == 1e300) {
+      // nothing pending but queued jobs: the server reports the stall to a
+      // client waiting on one of them; the client releases what it holds
+      uint64_t held_arena = 0;
+      for (uint64_t a : arena) held_arena += a;
+      const bool stalled = kc::stalled_on_results(
+          q, L.free_bytes(), max_bypass, 0, held_arena,
+          [&](const kc::QueuedJob& x) { return jobs[x.id].scratch + x.result_est; });
+      if (!stalled || held.empty()) {
+        std::printf("stuck %zu\n", q.size());
+        return 1;
+      }
+      ++stalls;
+      for (int id : held) L.sub(jobs[id].actual);
+      held.clear();
+      t = now;
     }
     now = t;
     while (!releases.empty() && releases.begin()->first <= now) {
@@ -63,6 +83,7 @@ int main() {
       const int id = ends.begin()->second;
       ends.erase(ends.begin());
       SimJob& j = jobs[id];
+      j.end = now;
       const int w = j.worker;
       L.sub(reserved_running[w]);
       reserved_running[w] = 0;
@@ -71,9 +92,29 @@ int main() {
         arena[w] = j.scratch;
       }
       L.add(j.actual);
-      releases.emplace(now + j.hold, id);
+      if (j.hold >= 0) releases.emplace(now + j.hold, id);
+      else held.push_back(id);
       busy[w] = -1;
       ++done;
+    }
+    // the in-order client releases the held results it has reached
+    for (;;) {
+      bool moved = false;
+      for (size_t i = 0; i < held.size(); ++i)
+        if (held[i] == consumed) {
+          L.sub(jobs[held[i]].actual);
+          held.erase(held.begin() + i);
+          ++consumed;
+          moved = true;
+          break;
+        }
+      if (!moved) {
+        if (consumed < n && jobs[consumed].end >= 0 && jobs[consumed].hold >= 0) {
+          ++consumed;  // released by time, not by the client
+          continue;
+        }
+        break;
+      }
     }
     while (next_arrival < jobs.size() && jobs[next_arrival].arrival <= now) {
       kc::QueuedJob qj;
@@ -118,5 +159,6 @@ int main() {
     std::printf("%d %.6f %.6f %d\n", i, jobs[i].start, jobs[i].start + jobs[i].duration,
                 jobs[i].worker);
   std::printf("peak %llu\n", (unsigned long long)L.peak);
+  std::printf("stalls %d\n", stalls);
   return 0;
 }

@@ -57,7 +57,7 @@ def test_struct_layouts_match_c_compiler(tmp_path):
     equal the ctypes mirrors of the binding."""
     mirrors = {"kc_options": kc.kc.KcOptions, "kc_stats": kc.kc.KcStats,
                "kc_job_info": kc.kc.KcJobInfo, "kc_serve_stats": kc.kc.KcServeStats,
-               "kc_ceilings": kc.kc.KcCeilings}
+               "kc_ceilings": kc.kc.KcCeilings, "kc_batch_wave": kc.kc.KcBatchWave}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kc.h"', '#include "kc_bench.h"',
              "int main(void) {"]
     for cname, py in mirrors.items():

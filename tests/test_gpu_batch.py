@@ -129,3 +129,63 @@ def test_batch_many_sets_c4_shape_sample():
     plan = kc.BatchPlan(sr, sb, ks, P=1)
     check_batch(plan, rt, ot, per_set, "plain")
     plan.close()
+
+
+def test_batch_k32_single_set_class_and_forced_overflow():
+    """A class of one k = 32 set (no set-id bits: the key is the whole word),
+    and a plan whose leaves overflow (no split below huge leaf sizes), so that
+    the per-set fallback counts the wave; both against the oracle."""
+    reads, offsets, sr, sb, ks, per_set = make_batch(5, 4, [32, 21, 31, 21], min_g=5000,
+                                                     max_g=20000)
+    rt, ot = to_device(reads, offsets)
+    print("batch: one k=32 set, default options", flush=True)
+    plan = kc.BatchPlan(sr, sb, ks, P=2)
+    assert any(w["n_classes"] >= 3 for w in plan.waves)
+    check_batch(plan, rt, ot, per_set, "oracle")
+    assert plan.stats()["n_overflow"] == 0
+    plan.close()
+    print("batch: forced overflow (leaf_attempt 2^30, 1024-slot tables)", flush=True)
+    plan = kc.BatchPlan(sr, sb, ks, P=2,
+                        opts=kc.options(leaf_attempt=1 << 30, table_slots_log2=10, shard_bits=1))
+    check_batch(plan, rt, ot, per_set, "oracle")
+    assert plan.stats()["n_overflow"] >= 1
+    plan.close()
+
+
+def test_batch_memory_waves_from_a_budget():
+    """A device budget cuts the sets into several waves; running all waves at
+    once and each wave from its own inputs both give the oracle's counts."""
+    import torch
+    reads, offsets, sr, sb, ks, per_set = make_batch(6, 40, [21, 31], min_g=2000, max_g=40000,
+                                                     cov=10)
+    rt, ot = to_device(reads, offsets)
+    one = kc.BatchPlan(sr, sb, ks, P=1)
+    assert len(one.waves) == 1
+    budget = one.waves[0]["device_bytes"] // 4
+    one.close()
+    plan = kc.BatchPlan(sr, sb, ks, P=1, hbm_budget=budget)
+    print("batch: %d waves under a budget of %d bytes" % (len(plan.waves), budget), flush=True)
+    assert len(plan.waves) >= 3
+    assert all(w["device_bytes"] <= budget for w in plan.waves)
+    assert sum(w["n_sets"] for w in plan.waves) == len(per_set)
+    keys, cnts, set_off = check_batch(plan, rt, ot, per_set, "oracle")
+    # wave by wave, each from a copy of only its reads
+    for wi, w in enumerate(plan.waves):
+        a, b = w["first_byte"], w["first_byte"] + w["n_bytes"]
+        r0, nr = w["first_read"], w["n_reads"]
+        wr = rt[a:b].clone()
+        wo = (ot[r0:r0 + nr + 1] - a).clone()
+        cap = max(1, int(b - a))
+        kk = torch.empty(cap, dtype=torch.int64, device=rt.device)
+        cc = torch.empty(cap, dtype=torch.int32, device=rt.device)
+        n, so = plan.run_wave_into(wi, wr, wo, kk, cc, cap)
+        s0 = w["first_set"]
+        base = int(set_off[s0])
+        assert n == int(set_off[s0 + w["n_sets"]]) - base
+        assert np.array_equal(so, set_off[s0:s0 + w["n_sets"] + 1] - np.uint64(base))
+        assert np.array_equal(kk[:n].cpu().numpy().view(np.uint64), keys[base:base + n])
+        assert np.array_equal(cc[:n].cpu().numpy().view(np.uint32), cnts[base:base + n])
+    plan.close()
+    with pytest.raises(kc.KcError) as e:
+        kc.BatchPlan(sr, sb, ks, P=1, hbm_budget=1 << 20)
+    assert e.value.status == -2

@@ -2,11 +2,12 @@
 Mbp uniform plus 90 Mbp of 50 repeat families with Zipf(1.2) copy numbers),
 40,000,000 reads of 150 bp at 30x, k = 31 and k = 21, P = 256.
 
-The oracle cannot sort 4.8e9 windows in test time, so this checks what it can
-compute one by one at full size: the counts of sampled output keys and of
-every key of sampled reads (oracle selected-key count over all reads), the
-number of valid windows against the sum of counts, and the device self-check
-(strictly increasing, canonical, in range)."""
+Element-wise: the GPU output is cut into four slices by the top two bits of
+the key, and each slice is compared pair by pair with the oracle's tally of
+the keys in that slice (the oracle decodes only the windows whose key falls
+in the slice, so each pass holds a quarter of the keys). The slices cover
+the whole key space, so the number of distinct keys is compared too; the
+number of valid windows is compared with the oracle's count of them."""
 import numpy as np
 import pytest
 
@@ -16,52 +17,49 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
+SLICE_BITS = 2
+
 
 @pytest.fixture(scope="module")
 def c3():
-    cfg = synth.make_config(3)
-    return cfg
+    return synth.make_config(3)
 
 
 @pytest.mark.parametrize("k", [31, 21])
-def test_config3_full_sampled(c3, k):
+def test_config3_full_element_wise(c3, k):
     import torch
     reads, offs = c3["reads"], c3["offsets"]
     dev = torch.device("cuda:0")
-    print("c3 k=%d: %d reads, %d bytes" % (k, offs.size - 1, reads.size), flush=True)
+    print("c3 k=%d: %d reads, %d bytes, P=%d" % (k, offs.size - 1, reads.size, c3["P"]),
+          flush=True)
     rt = torch.from_numpy(reads).to(dev)
     ot = torch.from_numpy(offs.view(np.int64)).to(dev)
     cap = kc.max_outputs(offs, k)
     keys = torch.empty(cap, dtype=torch.int64, device=dev)
     cnts = torch.empty(cap, dtype=torch.int32, device=dev)
-    n = kc.count_into(rt, ot, k, c3["P"], keys, cnts, cap,
-                      kc.options(check=1))
+    n = kc.count_into(rt, ot, k, c3["P"], keys, cnts, cap, kc.options(check=1))
     st = kc.last_stats()
     del rt, ot
-    W = oracle.valid_windows(reads, offs, k)
-    assert st["valid_windows"] == W and st["distinct"] == n
-    total = int(cnts[:n].to(torch.int64).sum().item())
-    assert total == W
-    rng = np.random.Generator(np.random.PCG64(0xC3 + k))
-    # sampled output entries, spread over the whole key range
-    idx = np.sort(rng.choice(n, size=3000, replace=False))
-    it = torch.from_numpy(idx.astype(np.int64)).to(dev)
-    sk = keys[it].cpu().numpy().view(np.uint64)
-    sc = cnts[it].cpu().numpy().view(np.uint32).astype(np.uint64)
-    assert np.array_equal(oracle.count_selected(reads, offs, k, sk), sc)
-    # every key of sampled reads is present with its full-input count
-    ridx = rng.choice(offs.size - 1, size=40, replace=False)
-    parts = [reads[int(offs[i]):int(offs[i + 1])] for i in ridx]
-    po = np.zeros(len(parts) + 1, dtype=np.uint64)
-    np.cumsum([p.size for p in parts], out=po[1:])
-    rk, _ = oracle.count(np.concatenate(parts), po, k)
-    rkt = torch.from_numpy(rk.view(np.int64)).to(dev)
-    pos = torch.searchsorted(keys[:n], rkt)  # keys are < 2^62: signed order is key order
-    assert int(pos.max().item()) < n
-    found = keys[pos].cpu().numpy().view(np.uint64)
-    assert np.array_equal(found, rk)
-    gc = cnts[pos].cpu().numpy().view(np.uint32).astype(np.uint64)
-    assert np.array_equal(oracle.count_selected(reads, offs, k, rk), gc)
+    torch.cuda.empty_cache()
+    assert st["valid_windows"] == oracle.valid_windows(reads, offs, k)
+    assert st["distinct"] == n
+    # keys are below 2^62, so signed order is key order for searchsorted
+    shift = 2 * k - SLICE_BITS
+    bounds = torch.tensor([s << shift for s in range(2 ** SLICE_BITS)] + [1 << (2 * k)],
+                          dtype=torch.int64, device=dev)
+    cut = torch.searchsorted(keys[:n], bounds).cpu().tolist()
+    assert cut[0] == 0 and cut[-1] == n
+    for s in range(2 ** SLICE_BITS):
+        a, b = cut[s], cut[s + 1]
+        got_k = keys[a:b].cpu().numpy().view(np.uint64)
+        got_c = cnts[a:b].cpu().numpy().view(np.uint32)
+        want_k, want_c = oracle.count_range(reads, offs, k, SLICE_BITS, s, s + 1,
+                                            capacity=2 * (b - a) + 1024)
+        print("  slice %d: %d pairs (oracle %d)" % (s, b - a, want_c.size), flush=True)
+        assert got_k.size == want_k.size, "slice %d: %d keys vs %d" % (s, got_k.size, want_k.size)
+        assert np.array_equal(got_k, want_k), "slice %d keys differ" % s
+        assert np.array_equal(got_c, want_c), "slice %d counts differ" % s
+        del got_k, got_c, want_k, want_c
     del keys, cnts
     kc.lib().kc_release_scratch()
     torch.cuda.empty_cache()

@@ -124,3 +124,44 @@ def test_server_errors():
         srv.release(b)
     finally:
         srv.close()
+
+
+def test_wait_reports_a_queue_stalled_on_held_results():
+    """Results the client holds stay charged to the budget. With a budget for
+    one job at a time, a second job cannot start while the first job's result
+    is held: waiting for it reports KC_E_NOMEM (instead of blocking for ever)
+    and leaves it queued; once the result is released it runs and matches
+    the oracle."""
+    import torch
+    c = synth.make_config(1)
+    print("served: stall report on workload 1", flush=True)
+    rt, ot = to_device(c["reads"], c["offsets"])
+    # the ledger peak of one job run alone: its scratch and reservation
+    probe = kc.Server(1 << 40, 1)
+    a = probe.submit(rt, ot, 31)
+    assert probe.wait(a) == "done"
+    result_bytes = probe.info(a)["result_bytes"]
+    peak = probe.stats()["bytes_peak"]
+    probe.release(a)
+    probe.close()
+    assert result_bytes > 0
+    srv = kc.Server(peak + result_bytes // 2, 1)
+    try:
+        a = srv.submit(rt, ot, 31)
+        assert srv.wait(a) == "done"
+        b = srv.submit(rt, ot, 31)
+        with pytest.raises(kc.KcError) as e:
+            srv.wait(b)
+        assert e.value.status == -2 and "release results" in str(e.value)
+        assert srv.info(b)["state"] == "queued"
+        ka, ca = srv.result(a)
+        srv.release(a)
+        assert srv.wait(b) == "done"
+        kb, cb = srv.result(b)
+        want = oracle.count(c["reads"], c["offsets"], 31)
+        assert_same(host(ka, ca), want, "first job")
+        assert_same(host(kb, cb), want, "second job")
+        srv.release(b)
+    finally:
+        srv.close()
+    torch.cuda.synchronize()

@@ -147,3 +147,35 @@ def test_generator_is_deterministic_and_thread_invariant():
     r2, o2 = synth.reads(g1, 3000, 150, err_rate=0.01, n_rate=0.01, seed=4, threads=7)
     assert np.array_equal(r1, r2) and np.array_equal(o1, o2)
     assert set(np.unique(r1).tolist()) <= set(b"ACGTN")
+
+
+@pytest.mark.parametrize("k", [3, 21, 31, 55, 100])
+def test_range_slices_concatenate_to_the_full_count(k):
+    """Slices over a partition of the top key bits, taken in order, are the
+    full histogram; every key of a slice has its top bits in the slice's range
+    (read off the key as a Python int)."""
+    text, offs = synth.ragged_reads(4242 + k, 300, 0, 2 * k + 60, b"ACGTACGTacgtN")
+    full_k, full_c = oracle.count(text, offs, k, threads=2)
+    bits = min(2 * k, 6)
+    cuts = [0, 1, 5, 17, 18, 40, 2 ** bits]
+    ks, cs = [], []
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        sk, sc = oracle.count_range(text, offs, k, bits, lo, hi, threads=3)
+        for key in keys_as_ints(sk, k):
+            assert lo <= key >> (2 * k - bits) < hi
+        ks.append(sk)
+        cs.append(sc)
+    assert np.array_equal(np.concatenate(ks), full_k)
+    assert np.array_equal(np.concatenate(cs), full_c)
+    # an empty range gives nothing
+    ek, ec = oracle.count_range(text, offs, k, bits, 7, 7)
+    assert ek.shape[0] == 0 and ec.size == 0
+
+
+def test_range_against_brute_force():
+    text, offs = synth.ragged_reads(99, 60, 0, 50, b"ACGTacgtN")
+    k = 5
+    want = brute.count_strings(brute.split_reads(text.tobytes(), offs), k)
+    for lo, hi in ((0, 300), (300, 700), (700, 1024)):  # top 10 bits = the whole key
+        sk, sc = oracle.count_range(text, offs, k, 10, lo, hi)
+        assert _pairs(sk, sc, k) == [(x, c) for x, c in want if lo <= x < hi]

@@ -35,10 +35,13 @@ def sim(tmp_path_factory):
                 continue
             if f[0] == "peak":
                 peak = int(f[1])
+            elif f[0] == "stalls":
+                run.stalls = int(f[1])
             else:
                 res.append((float(f[1]), float(f[2]), int(f[3])))
         return res, peak
 
+    run.stalls = 0
     return run
 
 
@@ -114,3 +117,29 @@ def test_tighter_estimates_admit_more(sim):
         assert peak <= 20_000
         lat.append(np.mean([e - j[0] for (s, e, w), j in zip(res, jobs)]))
     assert lat[0] < lat[1]
+
+
+def test_held_results_beyond_the_budget_are_reported_not_waited_for(sim):
+    """A client that waits for jobs in submission order and releases each
+    result after its wait. Job 5 needs much more scratch than the others, so
+    later small jobs pass it and finish; their results, held because the
+    client is waiting for job 5, fill the budget. Without the stall report the
+    queue would wait for ever (every worker idle, all scratch given back, job
+    5 not admitted). With it the client releases what it holds and every job
+    finishes; the ledger never passes the budget."""
+    jobs = []
+    for i in range(30):
+        if i == 5:
+            jobs.append((0.01 * i, 1.0, 2400, 300, 300, -1.0))
+        else:
+            jobs.append((0.01 * i, 0.2, 100, 300, 300, -1.0))
+    res, peak = sim(3000, 2, 8, jobs)
+    assert all(r[0] >= 0 for r in res)
+    assert peak <= 3000
+    assert sim.stalls >= 1
+
+
+def test_no_stall_reports_when_results_are_released_in_time(sim):
+    jobs = random_jobs(7, 80, hold=0.1)
+    res, peak = sim(20_000, 3, 8, jobs)
+    assert sim.stalls == 0
