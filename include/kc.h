@@ -71,7 +71,15 @@ typedef struct kc_options {
                           records and run-length accumulation (Algorithm 1's Sort +
                           Accumulate, as each owner does in Algorithm 3). Same result.
                           The batched form takes 0 only (and k <= 32). */
-  int reserved[5];
+  int scatter_tile;    /* window starts per thread of the owner scatter for keys of
+                          one word: 8 (8,192-record LDS tiles, two workgroups per CU;
+                          automatic) or 16 (16,384-record tiles, one workgroup per CU:
+                          longer runs per shard when there are many shards) */
+  int split_tile;      /* records per thread of the split scatter, likewise 8 or 16
+                          (automatic: 16) */
+  int refine_bits;     /* key bits by which an overflowed leaf is cut per refinement
+                          level: 1..8 (automatic: 3) */
+  int reserved[2];
 } kc_options;
 
 /* Statistics of the last successful call on this host thread. */
@@ -84,15 +92,18 @@ typedef struct kc_stats {
   uint64_t n_overflow;     /* leaf attempts that overflowed the table and were split */
   uint64_t max_leaf_windows;
   uint64_t max_owner_windows; /* windows in the largest of the P owner buckets */
-  uint64_t table_slots;    /* reserved (0) */
-  uint64_t large_records;   /* records counted by the 512-thread leaf kernel */
-  uint64_t large_distinct;  /* distinct keys it wrote */
+  uint64_t refined_records; /* records counted again by the refinement's block-wide
+                               leaf launches (parts of overflowed leaves) */
+  uint64_t large_records;   /* records counted by the block-wide leaf kernel's own
+                               launch (leaves above the one-wave size) */
+  uint64_t large_distinct;  /* distinct keys that launch wrote */
   double   ms_total;        /* host wall time of the call */
   double   ms_stage[12];    /* timing=1, device events on the call's stream (ms):
                                0 pack, 1 window histogram, 2 owner scatter (with the shard
                                plan), 3 split histogram, 4 split scatter (with the leaf plan),
                                5 small-leaf count (with leaf classification), 6 large-leaf
-                               count, 7 output offsets, 8 concat, 9 self-check, 10-11 unused */
+                               count, 7 output offsets, 8 concat, 9 self-check, 10 refinement
+                               of overflowed leaves (its splits and part counts), 11 unused */
 } kc_stats;
 
 /* Count canonical k-mers (plain form).

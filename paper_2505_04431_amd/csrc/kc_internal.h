@@ -67,7 +67,8 @@ constexpr uint32_t kLeafOverflow = 0xFFFFFFFFu;
 
 int max_leaf_slots_log2(int words);
 int max_shard_bits();
-int split_tile(int words);  // records per split work item
+// records per split work item (records_per_thread: 8, or 16 for one-word keys)
+int split_tile(int words, int records_per_thread);
 
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 
@@ -83,10 +84,12 @@ hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t*
                               unsigned long long* hist, unsigned long long* wcount,
                               hipStream_t s);
 
+// starts_per_thread: 8, or 16 for one-word keys (16,384-record LDS tiles).
 hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* inv,
                                  const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end,
                                  int k, int keybits, int shard_bits, const BatchSets* batch,
-                                 unsigned long long* cursor, void* out, hipStream_t s);
+                                 unsigned long long* cursor, void* out, int starts_per_thread,
+                                 hipStream_t s);
 
 // Device planning of the first split level. order[] lists shards
 // owner-major; sbegin[] receives each shard's record range start, cursor[] a
@@ -115,7 +118,8 @@ hipError_t launch_split_hist(int words, const void* src, const SplitItem* items,
 
 hipError_t launch_split_scatter(int words, const void* src, void* dst, const SplitItem* items,
                                 const DevState* st, uint64_t max_items, const SplitBin* bins,
-                                unsigned long long* cursor, hipStream_t s);
+                                unsigned long long* cursor, int records_per_thread,
+                                hipStream_t s);
 
 // Count each of the st->n_leaves leaves, write its sorted pairs next to it.
 // d_out[i] = distinct keys of leaf i, or kLeafOverflow (and st->overflow = 1)
@@ -125,13 +129,16 @@ hipError_t launch_split_scatter(int words, const void* src, void* dst, const Spl
 // in large_list, which holds max_leaves entries) to 512-thread workgroups.
 // mode 1: every non-empty leaf's records are sorted in LDS and run-length
 // accumulated (the launch_leaf_small call then only lists the leaves).
+// refine: the leaves are parts of overflowed leaves (first table full size;
+// the launches are separate kernel instantiations, so profiles tell them apart).
 hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
-                             uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode = 0);
+                             uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode,
+                             bool refine);
 hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
-                             hipStream_t s, int mode = 0);
+                             hipStream_t s, int mode, bool refine);
 uint64_t small_leaf_max(int words);
 
 // Exclusive scan of leaf counts into output offsets; st->D = total. bsum

@@ -657,6 +657,19 @@ __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restric
 // Plain 64-bit keys: registers capped so that two 1024-thread workgroups
 // share a CU (their LDS fits twice), which hides the per-tile barriers and
 // atomics. (The batch form keeps more values live and stays uncapped.)
+// The same with 16 window starts per thread: a tile of 16,384 records (128 KiB
+// of LDS staging, one workgroup per CU) gives each of many shards a run twice
+// as long per tile.
+template <typename K, typename Kc, int S, int TB, bool BATCH>
+__global__ void __launch_bounds__(TB)
+k_window_scatter64w(const uint64_t* __restrict__ packed, const uint64_t* __restrict__ inv,
+                    const uint64_t* __restrict__ endm, uint64_t t_begin, uint64_t t_end, int k,
+                    int keybits, int shard_bits, BatchSets bs,
+                    unsigned long long* __restrict__ cursor, K* __restrict__ out) {
+  window_scatter_body<K, Kc, S, TB, BATCH>(packed, inv, endm, t_begin, t_end, k, keybits,
+                                           shard_bits, bs, cursor, out);
+}
+
 template <typename K, typename Kc, int S, int TB, bool BATCH>
 __global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_window_scatter64(const uint64_t* __restrict__ packed, const uint64_t* __restrict__ inv,
@@ -1167,8 +1180,10 @@ __device__ bool occ64(unsigned long long c) { return c != 0; }
 
 // 64-bit keys: EMPTY (all ones) is never a canonical key for k <= 32, so a
 // slot is claimed by a 64-bit CAS of the key word itself; the count is then
-// added with an atomic add.
-template <int TB, int CMAX, int R>
+// added with an atomic add. FULL_FIRST: the first table is the full one (the
+// parts of a leaf that overflowed are rich in distinct keys: a half table
+// would mostly fill up and be retried).
+template <int TB, int CMAX, int R, bool FULL_FIRST>
 __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA, uint64_t* bufB,
                                                      uint32_t* __restrict__ tmp_cnt,
                                                      const Leaf* __restrict__ leaves,
@@ -1204,7 +1219,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
     // First try a table sized for half the records being distinct; if it
     // fills up, count the leaf again with a table large enough for all.
     const uint32_t Cfull = leaf_slots<TB, CMAX>(n, cmax_rt);
-    uint32_t Cn = leaf_slots<TB, CMAX>(n / 2, cmax_rt);
+    uint32_t Cn = FULL_FIRST ? Cfull : leaf_slots<TB, CMAX>(n / 2, cmax_rt);
     for (;;) {
     const uint32_t cmask = Cn - 1;
     const int slot_bits = 31 - __builtin_clz(Cn);
@@ -1309,7 +1324,9 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
 //   claimed through its 64-bit count word: 0 = empty, LOCK = being written;
 //   the claimer writes the key and then publishes the count; others seeing
 //   LOCK retry the same slot.
-template <typename K, int TB, int CMAX, int R, bool HI>
+// FULL_FIRST only names the launches that count refined parts apart (two-word
+// and wider keys always start with the full table).
+template <typename K, int TB, int CMAX, int R, bool HI, bool FULL_FIRST>
 __global__ void __launch_bounds__(TB) k_leaf_countw(int keybits, K* bufA, K* bufB,
                                                       uint32_t* __restrict__ tmp_cnt,
                                                       const Leaf* __restrict__ leaves,
@@ -1348,7 +1365,7 @@ __global__ void __launch_bounds__(TB) k_leaf_countw(int keybits, K* bufA, K* buf
     // keys of more than 64 bases are mostly distinct: their first table is the
     // full one (a half table would fill to its limit, with long probe runs,
     // before the retry)
-    uint32_t Cn = sizeof(K) >= 16 ? Cfull : leaf_slots<TB, CMAX>(n / 2, cmax_rt);
+    uint32_t Cn = (sizeof(K) >= 16 || FULL_FIRST) ? Cfull : leaf_slots<TB, CMAX>(n / 2, cmax_rt);
     for (;;) {
     const uint32_t cmask = Cn - 1;
     for (uint32_t i = threadIdx.x; i < Cn; i += TB) {
@@ -1839,8 +1856,9 @@ inline unsigned persistent(uint64_t max_n, unsigned cap) {
 
 int max_leaf_slots_log2(int words) { return words > 1 ? 11 : 12; }
 int max_shard_bits() { return kMaxShardBits; }
-int split_tile(int words) {
-  return (words == 4 ? kSplitTB256 : words == 2 ? kSplitTB128 : kSplitTB64) * kSplitR;
+int split_tile(int words, int records_per_thread) {
+  const int r = words == 1 && records_per_thread == 16 ? 16 : kSplitR;
+  return (words == 4 ? kSplitTB256 : words == 2 ? kSplitTB128 : kSplitTB64) * r;
 }
 
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v,
@@ -1866,6 +1884,9 @@ hipError_t launch_pack(const uint8_t* src, uint64_t n_bytes, const uint64_t* off
 #define KC_WINDOW_LAUNCH(KERNEL, K, KC, TB, BATCH, GRID)                                    \
   hipLaunchKernelGGL((KERNEL<K, KC, kWinStarts, TB, BATCH>), dim3(GRID), dim3(TB), 0, s, packed, \
                      inv, endm, t_begin, t_end, k, keybits, shard_bits, bs, ARG0, ARG1)
+#define KC_WINDOW_LAUNCH_S(KERNEL, K, KC, S, TB, BATCH, GRID)                                  \
+  hipLaunchKernelGGL((KERNEL<K, KC, S, TB, BATCH>), dim3(GRID), dim3(TB), 0, s, packed, inv, endm, \
+                     t_begin, t_end, k, keybits, shard_bits, bs, ARG0, ARG1)
 
 hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t* inv,
                               const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end, int k,
@@ -1896,7 +1917,24 @@ hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t*
 hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* inv,
                                  const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end,
                                  int k, int keybits, int shard_bits, const BatchSets* batch,
-                                 unsigned long long* cursor, void* out, hipStream_t s) {
+                                 unsigned long long* cursor, void* out, int starts_per_thread,
+                                 hipStream_t s) {
+  const BatchSets bs0 = batch ? *batch : BatchSets{nullptr, nullptr, 0};
+  if (words == 1 && starts_per_thread == 16) {
+    // byte_begin is a multiple of 32 (batch classes) or 0
+    constexpr int S = 16;
+    const uint64_t t_begin = byte_begin / S;
+    const uint64_t t_end = (byte_end + S - 1) / S;
+    const BatchSets bs = bs0;
+    const unsigned grid = grid_for(t_end - t_begin, kScatterTB64, 1u << 20);
+#define ARG0 cursor
+#define ARG1 (uint64_t*)out
+    if (batch) KC_WINDOW_LAUNCH_S(k_window_scatter64w, uint64_t, uint64_t, S, kScatterTB64, true, grid);
+    else KC_WINDOW_LAUNCH_S(k_window_scatter64w, uint64_t, uint64_t, S, kScatterTB64, false, grid);
+#undef ARG1
+#undef ARG0
+    return hipGetLastError();
+  }
   const uint64_t t_begin = byte_begin / kWinStarts;
   const uint64_t t_end = (byte_end + kWinStarts - 1) / kWinStarts;
   const BatchSets bs = batch ? *batch : BatchSets{nullptr, nullptr, 0};
@@ -1924,6 +1962,7 @@ hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64
   return hipGetLastError();
 }
 #undef KC_WINDOW_LAUNCH
+#undef KC_WINDOW_LAUNCH_S
 
 hipError_t launch_plan_shards(const unsigned long long* hist, const int* order, int shard_bits,
                               int keybits, uint64_t leaf_target, uint64_t leaf_attempt,
@@ -1968,8 +2007,15 @@ hipError_t launch_split_hist(int words, const void* src, const SplitItem* items,
 
 hipError_t launch_split_scatter(int words, const void* src, void* dst, const SplitItem* items,
                                 const DevState* st, uint64_t max_items, const SplitBin* bins,
-                                unsigned long long* cursor, hipStream_t s) {
+                                unsigned long long* cursor, int records_per_thread,
+                                hipStream_t s) {
   const unsigned grid = persistent(max_items, 2048);
+  if (words == 1 && records_per_thread == 16) {
+    // 16,384-record tiles: 128 KiB of LDS staging, one workgroup per CU
+    hipLaunchKernelGGL((k_split_scatter<uint64_t, kSplitTB64, 16>), dim3(grid), dim3(kSplitTB64),
+                       0, s, (const uint64_t*)src, (uint64_t*)dst, items, st, bins, cursor);
+    return hipGetLastError();
+  }
   if (words == 4)
     hipLaunchKernelGGL((k_split_scatter<u256, kSplitTB256, kSplitR>), dim3(grid),
                        dim3(kSplitTB256), 0, s, (const u256*)src, (u256*)dst, items, st, bins,
@@ -1992,7 +2038,8 @@ uint64_t small_leaf_max(int words) {
 
 hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
-                             uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode) {
+                             uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode,
+                             bool refine) {
   const bool wide = words == 2;
   const uint64_t small_max = mode == 1 ? 0 : small_leaf_max(words);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &st->n_large, (uint64_t)1, 0ull);
@@ -2004,26 +2051,32 @@ hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uin
     return hipGetLastError();
   }
   const unsigned gsmall = persistent(max_leaves, kSmallGrid);
-  if (wide)
-    if (keybits <= 126)
-      hipLaunchKernelGGL((k_leaf_countw<u128, 64, kSmallCmax128, 8, true>), dim3(gsmall), dim3(64), 0,
-                         s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
-                         __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max);
-    else
-      hipLaunchKernelGGL((k_leaf_countw<u128, 64, kSmallCmax128, 8, false>), dim3(gsmall), dim3(64), 0,
-                         s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
-                         __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max);
-  else
-    hipLaunchKernelGGL((k_leaf_count64<64, kSmallCmax64, 8>), dim3(gsmall), dim3(64), 0, s, keybits,
-                       (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
-                       __builtin_ctz(kSmallCmax64), (const uint32_t*)nullptr, small_max);
+#define KC_SMALLW(HI, FF)                                                                        \
+  hipLaunchKernelGGL((k_leaf_countw<u128, 64, kSmallCmax128, 8, HI, FF>), dim3(gsmall), dim3(64), \
+                     0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,        \
+                     __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max)
+#define KC_SMALL64(FF)                                                                           \
+  hipLaunchKernelGGL((k_leaf_count64<64, kSmallCmax64, 8, FF>), dim3(gsmall), dim3(64), 0, s,    \
+                     keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,      \
+                     __builtin_ctz(kSmallCmax64), (const uint32_t*)nullptr, small_max)
+  if (wide) {
+    if (keybits <= 126) {
+      if (refine) KC_SMALLW(true, true); else KC_SMALLW(true, false);
+    } else {
+      if (refine) KC_SMALLW(false, true); else KC_SMALLW(false, false);
+    }
+  } else {
+    if (refine) KC_SMALL64(true); else KC_SMALL64(false);
+  }
+#undef KC_SMALLW
+#undef KC_SMALL64
   return hipGetLastError();
 }
 
 hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
-                             hipStream_t s, int mode) {
+                             hipStream_t s, int mode, bool refine) {
   const bool wide = words == 2;
   const uint64_t small_max = small_leaf_max(words);
   const unsigned glarge = persistent(max_leaves, kPersistentGrid);
@@ -2042,23 +2095,30 @@ hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uin
                          leaves, st, d_out, large_list);
     return hipGetLastError();
   }
-  if (words == 4)
-    hipLaunchKernelGGL((k_leaf_countw<u256, kLeafTB, kLeafCmax256, 4, false>), dim3(glarge),
-                       dim3(kLeafTB), 0, s, keybits, (u256*)bufA, (u256*)bufB, tmp_cnt, leaves, st,
-                       d_out, slots_log2, large_list, small_max);
-  else if (wide)
-    if (keybits <= 126)
-      hipLaunchKernelGGL((k_leaf_countw<u128, kLeafTB, kLeafCmax128, 4, true>), dim3(glarge),
-                         dim3(kLeafTB), 0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves,
-                         st, d_out, slots_log2, large_list, small_max);
-    else
-      hipLaunchKernelGGL((k_leaf_countw<u128, kLeafTB, kLeafCmax128, 4, false>), dim3(glarge),
-                         dim3(kLeafTB), 0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves,
-                         st, d_out, slots_log2, large_list, small_max);
-  else
-    hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4>), dim3(glarge), dim3(kLeafTB), 0,
-                       s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
-                       slots_log2, large_list, small_max);
+#define KC_LARGEW(KT, CM, HI, FF)                                                               \
+  hipLaunchKernelGGL((k_leaf_countw<KT, kLeafTB, CM, 4, HI, FF>), dim3(glarge), dim3(kLeafTB), 0, \
+                     s, keybits, (KT*)bufA, (KT*)bufB, tmp_cnt, leaves, st, d_out, slots_log2,   \
+                     large_list, small_max)
+#define KC_LARGE64(FF)                                                                          \
+  hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4, FF>), dim3(glarge), dim3(kLeafTB), \
+                     0, s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out, \
+                     slots_log2, large_list, small_max)
+  if (words == 4) {
+    if (refine) KC_LARGEW(u256, kLeafCmax256, false, true);
+    else KC_LARGEW(u256, kLeafCmax256, false, false);
+  } else if (wide) {
+    if (keybits <= 126) {
+      if (refine) KC_LARGEW(u128, kLeafCmax128, true, true);
+      else KC_LARGEW(u128, kLeafCmax128, true, false);
+    } else {
+      if (refine) KC_LARGEW(u128, kLeafCmax128, false, true);
+      else KC_LARGEW(u128, kLeafCmax128, false, false);
+    }
+  } else {
+    if (refine) KC_LARGE64(true); else KC_LARGE64(false);
+  }
+#undef KC_LARGEW
+#undef KC_LARGE64
   return hipGetLastError();
 }
 

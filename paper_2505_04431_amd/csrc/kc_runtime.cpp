@@ -341,7 +341,8 @@ struct Timer {
 };
 
 enum { ST_PACK = 0, ST_HIST = 1, ST_SCATTER = 2, ST_SPLIT_HIST = 3, ST_SPLIT = 4,
-       ST_LEAF_SMALL = 5, ST_LEAF = 6, ST_OUT = 7, ST_CONCAT = 8, ST_CHECK = 9, ST_NONE = -1 };
+       ST_LEAF_SMALL = 5, ST_LEAF = 6, ST_OUT = 7, ST_CONCAT = 8, ST_CHECK = 9, ST_REFINE = 10,
+       ST_NONE = -1 };
 
 // Batch layout check: set s must own the bytes [set_byte_off[s], set_byte_off[s+1])
 // of the stream, i.e. offsets[set_first_read[s]] - offsets[0] == set_byte_off[s].
@@ -374,6 +375,7 @@ struct Call {
   uint64_t N = 0, off0 = 0;
   int words = 1;  // 64-bit words per key: 1, 2 or 4
   int keybits = 0, sb = 0, nb = 0, slots_log2 = 0;
+  int split_r = 8;
   size_t ksz = 8;
   uint64_t C = 0, T = 0, H = 0;
 };
@@ -498,8 +500,10 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
   }
   std::vector<Done> done;
   void* bufs[2] = {c.bufA.p, c.bufB.p};
-  constexpr int kRefineBits = 2;
-  const uint64_t tile = (uint64_t)kc::split_tile(q.words);
+  // three bits per level: 10 levels and 133.6 ms against 15 and 140.3 ms (two bits) and
+  // 8 and 134.0 ms (four) on 40,000,000 reads at k = 31
+  const int refine_bits = q.o.refine_bits > 0 ? q.o.refine_bits : 3;
+  const uint64_t tile = (uint64_t)kc::split_tile(q.words, q.split_r);
   int level = 0;
   while (!split.empty()) {
     ++level;
@@ -517,7 +521,7 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
       // few pieces by key, not by record count; pieces too rich in keys are
       // cut again at the next level.
       (void)n;
-      const int nbits = std::max(1, std::min(kRefineBits, remaining));
+      const int nbits = std::max(1, std::min(refine_bits, remaining));
       sbins[i] = kc::SplitBin{hoff, (uint32_t)(remaining - nbits), (uint32_t)nbits};
       hoff += 1ull << nbits;
       for (uint64_t a = b.begin; a < b.end; a += tile)
@@ -569,10 +573,10 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
       hipchk(kc::launch_split_scatter(q.words, bufs[src], bufs[1 - src],
                                       (kc::SplitItem*)c.items.p, dst_state, it_src.size(),
                                       (kc::SplitBin*)c.bins.p, (unsigned long long*)c.cursor2.p,
-                                      st),
+                                      q.split_r, st),
              "split scatter launch");
     }
-    tm.mark(ST_SPLIT);
+    tm.mark(ST_REFINE);
     // count every part
     const size_t na = next.size();
     std::vector<kc::Leaf> al(na);
@@ -586,13 +590,13 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
     upload_sync(&dst_state->n_leaves, &nlu, 8, st);
     hipchk(kc::launch_leaf_small(q.words, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
-                                 (uint32_t*)c.alarge.p, st, q.o.mode),
+                                 (uint32_t*)c.alarge.p, st, q.o.mode, true),
            "leaf count launch");
     hipchk(kc::launch_leaf_large(q.words, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
-                                 q.slots_log2, (uint32_t*)c.alarge.p, st, q.o.mode),
+                                 q.slots_log2, (uint32_t*)c.alarge.p, st, q.o.mode, true),
            "leaf count launch");
-    tm.mark(ST_LEAF);
+    tm.mark(ST_REFINE);
     uint32_t* hd = (uint32_t*)host_stage(c, na * 4 + 64);
     hipchk(hipMemcpyAsync(hd, c.adcnt.p, na * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
     hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -691,11 +695,24 @@ struct Pipe {
   uint64_t max_items = 0, max_leaves = 0;
   const kc::BatchSets* batch = nullptr;   // batch form (composite keys)
   int mode = 0;                           // leaf count: 0 hash tables, 1 sort
+  int scatter_s = 8, split_r = 8;         // LDS tile shape of the two scatters (one-word keys)
   const int* order = nullptr;             // device, owner-major shard order
 };
 
+// Tile shapes of the scatters from the options (0 = automatic).
+void tile_params(const kc_options& o, Pipe& p) {
+  for (int v : {o.scatter_tile, o.split_tile})
+    if (v != 0 && v != 8 && v != 16) fail(KC_E_INVAL, "scatter_tile / split_tile must be 0, 8 or 16");
+  // measured on 40,000,000 reads (k = 31 / 21): 16-record split tiles 26.3 / 28.6 ms against
+  // 29.0 / 31.5 ms; 1,000,000 reads: 0.56 against 0.61 ms. The owner scatter gains
+  // nothing from the larger tile (25.6 against 25.4 ms) and keeps two workgroups per CU.
+  p.scatter_s = o.scatter_tile ? o.scatter_tile : 8;
+  p.split_r = o.split_tile ? o.split_tile : 16;
+  if (p.words != 1) p.scatter_s = p.split_r = 8;
+}
+
 void pipe_bounds(Pipe& p) {
-  const uint64_t tile = (uint64_t)kc::split_tile(p.words);
+  const uint64_t tile = (uint64_t)kc::split_tile(p.words, p.split_r);
   const uint64_t nb = 1ull << p.sb;
   p.max_items = p.rec_bound / tile + nb + 1;
   p.max_leaves = std::min<uint64_t>(nb << kc::kSplitMaxBits, 2 * p.rec_bound / p.T + 2 * nb) + 1;
@@ -765,7 +782,7 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
          "window histogram launch");
   tm.mark(ST_HIST);
   hipchk(kc::launch_plan_shards((unsigned long long*)c.hist.p, p.order, p.sb, p.keybits, p.T, p.H,
-                                kc::split_tile(p.words), (unsigned long long*)c.sbegin.p,
+                                kc::split_tile(p.words, p.split_r), (unsigned long long*)c.sbegin.p,
                                 (unsigned long long*)c.cursor.p, (kc::SplitBin*)c.bins.p,
                                 (kc::SplitItem*)c.items.p, (unsigned long long*)c.itemoff.p,
                                 (unsigned long long*)c.subhist.p, p.max_leaves, p.max_items,
@@ -773,7 +790,8 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
          "plan_shards launch");
   hipchk(kc::launch_window_scatter(p.words, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
                                    (uint64_t*)c.endm.p, p.byte_begin, p.byte_end, p.k, p.keybits,
-                                   p.sb, p.batch, (unsigned long long*)c.cursor.p, c.bufA.p, st),
+                                   p.sb, p.batch, (unsigned long long*)c.cursor.p, c.bufA.p,
+                                   p.scatter_s, st),
          "owner scatter launch");
   tm.mark(ST_SCATTER);
   hipchk(kc::launch_split_hist(p.words, c.bufA.p, (kc::SplitItem*)c.items.p, dstate, p.max_items,
@@ -786,17 +804,17 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
          "plan_leaves launch");
   hipchk(kc::launch_split_scatter(p.words, c.bufA.p, c.bufB.p, (kc::SplitItem*)c.items.p, dstate,
                                   p.max_items, (kc::SplitBin*)c.bins.p,
-                                  (unsigned long long*)c.cursor2.p, st),
+                                  (unsigned long long*)c.cursor2.p, p.split_r, st),
          "split scatter launch");
   tm.mark(ST_SPLIT);
   hipchk(kc::launch_leaf_small(p.words, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
-                               (uint32_t*)c.large.p, st, p.mode),
+                               (uint32_t*)c.large.p, st, p.mode, false),
          "leaf count launch");
   tm.mark(ST_LEAF_SMALL);
   hipchk(kc::launch_leaf_large(p.words, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
-                               p.slots_log2, (uint32_t*)c.large.p, st, p.mode),
+                               p.slots_log2, (uint32_t*)c.large.p, st, p.mode, false),
          "leaf count launch");
   tm.mark(ST_LEAF);
   hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dstate, (unsigned long long*)c.bsum.p,
@@ -859,6 +877,7 @@ Pipe plain_pipe(uint64_t n_bytes, int k, int P, const kc_options& o) {
   p.byte_end = n_bytes;
   p.rec_bound = n_bytes;  // byte count: an upper bound of the window count
   p.mode = o.mode;
+  tile_params(o, p);
   pipe_bounds(p);
   return p;
 }
@@ -938,6 +957,8 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   table_params(q.o, q.words, q.slots_log2, q.C, q.T, q.H);
   q.sb = p0.sb;
   q.nb = 1 << q.sb;
+  q.split_r = p0.split_r;
+  if (q.o.refine_bits < 0 || q.o.refine_bits > 8) fail(KC_E_INVAL, "refine_bits must be in [0, 8]");
   Pipe p = p0;
   const uint64_t nchunks = packed_chunks(q.N);
   if (fixed) {
@@ -966,6 +987,9 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   kc::DevState ds = read_state(c, st);  // host sync 2 of 2 (3 with an output allocator)
   S.n_levels = 1;
   S.n_leaves = ds.n_leaves;
+  // the block-wide leaf kernel's own launch (refinement launches are counted apart)
+  S.large_records = ds.large_records;
+  S.large_distinct = ds.large_distinct;
   if (ds.overflow) {
     // some leaves had more distinct keys than their tables hold: partition
     // those further and count their parts
@@ -975,8 +999,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   }
   S.valid_windows = ds.W;
   S.distinct = ds.D;
-  S.large_records = ds.large_records;
-  S.large_distinct = ds.large_distinct;
+  S.refined_records = ds.large_records - S.large_records;
   if (ds.count_overflow) fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
   if (oa) {
     const int r = oa->fn(oa->user, ds.D, q.words, &out_keys, &out_counts);
@@ -1274,6 +1297,7 @@ int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_byt
       p.sb = std::max(1, std::min(p.sb, p.keybits));
       p.byte_begin = lo & ~31ull;
       p.byte_end = hi;
+      tile_params(b->o, p);
       pipe_bounds(p);
       pipeline_prepare(c, p);
       C.out_base = out_base;

@@ -39,7 +39,8 @@ class KcOptions(ctypes.Structure):
     _fields_ = [("shard_bits", ctypes.c_int), ("leaf_target", ctypes.c_int),
                 ("leaf_attempt", ctypes.c_int), ("table_slots_log2", ctypes.c_int),
                 ("check", ctypes.c_int), ("timing", ctypes.c_int), ("mode", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("scatter_tile", ctypes.c_int), ("split_tile", ctypes.c_int),
+                ("refine_bits", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class KcStats(ctypes.Structure):
@@ -47,7 +48,7 @@ class KcStats(ctypes.Structure):
                 ("distinct", ctypes.c_uint64), ("n_leaves", ctypes.c_uint64),
                 ("n_levels", ctypes.c_uint64), ("n_overflow", ctypes.c_uint64),
                 ("max_leaf_windows", ctypes.c_uint64), ("max_owner_windows", ctypes.c_uint64),
-                ("table_slots", ctypes.c_uint64), ("large_records", ctypes.c_uint64),
+                ("refined_records", ctypes.c_uint64), ("large_records", ctypes.c_uint64),
                 ("large_distinct", ctypes.c_uint64), ("ms_total", ctypes.c_double),
                 ("ms_stage", ctypes.c_double * 12)]
 
@@ -96,7 +97,7 @@ def measure_ceilings(table_bytes: int = 4 << 30, stream=None) -> dict:
 
 
 STAGES = ["pack", "window_hist", "owner_scatter", "split_hist", "split_scatter", "leaf_small",
-          "leaf_large", "out_offsets", "concat", "check", "unused10", "unused11"]
+          "leaf_large", "out_offsets", "concat", "check", "refine", "unused11"]
 
 
 class KcError(RuntimeError):

@@ -1,12 +1,14 @@
 """Merging two count results (kc_merge_counts) and counting in pieces
 (count_chunked). The defining property: the count of a read collection is the
 merge of the counts of any split of it, checked against the oracle's count of
-the whole collection; the merge itself is also checked against a numpy union
-of random sorted results (overlapping, disjoint, empty, 64- and 128-bit keys)."""
+the whole collection; the merge itself is also checked against the merge
+oracle (oracle/post.py) on random sorted results (overlapping, disjoint,
+empty, 64- and 128-bit keys)."""
 import numpy as np
 import pytest
 
 import oracle
+from oracle import post
 import paper_2505_04431_amd as kc
 import synth
 from gpu_util import assert_same, device, to_device
@@ -26,27 +28,6 @@ def _torch_counts(c):
 
 def _host(keys, counts):
     return keys.cpu().numpy().view(np.uint64), counts.cpu().numpy().view(np.uint32)
-
-
-def _union(ak, ac, bk, bc):
-    """Ordered union with counts added (numpy; 128-bit keys as (lo, hi) rows)."""
-    keys = np.concatenate([ak, bk])
-    cnt = np.concatenate([ac, bc]).astype(np.uint64)
-    if keys.ndim == 2:
-        order = np.lexsort((keys[:, 0], keys[:, 1]))
-        keys = keys[order]
-        first = np.ones(len(keys), bool)
-        first[1:] = (keys[1:] != keys[:-1]).any(axis=1)
-    else:
-        order = np.argsort(keys, kind="stable")
-        keys = keys[order]
-        first = np.ones(len(keys), bool)
-        first[1:] = keys[1:] != keys[:-1]
-    cnt = cnt[order]
-    grp = np.cumsum(first) - 1
-    sums = np.zeros(int(first.sum()), np.uint64)
-    np.add.at(sums, grp, cnt)
-    return keys[first], sums
 
 
 def _random_result(rng, n, words, universe):
@@ -83,8 +64,8 @@ def test_merge_matches_union(k, na, nb, universe):
         bk = bk.reshape(-1, 2)
     mk, mc = kc.merge_counts(_torch_keys(ak), _torch_counts(ac), _torch_keys(bk),
                              _torch_counts(bc), k)
-    wk, wc = _union(ak, ac, bk, bc)
-    assert_same(_host(mk, mc), (wk, wc.astype(np.uint32)), "merge na=%d nb=%d" % (na, nb))
+    wk, wc = post.merge(ak, ac, bk, bc, words)
+    assert_same(_host(mk, mc), (wk, wc), "merge na=%d nb=%d" % (na, nb))
 
 
 def test_merge_interleaved_and_identical():

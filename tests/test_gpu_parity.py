@@ -69,6 +69,11 @@ def test_p_invariance(P):
     dict(shard_bits=10, leaf_target=64, leaf_attempt=128),
     # split and unsplit shards whose leaves overflow: refinement from both buffers
     dict(shard_bits=6, leaf_target=30_000, leaf_attempt=40_000),
+    dict(shard_bits=6, leaf_target=30_000, leaf_attempt=40_000, refine_bits=7),
+    # 16,384-record LDS tiles in the owner and the split scatter
+    dict(scatter_tile=16, split_tile=16),
+    dict(scatter_tile=16, split_tile=8, shard_bits=10, leaf_target=64, leaf_attempt=128),
+    dict(scatter_tile=8, split_tile=16, table_slots_log2=11, leaf_target=300),
 ])
 def test_knob_invariance(opts):
     c = synth.make_config(2, frac=0.02)
