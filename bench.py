@@ -457,9 +457,9 @@ def served_leg(n_jobs: int, budget_gib: float, workers: int, load: float) -> dic
         for _ in inputs:
             arr.append(t)
             t += rng.expovariate(ld * capacity)
-        g0 = srv.stats()["arena_growths"]
+        g0 = srv.stats()["unplaced"]
         infos = run_pass(arr, hints)
-        growths.append(srv.stats()["arena_growths"] - g0)
+        growths.append(srv.stats()["unplaced"] - g0)
         slow.extend({"load": ld, "k": i["k"], "valid_windows": i["valid_windows"],
                      "worker": i["worker"], "wait_ms": round(i["t_start_ms"] - i["t_submit_ms"], 3),
                      "run_ms": round(i["t_end_ms"] - i["t_start_ms"], 3)}
@@ -476,7 +476,7 @@ def served_leg(n_jobs: int, budget_gib: float, workers: int, load: float) -> dic
     sweep = []
     for ld in (0.5, 0.9):  # the other arrival rates, beside the headline one
         _, lat_s, _, span_s, W_s, _, _, _ = poisson_pass(ld)
-        sweep.append({"load": ld, "value": round(W_s / span_s, 1), "arena_growths": growths[-1],
+        sweep.append({"load": ld, "value": round(W_s / span_s, 1), "unplaced_waits": growths[-1],
                       "latency_p50_ms": pct(lat_s, 0.5), "latency_p99_ms": pct(lat_s, 0.99)})
     rate = load * capacity
     infos, lat, wait, span, W, res_est, res_act, under = poisson_pass(load)
@@ -490,8 +490,8 @@ def served_leg(n_jobs: int, budget_gib: float, workers: int, load: float) -> dic
         "jobs_per_s": round(len(inputs) / span, 3),
         "capacity_jobs_per_s": round(capacity, 3), "arrival_rate_jobs_per_s": round(rate, 3),
         "cold_pass_ms": round(cold * 1e3, 1), "calibration_ms": round(cal_ms, 1),
-        "arena_growths": st["arena_growths"], "scratch_releases": st["scratch_releases"],
-        "arena_growths_in_pass": growths[-1],
+        "slab_bytes": st["slab_bytes"], "unplaced_waits": st["unplaced"],
+        "unplaced_waits_in_pass": growths[-1],
         "load": load, "latency_p50_ms": pct(lat, 0.5), "latency_p99_ms": pct(lat, 0.99),
         "wait_p50_ms": pct(wait, 0.5), "wait_p99_ms": pct(wait, 0.99),
         "peak_bytes": st["bytes_peak"],

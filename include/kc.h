@@ -198,18 +198,22 @@ int kc_batch_stats(const kc_batch* plan, kc_stats* out);
 void kc_batch_free(kc_batch* plan);
 
 /* ---- Served form: a request server counting many jobs side by side.
- * Each job is a plain count (same arguments and result as kc_count). A fixed
- * pool of worker threads, each with its own HIP stream and scratch memory,
- * takes jobs from one arrival-ordered queue; a worker starts the first queued
- * job whose device bytes fit in what the budget has left (the growth of the
- * worker's scratch plus a reservation for the result); a job passed over 8
- * times holds back the later ones until it fits. Results are allocated at
- * their exact size when the job's number of distinct keys is known and stay
- * on the device, owned by the server, until kc_server_release. A job's result
- * does not depend on what else runs beside it.
+ * Each job is a plain count (same arguments and result as kc_count). All of
+ * the server's device memory is one allocation made at creation (the budget,
+ * or what the device has free less a margin, whichever is smaller), from
+ * which each job's scratch block and each result are cut: serving maps and
+ * unmaps no device memory. A fixed pool of worker threads, each with its own
+ * HIP stream, takes jobs from one arrival-ordered queue; a worker starts the
+ * first queued job whose device bytes fit in what the budget has left (its
+ * scratch block plus a reservation for its result) and for whose scratch a
+ * free range exists; a job passed over 8 times holds back the later ones
+ * until it fits. Results are allocated at their exact size when the job's
+ * number of distinct keys is known and stay on the device, owned by the
+ * server, until kc_server_release. A job's result does not depend on what
+ * else runs beside it.
  *
- * kc_server_create: hbm_budget_bytes caps the device bytes the server
- *   accounts for (scratch, reservations, held results); n_workers in [1, 16]
+ * kc_server_create: hbm_budget_bytes caps the device bytes the server maps
+ *   and accounts for (scratch, reservations, held results); n_workers in [1, 16]
  *   (streams run concurrently); opt as in kc_count_ex (NULL = automatic),
  *   applied to every job. The calling thread's current device is used.
  * kc_server_submit: reads/offsets are DEVICE arrays as in kc_count that must
@@ -257,8 +261,9 @@ typedef struct kc_server_stats {
   uint64_t estimate_misses;        /* results larger than their reservation */
   uint64_t result_bytes_reserved;  /* sum over finished jobs */
   uint64_t result_bytes_actual;
-  uint64_t arena_growths;          /* jobs after which their worker's scratch arena grew */
-  uint64_t scratch_releases;       /* times an idle worker gave its arena back to fit a job */
+  uint64_t slab_bytes;             /* device memory the server mapped at creation */
+  uint64_t unplaced;               /* times a job that fit the budget waited because no free
+                                      range of that memory was large enough for its scratch */
   double latency_p50_ms, latency_p99_ms; /* completion - submission, completed jobs */
   double wait_p50_ms, wait_p99_ms;       /* start - submission */
   double busy_ms;                        /* first start to last completion */

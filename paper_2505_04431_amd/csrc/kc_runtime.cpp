@@ -54,6 +54,9 @@ static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 struct Carve {
   char* base;
   size_t cap, used;
+  bool static_host;                 // small host copies through the static host array
+  kc::Slab* spill;                  // if set: what does not fit is taken from here...
+  std::vector<void*>* spilled;      // ...and listed, to be returned when the call ends
 };
 thread_local Carve* g_carve = nullptr;
 alignas(64) char g_noalloc_host[kNoAllocHostBytes];
@@ -67,15 +70,28 @@ struct Fail;
 void carve(DevBuf& b, size_t bytes, const char* name) {
   Carve& cv = *g_carve;
   const size_t want = (std::max<size_t>(bytes, 256) + 255) & ~(size_t)255;
-  if (want > cv.cap - cv.used)
-    fail(KC_E_NOMEM, std::string("kc_count_noalloc: its fixed device scratch of ") +
-                         std::to_string(cv.cap >> 20) + " MiB is exhausted (" +
-                         std::to_string(bytes) + " more bytes for " + name + ")");
-  b.p = cv.base + cv.used;
-  b.cap = want;
   b.pooled = false;
   b.borrowed = true;
-  cv.used += want;
+  if (want <= cv.cap - cv.used) {
+    b.p = cv.base + cv.used;
+    b.cap = want;
+    cv.used += want;
+    return;
+  }
+  if (cv.spill) {
+    void* p = cv.spill->alloc(want, false);
+    if (!p)
+      fail(KC_E_NOMEM, std::string("server memory exhausted (") + std::to_string(bytes) +
+                           " bytes for " + name + " beyond the worker's arena block)");
+    cv.spilled->push_back(p);
+    b.p = p;
+    b.cap = want;
+    return;
+  }
+  b = DevBuf{};
+  fail(KC_E_NOMEM, std::string("kc_count_noalloc: its fixed device scratch of ") +
+                       std::to_string(cv.cap >> 20) + " MiB is exhausted (" +
+                       std::to_string(bytes) + " more bytes for " + name + ")");
 }
 
 struct Ctx {
@@ -243,7 +259,7 @@ void grow(DevBuf& b, size_t bytes, const char* name, hipStream_t st) {
 }
 
 void* host_stage(Ctx& c, size_t bytes) {
-  if (g_carve) {
+  if (g_carve && g_carve->static_host) {
     // allocation-free call: the static host array (held under g_noalloc_m)
     if (bytes > kNoAllocHostBytes)
       fail(KC_E_NOMEM, "kc_count_noalloc: " + std::to_string(bytes) +
@@ -1622,8 +1638,6 @@ hipError_t device_pool(int device, hipMemPool_t* pool) {
   return hipSuccess;
 }
 
-void release_thread_arena() { g_ctx.m.clear(); }
-
 void* thread_scratch(size_t bytes, hipStream_t st, std::string* err, int* code) noexcept {
   try {
     Ctx& c = context();
@@ -1664,55 +1678,193 @@ int count_with_alloc(const uint8_t* reads, const uint64_t* offsets, uint64_t n_r
   return r;
 }
 
-namespace {
-uint64_t growth_of(const Ctx* c, uint64_t n_bytes, int k, int P, const kc_options* opt) {
+uint64_t scratch_bytes(uint64_t n_bytes, int k, int P, const kc_options* opt) {
   if (n_bytes == 0 || k < 1 || k > 128 || P < 1) return 0;
   kc_options o;
   std::memset(&o, 0, sizeof(o));
   if (opt) o = *opt;
-  const Pipe p = plain_pipe(n_bytes, k, P, o);
-  uint64_t g = 0;
-  plain_needs(p, [&](DevBuf Ctx::*m, size_t bytes, const char*) {
-    const size_t have = c ? (c->*m).cap : 0;
-    // as grow() allocates: a buffer that grows again takes half its size more at least
-    if (have < std::max<size_t>(bytes, 1)) g += std::max(alloc_size(bytes), have + have / 2) - have;
-  });
-  return g;
-}
-}  // namespace
-
-uint64_t scratch_growth(uint64_t n_bytes, int k, int P, const kc_options* opt) {
   try {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return growth_of(nullptr, n_bytes, k, P, opt);
-    auto it = g_ctx.m.find(dev);
-    return growth_of(it == g_ctx.m.end() ? nullptr : it->second.get(), n_bytes, k, P, opt);
+    const Pipe p = plain_pipe(n_bytes, k, P, o);
+    uint64_t need = 0;
+    plain_needs(p, [&](DevBuf Ctx::*, size_t bytes, const char*) {
+      need += (std::max<size_t>(bytes, 256) + 255) & ~(size_t)255;
+    });
+    // room for the lists and tables of a refinement
+    return need + (16ull << 20) + need / 64;
   } catch (...) {
-    return growth_of(nullptr, n_bytes, k, P, opt);
+    return 0;
   }
 }
 
 void set_last_error(const std::string& msg) { g_err = msg; }
 
-uint64_t scratch_bytes(uint64_t n_bytes, int k, int P, const kc_options* opt) {
-  return growth_of(nullptr, n_bytes, k, P, opt);
+// ---- the server's slab
+
+Slab* Slab::create(uint64_t bytes, std::string* err) {
+  std::unique_ptr<Slab> s(new Slab());
+  bytes = (bytes + 255) & ~255ull;
+  void* p = nullptr;
+  const hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (err) *err = std::string("device allocation of the server slab (") + std::to_string(bytes) +
+                    " bytes) failed: " + hipGetErrorString(e);
+    return nullptr;
+  }
+  s->base_ = (char*)p;
+  s->cap_ = bytes;
+  s->free_[0] = bytes;
+  return s.release();
 }
 
-uint64_t arena_bytes() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  auto it = g_ctx.m.find(dev);
-  if (it == g_ctx.m.end() || !it->second) return 0;
-  const Ctx& c = *it->second;
-  const DevBuf* all[] = {&c.packed,  &c.inv,     &c.endm,   &c.bufA,    &c.bufB,   &c.tmpcnt,
-                         &c.hist,    &c.sbegin,  &c.cursor, &c.cursor2, &c.order,  &c.items,
-                         &c.bins,    &c.subhist, &c.leaves, &c.dcnt,    &c.outoff, &c.state,
-                         &c.large,   &c.bsum,    &c.itemoff, &c.rlist,  &c.rleaves, &c.rcount,
-                         &c.aleaves, &c.adcnt,   &c.alarge, &c.rparts,  &c.rcnt,   &c.leaves2,
-                         &c.dcnt2};
-  uint64_t t = 0;
-  for (const DevBuf* b : all) t += b->cap;
-  return t;
+Slab::~Slab() {
+  (void)hipDeviceSynchronize();  // nothing may still use the blocks
+  for (Pending& q : pending_) (void)hipEventDestroy(q.ev);
+  for (hipEvent_t e : events_) (void)hipEventDestroy(e);
+  if (base_) (void)hipFree(base_);
+}
+
+void Slab::insert_free(uint64_t off, uint64_t size) {
+  auto next = free_.lower_bound(off);
+  if (next != free_.end() && off + size == next->first) {  // merge with the range after
+    size += next->second;
+    next = free_.erase(next);
+  }
+  if (next != free_.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {  // merge with the range before
+      prev->second += size;
+      return;
+    }
+  }
+  free_[off] = size;
+}
+
+void Slab::reclaim(bool wait) {
+  size_t j = 0;
+  for (size_t i = 0; i < pending_.size(); ++i) {
+    Pending& q = pending_[i];
+    const hipError_t r = wait ? hipEventSynchronize(q.ev) : hipEventQuery(q.ev);
+    if (r == hipSuccess) {
+      insert_free(q.off, q.size);
+      events_.push_back(q.ev);
+    } else {
+      if (r != hipErrorNotReady) (void)hipGetLastError();
+      pending_[j++] = q;
+    }
+  }
+  pending_.resize(j);
+}
+
+void* Slab::alloc(uint64_t bytes, bool high) {
+  const uint64_t want = (std::max<uint64_t>(bytes, 256) + 255) & ~255ull;
+  std::lock_guard<std::mutex> lk(m_);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    reclaim(attempt == 1);
+    // best fit (the smallest free range that holds it; the lowest or highest
+    // of equal ones), cut from its low or high end
+    auto best = free_.end();
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < want) continue;
+      if (best == free_.end() || it->second < best->second ||
+          (it->second == best->second && high)) best = it;
+    }
+    if (best == free_.end()) continue;
+    const uint64_t off = high ? best->first + best->second - want : best->first;
+    const uint64_t rest = best->second - want;
+    const uint64_t at = best->first;
+    free_.erase(best);
+    if (rest) {
+      if (high) free_[at] = rest;
+      else free_[off + want] = rest;
+    }
+    live_[off] = want;
+    return base_ + off;
+  }
+  return nullptr;
+}
+
+void Slab::free(void* p, hipStream_t st) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(m_);
+  const uint64_t off = (uint64_t)((char*)p - base_);
+  auto it = live_.find(off);
+  if (it == live_.end()) return;
+  const uint64_t size = it->second;
+  live_.erase(it);
+  hipEvent_t ev = nullptr;
+  if (!events_.empty()) {
+    ev = events_.back();
+    events_.pop_back();
+  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    ev = nullptr;
+  }
+  if (ev && hipEventRecord(ev, st) == hipSuccess) {
+    pending_.push_back(Pending{off, size, ev});
+    return;
+  }
+  // no event: wait for the stream, then the block is free
+  (void)hipGetLastError();
+  (void)hipStreamSynchronize(st);
+  if (ev) events_.push_back(ev);
+  insert_free(off, size);
+}
+
+// ---- a server worker's count context
+
+}  // namespace kc
+
+struct kc::WorkerArena {
+  Ctx ctx;
+};
+
+namespace kc {
+
+WorkerArena* worker_arena_create(int device) {
+  try {
+    WorkerArena* wa = new WorkerArena();
+    wa->ctx.device = device;
+    return wa;
+  } catch (...) {
+    return nullptr;
+  }
+}
+
+void worker_arena_destroy(WorkerArena* wa) {
+  try {
+    delete wa;
+  } catch (...) {
+  }
+}
+
+int count_in_block(WorkerArena* wa, void* block, uint64_t block_bytes, Slab* spill,
+                   const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int P,
+                   const kc_options* opt, hipStream_t st, const OutAlloc& oa, uint64_t* n_out,
+                   kc_stats* stats, std::string* err) {
+  std::vector<void*> spilled;
+  Carve cv{(char*)block, (size_t)block_bytes, 0, false, spill, &spilled};
+  Ctx& c = wa->ctx;
+  // every buffer is carved afresh from the block for this job
+  DevBuf* all[] = {&c.packed,  &c.inv,     &c.endm,   &c.bufA,    &c.bufB,   &c.tmpcnt,
+                   &c.hist,    &c.sbegin,  &c.cursor, &c.cursor2, &c.order,  &c.items,
+                   &c.bins,    &c.subhist, &c.leaves, &c.dcnt,    &c.outoff, &c.state,
+                   &c.large,   &c.bsum,    &c.itemoff, &c.rlist,  &c.rleaves, &c.rcount,
+                   &c.aleaves, &c.adcnt,   &c.alarge, &c.rparts,  &c.rcnt,   &c.leaves2,
+                   &c.dcnt2,   &c.post};
+  for (DevBuf* b : all) *b = DevBuf{};
+  c.order_P = c.order_sb = -1;
+  g_carve = &cv;
+  const int r = guarded([&] {
+    return count_impl(reads, offsets, n_reads, k, P, nullptr, nullptr, 0, n_out, opt, st, &oa,
+                      &c);
+  });
+  g_carve = nullptr;
+  for (DevBuf* b : all) *b = DevBuf{};
+  for (void* p : spilled) spill->free(p, st);
+  if (r == KC_OK && stats) *stats = g_stats;
+  if (r != KC_OK && err) *err = g_err;
+  return r;
 }
 
 }  // namespace kc
@@ -1837,7 +1989,7 @@ int kc_count_noalloc(const uint8_t* reads, const uint64_t* offsets, uint64_t n_r
     hipchk(hipGetDevice(&dev), "hipGetDevice");
     char* base = noalloc_scratch(dev);
     std::lock_guard<std::mutex> lk(g_noalloc_m);
-    Carve cv{base, kNoAllocScratchBytes, 0};
+    Carve cv{base, kNoAllocScratchBytes, 0, true, nullptr, nullptr};
     const CarveScope scope(&cv);
     Ctx c;
     c.device = dev;

@@ -17,6 +17,9 @@ struct QueuedJob {
   int k = 0, P = 0;
   uint64_t result_est = 0;  // bytes reserved for its result until the true size is known
   uint32_t bypassed = 0;    // times a later job was started before it
+  // the server's memory epoch at which no free range could hold the job's
+  // scratch block; it is not tried again before the epoch changes
+  uint64_t unplaced_epoch = ~0ull;
 };
 
 // Device bytes the server has promised: scratch arenas, results held on the

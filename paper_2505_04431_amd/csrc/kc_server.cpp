@@ -1,17 +1,17 @@
 // Request server behind the kc_server_* entry points of include/kc.h.
 //
 // Jobs are plain counts submitted with device-resident inputs. A fixed pool
-// of worker threads, each with its own non-blocking HIP stream and its own
-// scratch arena, takes jobs from one queue: a worker starts the first queued
-// job whose device bytes (growth of the worker's arena plus a reservation for
-// the result) fit under the budget (policy in kc_sched.h), so jobs of
-// different sizes run side by side on the device and a finished job's slot is
-// refilled at once. Results are allocated at their exact size once the
-// number of distinct keys is known and stay on the device until released.
-// Results and arena growth come from the library's stream-ordered pool, which
-// keeps what is freed into it: a device free waits for every stream of the
-// device, so handing memory back to the driver while jobs run stalls all
-// workers.
+// of worker threads, each with its own non-blocking HIP stream, takes jobs
+// from one queue: a worker starts the first queued job whose device bytes
+// (its scratch block plus a reservation for its result) fit under the budget
+// (policy in kc_sched.h), so jobs of different sizes run side by side on the
+// device and a finished job's slot is refilled at once. Results are allocated
+// at their exact size once the number of distinct keys is known and stay on
+// the device until released. All of the server's device memory is one slab
+// mapped when it is created; each job's scratch block (returned when the job
+// ends) and each result are cut from it, so serving maps and unmaps nothing
+// (a device free waits for every stream of the device, and mapping fresh
+// memory while jobs ran stalled every worker).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,11 +55,11 @@ struct Job {
   Clock::time_point t_submit, t_start, t_end;
 };
 
-// Output allocation of one running job (stream-ordered on the worker's stream).
+// Output allocation of one running job: one block of the server's slab
+// (keys, then counts), cut from the slab's high end.
 struct JobAlloc {
   Job* job;
-  hipStream_t st;
-  hipMemPool_t pool;
+  kc::Slab* slab;
 };
 
 int alloc_result(void* user, uint64_t distinct, int key_words, uint64_t** keys, uint32_t** counts) {
@@ -67,31 +67,14 @@ int alloc_result(void* user, uint64_t distinct, int key_words, uint64_t** keys, 
   *keys = nullptr;
   *counts = nullptr;
   if (distinct == 0) return KC_OK;
-  void* pk = nullptr;
-  void* pc = nullptr;
-  // from the library pool, which keeps released results for later ones; when
-  // the device is short, the pool's idle blocks are returned and it is tried
-  // once more
-  const uint64_t kbytes = distinct * 8 * (uint64_t)key_words;
-  for (int attempt = 0;; ++attempt) {
-    if (hipMallocFromPoolAsync(&pk, kbytes, a->pool, a->st) == hipSuccess) {
-      if (hipMallocFromPoolAsync(&pc, distinct * 4, a->pool, a->st) == hipSuccess) break;
-      (void)hipGetLastError();
-      (void)hipFreeAsync(pk, a->st);
-      pk = nullptr;
-    } else {
-      (void)hipGetLastError();
-    }
-    if (attempt == 1) return KC_E_NOMEM;
-    int dev = 0;
-    (void)hipStreamSynchronize(a->st);
-    if (hipGetDevice(&dev) == hipSuccess) kc::trim_device_pool(dev);
-  }
-  a->job->keys = (uint64_t*)pk;
-  a->job->counts = (uint32_t*)pc;
-  a->job->result_bytes = distinct * (8 * (uint64_t)key_words + 4);
-  *keys = (uint64_t*)pk;
-  *counts = (uint32_t*)pc;
+  const uint64_t kbytes = (distinct * 8 * (uint64_t)key_words + 255) & ~255ull;
+  char* p = (char*)a->slab->alloc(kbytes + distinct * 4, true);
+  if (!p) return KC_E_NOMEM;
+  a->job->keys = (uint64_t*)p;
+  a->job->counts = (uint32_t*)(p + kbytes);
+  a->job->result_bytes = distinct * (8 * (uint64_t)key_words + 4);  // (plus < 256 bytes of alignment)
+  *keys = a->job->keys;
+  *counts = a->job->counts;
   return KC_OK;
 }
 
@@ -122,32 +105,35 @@ struct kc_server {
   std::deque<kc::QueuedJob> queue;
   std::map<uint64_t, std::unique_ptr<Job>> jobs;
   kc::Ledger ledger;
-  std::vector<uint64_t> arena;  // bytes held by each worker's scratch arena
+  std::vector<kc::WorkerArena*> wctx;  // each worker's count context
+  kc::Slab* slab = nullptr;     // all device memory of the server
+  uint64_t epoch = 0;           // advanced whenever slab memory is given back
   uint64_t next_id = 1;
   bool stop = false;
   uint64_t submitted = 0, completed = 0, failed = 0, running = 0, windows = 0;
-  uint64_t est_misses = 0, reserved_total = 0, actual_total = 0, growths = 0, releases = 0;
+  uint64_t est_misses = 0, reserved_total = 0, actual_total = 0, unplaced = 0;
   bool any_start = false;
   Clock::time_point first_start, last_end;
   std::vector<double> lat_ms, wait_ms;
 
   std::mutex submit_m;  // the control stream and its pinned staging
   hipStream_t ctl = nullptr;
-  hipMemPool_t pool = nullptr;  // results and worker arenas
   uint64_t* pinned = nullptr;
   std::vector<hipStream_t> streams;
   std::vector<std::thread> threads;
 
   void worker_main(int w);
   void finish_locked(Job* j, int w, uint64_t new_arena);
+  // Bytes a queued job would add to the ledger if started now: its scratch
+  // block and its result reservation; more than any budget while no free
+  // range of the slab could hold its block and no memory has come back since.
+  uint64_t need_of(const kc::QueuedJob& q) const {
+    if (q.unplaced_epoch == epoch) return ~0ull;
+    return kc::scratch_bytes(q.n_bytes, q.k, q.P, &opt) + q.result_est;
+  }
   bool stalled_locked() const {
-    uint64_t held = 0;
-    for (uint64_t a : arena) held += a;
-    return kc::stalled_on_results(queue, ledger.free_bytes(), max_bypass, running, held,
-                                  [&](const kc::QueuedJob& q) {
-                                    return kc::scratch_bytes(q.n_bytes, q.k, q.P, &opt) +
-                                           q.result_est;
-                                  });
+    return kc::stalled_on_results(queue, ledger.free_bytes(), max_bypass, running, 0,
+                                  [&](const kc::QueuedJob& q) { return need_of(q); });
   }
 };
 
@@ -156,20 +142,32 @@ void kc_server::worker_main(int w) {
   const hipStream_t st = streams[w];
   for (;;) {
     Job* job = nullptr;
+    void* block = nullptr;
+    uint64_t block_bytes = 0;
     {
       std::unique_lock<std::mutex> lk(m);
       for (;;) {
         if (stop) break;
         const long idx = kc::pick_job(queue, ledger.free_bytes(), max_bypass,
-                                      [&](const kc::QueuedJob& q) {
-                                        return kc::scratch_growth(q.n_bytes, q.k, q.P, &opt) +
-                                               q.result_est;
-                                      });
+                                      [&](const kc::QueuedJob& q) { return need_of(q); });
         if (idx >= 0) {
-          const kc::QueuedJob q = queue[(size_t)idx];
+          kc::QueuedJob& q = queue[(size_t)idx];
+          // the job's scratch: one block of the slab, for this job only
+          block_bytes = kc::scratch_bytes(q.n_bytes, q.k, q.P, &opt);
+          block = block_bytes ? slab->alloc(block_bytes, false) : nullptr;
+          if (block_bytes && !block) {
+            // the budget has room but no free range is large enough: the job
+            // stays queued until memory comes back (a job ends or a result is
+            // released)
+            q.unplaced_epoch = epoch;
+            ++unplaced;
+            cv_done.notify_all();  // a waiter may now find the queue stalled
+            continue;
+          }
+          const kc::QueuedJob qj = q;
           queue.erase(queue.begin() + idx);
-          job = jobs.at(q.id).get();
-          job->reserved = kc::scratch_growth(q.n_bytes, q.k, q.P, &opt) + q.result_est;
+          job = jobs.at(qj.id).get();
+          job->reserved = block_bytes + qj.result_est;
           ledger.add(job->reserved);
           job->state = KC_JOB_RUNNING;
           job->worker = w;
@@ -181,60 +179,38 @@ void kc_server::worker_main(int w) {
           ++running;
           break;
         }
-        if (!queue.empty() && arena[w] > 0 && running == 0) {
-          // nothing fits while every worker is idle: give this worker's
-          // scratch back so that the jobs' own needs can fit. Its blocks stay
-          // in the library pool for the next allocations (handing them to the
-          // driver would make every stream of the device wait)
-          lk.unlock();
-          kc::release_thread_arena();
-          lk.lock();
-          ledger.sub(arena[w]);
-          arena[w] = 0;
-          ++releases;
-          cv_work.notify_all();
-          cv_done.notify_all();  // a waiter may now find the queue stalled on held results
-          continue;
-        }
         cv_work.wait(lk);
       }
       if (!job) return;
     }
-    JobAlloc a{job, st, pool};
+    JobAlloc a{job, slab};
     kc::OutAlloc oa{alloc_result, &a};
     kc_stats S;
     std::memset(&S, 0, sizeof(S));
     uint64_t n_out = 0;
     std::string err;
-    const int r = kc::count_with_alloc(job->reads, job->offsets, job->n_reads, job->k, job->P,
-                                       &opt, st, oa, &n_out, &S, &err);
+    int r = kc::count_in_block(wctx[w], block, block_bytes, slab, job->reads, job->offsets,
+                               job->n_reads, job->k, job->P, &opt, st, oa, &n_out, &S, &err);
     if (r != KC_OK && job->keys) {
-      (void)hipFreeAsync(job->keys, st);
-      (void)hipFreeAsync(job->counts, st);
-      (void)hipStreamSynchronize(st);
+      slab->free(job->keys, st);
       job->keys = nullptr;
       job->counts = nullptr;
       job->result_bytes = 0;
     }
-    const uint64_t new_arena = kc::arena_bytes();
+    if (block) slab->free(block, st);  // the count has synchronized its stream
     std::lock_guard<std::mutex> lk(m);
     job->status = r;
     job->err = err;
     job->n_out = r == KC_OK ? n_out : 0;
     job->windows = r == KC_OK ? S.valid_windows : 0;
-    finish_locked(job, w, new_arena);
+    finish_locked(job, w, 0);
   }
 }
 
-void kc_server::finish_locked(Job* j, int w, uint64_t new_arena) {
-  ledger.sub(j->reserved);
+void kc_server::finish_locked(Job* j, int, uint64_t) {
+  ledger.sub(j->reserved);  // its scratch block and reservation
   j->reserved = 0;
-  if (new_arena > arena[w]) ++growths;
-  if (new_arena >= arena[w])
-    ledger.add(new_arena - arena[w]);
-  else
-    ledger.sub(arena[w] - new_arena);
-  arena[w] = new_arena;
+  ++epoch;                  // its block is back in the slab
   ledger.add(j->result_bytes);
   reserved_total += j->result_est;
   actual_total += j->result_bytes;
@@ -289,18 +265,15 @@ void destroy_server(kc_server* s) {
   for (std::thread& t : s->threads)
     if (t.joinable()) t.join();
   (void)hipSetDevice(s->device);
-  for (auto& kv : s->jobs) {
-    Job* j = kv.second.get();
-    if (j->keys) (void)hipFreeAsync(j->keys, s->ctl);
-    if (j->counts) (void)hipFreeAsync(j->counts, s->ctl);
-  }
-  if (s->ctl) (void)hipStreamSynchronize(s->ctl);
+  for (hipStream_t st : s->streams)
+    if (st) (void)hipStreamSynchronize(st);
+  for (kc::WorkerArena* wa : s->wctx) kc::worker_arena_destroy(wa);
   for (hipStream_t st : s->streams)
     if (st) (void)hipStreamDestroy(st);
   if (s->ctl) (void)hipStreamDestroy(s->ctl);
   if (s->pinned) (void)hipHostFree(s->pinned);
-  // the results and the workers' arenas (freed as their threads ended)
-  if (s->pool) kc::trim_device_pool(s->device);
+  // the results and the workers' blocks go with the slab
+  delete s->slab;
   delete s;
 }
 
@@ -319,13 +292,30 @@ int kc_server_create(uint64_t hbm_budget_bytes, int n_workers, const kc_options*
     std::unique_ptr<kc_server> s(new kc_server());
     if (hipGetDevice(&s->device) != hipSuccess) return set_err(KC_E_DEVICE, "hipGetDevice failed");
     if (opt) s->opt = *opt;
-    s->ledger.budget = hbm_budget_bytes;
     s->n_workers = n_workers;
     s->t0 = Clock::now();
-    s->arena.assign(n_workers, 0);
-    if (kc::device_pool(s->device, &s->pool) != hipSuccess) {
+    // all device memory of the server, mapped now: the budget, or what the
+    // device has free less a margin for the rest of the process
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
       (void)hipGetLastError();
-      return set_err(KC_E_DEVICE, "device memory pool creation failed");
+      return set_err(KC_E_DEVICE, "hipMemGetInfo failed");
+    }
+    const uint64_t margin = std::max<uint64_t>(2ull << 30, total_b / 50);
+    const uint64_t room = free_b > margin ? free_b - margin : 0;
+    const uint64_t slab_bytes = std::min<uint64_t>(hbm_budget_bytes, room);
+    std::string err;
+    if (slab_bytes < 4096 || !(s->slab = kc::Slab::create(slab_bytes, &err)))
+      return set_err(KC_E_NOMEM, err.empty() ? "too little free device memory for a server"
+                                             : err);
+    s->ledger.budget = s->slab->capacity();
+    for (int w = 0; w < n_workers; ++w) {
+      s->wctx.push_back(kc::worker_arena_create(s->device));
+      if (!s->wctx.back()) {
+        kc_server* raw = s.release();
+        destroy_server(raw);
+        return set_err(KC_E_NOMEM, "worker context creation failed");
+      }
     }
     if (hipStreamCreateWithFlags(&s->ctl, hipStreamNonBlocking) != hipSuccess ||
         hipHostMalloc((void**)&s->pinned, 64, hipHostMallocDefault) != hipSuccess) {
@@ -535,14 +525,14 @@ int kc_server_release(kc_server* s, uint64_t job_id) {
     Job* j = it->second.get();
     if (j->state != KC_JOB_DONE && j->state != KC_JOB_FAILED)
       return set_err(KC_E_INVAL, "job has not finished");
-    if (j->keys || j->counts) {
+    if (j->keys) {
+      // the job's stream finished before it was marked done: nothing uses it
       std::lock_guard<std::mutex> lk2(s->submit_m);
       (void)hipSetDevice(s->device);
-      if (j->keys) (void)hipFreeAsync(j->keys, s->ctl);
-      if (j->counts) (void)hipFreeAsync(j->counts, s->ctl);
-      (void)hipStreamSynchronize(s->ctl);
+      s->slab->free(j->keys, s->ctl);
     }
     s->ledger.sub(j->result_bytes);
+    if (j->result_bytes) ++s->epoch;  // its block is back in the slab
     s->jobs.erase(it);
     s->cv_work.notify_all();
     return KC_OK;
@@ -566,8 +556,8 @@ int kc_server_stats(kc_server* s, kc_serve_stats* out) {
     out->estimate_misses = s->est_misses;
     out->result_bytes_reserved = s->reserved_total;
     out->result_bytes_actual = s->actual_total;
-    out->arena_growths = s->growths;
-    out->scratch_releases = s->releases;
+    out->slab_bytes = s->slab->capacity();
+    out->unplaced = s->unplaced;
     out->latency_p50_ms = percentile(s->lat_ms, 0.50);
     out->latency_p99_ms = percentile(s->lat_ms, 0.99);
     out->wait_p50_ms = percentile(s->wait_ms, 0.50);

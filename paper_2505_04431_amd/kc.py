@@ -66,8 +66,8 @@ class KcServeStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("submitted", "completed", "failed", "queued", "running", "valid_windows",
                  "budget", "bytes_in_use", "bytes_peak", "estimate_misses",
-                 "result_bytes_reserved", "result_bytes_actual", "arena_growths",
-                 "scratch_releases")] + \
+                 "result_bytes_reserved", "result_bytes_actual", "slab_bytes",
+                 "unplaced")] + \
                [(n, ctypes.c_double) for n in
                 ("latency_p50_ms", "latency_p99_ms", "wait_p50_ms", "wait_p99_ms", "busy_ms")]
 

@@ -4,13 +4,13 @@
 //   budget workers max_bypass n
 //   then n lines: arrival duration scratch result_est result_actual hold
 // and prints one line per job: id start end worker, then "peak <bytes>".
-// A worker keeps its scratch (grows to the largest job it ran) and gives it
-// back only when every worker is idle and no queued job fits, as the server
-// does; a result is held from the job's end until end + hold. A negative hold
-// models a client that waits for the jobs in submission order and releases
-// each result once it has waited for it: when the server reports that the
-// queue is stalled on held results (kc_server_wait's KC_E_NOMEM), that client
-// releases every result it holds. The last line is "stalls <reports>".
+// A job holds its scratch only while it runs (the server cuts one block per
+// job from its slab and takes it back when the job ends); a result is held
+// from the job's end until end + hold. A negative hold models a client that
+// waits for the jobs in submission order and releases each result once it
+// has waited for it: when the server reports that the queue is stalled on
+// held results (kc_server_wait's KC_E_NOMEM), that client releases every
+// result it holds. The last line is "stalls <reports>".
 #include <cstdio>
 #include <deque>
 #include <map>
@@ -41,7 +41,6 @@ int main() {
   kc::Ledger L;
   L.budget = budget;
   std::deque<kc::QueuedJob> q;
-  std::vector<uint64_t> arena(workers, 0);
   std::vector<int> busy(workers, -1);
   std::multimap<double, int> ends, releases;  // time -> job
   size_t next_arrival = 0;
@@ -60,10 +59,8 @@ int main() {
     if (t == 1e300) {
       // nothing pending but queued jobs: the server reports the stall to a
       // client waiting on one of them; the client releases what it holds
-      uint64_t held_arena = 0;
-      for (uint64_t a : arena) held_arena += a;
       const bool stalled = kc::stalled_on_results(
-          q, L.free_bytes(), max_bypass, 0, held_arena,
+          q, L.free_bytes(), max_bypass, 0, 0,
           [&](const kc::QueuedJob& x) { return jobs[x.id].scratch + x.result_est; });
       if (!stalled || held.empty()) {
         std::printf("stuck %zu\n", q.size());
@@ -85,12 +82,8 @@ int main() {
       SimJob& j = jobs[id];
       j.end = now;
       const int w = j.worker;
-      L.sub(reserved_running[w]);
+      L.sub(reserved_running[w]);  // its scratch and its reservation
       reserved_running[w] = 0;
-      if (j.scratch > arena[w]) {
-        L.add(j.scratch - arena[w]);
-        arena[w] = j.scratch;
-      }
       L.add(j.actual);
       if (j.hold >= 0) releases.emplace(now + j.hold, id);
       else held.push_back(id);
@@ -132,14 +125,13 @@ int main() {
       for (int w = 0; w < workers; ++w) {
         if (busy[w] >= 0) continue;
         const long i = kc::pick_job(q, L.free_bytes(), max_bypass, [&](const kc::QueuedJob& x) {
-          const SimJob& j = jobs[x.id];
-          return (j.scratch > arena[w] ? j.scratch - arena[w] : 0) + x.result_est;
+          return jobs[x.id].scratch + x.result_est;
         });
         if (i >= 0) {
           const int id = (int)q[(size_t)i].id;
           q.erase(q.begin() + i);
           SimJob& j = jobs[id];
-          reserved_running[w] = (j.scratch > arena[w] ? j.scratch - arena[w] : 0) + j.est;
+          reserved_running[w] = j.scratch + j.est;
           L.add(reserved_running[w]);
           j.start = now;
           j.worker = w;
@@ -147,10 +139,6 @@ int main() {
           ends.emplace(now + j.duration, id);
           progress = true;
           ++running;
-        } else if (!q.empty() && arena[w] > 0 && running == 0) {
-          L.sub(arena[w]);
-          arena[w] = 0;
-          progress = true;
         }
       }
     }

@@ -96,9 +96,10 @@ def test_bypass_bound(sim):
     assert peak <= 12_000
 
 
-def test_idle_workers_give_back_scratch(sim):
-    # four workers each grow a large scratch; then one job needs almost the
-    # whole budget: it can only start once the idle workers trimmed theirs
+def test_scratch_is_held_only_while_running(sim):
+    # four jobs with large scratch run side by side; then one job needs almost
+    # the whole budget: it starts as soon as it arrives, since finished jobs
+    # hold no scratch
     jobs = [(0.0 + 0.01 * i, 1.0, 3_000, 10, 10, 0.0) for i in range(4)]
     jobs.append((5.0, 1.0, 11_500, 100, 100, 0.0))
     res, peak = sim(12_000, 4, 8, jobs)
@@ -124,8 +125,7 @@ def test_held_results_beyond_the_budget_are_reported_not_waited_for(sim):
     result after its wait. Job 5 needs much more scratch than the others, so
     later small jobs pass it and finish; their results, held because the
     client is waiting for job 5, fill the budget. Without the stall report the
-    queue would wait for ever (every worker idle, all scratch given back, job
-    5 not admitted). With it the client releases what it holds and every job
+    queue would wait for ever (every worker idle, job 5 not admitted). With it the client releases what it holds and every job
     finishes; the ledger never passes the budget."""
     jobs = []
     for i in range(30):
