@@ -61,7 +61,7 @@ def stage_bytes(st: dict, k: int) -> dict:
 
 
 KERNEL_NAMES = {  # rocprofv3 names of the kernel behind each single-kernel stage
-    ("leaf_large", 1): "k_leaf_count64<512, 4096, 4, false>",
+    ("leaf_large", 1): "k_leaf_count64<512, 4096, 4, false, false>",
     ("leaf_large", 2): "k_leaf_countw<unsigned __int128, 512, 2048, 4, true, false>",
     ("split_scatter", 1): "k_split_scatter<unsigned long, 1024, 16>",
     ("owner_scatter", 1): "k_window_scatter64<unsigned long, unsigned long, 8, 1024, false>",

@@ -8,11 +8,11 @@
  *     is A/C/G/T (either case); windows touching any other byte ('N', IUPAC
  *     codes, ...) are skipped;
  *   - bases are coded A=0, C=1, G=2, T=3 with the first base most
- *     significant (Encode / GetFirstKmer of Algorithm 1), masked to 2k bits;
+ *     significant (as Algorithm 1 builds a k-mer), masked to 2k bits;
  *   - the counted key is the canonical k-mer min(kmer, reverse complement)
  *     as an unsigned 2k-bit integer;
  *   - the result is every distinct key with its number of valid windows,
- *     sorted by key ascending ("ordered array of {k-mer, count}", Algorithm 1),
+ *     sorted by key ascending (the result of Algorithm 1),
  *     from count 1 up (Section VI counts from 1 to the maximum).
  * The P owner partitions stand in for the paper's P processing elements
  * (OwnerPE, Algorithms 2-4); the result does not depend on P.
@@ -68,8 +68,9 @@ typedef struct kc_options {
   int timing;          /* 1 = record per-stage times (kc_last_stats) */
   int mode;            /* how each leaf partition is counted: 0 = LDS open-addressing
                           table, then a sort of its distinct keys; 1 = sort of its
-                          records and run-length accumulation (Algorithm 1's Sort +
-                          Accumulate, as each owner does in Algorithm 3). Same result.
+                          records and run-length accumulation (the counting by
+                          sorting of Algorithm 1, as each owner does in Algorithm 3).
+                          Same result.
                           The batched form takes 0 only (and k <= 32). */
   int scatter_tile;    /* window starts per thread of the owner scatter for keys of
                           one word: 8 (8,192-record LDS tiles, two workgroups per CU;
@@ -79,7 +80,13 @@ typedef struct kc_options {
                           (automatic: 16) */
   int refine_bits;     /* key bits by which an overflowed leaf is cut per refinement
                           level: 1..8 (automatic: 3) */
-  int reserved[2];
+  int preagg;          /* pre-aggregation of equal keys in the split scatter (the
+                          heavy-hitter aggregation of Section IV-D): runs of equal keys
+                          in a tile's LDS staging leave as one (key, count) record, the
+                          count in the key bits the shard makes redundant (keys of one
+                          word in plain calls with 16-record split tiles). 0 automatic
+                          (off), 1 on, 2 off. Same result either way. */
+  int reserved[1];
 } kc_options;
 
 /* Statistics of the last successful call on this host thread. */
@@ -315,6 +322,18 @@ int kc_pred_adam_step(kc_predictor* pred, float lr, void* stream);
 void kc_pred_free(kc_predictor* pred);
 
 /* ---- Uses of a result (keys and counts as kc_count writes them; DEVICE arrays).
+ * The histogram is an input to the applications the paper lists in Section I
+ * (assembly, error correction, repeat detection, genome quality assessment):
+ * those read it as a spectrum (how many keys occur c times: error and repeat
+ * peaks) and drop rare keys below a count cut-off, as the Bloom-filter and
+ * quotient-filter counters cited in Section II-A do for singletons. Section VI
+ * counts every key from count 1 up, so kc_count itself filters nothing.
+ * kc_merge_counts rests on the same fact as the partitioned counting of
+ * Algorithms 2 and 3: a histogram is the sum of the histograms of any split of
+ * the reads (each part is counted on its own, the parts' counts are added),
+ * which lets an input larger than device memory be counted in pieces (the
+ * paper's largest data set, Table V, exceeds one device's memory).
+ *
  * kc_spectrum: the k-mer spectrum of a result: host_hist (max_count + 1
  *   entries) receives in host_hist[c] the number of keys with count c for
  *   1 <= c < max_count, in host_hist[max_count] the number with count >=

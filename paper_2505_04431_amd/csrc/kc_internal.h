@@ -24,9 +24,13 @@ struct SplitBin {
 // A leaf partition: records [begin, end) of buffer `buf` (0 = A, 1 = B) whose
 // keys share their top `bits` key bits. Its sorted (key, count) pairs are
 // written to the other buffer (and the pair-count array) at [begin, begin + d).
+// cshift != 0: the records are pre-aggregated (one-word keys only): bits
+// [cshift, 64) of a record hold its count minus one in place of the key's top
+// bits, which are `shard` (the key is (shard << cshift) | (record & (2^cshift - 1))).
 struct Leaf {
   uint64_t begin, end;
   uint32_t buf, bits;
+  uint32_t cshift, shard;
 };
 
 // Device-side result flags of the output self-check.
@@ -106,20 +110,29 @@ hipError_t launch_plan_shards(const unsigned long long* hist, const int* order, 
 
 // Device planning of the leaves (one block): leaf table in key order and the
 // sub-bin cursors of the split shards.
+// merge_cshift != 0: the split scatter pre-aggregates (the leaves of split
+// shards get cshift = merge_cshift and their shard).
 hipError_t launch_plan_leaves(const unsigned long long* hist, const unsigned long long* sbegin,
                               const SplitBin* bins, int shard_bits,
                               const unsigned long long* subhist, Leaf* leaves,
-                              unsigned long long* cursor, hipStream_t s);
+                              unsigned long long* cursor, int merge_cshift, hipStream_t s);
 
 // Split kernels loop over st->n_items items (persistent grid of at most max_items blocks).
 hipError_t launch_split_hist(int words, const void* src, const SplitItem* items,
                              const DevState* st, uint64_t max_items, const SplitBin* bins,
                              unsigned long long* subhist, hipStream_t s);
 
+// merge_cshift != 0 (one-word keys, 16 records per thread): equal keys next
+// to each other in a tile's LDS staging (same sub-bin) leave as one record
+// carrying its count minus one in bits [merge_cshift, 64); the cursors then
+// advance by the records written, and launch_leaf_ends records where each
+// split leaf's records end.
 hipError_t launch_split_scatter(int words, const void* src, void* dst, const SplitItem* items,
                                 const DevState* st, uint64_t max_items, const SplitBin* bins,
                                 unsigned long long* cursor, int records_per_thread,
-                                hipStream_t s);
+                                int merge_cshift, hipStream_t s);
+hipError_t launch_leaf_ends(Leaf* leaves, const unsigned long long* cursor, const DevState* st,
+                            uint64_t max_leaves, hipStream_t s);
 
 // Count each of the st->n_leaves leaves, write its sorted pairs next to it.
 // d_out[i] = distinct keys of leaf i, or kLeafOverflow (and st->overflow = 1)
@@ -131,14 +144,15 @@ hipError_t launch_split_scatter(int words, const void* src, void* dst, const Spl
 // accumulated (the launch_leaf_small call then only lists the leaves).
 // refine: the leaves are parts of overflowed leaves (first table full size;
 // the launches are separate kernel instantiations, so profiles tell them apart).
+// merged: leaves may hold pre-aggregated records (one-word keys).
 hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode,
-                             bool refine);
+                             bool refine, bool merged);
 hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
-                             hipStream_t s, int mode, bool refine);
+                             hipStream_t s, int mode, bool refine, bool merged);
 uint64_t small_leaf_max(int words);
 
 // Exclusive scan of leaf counts into output offsets; st->D = total. bsum

@@ -759,7 +759,7 @@ __global__ void __launch_bounds__(kPlanTB) k_plan_leaves(
     const unsigned long long* __restrict__ hist, const unsigned long long* __restrict__ sbegin,
     const SplitBin* __restrict__ bins, int shard_bits,
     const unsigned long long* __restrict__ subhist, Leaf* __restrict__ leaves,
-    unsigned long long* __restrict__ cursor) {
+    unsigned long long* __restrict__ cursor, int merge_cshift) {
   __shared__ unsigned long long wsum[kPlanTB / 64];
   const int c = blockIdx.x;
   const unsigned long long h = hist[c];
@@ -776,7 +776,8 @@ __global__ void __launch_bounds__(kPlanTB) k_plan_leaves(
   const unsigned long long off = block_exscan<kPlanTB, unsigned long long>(n, wsum, &total);
   if (j < nsub) {
     const unsigned long long run = sbegin[c] + off;
-    leaves[b.hist_off + j] = Leaf{run, run + n, 1u, (uint32_t)(shard_bits + b.nbits)};
+    leaves[b.hist_off + j] = Leaf{run, run + n, 1u, (uint32_t)(shard_bits + b.nbits),
+                                  (uint32_t)merge_cshift, (uint32_t)c};
     cursor[b.hist_off + j] = run;
   }
 }
@@ -855,7 +856,7 @@ __global__ void k_classify_leaves(const Leaf* __restrict__ leaves, DevState* __r
   const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
   for (unsigned long long i0 = (unsigned long long)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
     const unsigned long long i = i0 + threadIdx.x;
-    const Leaf lf = i < n ? leaves[i] : Leaf{0, 0, 0, 0};
+    const Leaf lf = i < n ? leaves[i] : Leaf{0, 0, 0, 0, 0, 0};
     const bool big = lf.end - lf.begin > small_max;
     const unsigned long long m = __ballot(big);
     if (!m) continue;
@@ -1033,6 +1034,121 @@ __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
   }
 }
 
+// Split scatter with pre-aggregation of equal keys (the heavy-hitter
+// aggregation of Section IV-D, on one tile of one shard's records: keys that
+// occur many times in the input are concentrated in one shard and one
+// sub-bin, where their copies meet in the tile). After the tile is staged by
+// sub-bin in LDS, each thread takes R consecutive staged records; a run of
+// equal keys among them (always inside one sub-bin) leaves as one record with
+// its length minus one in bits [cshift, 64), where the key's top bits (the
+// shard, common to the leaf) were. The first record of each thread's segment
+// starts a run, so a run never exceeds R. The tile's cursors advance by the
+// records written.
+template <int TB, int R>
+__global__ void __launch_bounds__(TB) k_split_scatter_merge(const uint64_t* __restrict__ src,
+                                                            uint64_t* __restrict__ dst,
+                                                            const SplitItem* __restrict__ items,
+                                                            const DevState* __restrict__ st,
+                                                            const SplitBin* __restrict__ bins,
+                                                            unsigned long long* __restrict__ cursor,
+                                                            int cshift) {
+  constexpr int NS = 1 << kSplitMaxBits;
+  __shared__ uint64_t stage[TB * R];
+  __shared__ uint32_t loff[NS];        // per sub-bin: records of the tile, then their offsets
+  __shared__ uint32_t mstart[NS + 1];  // per sub-bin: offset of its first merged record
+  __shared__ uint32_t tbase[TB];       // per thread: merged records before its segment
+  __shared__ unsigned long long gbase[NS];
+  __shared__ uint32_t wsum[TB / 64];
+  const uint64_t low = (1ull << cshift) - 1;
+  const unsigned long long n_items = st->n_items;
+  for (unsigned long long w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const SplitItem it = items[w];
+    const SplitBin bn = bins[it.bin];
+    const int nsub = 1 << bn.nbits;
+    for (int i = threadIdx.x; i < nsub; i += TB) loff[i] = 0;
+    __syncthreads();
+    uint64_t key[R];
+    uint32_t sub[R], rank[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint64_t r = it.begin + threadIdx.x + (uint64_t)j * TB;
+      if (r < it.end) {
+        key[j] = src[r];
+        sub[j] = Key<uint64_t>::bits(key[j], bn.shift, bn.nbits);
+        rank[j] = atomicAdd(&loff[sub[j]], 1u);
+      }
+    }
+    __syncthreads();
+    const uint32_t total = block_exscan_inplace<TB>(loff, nsub, wsum);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint64_t r = it.begin + threadIdx.x + (uint64_t)j * TB;
+      if (r < it.end) stage[loff[sub[j]] + rank[j]] = key[j];
+    }
+    __syncthreads();
+    // runs of equal keys in this thread's segment [R*t, R*t + R) of the stage
+    const uint32_t s0 = (uint32_t)threadIdx.x * R;
+    uint64_t seg[R];
+    uint32_t heads = 0;  // bit j: a run starts at s0 + j
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint32_t i = s0 + j;
+      seg[j] = i < total ? stage[i] : 0;
+      if (i < total && (j == 0 || seg[j] != seg[j - 1])) heads |= 1u << j;
+    }
+    uint32_t nh_all;
+    const uint32_t base = block_exscan<TB, uint32_t>(__builtin_popcount(heads), wsum, &nh_all);
+    tbase[threadIdx.x] = base;
+    __syncthreads();
+    // merged records before each sub-bin: heads before its first staged record
+    for (int b = threadIdx.x; b <= nsub; b += TB) {
+      const uint32_t i = b < nsub ? loff[b] : total;
+      if (i >= total) {
+        mstart[b] = nh_all;
+        continue;
+      }
+      const uint32_t t = i / R, j0 = t * R;
+      uint32_t h = tbase[t];
+      for (uint32_t q = j0; q < i; ++q) h += (q == j0 || stage[q] != stage[q - 1]) ? 1u : 0u;
+      mstart[b] = h;
+    }
+    __syncthreads();  // every staged record has been read: the stage is rewritten below
+    {
+      uint32_t at = base;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (!(heads & (1u << j))) continue;
+        const uint32_t rest = heads >> (j + 1);
+        const uint32_t next = rest ? (uint32_t)(j + 1 + __builtin_ctz(rest)) : (uint32_t)R;
+        const uint32_t end = min(next, total - s0);
+        const uint64_t len = end - (uint32_t)j;
+        stage[at++] = ((len - 1) << cshift) | (seg[j] & low);
+      }
+    }
+    for (int b = threadIdx.x; b < nsub; b += TB) {
+      const uint32_t cnt = mstart[b + 1] - mstart[b];
+      if (cnt) gbase[b] = atomicAdd(&cursor[bn.hist_off + b], (unsigned long long)cnt);
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < nh_all; j += TB) {
+      const uint64_t kk = stage[j];
+      const uint32_t b = Key<uint64_t>::bits(kk, bn.shift, bn.nbits);
+      dst[gbase[b] + (j - mstart[b])] = kk;
+    }
+    __syncthreads();
+  }
+}
+
+// Records of pre-aggregated leaves end where the split scatter's cursor
+// stopped (fewer records than windows).
+__global__ void k_leaf_ends(Leaf* __restrict__ leaves, const unsigned long long* __restrict__ cursor,
+                            const DevState* __restrict__ st) {
+  const unsigned long long n = st->n_leaves;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x)
+    if (leaves[i].cshift) leaves[i].end = cursor[i];
+}
+
 // ---------------------------------------------------------------- leaf count
 
 // Bitonic sort of (keys, counts) in LDS, n a power of two (fallback sort).
@@ -1183,7 +1299,9 @@ __device__ bool occ64(unsigned long long c) { return c != 0; }
 // added with an atomic add. FULL_FIRST: the first table is the full one (the
 // parts of a leaf that overflowed are rich in distinct keys: a half table
 // would mostly fill up and be retried).
-template <int TB, int CMAX, int R, bool FULL_FIRST>
+// MERGED: some leaves may hold pre-aggregated records (Leaf::cshift); the
+// plain instantiation has no decoding in its insert loop.
+template <int TB, int CMAX, int R, bool FULL_FIRST, bool MERGED>
 __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA, uint64_t* bufB,
                                                      uint32_t* __restrict__ tmp_cnt,
                                                      const Leaf* __restrict__ leaves,
@@ -1197,7 +1315,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
   __shared__ uint32_t aux[CMAX];
   __shared__ uint32_t wsum[TB / 64];
   __shared__ uint32_t s_nd, s_max, s_cov;
-  __shared__ unsigned long long s_sum;
+  __shared__ unsigned long long s_sum, s_windows;
   __shared__ uint32_t s_ovf;  // accessed only through ovf_get / ovf_set
   const unsigned long long EMPTY = ~0ull;
   const uint32_t cmax_rt = 1u << slots_log2;
@@ -1220,6 +1338,11 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
     // fills up, count the leaf again with a table large enough for all.
     const uint32_t Cfull = leaf_slots<TB, CMAX>(n, cmax_rt);
     uint32_t Cn = FULL_FIRST ? Cfull : leaf_slots<TB, CMAX>(n / 2, cmax_rt);
+    // pre-aggregated records: (count - 1) in bits [cshift, 64), the shard above
+    const uint32_t cshift = MERGED ? lf.cshift : 0u;
+    const uint64_t low = cshift ? (1ull << cshift) - 1 : ~0ull;
+    const uint64_t top = cshift ? (uint64_t)lf.shard << cshift : 0ull;
+    unsigned long long my_windows = 0;  // this thread's share of the leaf's windows
     for (;;) {
     const uint32_t cmask = Cn - 1;
     const int slot_bits = 31 - __builtin_clz(Cn);
@@ -1230,11 +1353,13 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
     if (threadIdx.x == 0) {
       s_nd = 0;
       s_cov = 0;
+      s_windows = 0;
       __hip_atomic_store(&s_ovf, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
     const uint32_t limit = Cn - (Cn >> 3);
     const bool track = n >= limit;  // fewer records than the limit cannot overflow
+    my_windows = 0;
     // records are loaded R per thread before inserting, so that the loads of a
     // batch are in flight together instead of one round trip per insert. The
     // probe loop has a single exit flag (always-CAS: a CAS on a slot holding
@@ -1250,7 +1375,15 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
       }
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        const unsigned long long key = kb[j];
+        unsigned long long key = kb[j];
+        uint32_t cnt = 1;
+        if constexpr (MERGED) {
+          if (cshift && key != EMPTY) {  // uniform per leaf
+            cnt = (uint32_t)(key >> cshift) + 1u;
+            key = top | (key & low);
+            my_windows += cnt;
+          }
+        }
         uint32_t pos = slot_hash(key, slot_bits);
         bool todo = key != EMPTY;
         uint32_t probes = 0;
@@ -1258,7 +1391,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
           const unsigned long long prev = atomicCAS(&tk[pos], EMPTY, key);
           const bool hit = (prev == EMPTY) | (prev == key);
           if (hit) {
-            atomicAdd(&tc[pos], 1u);
+            atomicAdd(&tc[pos], cnt);
             if (track && prev == EMPTY && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
           }
           pos = (pos + 1) & cmask;
@@ -1283,16 +1416,23 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
       __syncthreads();
       continue;
     }
-    if (n > 0xFFFFFFFFull) {
-      // a leaf of 2^32 records or more may hold a count that wrapped past 32
-      // bits; the counts then sum to less than the records
+    // windows of the leaf: its records, or the sum of pre-aggregated counts
+    unsigned long long windows = n;
+    if (MERGED && cshift) {
+      if (my_windows) atomicAdd(&s_windows, my_windows);
+      __syncthreads();
+      windows = s_windows;
+    }
+    if (windows > 0xFFFFFFFFull) {
+      // a leaf of 2^32 windows or more may hold a count that wrapped past 32
+      // bits; the counts then sum to less than the windows
       if (threadIdx.x == 0) s_sum = 0;
       __syncthreads();
       unsigned long long part = 0;
       for (uint32_t i = threadIdx.x; i < Cn; i += TB) part += tc[i];
       atomicAdd(&s_sum, part);
       __syncthreads();
-      if (threadIdx.x == 0 && s_sum != n) s_cov = 1;
+      if (threadIdx.x == 0 && s_sum != windows) s_cov = 1;
     }
     const uint32_t d = leaf_sort_write<unsigned long long, uint32_t, TB, CMAX / TB>(
         tk, tc, aux, wsum, &s_max, Cn, keybits, (int)lf.bits, (unsigned long long*)dst, tmp_cnt,
@@ -1512,8 +1652,8 @@ __global__ void __launch_bounds__(TB) k_leaf_countw(int keybits, K* bufA, K* buf
 
 // ---------------------------------------------------------------- sort-based leaf count
 
-// The paper's own way to count an owner's k-mers (Algorithm 1 Sort +
-// Accumulate, run by every owner in Algorithm 3), applied to a leaf: its
+// The paper's own way to count an owner's k-mers (counting by sorting, as in
+// Algorithm 1 and by every owner in Algorithm 3), applied to a leaf: its
 // records are sorted in LDS and each run of equal keys becomes one pair. A
 // leaf of more records than fit is marked overflowed and cut further by key
 // (refinement); a leaf whose key range is a single key is counted without
@@ -1593,6 +1733,174 @@ __global__ void __launch_bounds__(TB) k_leaf_sort(int keybits, K* bufA, K* bufB,
       const uint32_t i = sp[q];
       dst[lf.begin + q] = sk[i];
       tmp_cnt[lf.begin + q] = sp[q + 1] - i;
+    }
+    if (threadIdx.x == 0) {
+      d_out[l] = d;
+      my_records += n;
+      my_distinct += d;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && my_records) {
+    atomicAdd(&st->large_records, my_records);
+    atomicAdd(&st->large_distinct, my_distinct);
+  }
+}
+
+// Lanes of this wave whose digit d (nb bits) equals this lane's, among the
+// lanes with v set (ballots over the digit's bits).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool v, int nb) {
+  uint64_t m = __ballot(v);
+  for (int bit = 0; bit < nb; ++bit) {
+    const bool on = (d >> bit) & 1u;
+    const uint64_t set = __ballot(v && on);
+    m &= on ? set : ~set;
+  }
+  return m;
+}
+
+// Stable LSD radix sort in LDS of n one-word keys (and their counts) by bits
+// [0, nbits), 8-bit digits. Per pass, wave w walks its contiguous chunk of
+// the elements 64 at a time: lanes holding the same digit find each other by
+// ballots, so each digit's count per wave and each element's rank among the
+// wave's equal digits come without atomics; a block scan of the counts in
+// digit-major order gives every (digit, wave) its first position, and a
+// second walk places the elements there in order (stable). Ping-pong between
+// (ka, ca) and (kb, cb); returns true if the result ended in (kb, cb).
+template <int TB>
+__device__ bool lds_radix_sort64(uint64_t* ka, uint32_t* ca, uint64_t* kb, uint32_t* cb,
+                                 uint32_t n, int nbits, uint32_t* whist, uint32_t* wsum) {
+  constexpr int NW = TB / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t chunk = (n + NW - 1) / NW;
+  const uint32_t c0 = min(n, (uint32_t)w * chunk), c1 = min(n, c0 + chunk);
+  const uint64_t below = (1ull << lane) - 1;
+  bool flipped = false;
+  for (int shift = 0; shift < nbits; shift += 8) {
+    const int nb = min(8, nbits - shift);
+    for (int i = threadIdx.x; i < 256 * NW; i += TB) whist[i] = 0;
+    __syncthreads();
+    for (uint32_t r0 = c0; r0 < c1; r0 += 64) {
+      const uint32_t i = r0 + lane;
+      const bool v = i < c1;
+      const uint32_t d = v ? (uint32_t)(ka[i] >> shift) & ((1u << nb) - 1u) : 0u;
+      const uint64_t peers = digit_peers(d, v, nb);
+      if (v && lane == __ffsll((long long)peers) - 1) whist[d * NW + w] += __popcll(peers);
+    }
+    __syncthreads();
+    (void)block_exscan_inplace<TB>(whist, 256 * NW, wsum);
+    for (uint32_t r0 = c0; r0 < c1; r0 += 64) {
+      const uint32_t i = r0 + lane;
+      const bool v = i < c1;
+      const uint64_t key = v ? ka[i] : 0ull;
+      const uint32_t d = (uint32_t)(key >> shift) & ((1u << nb) - 1u);
+      const uint64_t peers = digit_peers(d, v, nb);
+      if (v) {
+        const uint32_t pos = whist[d * NW + w] + (uint32_t)__popcll(peers & below);
+        kb[pos] = key;
+        cb[pos] = ca[i];
+      }
+      // every lane has read its digit's base before the leader advances it
+      if (v && lane == __ffsll((long long)peers) - 1) whist[d * NW + w] += __popcll(peers);
+    }
+    __syncthreads();
+    uint64_t* tk = ka;
+    ka = kb;
+    kb = tk;
+    uint32_t* tc = ca;
+    ca = cb;
+    cb = tc;
+    flipped = !flipped;
+  }
+  return flipped;
+}
+
+// The paper's counting step on one-word keys, with a radix sort: a leaf's
+// records (up to SMAX; pre-aggregated ones carry their counts) are loaded into
+// LDS, radix-sorted by the key bits below the leaf's common prefix, and each
+// run of equal keys becomes one pair whose count is the sum of its records'
+// counts (the Sort and Accumulate of Algorithm 1, run by each owner in
+// Algorithm 3, on records shaped like the HEAVY (k-mer, count) and NORMAL
+// (k-mer) messages of Section IV-D). A larger leaf is marked overflowed and cut
+// further by key; a leaf whose range is one key is summed without sorting.
+template <int TB, int SMAX>
+__global__ void __launch_bounds__(TB) k_leaf_radix64(int keybits, uint64_t* bufA, uint64_t* bufB,
+                                                     uint32_t* __restrict__ tmp_cnt,
+                                                     const Leaf* __restrict__ leaves,
+                                                     DevState* __restrict__ st,
+                                                     uint32_t* __restrict__ d_out,
+                                                     const uint32_t* __restrict__ list) {
+  __shared__ uint64_t ka[SMAX], kb[SMAX];
+  __shared__ uint32_t ca[SMAX], cb[SMAX];
+  __shared__ uint32_t sp[SMAX + 1];  // run starts; then their count prefix sums
+  __shared__ uint32_t whist[256 * (TB / 64)];
+  __shared__ uint32_t wsum[TB / 64];
+  __shared__ unsigned long long s_sum;
+  const unsigned long long count = st->n_large;
+  unsigned long long my_records = 0, my_distinct = 0;
+  for (unsigned long long it = blockIdx.x; it < count; it += gridDim.x) {
+    const uint32_t l = list[it];
+    const Leaf lf = leaves[l];
+    const uint64_t n = lf.end - lf.begin;
+    const uint64_t* src = lf.buf ? bufB : bufA;
+    uint64_t* dst = lf.buf ? bufA : bufB;
+    const uint32_t cshift = lf.cshift;
+    const uint64_t low = cshift ? (1ull << cshift) - 1 : ~0ull;
+    const uint64_t top = cshift ? (uint64_t)lf.shard << cshift : 0ull;
+    if ((int)lf.bits >= keybits) {  // the leaf's range is one key: sum its records' counts
+      if (threadIdx.x == 0) s_sum = 0;
+      __syncthreads();
+      unsigned long long part = 0;
+      for (uint64_t r = lf.begin + threadIdx.x; r < lf.end; r += TB)
+        part += cshift ? (src[r] >> cshift) + 1 : 1;
+      if (part) atomicAdd(&s_sum, part);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint64_t w0 = src[lf.begin];
+        dst[lf.begin] = cshift ? top | (w0 & low) : w0;
+        tmp_cnt[lf.begin] = (uint32_t)s_sum;
+        if (s_sum > 0xFFFFFFFFull) atomicOr(&st->count_overflow, 1u);
+        d_out[l] = 1;
+        my_records += n;
+        my_distinct += 1;
+      }
+      __syncthreads();
+      continue;
+    }
+    if (n > SMAX) {
+      if (threadIdx.x == 0) {
+        d_out[l] = kLeafOverflow;
+        atomicOr(&st->overflow, 1u);
+      }
+      continue;
+    }
+    const uint32_t m = (uint32_t)n;
+    for (uint32_t i = threadIdx.x; i < m; i += TB) {
+      const uint64_t x = src[lf.begin + i];
+      ka[i] = cshift ? top | (x & low) : x;
+      ca[i] = cshift ? (uint32_t)(x >> cshift) + 1u : 1u;
+    }
+    __syncthreads();
+    const bool in_b = lds_radix_sort64<TB>(ka, ca, kb, cb, m, keybits - (int)lf.bits, whist, wsum);
+    const uint64_t* sk = in_b ? kb : ka;
+    uint32_t* sc = in_b ? cb : ca;
+    // run starts: thread t looks at positions [t*per, t*per + per)
+    const uint32_t per = (m + TB - 1) / TB;
+    const uint32_t b = threadIdx.x * per, e = min(m, b + per);
+    uint32_t c = 0;
+    for (uint32_t i = b; i < e; ++i) c += (i == 0 || sk[i] != sk[i - 1]) ? 1u : 0u;
+    uint32_t d = 0;
+    uint32_t at = block_exscan<TB, uint32_t>(c, wsum, &d);
+    for (uint32_t i = b; i < e; ++i)
+      if (i == 0 || sk[i] != sk[i - 1]) sp[at++] = i;
+    if (threadIdx.x == 0) sp[d] = m;
+    __syncthreads();
+    // counts of the runs: exclusive prefix sums of the sorted records' counts
+    const uint32_t all = block_exscan_inplace<TB>(sc, m, wsum);
+    for (uint32_t q = threadIdx.x; q < d; q += TB) {
+      const uint32_t i = sp[q], j = sp[q + 1];
+      dst[lf.begin + q] = sk[i];
+      tmp_cnt[lf.begin + q] = (j < m ? sc[j] : all) - sc[i];
     }
     if (threadIdx.x == 0) {
       d_out[l] = d;
@@ -1838,7 +2146,7 @@ constexpr unsigned kPersistentGrid = 1024;  // blocks of the persistent kernels
 constexpr int kSmallCmax64 = 1024;  // one-wave leaf kernel: slots of its private table
 constexpr int kSmallCmax128 = 512;
 constexpr unsigned kSmallGrid = 256 * 20;
-constexpr int kSortMax64 = 8192;   // records per leaf of the sort-based count
+constexpr int kSortMax64 = 5120;   // records per leaf of the sort-based count (radix: 148 KiB LDS)
 constexpr int kSortMax128 = 4096;
 constexpr int kSortMax256 = 2048;
 
@@ -1983,9 +2291,16 @@ hipError_t launch_plan_shards(const unsigned long long* hist, const int* order, 
 hipError_t launch_plan_leaves(const unsigned long long* hist, const unsigned long long* sbegin,
                               const SplitBin* bins, int shard_bits,
                               const unsigned long long* subhist, Leaf* leaves,
-                              unsigned long long* cursor, hipStream_t s) {
+                              unsigned long long* cursor, int merge_cshift, hipStream_t s) {
   hipLaunchKernelGGL(k_plan_leaves, dim3(1u << shard_bits), dim3(kPlanTB), 0, s, hist, sbegin,
-                     bins, shard_bits, subhist, leaves, cursor);
+                     bins, shard_bits, subhist, leaves, cursor, merge_cshift);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_ends(Leaf* leaves, const unsigned long long* cursor, const DevState* st,
+                            uint64_t max_leaves, hipStream_t s) {
+  hipLaunchKernelGGL(k_leaf_ends, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s, leaves,
+                     cursor, st);
   return hipGetLastError();
 }
 
@@ -2008,8 +2323,15 @@ hipError_t launch_split_hist(int words, const void* src, const SplitItem* items,
 hipError_t launch_split_scatter(int words, const void* src, void* dst, const SplitItem* items,
                                 const DevState* st, uint64_t max_items, const SplitBin* bins,
                                 unsigned long long* cursor, int records_per_thread,
-                                hipStream_t s) {
+                                int merge_cshift, hipStream_t s) {
   const unsigned grid = persistent(max_items, 2048);
+  if (merge_cshift) {
+    if (words != 1 || records_per_thread != 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_split_scatter_merge<kSplitTB64, 16>), dim3(grid), dim3(kSplitTB64), 0,
+                       s, (const uint64_t*)src, (uint64_t*)dst, items, st, bins, cursor,
+                       merge_cshift);
+    return hipGetLastError();
+  }
   if (words == 1 && records_per_thread == 16) {
     // 16,384-record tiles: 128 KiB of LDS staging, one workgroup per CU
     hipLaunchKernelGGL((k_split_scatter<uint64_t, kSplitTB64, 16>), dim3(grid), dim3(kSplitTB64),
@@ -2039,7 +2361,7 @@ uint64_t small_leaf_max(int words) {
 hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode,
-                             bool refine) {
+                             bool refine, bool merged) {
   const bool wide = words == 2;
   const uint64_t small_max = mode == 1 ? 0 : small_leaf_max(words);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &st->n_large, (uint64_t)1, 0ull);
@@ -2055,8 +2377,8 @@ hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uin
   hipLaunchKernelGGL((k_leaf_countw<u128, 64, kSmallCmax128, 8, HI, FF>), dim3(gsmall), dim3(64), \
                      0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,        \
                      __builtin_ctz(kSmallCmax128), (const uint32_t*)nullptr, small_max)
-#define KC_SMALL64(FF)                                                                           \
-  hipLaunchKernelGGL((k_leaf_count64<64, kSmallCmax64, 8, FF>), dim3(gsmall), dim3(64), 0, s,    \
+#define KC_SMALL64(FF, MG)                                                                       \
+  hipLaunchKernelGGL((k_leaf_count64<64, kSmallCmax64, 8, FF, MG>), dim3(gsmall), dim3(64), 0, s, \
                      keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,      \
                      __builtin_ctz(kSmallCmax64), (const uint32_t*)nullptr, small_max)
   if (wide) {
@@ -2066,7 +2388,11 @@ hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uin
       if (refine) KC_SMALLW(false, true); else KC_SMALLW(false, false);
     }
   } else {
-    if (refine) KC_SMALL64(true); else KC_SMALL64(false);
+    if (merged) {
+      if (refine) KC_SMALL64(true, true); else KC_SMALL64(false, true);
+    } else {
+      if (refine) KC_SMALL64(true, false); else KC_SMALL64(false, false);
+    }
   }
 #undef KC_SMALLW
 #undef KC_SMALL64
@@ -2076,7 +2402,7 @@ hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uin
 hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
-                             hipStream_t s, int mode, bool refine) {
+                             hipStream_t s, int mode, bool refine, bool merged) {
   const bool wide = words == 2;
   const uint64_t small_max = small_leaf_max(words);
   const unsigned glarge = persistent(max_leaves, kPersistentGrid);
@@ -2090,19 +2416,19 @@ hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uin
                          0, s, keybits, (u128*)bufA, (u128*)bufB, tmp_cnt, leaves, st, d_out,
                          large_list);
     else
-      hipLaunchKernelGGL((k_leaf_sort<uint64_t, kLeafTB, kSortMax64>), dim3(glarge),
-                         dim3(kLeafTB), 0, s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt,
-                         leaves, st, d_out, large_list);
+      hipLaunchKernelGGL((k_leaf_radix64<kLeafTB, kSortMax64>), dim3(glarge), dim3(kLeafTB), 0, s,
+                         keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,
+                         large_list);
     return hipGetLastError();
   }
 #define KC_LARGEW(KT, CM, HI, FF)                                                               \
   hipLaunchKernelGGL((k_leaf_countw<KT, kLeafTB, CM, 4, HI, FF>), dim3(glarge), dim3(kLeafTB), 0, \
                      s, keybits, (KT*)bufA, (KT*)bufB, tmp_cnt, leaves, st, d_out, slots_log2,   \
                      large_list, small_max)
-#define KC_LARGE64(FF)                                                                          \
-  hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4, FF>), dim3(glarge), dim3(kLeafTB), \
-                     0, s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out, \
-                     slots_log2, large_list, small_max)
+#define KC_LARGE64(FF, MG)                                                                      \
+  hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4, FF, MG>), dim3(glarge),            \
+                     dim3(kLeafTB), 0, s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt,    \
+                     leaves, st, d_out, slots_log2, large_list, small_max)
   if (words == 4) {
     if (refine) KC_LARGEW(u256, kLeafCmax256, false, true);
     else KC_LARGEW(u256, kLeafCmax256, false, false);
@@ -2115,7 +2441,11 @@ hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uin
       else KC_LARGEW(u128, kLeafCmax128, false, false);
     }
   } else {
-    if (refine) KC_LARGE64(true); else KC_LARGE64(false);
+    if (merged) {
+      if (refine) KC_LARGE64(true, true); else KC_LARGE64(false, true);
+    } else {
+      if (refine) KC_LARGE64(true, false); else KC_LARGE64(false, false);
+    }
   }
 #undef KC_LARGEW
 #undef KC_LARGE64

@@ -392,6 +392,7 @@ struct Call {
   int words = 1;  // 64-bit words per key: 1, 2 or 4
   int keybits = 0, sb = 0, nb = 0, slots_log2 = 0;
   int split_r = 8;
+  bool merged = false;  // the split scatter pre-aggregated (leaves may carry counts)
   size_t ksz = 8;
   uint64_t C = 0, T = 0, H = 0;
 };
@@ -500,6 +501,7 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
     int bits;     // key bits consumed in total (from the most significant end)
     int buf;      // buffer holding its records
     uint32_t root;
+    uint32_t cshift, shard;  // record format of the root leaf (pre-aggregated or not)
   };
   struct Done {
     uint32_t root;
@@ -511,7 +513,8 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
   for (uint32_t r = 0; r < R; ++r) {
     const kc::Leaf& lf = rlv[ord[r]];
     if ((int)lf.bits >= q.keybits) fail(KC_E_INTERNAL, "single-key partition overflowed its table");
-    split.push_back(Part{lf.begin, lf.end, Rel{}, (int)lf.bits, (int)lf.buf, r});  // root = rank r
+    split.push_back(Part{lf.begin, lf.end, Rel{}, (int)lf.bits, (int)lf.buf, r, lf.cshift,
+                         lf.shard});  // root = rank r
     ++S.n_overflow;
   }
   std::vector<Done> done;
@@ -535,7 +538,10 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
       // A part overflowed because of its distinct keys, not its records (a
       // part of many records and few keys counts fine), so it is cut in a
       // few pieces by key, not by record count; pieces too rich in keys are
-      // cut again at the next level.
+      // cut again at the next level. (Cutting into pieces of a leaf target of
+      // records each, up to 8 bits a level, took 19.7 against 30.9 ms on a
+      // satellite-repeat input but 184 against 136 ms on the 40,000,000-read
+      // workload at k = 31: millions of small parts to plan and splice.)
       (void)n;
       const int nbits = std::max(1, std::min(refine_bits, remaining));
       sbins[i] = kc::SplitBin{hoff, (uint32_t)(remaining - nbits), (uint32_t)nbits};
@@ -579,7 +585,8 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
           if (cnt) {
             Rel nr = b.rel.shl((int)sbn.nbits);
             nr.lo |= (u128)j;
-            next.push_back(Part{r, r + cnt, nr, b.bits + (int)sbn.nbits, 1 - b.buf, b.root});
+            next.push_back(Part{r, r + cnt, nr, b.bits + (int)sbn.nbits, 1 - b.buf, b.root,
+                                b.cshift, b.shard});
           }
           r += cnt;
         }
@@ -589,7 +596,7 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
       hipchk(kc::launch_split_scatter(q.words, bufs[src], bufs[1 - src],
                                       (kc::SplitItem*)c.items.p, dst_state, it_src.size(),
                                       (kc::SplitBin*)c.bins.p, (unsigned long long*)c.cursor2.p,
-                                      q.split_r, st),
+                                      q.split_r, 0, st),
              "split scatter launch");
     }
     tm.mark(ST_REFINE);
@@ -597,7 +604,8 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
     const size_t na = next.size();
     std::vector<kc::Leaf> al(na);
     for (size_t i = 0; i < na; ++i)
-      al[i] = kc::Leaf{next[i].begin, next[i].end, (uint32_t)next[i].buf, (uint32_t)next[i].bits};
+      al[i] = kc::Leaf{next[i].begin, next[i].end, (uint32_t)next[i].buf, (uint32_t)next[i].bits,
+                       next[i].cshift, next[i].shard};
     grow(c.aleaves, na * sizeof(kc::Leaf), "part table", st);
     grow(c.adcnt, na * 4, "part counts", st);
     grow(c.alarge, na * 4, "large-part list", st);
@@ -606,11 +614,12 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
     upload_sync(&dst_state->n_leaves, &nlu, 8, st);
     hipchk(kc::launch_leaf_small(q.words, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
-                                 (uint32_t*)c.alarge.p, st, q.o.mode, true),
+                                 (uint32_t*)c.alarge.p, st, q.o.mode, true, q.merged),
            "leaf count launch");
     hipchk(kc::launch_leaf_large(q.words, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
-                                 q.slots_log2, (uint32_t*)c.alarge.p, st, q.o.mode, true),
+                                 q.slots_log2, (uint32_t*)c.alarge.p, st, q.o.mode, true,
+                                 q.merged),
            "leaf count launch");
     tm.mark(ST_REFINE);
     uint32_t* hd = (uint32_t*)host_stage(c, na * 4 + 64);
@@ -712,6 +721,7 @@ struct Pipe {
   const kc::BatchSets* batch = nullptr;   // batch form (composite keys)
   int mode = 0;                           // leaf count: 0 hash tables, 1 sort
   int scatter_s = 8, split_r = 8;         // LDS tile shape of the two scatters (one-word keys)
+  int merge_cshift = 0;                   // != 0: the split scatter pre-aggregates equal keys
   const int* order = nullptr;             // device, owner-major shard order
 };
 
@@ -816,21 +826,28 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
   tm.mark(ST_SPLIT_HIST);
   hipchk(kc::launch_plan_leaves((unsigned long long*)c.hist.p, (unsigned long long*)c.sbegin.p,
                                 (kc::SplitBin*)c.bins.p, p.sb, (unsigned long long*)c.subhist.p,
-                                (kc::Leaf*)c.leaves.p, (unsigned long long*)c.cursor2.p, st),
+                                (kc::Leaf*)c.leaves.p, (unsigned long long*)c.cursor2.p,
+                                p.merge_cshift, st),
          "plan_leaves launch");
   hipchk(kc::launch_split_scatter(p.words, c.bufA.p, c.bufB.p, (kc::SplitItem*)c.items.p, dstate,
                                   p.max_items, (kc::SplitBin*)c.bins.p,
-                                  (unsigned long long*)c.cursor2.p, p.split_r, st),
+                                  (unsigned long long*)c.cursor2.p, p.split_r, p.merge_cshift,
+                                  st),
          "split scatter launch");
+  if (p.merge_cshift)
+    hipchk(kc::launch_leaf_ends((kc::Leaf*)c.leaves.p, (unsigned long long*)c.cursor2.p, dstate,
+                                p.max_leaves, st),
+           "leaf ends launch");
   tm.mark(ST_SPLIT);
   hipchk(kc::launch_leaf_small(p.words, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
-                               (uint32_t*)c.large.p, st, p.mode, false),
+                               (uint32_t*)c.large.p, st, p.mode, false, p.merge_cshift != 0),
          "leaf count launch");
   tm.mark(ST_LEAF_SMALL);
   hipchk(kc::launch_leaf_large(p.words, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
-                               p.slots_log2, (uint32_t*)c.large.p, st, p.mode, false),
+                               p.slots_log2, (uint32_t*)c.large.p, st, p.mode, false,
+                               p.merge_cshift != 0),
          "leaf count launch");
   tm.mark(ST_LEAF);
   hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dstate, (unsigned long long*)c.bsum.p,
@@ -894,6 +911,11 @@ Pipe plain_pipe(uint64_t n_bytes, int k, int P, const kc_options& o) {
   p.rec_bound = n_bytes;  // byte count: an upper bound of the window count
   p.mode = o.mode;
   tile_params(o, p);
+  if (o.preagg < 0 || o.preagg > 2) fail(KC_E_INVAL, "preagg must be 0, 1 or 2");
+  // a record's count (up to 16) takes the bits from 2k - shard bits up, which
+  // the shard makes redundant: 4 of them at least
+  const int cshift = p.keybits - p.sb;
+  if (p.words == 1 && p.split_r == 16 && o.preagg == 1 && cshift <= 60) p.merge_cshift = cshift;
   pipe_bounds(p);
   return p;
 }
@@ -974,6 +996,7 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   q.sb = p0.sb;
   q.nb = 1 << q.sb;
   q.split_r = p0.split_r;
+  q.merged = p0.merge_cshift != 0;
   if (q.o.refine_bits < 0 || q.o.refine_bits > 8) fail(KC_E_INVAL, "refine_bits must be in [0, 8]");
   Pipe p = p0;
   const uint64_t nchunks = packed_chunks(q.N);

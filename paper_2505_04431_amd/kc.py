@@ -40,7 +40,8 @@ class KcOptions(ctypes.Structure):
                 ("leaf_attempt", ctypes.c_int), ("table_slots_log2", ctypes.c_int),
                 ("check", ctypes.c_int), ("timing", ctypes.c_int), ("mode", ctypes.c_int),
                 ("scatter_tile", ctypes.c_int), ("split_tile", ctypes.c_int),
-                ("refine_bits", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
+                ("refine_bits", ctypes.c_int), ("preagg", ctypes.c_int),
+                ("reserved", ctypes.c_int * 1)]
 
 
 class KcStats(ctypes.Structure):

@@ -74,6 +74,7 @@ def test_p_invariance(P):
     dict(scatter_tile=16, split_tile=16),
     dict(scatter_tile=16, split_tile=8, shard_bits=10, leaf_target=64, leaf_attempt=128),
     dict(scatter_tile=8, split_tile=16, table_slots_log2=11, leaf_target=300),
+    dict(preagg=2), dict(preagg=2, mode=1), dict(split_tile=8, preagg=1),
 ])
 def test_knob_invariance(opts):
     c = synth.make_config(2, frac=0.02)
@@ -315,3 +316,28 @@ def test_arena_regrowth_sizes():
         assert_same(gpu_count(r, o, k, P=8), oracle.count(r, o, k), "n=%d k=%d" % (n, k))
         if i == 4:
             kc.lib().kc_release_scratch()
+
+
+@pytest.mark.parametrize("k", [31, 21, 27])
+def test_preaggregation_on_off_and_sort_mode(k):
+    """Equal keys merged in the split scatter (records carrying counts) give
+    the same histogram as plain records, through the hash-table leaves, the
+    radix-sorted leaves and the refinement of overflowed leaves; on an input
+    with heavy repeats the leaves read fewer records than there are windows."""
+    import paper_2505_04431_amd as kc
+    print("preagg k=%d: a 60 kbp genome with a 3 kbp family in 300 exact copies" % k, flush=True)
+    g = synth.genome(4711, 60_000, [(3000, 300, 0.0)])
+    reads, offs = synth.reads(g, 60_000, 150, err_rate=0.002, n_rate=0.0, seed=9)
+    want = oracle.count(reads, offs, k)
+    runs = {}
+    for name, opts in (("on", dict(preagg=1)), ("off", dict(preagg=2)),
+                       ("on, sort mode", dict(preagg=1, mode=1)),
+                       ("on, refined", dict(preagg=1, shard_bits=4, leaf_target=60_000,
+                                            leaf_attempt=70_000, table_slots_log2=10)),
+                       ("on, refined sort", dict(preagg=1, mode=1, shard_bits=4,
+                                                 leaf_target=60_000, leaf_attempt=70_000))):
+        assert_same(gpu_count(reads, offs, k, P=5, check=1, **opts), want, name)
+        runs[name] = kc.last_stats()
+    W = runs["off"]["valid_windows"]
+    assert runs["on"]["large_records"] < 0.9 * W
+    assert runs["off"]["large_records"] + 0.01 * W >= runs["on"]["large_records"]
