@@ -80,17 +80,27 @@ hipError_t launch_pack(const uint8_t* src, uint64_t n_bytes, const uint64_t* off
                        uint64_t n_reads, uint64_t off0, uint64_t* packed, uint64_t* inv,
                        uint64_t* endm, uint64_t nchunks, hipStream_t s);
 
-// Window kernels over the bytes [byte_begin, byte_end) of the packed stream.
+// Valid-start mask of the windows of k bytes starting in [byte_begin,
+// byte_end), from the invalid-byte and read-end masks of launch_pack: bit j of
+// valid[w] is set iff the window starting at byte 64w + j is valid. Writes the
+// words the window kernels below read for the same byte range (valid holds as
+// many words as inv).
+hipError_t launch_valid_mask(int words, const uint64_t* inv, const uint64_t* endm,
+                             uint64_t byte_begin, uint64_t byte_end, int k, uint64_t* valid,
+                             hipStream_t s);
+
+// Window kernels over the bytes [byte_begin, byte_end) of the packed stream,
+// with the valid-start mask of launch_valid_mask for the same range and k.
 // keybits = 2k (plain) or 2k + set id bits (batch: batch != nullptr).
-hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t* inv,
-                              const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end, int k,
+hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t* valid,
+                              uint64_t byte_begin, uint64_t byte_end, int k,
                               int keybits, int shard_bits, const BatchSets* batch,
                               unsigned long long* hist, unsigned long long* wcount,
                               hipStream_t s);
 
 // starts_per_thread: 8, or 16 for one-word keys (16,384-record LDS tiles).
-hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* inv,
-                                 const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end,
+hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* valid,
+                                 uint64_t byte_begin, uint64_t byte_end,
                                  int k, int keybits, int shard_bits, const BatchSets* batch,
                                  unsigned long long* cursor, void* out, int starts_per_thread,
                                  hipStream_t s);

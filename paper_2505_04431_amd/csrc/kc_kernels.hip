@@ -375,16 +375,14 @@ __global__ void __launch_bounds__(256) k_read_ends(const uint64_t* __restrict__ 
 
 // ---------------------------------------------------------------- windows
 
-// Bit i of the result is set iff the window starting at byte g+i (i < S) is
-// valid: no invalid byte in [g+i, g+i+k) and no read end in [g+i, g+i+k-1).
-// g is a multiple of S; the mask arrays are padded by two words.
-__device__ __forceinline__ u128 load_bits(const uint64_t* __restrict__ m, uint64_t g) {
-  const uint64_t w = g >> 6;
-  const int off = (int)(g & 63);
-  const uint64_t a = m[w], b = m[w + 1], c = m[w + 2];
-  const uint64_t lo = off ? (a >> off) | (b << (64 - off)) : a;
-  const uint64_t hi = off ? (b >> off) | (c << (64 - off)) : b;
-  return ((u128)hi << 64) | lo;
+// Window validity. Bit j of valid[w] is set iff the window of k bytes
+// starting at byte 64w + j is valid: no invalid byte in it and no read end
+// before its last byte. The mask is built once per k by k_valid_mask, so that
+// the window kernels test a start with one shift.
+
+// Bits [64w, 64w + 128) of a bit array (the arrays are padded by two words).
+__device__ __forceinline__ u128 load_bits(const uint64_t* __restrict__ m, uint64_t w) {
+  return ((u128)m[w + 1] << 64) | m[w];
 }
 
 // r[i] = OR of x[i .. i+len) (len >= 1).
@@ -398,27 +396,10 @@ __device__ __forceinline__ u128 smear(u128 x, int len) {
   return x;
 }
 
-template <int S>
-__device__ __forceinline__ uint32_t valid_starts(const uint64_t* __restrict__ inv,
-                                                 const uint64_t* __restrict__ endm, uint64_t g,
-                                                 int k) {
-  u128 bad = smear(load_bits(inv, g), k);
-  if (k > 1) bad |= smear(load_bits(endm, g), k - 1);
-  return ~(uint32_t)bad & (S >= 32 ? 0xFFFFFFFFu : ((1u << S) - 1u));
-}
-
-// The same for keys of more than 64 bases: S + k - 1 may pass 128 bits, so
-// the masks are read and smeared as 256-bit values (the mask arrays are padded
-// by five words).
-__device__ __forceinline__ u256 load_bits256(const uint64_t* __restrict__ m, uint64_t g) {
-  const uint64_t w = g >> 6;
-  const int off = (int)(g & 63);
-  uint64_t a[5], r[4];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) a[i] = m[w + i];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) r[i] = off ? (a[i] >> off) | (a[i + 1] << (64 - off)) : a[i];
-  return u256(((u128)r[1] << 64) | r[0], ((u128)r[3] << 64) | r[2]);
+// The same over 256 bits, for keys of more than 64 bases (64 + k - 1 may pass
+// 128 bits; the arrays are padded by five words).
+__device__ __forceinline__ u256 load_bits256(const uint64_t* __restrict__ m, uint64_t w) {
+  return u256(((u128)m[w + 1] << 64) | m[w], ((u128)m[w + 3] << 64) | m[w + 2]);
 }
 
 __device__ __forceinline__ u256 smear256(u256 x, int len) {
@@ -431,22 +412,32 @@ __device__ __forceinline__ u256 smear256(u256 x, int len) {
   return x;
 }
 
-template <int S>
-__device__ __forceinline__ uint32_t valid_starts256(const uint64_t* __restrict__ inv,
-                                                    const uint64_t* __restrict__ endm, uint64_t g,
-                                                    int k) {
-  u256 bad = smear256(load_bits256(inv, g), k);
-  if (k > 1) bad |= smear256(load_bits256(endm, g), k - 1);
-  return ~(uint32_t)bad & (S >= 32 ? 0xFFFFFFFFu : ((1u << S) - 1u));
+// One thread per mask word w in [w_begin, w_end).
+template <bool WIDE>
+__global__ void __launch_bounds__(256) k_valid_mask(const uint64_t* __restrict__ inv,
+                                                    const uint64_t* __restrict__ endm,
+                                                    uint64_t w_begin, uint64_t w_end, int k,
+                                                    uint64_t* __restrict__ valid) {
+  const uint64_t w = w_begin + (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (w >= w_end) return;
+  uint64_t bad;
+  if constexpr (WIDE) {
+    u256 b = smear256(load_bits256(inv, w), k);
+    if (k > 1) b |= smear256(load_bits256(endm, w), k - 1);
+    bad = (uint64_t)b;
+  } else {
+    u128 b = smear(load_bits(inv, w), k);
+    if (k > 1) b |= smear(load_bits(endm, w), k - 1);
+    bad = (uint64_t)b;
+  }
+  valid[w] = ~bad;
 }
 
-// Valid starts for the key width of Kc.
-template <typename Kc, int S>
-__device__ __forceinline__ uint32_t valid_starts_for(const uint64_t* __restrict__ inv,
-                                                     const uint64_t* __restrict__ endm,
-                                                     uint64_t g, int k) {
-  if constexpr (Key<Kc>::kWords == 4) return valid_starts256<S>(inv, endm, g, k);
-  else return valid_starts<S>(inv, endm, g, k);
+// Valid starts among the S window starts g .. g+S-1 (g a multiple of S, S
+// dividing 64): bit i for start g+i.
+template <int S>
+__device__ __forceinline__ uint32_t valid_starts(const uint64_t* __restrict__ valid, uint64_t g) {
+  return (uint32_t)(valid[g >> 6] >> (g & 63)) & (S >= 32 ? 0xFFFFFFFFu : ((1u << S) - 1u));
 }
 
 template <typename K, int S>
@@ -559,8 +550,7 @@ __device__ __forceinline__ uint32_t window_keys(const uint64_t* __restrict__ pac
 // Threads t in [t_begin, t_end) each take window starts [t*S, t*S + S).
 template <typename K, typename Kc, int S, int TB, bool BATCH>
 __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__ packed,
-                                                    const uint64_t* __restrict__ inv,
-                                                    const uint64_t* __restrict__ endm,
+                                                    const uint64_t* __restrict__ valid,
                                                     uint64_t t_begin, uint64_t t_end, int k,
                                                     int keybits, int shard_bits, BatchSets bs,
                                                     unsigned long long* __restrict__ hist,
@@ -573,7 +563,7 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
   for (uint64_t t = t_begin + (uint64_t)blockIdx.x * TB + threadIdx.x; t < t_end;
        t += (uint64_t)gridDim.x * TB) {
     const uint64_t g = t * S;
-    uint32_t vm = valid_starts_for<Kc, S>(inv, endm, g, k);
+    uint32_t vm = valid_starts<S>(valid, g);
     if (!vm) continue;
     K keys[S];
     vm = window_keys<K, Kc, S, BATCH>(packed, g, k, vm, bs, keys);
@@ -596,8 +586,7 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
 // global atomic, and the runs leave LDS as coalesced writes.
 template <typename K, typename Kc, int S, int TB, bool BATCH>
 __device__ __forceinline__ void window_scatter_body(const uint64_t* __restrict__ packed,
-                                                    const uint64_t* __restrict__ inv,
-                                                    const uint64_t* __restrict__ endm,
+                                                    const uint64_t* __restrict__ valid,
                                                     uint64_t t_begin, uint64_t t_end, int k,
                                                     int keybits, int shard_bits, BatchSets bs,
                                                     unsigned long long* __restrict__ cursor,
@@ -614,7 +603,7 @@ __device__ __forceinline__ void window_scatter_body(const uint64_t* __restrict__
     __syncthreads();
     const uint64_t t = t_begin + tile * TB + threadIdx.x;
     const uint64_t g = t * S;
-    uint32_t vm = t < t_end ? valid_starts_for<Kc, S>(inv, endm, g, k) : 0u;
+    uint32_t vm = t < t_end ? valid_starts<S>(valid, g) : 0u;
     K key[S];
     uint32_t rank[S];  // (the shard is recomputed from the key: fewer live registers)
     if (vm) {
@@ -644,13 +633,12 @@ __device__ __forceinline__ void window_scatter_body(const uint64_t* __restrict__
 
 template <typename K, typename Kc, int S, int TB, bool BATCH>
 __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restrict__ packed,
-                                                       const uint64_t* __restrict__ inv,
-                                                       const uint64_t* __restrict__ endm,
+                                                       const uint64_t* __restrict__ valid,
                                                        uint64_t t_begin, uint64_t t_end, int k,
                                                        int keybits, int shard_bits, BatchSets bs,
                                                        unsigned long long* __restrict__ cursor,
                                                        K* __restrict__ out) {
-  window_scatter_body<K, Kc, S, TB, BATCH>(packed, inv, endm, t_begin, t_end, k, keybits,
+  window_scatter_body<K, Kc, S, TB, BATCH>(packed, valid, t_begin, t_end, k, keybits,
                                            shard_bits, bs, cursor, out);
 }
 
@@ -662,21 +650,19 @@ __global__ void __launch_bounds__(TB) k_window_scatter(const uint64_t* __restric
 // as long per tile.
 template <typename K, typename Kc, int S, int TB, bool BATCH>
 __global__ void __launch_bounds__(TB)
-k_window_scatter64w(const uint64_t* __restrict__ packed, const uint64_t* __restrict__ inv,
-                    const uint64_t* __restrict__ endm, uint64_t t_begin, uint64_t t_end, int k,
+k_window_scatter64w(const uint64_t* __restrict__ packed, const uint64_t* __restrict__ valid, uint64_t t_begin, uint64_t t_end, int k,
                     int keybits, int shard_bits, BatchSets bs,
                     unsigned long long* __restrict__ cursor, K* __restrict__ out) {
-  window_scatter_body<K, Kc, S, TB, BATCH>(packed, inv, endm, t_begin, t_end, k, keybits,
+  window_scatter_body<K, Kc, S, TB, BATCH>(packed, valid, t_begin, t_end, k, keybits,
                                            shard_bits, bs, cursor, out);
 }
 
 template <typename K, typename Kc, int S, int TB, bool BATCH>
 __global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(8, 8)))
-k_window_scatter64(const uint64_t* __restrict__ packed, const uint64_t* __restrict__ inv,
-                   const uint64_t* __restrict__ endm, uint64_t t_begin, uint64_t t_end, int k,
+k_window_scatter64(const uint64_t* __restrict__ packed, const uint64_t* __restrict__ valid, uint64_t t_begin, uint64_t t_end, int k,
                    int keybits, int shard_bits, BatchSets bs,
                    unsigned long long* __restrict__ cursor, K* __restrict__ out) {
-  window_scatter_body<K, Kc, S, TB, BATCH>(packed, inv, endm, t_begin, t_end, k, keybits,
+  window_scatter_body<K, Kc, S, TB, BATCH>(packed, valid, t_begin, t_end, k, keybits,
                                            shard_bits, bs, cursor, out);
 }
 
@@ -2191,13 +2177,30 @@ hipError_t launch_pack(const uint8_t* src, uint64_t n_bytes, const uint64_t* off
 
 #define KC_WINDOW_LAUNCH(KERNEL, K, KC, TB, BATCH, GRID)                                    \
   hipLaunchKernelGGL((KERNEL<K, KC, kWinStarts, TB, BATCH>), dim3(GRID), dim3(TB), 0, s, packed, \
-                     inv, endm, t_begin, t_end, k, keybits, shard_bits, bs, ARG0, ARG1)
+                     valid, t_begin, t_end, k, keybits, shard_bits, bs, ARG0, ARG1)
 #define KC_WINDOW_LAUNCH_S(KERNEL, K, KC, S, TB, BATCH, GRID)                                  \
-  hipLaunchKernelGGL((KERNEL<K, KC, S, TB, BATCH>), dim3(GRID), dim3(TB), 0, s, packed, inv, endm, \
+  hipLaunchKernelGGL((KERNEL<K, KC, S, TB, BATCH>), dim3(GRID), dim3(TB), 0, s, packed, valid,     \
                      t_begin, t_end, k, keybits, shard_bits, bs, ARG0, ARG1)
 
-hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t* inv,
-                              const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end, int k,
+hipError_t launch_valid_mask(int words, const uint64_t* inv, const uint64_t* endm,
+                             uint64_t byte_begin, uint64_t byte_end, int k, uint64_t* valid,
+                             hipStream_t s) {
+  // the words the window kernels read: starts [byte_begin, byte_end) rounded
+  // out to whole threads, which stay inside whole words
+  const uint64_t w_begin = byte_begin >> 6, w_end = (byte_end + 63) >> 6;
+  if (w_end <= w_begin) return hipSuccess;
+  const unsigned grid = (unsigned)((w_end - w_begin + 255) / 256);
+  if (words == 4)
+    hipLaunchKernelGGL(k_valid_mask<true>, dim3(grid), dim3(256), 0, s, inv, endm, w_begin, w_end,
+                       k, valid);
+  else
+    hipLaunchKernelGGL(k_valid_mask<false>, dim3(grid), dim3(256), 0, s, inv, endm, w_begin,
+                       w_end, k, valid);
+  return hipGetLastError();
+}
+
+hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t* valid,
+                              uint64_t byte_begin, uint64_t byte_end, int k,
                               int keybits, int shard_bits, const BatchSets* batch,
                               unsigned long long* hist, unsigned long long* wcount,
                               hipStream_t s) {
@@ -2222,8 +2225,8 @@ hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t*
   return hipGetLastError();
 }
 
-hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* inv,
-                                 const uint64_t* endm, uint64_t byte_begin, uint64_t byte_end,
+hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* valid,
+                                 uint64_t byte_begin, uint64_t byte_end,
                                  int k, int keybits, int shard_bits, const BatchSets* batch,
                                  unsigned long long* cursor, void* out, int starts_per_thread,
                                  hipStream_t s) {

@@ -96,7 +96,7 @@ void carve(DevBuf& b, size_t bytes, const char* name) {
 
 struct Ctx {
   int device = -1;
-  DevBuf packed, inv, endm, bufA, bufB, tmpcnt;
+  DevBuf packed, inv, endm, valid, bufA, bufB, tmpcnt;
   DevBuf hist, sbegin, cursor, cursor2, order, items, bins, subhist, leaves, dcnt, outoff, state;
   DevBuf large, bsum, itemoff;
   // overflow refinement: overflowed leaves, part attempts, the spliced list
@@ -117,7 +117,7 @@ struct Ctx {
   ~Ctx() {
     int prev = -1;
     if (hipGetDevice(&prev) == hipSuccess && device >= 0) (void)hipSetDevice(device);
-    DevBuf* all[] = {&packed,  &inv,     &endm,   &bufA,    &bufB,   &tmpcnt,  &hist,
+    DevBuf* all[] = {&packed,  &inv,     &endm,   &valid,   &bufA,   &bufB,    &tmpcnt,  &hist,
                      &sbegin,  &cursor,  &cursor2, &order,  &items,  &bins,    &subhist,
                      &leaves,  &dcnt,    &outoff, &state,   &large,  &bsum,    &itemoff,
                      &rlist,   &rleaves, &rcount, &aleaves, &adcnt,  &alarge,  &rparts,
@@ -750,7 +750,7 @@ uint64_t packed_chunks(uint64_t n_bytes) { return (n_bytes + 63) / 64 + 5; }
 
 // The arena buffers a pipeline run needs: f(member, bytes, name) per buffer.
 // The one list both allocation (pipeline_prepare) and the memory estimates of
-// the server (scratch_growth) read.
+// the server (scratch_bytes) read.
 template <class F>
 void pipeline_needs(const Pipe& p, F&& f) {
   const size_t ksz = 8 * p.words;
@@ -784,6 +784,7 @@ void plain_needs(const Pipe& p, F&& f) {
   f(&Ctx::packed, nchunks * 16, "packed bases");
   f(&Ctx::inv, nchunks * 8, "invalid mask");
   f(&Ctx::endm, nchunks * 8, "end mask");
+  f(&Ctx::valid, nchunks * 8, "valid-start mask");
   f(&Ctx::state, sizeof(kc::DevState), "device state");
   f(&Ctx::order, (size_t)(1ull << p.sb) * 4, "owner order");
   pipeline_needs(p, f);
@@ -802,8 +803,11 @@ struct PipeOut {
 void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, const PipeOut& out,
                       hipStream_t st) {
   hipchk(kc::launch_fill_u64((unsigned long long*)c.hist.p, 1ull << p.sb, 0, st), "fill launch");
-  hipchk(kc::launch_window_hist(p.words, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
-                                (uint64_t*)c.endm.p, p.byte_begin, p.byte_end, p.k, p.keybits,
+  hipchk(kc::launch_valid_mask(p.words, (uint64_t*)c.inv.p, (uint64_t*)c.endm.p, p.byte_begin,
+                               p.byte_end, p.k, (uint64_t*)c.valid.p, st),
+         "valid mask launch");
+  hipchk(kc::launch_window_hist(p.words, (uint64_t*)c.packed.p, (uint64_t*)c.valid.p,
+                                p.byte_begin, p.byte_end, p.k, p.keybits,
                                 p.sb, p.batch, (unsigned long long*)c.hist.p, &dstate->W, st),
          "window histogram launch");
   tm.mark(ST_HIST);
@@ -814,8 +818,8 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
                                 (unsigned long long*)c.subhist.p, p.max_leaves, p.max_items,
                                 dstate, st),
          "plan_shards launch");
-  hipchk(kc::launch_window_scatter(p.words, (uint64_t*)c.packed.p, (uint64_t*)c.inv.p,
-                                   (uint64_t*)c.endm.p, p.byte_begin, p.byte_end, p.k, p.keybits,
+  hipchk(kc::launch_window_scatter(p.words, (uint64_t*)c.packed.p, (uint64_t*)c.valid.p,
+                                   p.byte_begin, p.byte_end, p.k, p.keybits,
                                    p.sb, p.batch, (unsigned long long*)c.cursor.p, c.bufA.p,
                                    p.scatter_s, st),
          "owner scatter launch");
@@ -1180,7 +1184,7 @@ uint64_t wave_bytes(uint64_t bytes, const std::map<int, std::pair<uint64_t, uint
   uint64_t pipe = 0;
   for (const auto& kv : by_k)
     pipe = std::max(pipe, class_pipe_bytes(kv.second.first, kv.first, kv.second.second, o));
-  return packed_chunks(bytes) * 32 + alloc_size(bytes * 16) + pipe + n_sets * 96 + (1 << 20);
+  return packed_chunks(bytes) * 40 + alloc_size(bytes * 16) + pipe + n_sets * 96 + (1 << 20);
 }
 
 // Classes of a wave: sets of one k counted together with keys (set id << 2k)
@@ -1389,6 +1393,7 @@ int batch_plan_impl(const uint64_t* host_set_reads, const uint64_t* host_set_byt
   ensure(c.packed, nchunks * 16, "packed bases");
   ensure(c.inv, nchunks * 8, "invalid mask");
   ensure(c.endm, nchunks * 8, "end mask");
+  ensure(c.valid, nchunks * 8, "valid-start mask");
   ensure(c.state, sizeof(kc::DevState), "device state");
   ensure(b->cls_keys, max_out * 8, "class outputs");
   ensure(b->cls_counts, max_out * 4, "class outputs");
@@ -1869,7 +1874,7 @@ int count_in_block(WorkerArena* wa, void* block, uint64_t block_bytes, Slab* spi
   Carve cv{(char*)block, (size_t)block_bytes, 0, false, spill, &spilled};
   Ctx& c = wa->ctx;
   // every buffer is carved afresh from the block for this job
-  DevBuf* all[] = {&c.packed,  &c.inv,     &c.endm,   &c.bufA,    &c.bufB,   &c.tmpcnt,
+  DevBuf* all[] = {&c.packed,  &c.inv,     &c.endm,   &c.valid,   &c.bufA,   &c.bufB,   &c.tmpcnt,
                    &c.hist,    &c.sbegin,  &c.cursor, &c.cursor2, &c.order,  &c.items,
                    &c.bins,    &c.subhist, &c.leaves, &c.dcnt,    &c.outoff, &c.state,
                    &c.large,   &c.bsum,    &c.itemoff, &c.rlist,  &c.rleaves, &c.rcount,
