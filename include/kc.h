@@ -79,7 +79,7 @@ typedef struct kc_options {
   int split_tile;      /* records per thread of the split scatter, likewise 8 or 16
                           (automatic: 16) */
   int refine_bits;     /* key bits by which an overflowed leaf is cut per refinement
-                          level: 1..8 (automatic: 3) */
+                          level: 1..8 (automatic: 5) */
   int preagg;          /* pre-aggregation of equal keys in the split scatter (the
                           heavy-hitter aggregation of Section IV-D): runs of equal keys
                           in a tile's LDS staging leave as one (key, count) record, the
@@ -96,20 +96,23 @@ typedef struct kc_stats {
   uint64_t distinct;       /* D: distinct canonical keys (= *n_out) */
   uint64_t n_leaves;       /* leaf partitions counted */
   uint64_t n_levels;       /* partitioning levels below the shard level */
-  uint64_t n_overflow;     /* leaf attempts that overflowed the table and were split */
+  uint64_t n_overflow;     /* leaf attempts that overflowed their table and were split
+                              (one-word keys: after a second count with a table twice
+                              as large also overflowed) */
   uint64_t max_leaf_windows;
   uint64_t max_owner_windows; /* windows in the largest of the P owner buckets */
   uint64_t refined_records; /* records counted again by the refinement's block-wide
                                leaf launches (parts of overflowed leaves) */
   uint64_t large_records;   /* records counted by the block-wide leaf kernel's own
-                               launch (leaves above the one-wave size) */
+                               launches (leaves above the one-wave size, and the
+                               second count of those that overflowed) */
   uint64_t large_distinct;  /* distinct keys that launch wrote */
   double   ms_total;        /* host wall time of the call */
   double   ms_stage[12];    /* timing=1, device events on the call's stream (ms):
                                0 pack, 1 window histogram, 2 owner scatter (with the shard
                                plan), 3 split histogram, 4 split scatter (with the leaf plan),
                                5 small-leaf count (with leaf classification), 6 large-leaf
-                               count, 7 output offsets, 8 concat, 9 self-check, 10 refinement
+                               count (with the second count of overflowed leaves), 7 output offsets, 8 concat, 9 self-check, 10 refinement
                                of overflowed leaves (its splits and part counts), 11 unused */
 } kc_stats;
 

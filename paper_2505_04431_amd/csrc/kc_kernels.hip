@@ -835,6 +835,13 @@ __global__ void k_splice_parts(const uint32_t* __restrict__ root_leaf,
   }
 }
 
+// Before a second-chance count of overflowed leaves: the flag is raised again
+// by that count's own overflows (and by the output-offset scan, from the leaf
+// counts).
+__global__ void k_clear_overflow(DevState* __restrict__ st) {
+  if (threadIdx.x == 0) st->overflow = 0;
+}
+
 // Leaves above the small-leaf size go to a list of their own (order irrelevant).
 __global__ void k_classify_leaves(const Leaf* __restrict__ leaves, DevState* __restrict__ st,
                                   uint64_t small_max, uint32_t* __restrict__ large) {
@@ -1287,6 +1294,11 @@ __device__ bool occ64(unsigned long long c) { return c != 0; }
 // would mostly fill up and be retried).
 // MERGED: some leaves may hold pre-aggregated records (Leaf::cshift); the
 // plain instantiation has no decoding in its insert loop.
+// list != nullptr: the leaves listed there, *n_list of them (large ones, or
+// those whose table overflowed in an earlier launch); else every leaf of at
+// most small_max records. ovf_list != nullptr: the leaves whose table
+// overflows are also appended there (count in st->n_ovf) for a second launch
+// with a larger table.
 template <int TB, int CMAX, int R, bool FULL_FIRST, bool MERGED>
 __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA, uint64_t* bufB,
                                                      uint32_t* __restrict__ tmp_cnt,
@@ -1295,6 +1307,8 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
                                                      uint32_t* __restrict__ d_out,
                                                      int slots_log2,
                                                      const uint32_t* __restrict__ list,
+                                                     const unsigned long long* __restrict__ n_list,
+                                                     uint32_t* __restrict__ ovf_list,
                                                      uint64_t small_max) {
   __shared__ unsigned long long tk[CMAX];
   __shared__ uint32_t tc[CMAX];
@@ -1305,9 +1319,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
   __shared__ uint32_t s_ovf;  // accessed only through ovf_get / ovf_set
   const unsigned long long EMPTY = ~0ull;
   const uint32_t cmax_rt = 1u << slots_log2;
-  // list != nullptr: the leaves listed there (large ones); else every leaf of
-  // at most small_max records.
-  const unsigned long long count = list ? st->n_large : st->n_leaves;
+  const unsigned long long count = list ? *n_list : st->n_leaves;
   unsigned long long my_records = 0, my_distinct = 0;  // thread 0: this workgroup's totals
   for (unsigned long long it = blockIdx.x; it < count; it += gridDim.x) {
     const unsigned long long l = list ? (unsigned long long)list[it] : it;
@@ -1398,6 +1410,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
       if (threadIdx.x == 0) {
         d_out[l] = kLeafOverflow;
         atomicOr(&st->overflow, 1u);
+        if (ovf_list) ovf_list[atomicAdd(&st->n_ovf, 1ull)] = (uint32_t)l;
       }
       __syncthreads();
       continue;
@@ -2126,6 +2139,12 @@ constexpr int kSplitTB256 = 256;
 constexpr int kSplitR = 8;
 constexpr int kLeafTB = 512;
 constexpr int kLeafCmax64 = 4096;
+// second-chance count of overflowed one-word leaves: 8,192 slots (128 KiB of
+// LDS with the epilogue's counters: one 1,024-thread workgroup per CU)
+constexpr int kRescueTB = 1024;
+constexpr int kRescueCmax64 = 8192;
+constexpr int kRescueSlotsLog2 = 13;
+constexpr unsigned kRescueGrid = 256;
 constexpr int kLeafCmax128 = 2048;
 constexpr int kLeafCmax256 = 2048;  // 44 bytes a slot: key, 64-bit count, sort aux
 constexpr unsigned kPersistentGrid = 1024;  // blocks of the persistent kernels
@@ -2367,7 +2386,8 @@ hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uin
                              bool refine, bool merged) {
   const bool wide = words == 2;
   const uint64_t small_max = mode == 1 ? 0 : small_leaf_max(words);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &st->n_large, (uint64_t)1, 0ull);
+  // n_large and n_ovf
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &st->n_large, (uint64_t)2, 0ull);
   hipLaunchKernelGGL(k_classify_leaves, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s,
                      leaves, st, small_max, large_list);
   if (mode == 1 || words == 4) {  // every non-empty leaf is in the list
@@ -2383,7 +2403,8 @@ hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uin
 #define KC_SMALL64(FF, MG)                                                                       \
   hipLaunchKernelGGL((k_leaf_count64<64, kSmallCmax64, 8, FF, MG>), dim3(gsmall), dim3(64), 0, s, \
                      keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,      \
-                     __builtin_ctz(kSmallCmax64), (const uint32_t*)nullptr, small_max)
+                     __builtin_ctz(kSmallCmax64), (const uint32_t*)nullptr,                      \
+                     (const unsigned long long*)nullptr, (uint32_t*)nullptr, small_max)
   if (wide) {
     if (keybits <= 126) {
       if (refine) KC_SMALLW(true, true); else KC_SMALLW(true, false);
@@ -2405,7 +2426,8 @@ hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uin
 hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
-                             hipStream_t s, int mode, bool refine, bool merged) {
+                             uint32_t* ovf_list, hipStream_t s, int mode, bool refine,
+                             bool merged) {
   const bool wide = words == 2;
   const uint64_t small_max = small_leaf_max(words);
   const unsigned glarge = persistent(max_leaves, kPersistentGrid);
@@ -2428,10 +2450,26 @@ hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uin
   hipLaunchKernelGGL((k_leaf_countw<KT, kLeafTB, CM, 4, HI, FF>), dim3(glarge), dim3(kLeafTB), 0, \
                      s, keybits, (KT*)bufA, (KT*)bufB, tmp_cnt, leaves, st, d_out, slots_log2,   \
                      large_list, small_max)
+  // one-word keys: the leaves whose table overflows are counted again at once
+  // by a workgroup per CU with a table twice as large (a leaf overflows
+  // because of its distinct keys: clusters of keys that share a long prefix,
+  // the erroneous and diverged copies of frequent k-mers, which a split on the
+  // next key bits barely thins out)
+  uint32_t* const second = words == 1 && slots_log2 < kRescueSlotsLog2 ? ovf_list : nullptr;
 #define KC_LARGE64(FF, MG)                                                                      \
-  hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4, FF, MG>), dim3(glarge),            \
-                     dim3(kLeafTB), 0, s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt,    \
-                     leaves, st, d_out, slots_log2, large_list, small_max)
+  do {                                                                                          \
+    hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4, FF, MG>), dim3(glarge),          \
+                       dim3(kLeafTB), 0, s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt,  \
+                       leaves, st, d_out, slots_log2, large_list, &st->n_large, second,          \
+                       small_max);                                                              \
+    if (second) {                                                                               \
+      hipLaunchKernelGGL(k_clear_overflow, dim3(1), dim3(64), 0, s, st);                        \
+      hipLaunchKernelGGL((k_leaf_count64<kRescueTB, kRescueCmax64, 4, true, MG>),               \
+                         dim3(kRescueGrid), dim3(kRescueTB), 0, s, keybits, (uint64_t*)bufA,    \
+                         (uint64_t*)bufB, tmp_cnt, leaves, st, d_out, slots_log2 + 1,           \
+                         (const uint32_t*)second, &st->n_ovf, (uint32_t*)nullptr, small_max);   \
+    }                                                                                           \
+  } while (0)
   if (words == 4) {
     if (refine) KC_LARGEW(u256, kLeafCmax256, false, true);
     else KC_LARGEW(u256, kLeafCmax256, false, false);

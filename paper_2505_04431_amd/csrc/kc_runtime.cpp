@@ -98,9 +98,9 @@ struct Ctx {
   int device = -1;
   DevBuf packed, inv, endm, valid, bufA, bufB, tmpcnt;
   DevBuf hist, sbegin, cursor, cursor2, order, items, bins, subhist, leaves, dcnt, outoff, state;
-  DevBuf large, bsum, itemoff;
+  DevBuf large, ovfl, bsum, itemoff;
   // overflow refinement: overflowed leaves, part attempts, the spliced list
-  DevBuf rlist, rleaves, rcount, aleaves, adcnt, alarge, rparts, rcnt, leaves2, dcnt2;
+  DevBuf rlist, rleaves, rcount, aleaves, adcnt, alarge, aovfl, rparts, rcnt, leaves2, dcnt2;
   DevBuf post;  // temporaries of kc_merge_counts / kc_filter_min_count
   std::vector<int> order_host;
   int order_P = -1, order_sb = -1;
@@ -119,9 +119,9 @@ struct Ctx {
     if (hipGetDevice(&prev) == hipSuccess && device >= 0) (void)hipSetDevice(device);
     DevBuf* all[] = {&packed,  &inv,     &endm,   &valid,   &bufA,   &bufB,    &tmpcnt,  &hist,
                      &sbegin,  &cursor,  &cursor2, &order,  &items,  &bins,    &subhist,
-                     &leaves,  &dcnt,    &outoff, &state,   &large,  &bsum,    &itemoff,
-                     &rlist,   &rleaves, &rcount, &aleaves, &adcnt,  &alarge,  &rparts,
-                     &rcnt,    &leaves2, &dcnt2,  &post};
+                     &leaves,  &dcnt,    &outoff, &state,   &large,  &ovfl,    &bsum,
+                     &itemoff, &rlist,   &rleaves, &rcount, &aleaves, &adcnt,  &alarge,
+                     &aovfl,   &rparts,  &rcnt,   &leaves2, &dcnt2,  &post};
     // the last call's kernels may still read the buffers
     if (done_set) (void)hipEventSynchronize(done);
     for (DevBuf* b : all) drop(*b);
@@ -519,9 +519,13 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
   }
   std::vector<Done> done;
   void* bufs[2] = {c.bufA.p, c.bufB.p};
-  // three bits per level: 10 levels and 133.6 ms against 15 and 140.3 ms (two bits) and
-  // 8 and 134.0 ms (four) on 40,000,000 reads at k = 31
-  const int refine_bits = q.o.refine_bits > 0 ? q.o.refine_bits : 3;
+  // five bits per level. What reaches this point has overflowed a table of twice
+  // the leaf kernel's size as well (one-word keys): a few dense clusters, cut
+  // by 5 bits in 5 levels and 120.2 ms against 8 levels and 123.2 ms (3 bits)
+  // and 4 levels and 120.2 ms (8 bits) on 40,000,000 reads at k = 31. (Before
+  // that second table, 3 bits were best: 4,323 overflowed leaves of 490
+  // million records, and 6 bits made 275,703 parts at the first level.)
+  const int refine_bits = q.o.refine_bits > 0 ? q.o.refine_bits : 5;
   const uint64_t tile = (uint64_t)kc::split_tile(q.words, q.split_r);
   int level = 0;
   while (!split.empty()) {
@@ -609,6 +613,7 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
     grow(c.aleaves, na * sizeof(kc::Leaf), "part table", st);
     grow(c.adcnt, na * 4, "part counts", st);
     grow(c.alarge, na * 4, "large-part list", st);
+    grow(c.aovfl, na * 4, "overflowed-part list", st);
     upload_sync(c.aleaves.p, al.data(), na * sizeof(kc::Leaf), st);
     unsigned long long nlu = na;
     upload_sync(&dst_state->n_leaves, &nlu, 8, st);
@@ -618,8 +623,8 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
            "leaf count launch");
     hipchk(kc::launch_leaf_large(q.words, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
-                                 q.slots_log2, (uint32_t*)c.alarge.p, st, q.o.mode, true,
-                                 q.merged),
+                                 q.slots_log2, (uint32_t*)c.alarge.p, (uint32_t*)c.aovfl.p, st,
+                                 q.o.mode, true, q.merged),
            "leaf count launch");
     tm.mark(ST_REFINE);
     uint32_t* hd = (uint32_t*)host_stage(c, na * 4 + 64);
@@ -770,6 +775,7 @@ void pipeline_needs(const Pipe& p, F&& f) {
   f(&Ctx::dcnt, p.max_leaves * 4, "leaf counts");
   f(&Ctx::outoff, p.max_leaves * 8, "output offsets");
   f(&Ctx::large, p.max_leaves * 4, "large-leaf list");
+  f(&Ctx::ovfl, p.max_leaves * 4, "overflowed-leaf list");
   f(&Ctx::bsum, kc::scan_blocks(p.max_leaves) * 8, "scan block sums");
 }
 
@@ -850,8 +856,8 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
   tm.mark(ST_LEAF_SMALL);
   hipchk(kc::launch_leaf_large(p.words, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
-                               p.slots_log2, (uint32_t*)c.large.p, st, p.mode, false,
-                               p.merge_cshift != 0),
+                               p.slots_log2, (uint32_t*)c.large.p, (uint32_t*)c.ovfl.p, st,
+                               p.mode, false, p.merge_cshift != 0),
          "leaf count launch");
   tm.mark(ST_LEAF);
   hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dstate, (unsigned long long*)c.bsum.p,
@@ -1877,9 +1883,9 @@ int count_in_block(WorkerArena* wa, void* block, uint64_t block_bytes, Slab* spi
   DevBuf* all[] = {&c.packed,  &c.inv,     &c.endm,   &c.valid,   &c.bufA,   &c.bufB,   &c.tmpcnt,
                    &c.hist,    &c.sbegin,  &c.cursor, &c.cursor2, &c.order,  &c.items,
                    &c.bins,    &c.subhist, &c.leaves, &c.dcnt,    &c.outoff, &c.state,
-                   &c.large,   &c.bsum,    &c.itemoff, &c.rlist,  &c.rleaves, &c.rcount,
-                   &c.aleaves, &c.adcnt,   &c.alarge, &c.rparts,  &c.rcnt,   &c.leaves2,
-                   &c.dcnt2,   &c.post};
+                   &c.large,   &c.ovfl,    &c.bsum,   &c.itemoff, &c.rlist, &c.rleaves,
+                   &c.rcount,  &c.aleaves, &c.adcnt,  &c.alarge,  &c.aovfl, &c.rparts,
+                   &c.rcnt,    &c.leaves2, &c.dcnt2,  &c.post};
   for (DevBuf* b : all) *b = DevBuf{};
   c.order_P = c.order_sb = -1;
   g_carve = &cv;
