@@ -42,7 +42,9 @@ def stage_bytes(st: dict, k: int) -> dict:
     the split histogram, read and written by the split scatter, read by the
     leaf count, which writes (key, count) pairs that the concat reads and
     writes to the output. The block-wide leaf kernel's launch reads its
-    records (large_records) and writes its pairs (large_distinct).
+    records (large_records) and writes its pairs (large_distinct); the second
+    count of the leaves whose table overflowed likewise (second_records,
+    second_distinct).
     """
     N = st["n_bases"]
     W = st["valid_windows"]
@@ -56,6 +58,7 @@ def stage_bytes(st: dict, k: int) -> dict:
         "split_hist": K * W,                 # read records
         "split_scatter": 2 * K * W,          # read + write records
         "leaf_large": K * st["large_records"] + (K + 4) * st["large_distinct"],
+        "leaf_second": K * st["second_records"] + (K + 4) * st["second_distinct"],
         "concat": 2 * (K + 4) * D,           # read pairs, write output
     }
 
@@ -63,6 +66,7 @@ def stage_bytes(st: dict, k: int) -> dict:
 KERNEL_NAMES = {  # rocprofv3 names of the kernel behind each single-kernel stage
     ("leaf_large", 1): "k_leaf_count64<512, 4096, 4, false, false>",
     ("leaf_large", 2): "k_leaf_countw<unsigned __int128, 512, 2048, 4, true, false>",
+    ("leaf_second", 1): "k_leaf_count64<1024, 8192, 4, true, false>",
     ("split_scatter", 1): "k_split_scatter<unsigned long, 1024, 16>",
     ("owner_scatter", 1): "k_window_scatter64<unsigned long, unsigned long, 8, 1024, false>",
     ("window_hist", 1): "k_window_hist<unsigned long, unsigned long, 8, 256, false>",
@@ -620,7 +624,8 @@ def main() -> int:
                   "unit": "k-mers/s", "ms_per_step": round(r2["ms_step"], 4),
                   "ms_median": round(float(np.median(r2["step_ms"])), 4),
                   "valid_windows": s2["valid_windows"], "distinct": r2["n_out"],
-                  "refined_leaves": s2["n_overflow"],
+                  "second_count_records": s2["second_records"],
+                  "refined_leaves": s2["n_overflow"], "refined_records": s2["refined_records"],
                   "roofline": roofline_of(r2, k2, cfg["name"], copy_gbs, ceil)}
     t_h2d = h2d_ms(torch, dev, reads, offs)
     del rt, ot, keys, cnts
@@ -757,7 +762,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": cfg["name"], "k": k, "P": P, "reads": len(offs) - 1,
                    "read_len": 150, "valid_windows": W, "distinct": head["n_out"],
-                   "refined_leaves": st["n_overflow"], "mode": "plain"},
+                   "second_count_records": st["second_records"],
+                   "refined_leaves": st["n_overflow"], "refined_records": st["refined_records"],
+                   "mode": "plain"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "second_k": second,

@@ -104,16 +104,19 @@ typedef struct kc_stats {
   uint64_t refined_records; /* records counted again by the refinement's block-wide
                                leaf launches (parts of overflowed leaves) */
   uint64_t large_records;   /* records counted by the block-wide leaf kernel's own
-                               launches (leaves above the one-wave size, and the
-                               second count of those that overflowed) */
+                               launch (leaves above the one-wave size) */
   uint64_t large_distinct;  /* distinct keys that launch wrote */
+  uint64_t second_records;  /* records counted by the second count of overflowed
+                               leaves (one-word keys), refinement excluded */
+  uint64_t second_distinct; /* distinct keys it wrote */
   double   ms_total;        /* host wall time of the call */
   double   ms_stage[12];    /* timing=1, device events on the call's stream (ms):
                                0 pack, 1 window histogram, 2 owner scatter (with the shard
                                plan), 3 split histogram, 4 split scatter (with the leaf plan),
                                5 small-leaf count (with leaf classification), 6 large-leaf
-                               count (with the second count of overflowed leaves), 7 output offsets, 8 concat, 9 self-check, 10 refinement
-                               of overflowed leaves (its splits and part counts), 11 unused */
+                               count, 7 output offsets, 8 concat, 9 self-check, 10 refinement
+                               of overflowed leaves (its splits and part counts), 11 second
+                               count of the leaves whose table overflowed (one-word keys) */
 } kc_stats;
 
 /* Count canonical k-mers (plain form).

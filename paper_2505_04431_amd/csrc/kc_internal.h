@@ -48,6 +48,7 @@ struct DevState {
   unsigned long long n_large;   // leaves handled by the block-wide leaf kernel
   unsigned long long n_ovf;     // of those, leaves whose table overflowed (second-chance list)
   unsigned long long large_records, large_distinct;  // work of the block-wide leaf kernel
+  unsigned long long second_records, second_distinct;  // work of its second count
   unsigned int overflow;        // a leaf table overflowed (device-planned path cannot finish)
   unsigned int count_overflow;  // a count exceeds 2^32-1
   unsigned int pad[2];
@@ -157,9 +158,7 @@ hipError_t launch_leaf_ends(Leaf* leaves, const unsigned long long* cursor, cons
 // the launches are separate kernel instantiations, so profiles tell them apart).
 // merged: leaves may hold pre-aggregated records (one-word keys).
 // ovf_list (max_leaves entries, or nullptr): one-word keys in mode 0 list
-// there the leaves whose table overflows, and a second launch counts them
-// with a table twice as large (one 1,024-thread workgroup per CU); only what
-// overflows that table too stays marked overflowed.
+// there the leaves whose table overflows, for launch_leaf_second.
 hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode,
@@ -169,6 +168,14 @@ hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uin
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,
                              uint32_t* ovf_list, hipStream_t s, int mode, bool refine,
                              bool merged);
+// Second count of the leaves launch_leaf_large listed in ovf_list, with a
+// table twice as large (one 1,024-thread workgroup per CU); only what
+// overflows that table too stays marked overflowed (st->overflow is raised
+// again by those, and by launch_plan_out from the leaf counts). A no-op
+// where launch_leaf_large lists nothing.
+hipError_t launch_leaf_second(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
+                              const Leaf* leaves, DevState* st, uint32_t* d_out, int slots_log2,
+                              const uint32_t* ovf_list, hipStream_t s, int mode, bool merged);
 uint64_t small_leaf_max(int words);
 
 // Exclusive scan of leaf counts into output offsets; st->D = total. bsum

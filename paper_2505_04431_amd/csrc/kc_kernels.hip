@@ -1295,10 +1295,11 @@ __device__ bool occ64(unsigned long long c) { return c != 0; }
 // MERGED: some leaves may hold pre-aggregated records (Leaf::cshift); the
 // plain instantiation has no decoding in its insert loop.
 // list != nullptr: the leaves listed there, *n_list of them (large ones, or
-// those whose table overflowed in an earlier launch); else every leaf of at
-// most small_max records. ovf_list != nullptr: the leaves whose table
-// overflows are also appended there (count in st->n_ovf) for a second launch
-// with a larger table.
+// those whose table overflowed in an earlier launch), with the records and
+// distinct keys of the leaves counted added to acc[0] and acc[1]; else every
+// leaf of at most small_max records. ovf_list != nullptr: the leaves whose
+// table overflows are also appended there (count in st->n_ovf) for a second
+// launch with a larger table.
 template <int TB, int CMAX, int R, bool FULL_FIRST, bool MERGED>
 __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA, uint64_t* bufB,
                                                      uint32_t* __restrict__ tmp_cnt,
@@ -1309,6 +1310,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
                                                      const uint32_t* __restrict__ list,
                                                      const unsigned long long* __restrict__ n_list,
                                                      uint32_t* __restrict__ ovf_list,
+                                                     unsigned long long* __restrict__ acc,
                                                      uint64_t small_max) {
   __shared__ unsigned long long tk[CMAX];
   __shared__ uint32_t tc[CMAX];
@@ -1447,8 +1449,8 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
   // one update of the shared totals per workgroup (not per leaf: same-address
   // atomics from every workgroup would serialise)
   if (list && threadIdx.x == 0 && my_records) {
-    atomicAdd(&st->large_records, my_records);
-    atomicAdd(&st->large_distinct, my_distinct);
+    atomicAdd(&acc[0], my_records);
+    atomicAdd(&acc[1], my_distinct);
   }
 }
 
@@ -2404,7 +2406,8 @@ hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uin
   hipLaunchKernelGGL((k_leaf_count64<64, kSmallCmax64, 8, FF, MG>), dim3(gsmall), dim3(64), 0, s, \
                      keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt, leaves, st, d_out,      \
                      __builtin_ctz(kSmallCmax64), (const uint32_t*)nullptr,                      \
-                     (const unsigned long long*)nullptr, (uint32_t*)nullptr, small_max)
+                     (const unsigned long long*)nullptr, (uint32_t*)nullptr, &st->large_records, \
+                     small_max)
   if (wide) {
     if (keybits <= 126) {
       if (refine) KC_SMALLW(true, true); else KC_SMALLW(true, false);
@@ -2450,26 +2453,14 @@ hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uin
   hipLaunchKernelGGL((k_leaf_countw<KT, kLeafTB, CM, 4, HI, FF>), dim3(glarge), dim3(kLeafTB), 0, \
                      s, keybits, (KT*)bufA, (KT*)bufB, tmp_cnt, leaves, st, d_out, slots_log2,   \
                      large_list, small_max)
-  // one-word keys: the leaves whose table overflows are counted again at once
-  // by a workgroup per CU with a table twice as large (a leaf overflows
-  // because of its distinct keys: clusters of keys that share a long prefix,
-  // the erroneous and diverged copies of frequent k-mers, which a split on the
-  // next key bits barely thins out)
+  // one-word keys: the leaves whose table overflows are listed for
+  // launch_leaf_second
   uint32_t* const second = words == 1 && slots_log2 < kRescueSlotsLog2 ? ovf_list : nullptr;
 #define KC_LARGE64(FF, MG)                                                                      \
-  do {                                                                                          \
-    hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4, FF, MG>), dim3(glarge),          \
-                       dim3(kLeafTB), 0, s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt,  \
-                       leaves, st, d_out, slots_log2, large_list, &st->n_large, second,          \
-                       small_max);                                                              \
-    if (second) {                                                                               \
-      hipLaunchKernelGGL(k_clear_overflow, dim3(1), dim3(64), 0, s, st);                        \
-      hipLaunchKernelGGL((k_leaf_count64<kRescueTB, kRescueCmax64, 4, true, MG>),               \
-                         dim3(kRescueGrid), dim3(kRescueTB), 0, s, keybits, (uint64_t*)bufA,    \
-                         (uint64_t*)bufB, tmp_cnt, leaves, st, d_out, slots_log2 + 1,           \
-                         (const uint32_t*)second, &st->n_ovf, (uint32_t*)nullptr, small_max);   \
-    }                                                                                           \
-  } while (0)
+  hipLaunchKernelGGL((k_leaf_count64<kLeafTB, kLeafCmax64, 4, FF, MG>), dim3(glarge),            \
+                     dim3(kLeafTB), 0, s, keybits, (uint64_t*)bufA, (uint64_t*)bufB, tmp_cnt,    \
+                     leaves, st, d_out, slots_log2, large_list, &st->n_large, second,            \
+                     &st->large_records, small_max)
   if (words == 4) {
     if (refine) KC_LARGEW(u256, kLeafCmax256, false, true);
     else KC_LARGEW(u256, kLeafCmax256, false, false);
@@ -2490,6 +2481,29 @@ hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uin
   }
 #undef KC_LARGEW
 #undef KC_LARGE64
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_second(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
+                              const Leaf* leaves, DevState* st, uint32_t* d_out, int slots_log2,
+                              const uint32_t* ovf_list, hipStream_t s, int mode, bool merged) {
+  if (words != 1 || mode == 1 || slots_log2 >= kRescueSlotsLog2 || !ovf_list) return hipSuccess;
+  // the leaves whose table overflowed are counted again at once by a
+  // workgroup per CU with a table twice as large (a leaf overflows because of
+  // its distinct keys: clusters of keys that share a long prefix, the
+  // erroneous and diverged copies of frequent k-mers, which a split on the
+  // next key bits barely thins out)
+  hipLaunchKernelGGL(k_clear_overflow, dim3(1), dim3(64), 0, s, st);
+  if (merged)
+    hipLaunchKernelGGL((k_leaf_count64<kRescueTB, kRescueCmax64, 4, true, true>),
+                       dim3(kRescueGrid), dim3(kRescueTB), 0, s, keybits, (uint64_t*)bufA,
+                       (uint64_t*)bufB, tmp_cnt, leaves, st, d_out, slots_log2 + 1, ovf_list,
+                       &st->n_ovf, (uint32_t*)nullptr, &st->second_records, (uint64_t)0);
+  else
+    hipLaunchKernelGGL((k_leaf_count64<kRescueTB, kRescueCmax64, 4, true, false>),
+                       dim3(kRescueGrid), dim3(kRescueTB), 0, s, keybits, (uint64_t*)bufA,
+                       (uint64_t*)bufB, tmp_cnt, leaves, st, d_out, slots_log2 + 1, ovf_list,
+                       &st->n_ovf, (uint32_t*)nullptr, &st->second_records, (uint64_t)0);
   return hipGetLastError();
 }
 

@@ -358,7 +358,7 @@ struct Timer {
 
 enum { ST_PACK = 0, ST_HIST = 1, ST_SCATTER = 2, ST_SPLIT_HIST = 3, ST_SPLIT = 4,
        ST_LEAF_SMALL = 5, ST_LEAF = 6, ST_OUT = 7, ST_CONCAT = 8, ST_CHECK = 9, ST_REFINE = 10,
-       ST_NONE = -1 };
+       ST_LEAF_SECOND = 11, ST_NONE = -1 };
 
 // Batch layout check: set s must own the bytes [set_byte_off[s], set_byte_off[s+1])
 // of the stream, i.e. offsets[set_first_read[s]] - offsets[0] == set_byte_off[s].
@@ -626,6 +626,10 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
                                  q.slots_log2, (uint32_t*)c.alarge.p, (uint32_t*)c.aovfl.p, st,
                                  q.o.mode, true, q.merged),
            "leaf count launch");
+    hipchk(kc::launch_leaf_second(q.words, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                                  (kc::Leaf*)c.aleaves.p, dst_state, (uint32_t*)c.adcnt.p,
+                                  q.slots_log2, (uint32_t*)c.aovfl.p, st, q.o.mode, q.merged),
+           "leaf count launch");
     tm.mark(ST_REFINE);
     uint32_t* hd = (uint32_t*)host_stage(c, na * 4 + 64);
     hipchk(hipMemcpyAsync(hd, c.adcnt.p, na * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
@@ -860,6 +864,11 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
                                p.mode, false, p.merge_cshift != 0),
          "leaf count launch");
   tm.mark(ST_LEAF);
+  hipchk(kc::launch_leaf_second(p.words, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
+                                (kc::Leaf*)c.leaves.p, dstate, (uint32_t*)c.dcnt.p, p.slots_log2,
+                                (uint32_t*)c.ovfl.p, st, p.mode, p.merge_cshift != 0),
+         "leaf count launch");
+  tm.mark(ST_LEAF_SECOND);
   hipchk(kc::launch_plan_out((uint32_t*)c.dcnt.p, dstate, (unsigned long long*)c.bsum.p,
                              p.max_leaves, (unsigned long long*)c.outoff.p, st),
          "plan_out launch");
@@ -1039,6 +1048,8 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   // the block-wide leaf kernel's own launch (refinement launches are counted apart)
   S.large_records = ds.large_records;
   S.large_distinct = ds.large_distinct;
+  S.second_records = ds.second_records;
+  S.second_distinct = ds.second_distinct;
   if (ds.overflow) {
     // some leaves had more distinct keys than their tables hold: partition
     // those further and count their parts
@@ -1048,7 +1059,8 @@ int count_impl(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, 
   }
   S.valid_windows = ds.W;
   S.distinct = ds.D;
-  S.refined_records = ds.large_records - S.large_records;
+  S.refined_records =
+      ds.large_records + ds.second_records - S.large_records - S.second_records;
   if (ds.count_overflow) fail(KC_E_OVERFLOW, "a k-mer occurs more than 2^32-1 times");
   if (oa) {
     const int r = oa->fn(oa->user, ds.D, q.words, &out_keys, &out_counts);
@@ -1543,6 +1555,8 @@ uint64_t run_wave(kc_batch* b, uint32_t wi, const uint8_t* reads, const uint64_t
     w.stats.n_leaves += ds.n_leaves;
     w.stats.large_records += ds.large_records;
     w.stats.large_distinct += ds.large_distinct;
+    w.stats.second_records += ds.second_records;
+    w.stats.second_distinct += ds.second_distinct;
   }
   w.stats.n_bases = w.nbytes;
   std::memcpy(host_set_off, hs + nst * sizeof(kc::DevState), (w.ns + 1) * 8);
@@ -1606,6 +1620,8 @@ int batch_run_impl(kc_batch* b, const uint8_t* reads, const uint64_t* offsets, u
     b->stats.n_overflow += ws.n_overflow;
     b->stats.large_records += ws.large_records;
     b->stats.large_distinct += ws.large_distinct;
+    b->stats.second_records += ws.second_records;
+    b->stats.second_distinct += ws.second_distinct;
   }
   *n_out = base;
   b->stats.ms_total =

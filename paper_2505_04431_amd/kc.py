@@ -50,7 +50,8 @@ class KcStats(ctypes.Structure):
                 ("n_levels", ctypes.c_uint64), ("n_overflow", ctypes.c_uint64),
                 ("max_leaf_windows", ctypes.c_uint64), ("max_owner_windows", ctypes.c_uint64),
                 ("refined_records", ctypes.c_uint64), ("large_records", ctypes.c_uint64),
-                ("large_distinct", ctypes.c_uint64), ("ms_total", ctypes.c_double),
+                ("large_distinct", ctypes.c_uint64), ("second_records", ctypes.c_uint64),
+                ("second_distinct", ctypes.c_uint64), ("ms_total", ctypes.c_double),
                 ("ms_stage", ctypes.c_double * 12)]
 
 
@@ -98,7 +99,7 @@ def measure_ceilings(table_bytes: int = 4 << 30, stream=None) -> dict:
 
 
 STAGES = ["pack", "window_hist", "owner_scatter", "split_hist", "split_scatter", "leaf_small",
-          "leaf_large", "out_offsets", "concat", "check", "refine", "unused11"]
+          "leaf_large", "out_offsets", "concat", "check", "refine", "leaf_second"]
 
 
 class KcError(RuntimeError):

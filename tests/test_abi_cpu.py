@@ -47,9 +47,9 @@ def test_max_outputs_and_strerror():
 
 
 def test_options_layout_matches_header():
-    # kc_options: 7 ints + 5 reserved; kc_stats: 11 uint64 + 13 doubles
+    # kc_options: 11 ints + 1 reserved; kc_stats: 13 uint64 + 13 doubles
     assert ctypes.sizeof(kc.kc.KcOptions) == 12 * 4
-    assert ctypes.sizeof(kc.kc.KcStats) == 11 * 8 + 13 * 8
+    assert ctypes.sizeof(kc.kc.KcStats) == 13 * 8 + 13 * 8
 
 
 def test_struct_layouts_match_c_compiler(tmp_path):
