@@ -1949,22 +1949,39 @@ __global__ void __launch_bounds__(256) k_concat(const K* __restrict__ bufA,
     const Leaf lf = leaves[l];
     const K* src = lf.buf ? bufA : bufB;  // sorted pairs sit in the other buffer
     const unsigned long long base = out_off[l];
-    for (uint32_t i = lane; i < n; i += 64) {
-      const uint64_t o = base + i;
-      if (o >= cap) break;
-      const K key = src[lf.begin + i];
-      if constexpr (Key<K>::kWords == 4) {
-        out_keys[4 * o] = (uint64_t)key.lo;
-        out_keys[4 * o + 1] = (uint64_t)(key.lo >> 64);
-        out_keys[4 * o + 2] = (uint64_t)key.hi;
-        out_keys[4 * o + 3] = (uint64_t)(key.hi >> 64);
-      } else if constexpr (Key<K>::kWords == 2) {
-        out_keys[2 * o] = (uint64_t)key;
-        out_keys[2 * o + 1] = (uint64_t)((u128)key >> 64);
-      } else {
-        out_keys[o] = (uint64_t)key;
+    // U pairs per lane per step, all loaded before any is stored (more bytes
+    // in flight per wave)
+    constexpr uint32_t U = Key<K>::kWords == 4 ? 1 : 4;
+    const uint64_t lim = base >= cap ? 0 : min((uint64_t)n, cap - base);
+    for (uint32_t i0 = 0; i0 < lim; i0 += 64 * U) {
+      K key[U];
+      uint32_t cnt[U];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t i = i0 + u * 64 + lane;
+        if (i < lim) {
+          key[u] = src[lf.begin + i];
+          cnt[u] = tmp_cnt[lf.begin + i];
+        }
       }
-      out_counts[o] = tmp_cnt[lf.begin + i];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t i = i0 + u * 64 + lane;
+        if (i >= lim) break;
+        const uint64_t o = base + i;
+        if constexpr (Key<K>::kWords == 4) {
+          out_keys[4 * o] = (uint64_t)key[u].lo;
+          out_keys[4 * o + 1] = (uint64_t)(key[u].lo >> 64);
+          out_keys[4 * o + 2] = (uint64_t)key[u].hi;
+          out_keys[4 * o + 3] = (uint64_t)(key[u].hi >> 64);
+        } else if constexpr (Key<K>::kWords == 2) {
+          out_keys[2 * o] = (uint64_t)key[u];
+          out_keys[2 * o + 1] = (uint64_t)((u128)key[u] >> 64);
+        } else {
+          out_keys[o] = (uint64_t)key[u];
+        }
+        out_counts[o] = cnt[u];
+      }
     }
   }
 }
@@ -1990,13 +2007,28 @@ __global__ void __launch_bounds__(256) k_concat_batch(
     const Leaf lf = leaves[l];
     const K* src = lf.buf ? bufA : bufB;
     const unsigned long long base = out_off[l];
-    for (uint32_t i = lane; i < n; i += 64) {
-      const uint64_t o = base + i;
-      if (o >= cap) break;
-      const K key = src[lf.begin + i];
-      out_keys[o] = (uint64_t)(key & kmask);
-      out_set[o] = has_set_bits ? (uint32_t)(key >> (2 * k)) : 0u;
-      out_counts[o] = tmp_cnt[lf.begin + i];
+    constexpr uint32_t U = 4;  // as in k_concat
+    const uint64_t lim = base >= cap ? 0 : min((uint64_t)n, cap - base);
+    for (uint32_t i0 = 0; i0 < lim; i0 += 64 * U) {
+      K key[U];
+      uint32_t cnt[U];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t i = i0 + u * 64 + lane;
+        if (i < lim) {
+          key[u] = src[lf.begin + i];
+          cnt[u] = tmp_cnt[lf.begin + i];
+        }
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t i = i0 + u * 64 + lane;
+        if (i >= lim) break;
+        const uint64_t o = base + i;
+        out_keys[o] = (uint64_t)(key[u] & kmask);
+        out_set[o] = has_set_bits ? (uint32_t)(key[u] >> (2 * k)) : 0u;
+        out_counts[o] = cnt[u];
+      }
     }
   }
 }
