@@ -986,19 +986,25 @@ __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
   __shared__ unsigned long long gbase[NS];
   __shared__ uint32_t wsum[TB / 64];
   const unsigned long long n_items = st->n_items;
+  // the records of the workgroup's next item are loaded while the current
+  // one's runs leave LDS (its keys' registers are free once it is staged)
+  K key[R];
+  SplitItem it = blockIdx.x < n_items ? items[blockIdx.x] : SplitItem{0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const uint64_t r = it.begin + threadIdx.x + (uint64_t)j * TB;
+    if (r < it.end) key[j] = src[r];
+  }
   for (unsigned long long w = blockIdx.x; w < n_items; w += gridDim.x) {
-    const SplitItem it = items[w];
     const SplitBin bn = bins[it.bin];
     const int nsub = 1 << bn.nbits;
     for (int i = threadIdx.x; i < nsub; i += TB) hist[i] = 0;
     __syncthreads();
-    K key[R];
     uint32_t sub[R], rank[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const uint64_t r = it.begin + threadIdx.x + (uint64_t)j * TB;
       if (r < it.end) {
-        key[j] = src[r];
         sub[j] = Key<K>::bits(key[j], bn.shift, bn.nbits);
         rank[j] = atomicAdd(&hist[sub[j]], 1u);
       }
@@ -1018,11 +1024,19 @@ __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
       }
     }
     __syncthreads();
+    const unsigned long long wn = w + gridDim.x;
+    const SplitItem nx = wn < n_items ? items[wn] : SplitItem{0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint64_t r = nx.begin + threadIdx.x + (uint64_t)j * TB;
+      if (r < nx.end) key[j] = src[r];
+    }
     for (uint32_t j = threadIdx.x; j < total; j += TB) {
       const K kk = stage[j];
       const uint32_t b = Key<K>::bits(kk, bn.shift, bn.nbits);
       dst[gbase[b] + (j - loff[b])] = kk;
     }
+    it = nx;
     __syncthreads();
   }
 }
