@@ -199,6 +199,10 @@ hipError_t launch_splice(const Leaf* leaves, const uint32_t* d, uint64_t n,
                          unsigned long long* bsum, unsigned long long* pos, Leaf* out,
                          uint32_t* out_d, hipStream_t s);
 
+// Output of the leaves in key order (up to cap pairs). Does nothing while
+// st->overflow is set: the host refines the overflowed leaves first and
+// launches it again (the concat of a batch class likewise: the class is
+// recounted set by set).
 hipError_t launch_concat(int words, const void* bufA, const void* bufB, const uint32_t* tmp_cnt,
                          const Leaf* leaves, const uint32_t* d, const unsigned long long* out_off,
                          const DevState* st, uint64_t max_leaves, uint64_t cap,

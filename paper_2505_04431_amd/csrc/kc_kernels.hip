@@ -1952,6 +1952,9 @@ __global__ void __launch_bounds__(256) k_concat(const K* __restrict__ bufA,
                                                 const DevState* __restrict__ st, uint64_t cap,
                                                 uint64_t* __restrict__ out_keys,
                                                 uint32_t* __restrict__ out_counts) {
+  // a leaf overflowed: the host refines it and concatenates afterwards, so
+  // this launch (enqueued before the host could know) has nothing to do
+  if (st->overflow) return;
   // one wave per leaf, many leaves in flight per CU
   const unsigned long long n_leaves = st->n_leaves;
   const unsigned lane = threadIdx.x & 63;
@@ -2009,6 +2012,7 @@ __global__ void __launch_bounds__(256) k_concat_batch(
     const unsigned long long* __restrict__ out_off, const DevState* __restrict__ st, uint64_t cap,
     int k, uint64_t* __restrict__ out_keys, uint32_t* __restrict__ out_counts,
     uint32_t* __restrict__ out_set) {
+  if (st->overflow) return;  // the class is recounted set by set
   const unsigned long long n_leaves = st->n_leaves;
   const unsigned lane = threadIdx.x & 63;
   const unsigned long long nw = (unsigned long long)gridDim.x * 4;
