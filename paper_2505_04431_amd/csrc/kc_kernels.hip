@@ -1387,30 +1387,46 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
         const uint64_t r = base + (uint64_t)j * TB + threadIdx.x;
         kb[j] = r < lf.end ? src[r] : EMPTY;
       }
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        unsigned long long key = kb[j];
-        uint32_t cnt = 1;
+      // one probe loop over the thread's R records: a lane moves on to its
+      // next record as soon as the current one is placed, so a wave runs
+      // about as many iterations as its slowest lane's probes in total, not
+      // the sum over the R records of the slowest lane's probes (records past
+      // the leaf's end, EMPTY, come last)
+      unsigned long long key = EMPTY;
+      uint32_t cnt = 1, pos = 0, probes = 0;
+      int j = 0;
+      auto take = [&](unsigned long long x) {
+        key = x;
+        cnt = 1;
         if constexpr (MERGED) {
-          if (cshift && key != EMPTY) {  // uniform per leaf
-            cnt = (uint32_t)(key >> cshift) + 1u;
-            key = top | (key & low);
+          if (cshift) {  // uniform per leaf
+            cnt = (uint32_t)(x >> cshift) + 1u;
+            key = top | (x & low);
             my_windows += cnt;
           }
         }
-        uint32_t pos = slot_hash(key, slot_bits);
-        bool todo = key != EMPTY;
-        uint32_t probes = 0;
-        while (todo) {
-          const unsigned long long prev = atomicCAS(&tk[pos], EMPTY, key);
-          const bool hit = (prev == EMPTY) | (prev == key);
-          if (hit) {
-            atomicAdd(&tc[pos], cnt);
-            if (track && prev == EMPTY && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
-          }
+        pos = slot_hash(key, slot_bits);
+        probes = 0;
+      };
+      bool todo = kb[0] != EMPTY;
+      if (todo) take(kb[0]);
+      while (todo) {
+        const unsigned long long prev = atomicCAS(&tk[pos], EMPTY, key);
+        const bool hit = (prev == EMPTY) | (prev == key);
+        if (hit) {
+          atomicAdd(&tc[pos], cnt);
+          if (track && prev == EMPTY && atomicAdd(&s_nd, 1u) + 1 >= limit) ovf_set(&s_ovf);
+          ++j;
+          unsigned long long nx = EMPTY;
+#pragma unroll
+          for (int q = 1; q < R; ++q)
+            if (j == q) nx = kb[q];
+          todo = nx != EMPTY;
+          if (todo) take(nx);
+        } else {
           pos = (pos + 1) & cmask;
-          todo = !hit & (++probes < Cn);
-          if (!hit && probes >= Cn) ovf_set(&s_ovf);
+          todo = ++probes < Cn;
+          if (!todo) ovf_set(&s_ovf);  // table full: the leaf overflows
         }
       }
     }
