@@ -274,8 +274,8 @@ def batched_leg(n_sets: int, budget_gib: float, tune: bool) -> dict:
                                            ks[:w0["n_sets"]], P=1, opts=kc.options(**o))
             cur["plan"].run_into(rt, ot, keys, cnts, cap)
             torch.cuda.synchronize()
-        cands = [{}, {"split_tile": 8}, {"scatter_tile": 16}, {"leaf_target": 2560},
-                 {"leaf_target": 3500}, {"table_slots_log2": 11}]
+        cands = [{}, {"split_tile": 8}, {"scatter_tile": 16}, {"leaf_target": 3072},
+                 {"leaf_target": 8192}, {"table_slots_log2": 11}]
         tune_info = tuner.tune(tuner.class_key("batch", ks[:w0["n_sets"]], r0.size), run,
                                candidates=cands, reps=2, use_cache=False)
         tuned = tune_info["options"]

@@ -59,7 +59,9 @@ extern "C" {
 typedef struct kc_options {
   int shard_bits;      /* log2 of the number of first-level key-range shards
                           (owner buckets are unions of shards); 1..10 */
-  int leaf_target;     /* target valid windows per leaf partition when splitting */
+  int leaf_target;     /* target valid windows per leaf partition when splitting
+                          (automatic: 1.5 x the largest table for k <= 32, 0.75 x
+                          for wider keys) */
   int leaf_attempt;    /* partitions up to this many windows are counted directly */
   int table_slots_log2;/* log2 of the largest LDS open-addressing table per leaf
                           (10..12 for k<=32, 10..11 for k>32) */

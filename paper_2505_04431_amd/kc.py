@@ -245,14 +245,29 @@ def _check_tensor(t, what, dtypes):
         raise ValueError("%s must be contiguous" % what)
 
 
+def _check_outputs(out_keys, out_counts, capacity: int, k: int) -> None:
+    # the library writes up to capacity keys of key_words(k) words each: the
+    # tensors must hold them (it cannot check raw pointers itself)
+    if not 1 <= k <= 128:
+        return  # the library refuses k itself
+    if out_keys.numel() < capacity * key_words(k):
+        raise ValueError("out_keys holds %d words; capacity %d at k = %d needs %d"
+                         % (out_keys.numel(), capacity, k, capacity * key_words(k)))
+    if out_counts.numel() < capacity:
+        raise ValueError("out_counts holds %d counts; capacity is %d" % (out_counts.numel(), capacity))
+
+
 def count_into(reads, offsets, k: int, P: int, out_keys, out_counts, capacity: int,
                opts: KcOptions | None = None, stream=None) -> int:
-    """Call kc_count_ex on torch device tensors; returns the number of keys written."""
+    """Call kc_count_ex on torch device tensors; returns the number of keys written.
+    out_keys must hold capacity * key_words(k) int64 words, out_counts capacity
+    counts (checked)."""
     import torch
     _check_tensor(reads, "reads", (torch.uint8,))
     _check_tensor(offsets, "offsets", (torch.int64, torch.uint64))
     _check_tensor(out_keys, "out_keys", (torch.int64, torch.uint64))
     _check_tensor(out_counts, "out_counts", (torch.int32, torch.uint32))
+    _check_outputs(out_keys, out_counts, capacity, k)
     if stream is None:
         stream = torch.cuda.current_stream(reads.device).cuda_stream
     n_out = ctypes.c_uint64(0)
@@ -269,12 +284,14 @@ def count_into(reads, offsets, k: int, P: int, out_keys, out_counts, capacity: i
 def count_noalloc_into(reads, offsets, k: int, P: int, out_keys, out_counts, capacity: int,
                        opts: KcOptions | None = None, stream=None) -> int:
     """Call kc_count_noalloc (the allocation-free form: fixed device scratch,
-    synchronous) on torch device tensors; returns the number of keys written."""
+    synchronous) on torch device tensors; returns the number of keys written
+    (outputs checked as in count_into)."""
     import torch
     _check_tensor(reads, "reads", (torch.uint8,))
     _check_tensor(offsets, "offsets", (torch.int64, torch.uint64))
     _check_tensor(out_keys, "out_keys", (torch.int64, torch.uint64))
     _check_tensor(out_counts, "out_counts", (torch.int32, torch.uint32))
+    _check_outputs(out_keys, out_counts, capacity, k)
     if stream is None:
         stream = torch.cuda.current_stream(reads.device).cuda_stream
     n_out = ctypes.c_uint64(0)

@@ -17,10 +17,10 @@ from . import kc
 
 DEFAULT_CANDIDATES = [
     {},
-    {"leaf_target": 2560},
-    {"leaf_target": 3500},
-    {"leaf_target": 3500, "shard_bits": 9},
-    {"leaf_target": 3500, "shard_bits": 10},
+    {"leaf_target": 3072},
+    {"leaf_target": 8192},
+    {"leaf_target": 8192, "shard_bits": 9},
+    {"scatter_tile": 16},
     {"table_slots_log2": 11},
 ]
 

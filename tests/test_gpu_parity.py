@@ -169,6 +169,26 @@ def test_error_paths():
     assert e.value.status == -1
 
 
+def test_output_tensors_too_small_are_refused():
+    """The binding refuses output tensors that cannot hold `capacity` keys of
+    the key width (the library itself only sees raw pointers)."""
+    import torch
+    import paper_2505_04431_amd as kc
+    r, o = to_arrays(["ACGTACGTACGTTTGCA" * 8])
+    rt, ot = to_device(r, o)
+    dev = rt.device
+    for k, words in ((31, 1), (55, 2), (100, 4)):
+        short_keys = torch.empty(8 * words - 1, dtype=torch.int64, device=dev)
+        cnt = torch.empty(8, dtype=torch.int32, device=dev)
+        with pytest.raises(ValueError):
+            kc.count_into(rt, ot, k, 1, short_keys, cnt, 8)
+        with pytest.raises(ValueError):
+            kc.count_noalloc_into(rt, ot, k, 1, short_keys, cnt, 8)
+        keys = torch.empty(8 * words, dtype=torch.int64, device=dev)
+        with pytest.raises(ValueError):
+            kc.count_into(rt, ot, k, 1, keys, cnt[:7], 8)
+
+
 def test_config2_full_element_wise():
     """The benchmark workload (5 Mbp + repeats, 1M reads, k=31, P=64), full size."""
     c = synth.make_config(2)
