@@ -547,6 +547,18 @@ __device__ __forceinline__ uint32_t window_keys(const uint64_t* __restrict__ pac
   }
 }
 
+// 24 bits of the packed stream (p1:p0) from bit q (q < 128 - 24).
+__device__ __forceinline__ uint32_t bits24(uint64_t p0, uint64_t p1, int q) {
+  const uint64_t lo = q >= 64 ? p1 >> (q - 64) : (p0 >> q) | (q ? p1 << (64 - q) : 0ull);
+  return (uint32_t)lo & 0xFFFFFFu;
+}
+
+// Five 2-bit bases in stream order (first base in the low bits) as a 10-bit
+// value with the first base most significant.
+__device__ __forceinline__ uint32_t rev5(uint32_t x) {
+  return ((x & 0x3u) << 8) | ((x & 0xCu) << 4) | (x & 0x30u) | ((x >> 4) & 0xCu) | (x >> 8);
+}
+
 // Threads t in [t_begin, t_end) each take window starts [t*S, t*S + S).
 template <typename K, typename Kc, int S, int TB, bool BATCH>
 __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__ packed,
@@ -565,6 +577,28 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
     const uint64_t g = t * S;
     uint32_t vm = valid_starts<S>(valid, g);
     if (!vm) continue;
+    if constexpr (!BATCH && std::is_same<Kc, uint64_t>::value && S <= 8) {
+      if (k >= 5) {
+        // only the shard is needed: the top bits of min(fwd, rc) are the
+        // smaller of the top bits of fwd and of rc (if those are equal, so
+        // are both keys' top bits). The top 10 bits of fwd are its first 5
+        // bases, those of rc the complements of its last 5 bases, last first.
+        const uint64_t w0 = g >> 5;
+        const uint64_t p0 = packed[w0], p1 = packed[w0 + 1];
+        const int s0 = (int)(g & 31);
+        const uint32_t head = bits24(p0, p1, 2 * s0);            // bases g .. g+11
+        const uint32_t tail = bits24(p0, p1, 2 * (s0 + k - 5));  // bases g+k-5 .. g+k+6
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          if (!(vm & (1u << i))) continue;
+          const uint32_t f = rev5((head >> (2 * i)) & 0x3FFu);   // first base most significant
+          const uint32_t r = ((tail >> (2 * i)) & 0x3FFu) ^ 0x3FFu;
+          atomicAdd(&sh[min(f, r) >> (10 - shard_bits)], 1u);
+        }
+        w += __builtin_popcount(vm);
+        continue;
+      }
+    }
     K keys[S];
     vm = window_keys<K, Kc, S, BATCH>(packed, g, k, vm, bs, keys);
 #pragma unroll
