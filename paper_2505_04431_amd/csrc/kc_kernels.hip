@@ -306,6 +306,10 @@ __global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
 // ---------------------------------------------------------------- pack
 
 __device__ __forceinline__ uint32_t base_code(uint32_t b) { return ((b >> 1) ^ (b >> 2)) & 3u; }
+// Top bit of each byte of v set iff that byte is not zero (no carry between bytes).
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t v) {
+  return (((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u;
+}
 __device__ __forceinline__ bool base_valid(uint32_t b) {
   uint32_t u = b | 0x20u;
   return u == 'a' || u == 'c' || u == 'g' || u == 't';
@@ -333,13 +337,19 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t* __restrict__ src, u
       uint32_t w[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
       for (int d = 0; d < 4; ++d) {
-#pragma unroll
-        for (int by = 0; by < 4; ++by) {
-          const int j = v * 16 + d * 4 + by;
-          const uint32_t b = (w[d] >> (8 * by)) & 0xFFu;
-          p[j >> 5] |= (uint64_t)base_code(b) << (2 * (j & 31));
-          if (!base_valid(b)) iv |= 1ull << j;
-        }
+        // four bytes at once (SWAR): base_code of each byte, then the four
+        // 2-bit codes gathered into 8 bits; a byte is invalid iff its
+        // lowercase form differs from each of a, c, g, t (nonzero_bytes sets
+        // a byte's top bit iff the byte is not 0), the four top bits gathered
+        // into 4 bits by one multiply
+        const int j = v * 16 + d * 4;
+        const uint32_t c = ((w[d] >> 1) ^ (w[d] >> 2)) & 0x03030303u;
+        const uint32_t t = c | (c >> 6);
+        p[j >> 5] |= (uint64_t)((t & 0xFu) | ((t >> 12) & 0xF0u)) << (2 * (j & 31));
+        const uint32_t l = w[d] | 0x20202020u;
+        const uint32_t bad = nonzero_bytes(l ^ 0x61616161u) & nonzero_bytes(l ^ 0x63636363u) &
+                             nonzero_bytes(l ^ 0x67676767u) & nonzero_bytes(l ^ 0x74747474u);
+        iv |= (uint64_t)(((bad & 0x80808080u) * 0x00204081u) >> 28) << j;
       }
     }
   } else {
