@@ -903,8 +903,11 @@ void table_params(const kc_options& o, int words, int& slots_log2, uint64_t& C, 
   // clearing, compacting and sorting the table is spread over more records).
   // Wider keys, mostly distinct: three quarters of the largest table (1.5
   // tables overflowed 122 leaves at k = 55 and 8,896 at k = 100: 5.35 and
-  // 59.1 ms against 4.68 and 8.4 ms).
-  T = o.leaf_target > 0 ? (uint64_t)o.leaf_target : (words == 1 ? (C * 3) / 2 : (C * 3) / 4);
+  // 59.1 ms against 4.68 and 8.4 ms). The sort-based leaves (mode 1) sort
+  // all their records in LDS, so they keep three quarters of a table too
+  // (1.5 tables: 39 ms against 12 ms on the 1,000,000 reads).
+  const bool big = words == 1 && o.mode != 1;
+  T = o.leaf_target > 0 ? (uint64_t)o.leaf_target : (big ? (C * 3) / 2 : (C * 3) / 4);
   H = o.leaf_attempt > 0 ? (uint64_t)o.leaf_attempt : (C * 7) / 8;
 }
 
