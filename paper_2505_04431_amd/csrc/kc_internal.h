@@ -159,10 +159,14 @@ hipError_t launch_leaf_ends(Leaf* leaves, const unsigned long long* cursor, cons
 // merged: leaves may hold pre-aggregated records (one-word keys).
 // ovf_list (max_leaves entries, or nullptr): one-word keys in mode 0 list
 // there the leaves whose table overflows, for launch_leaf_second.
+// launch_leaf_small also classifies the leaves: large ones into large_list;
+// for one-word keys in mode 0 with ovf_list (and the second count running,
+// slots_log2 below its table), leaves of more than 8 << slots_log2 records
+// straight into ovf_list for launch_leaf_second.
 hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
-                             uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode,
-                             bool refine, bool merged);
+                             uint32_t* d_out, uint32_t* large_list, uint32_t* ovf_list,
+                             int slots_log2, hipStream_t s, int mode, bool refine, bool merged);
 hipError_t launch_leaf_large(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
                              uint32_t* d_out, int slots_log2, const uint32_t* large_list,

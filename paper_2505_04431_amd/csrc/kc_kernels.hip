@@ -886,23 +886,41 @@ __global__ void k_clear_overflow(DevState* __restrict__ st) {
   if (threadIdx.x == 0) st->overflow = 0;
 }
 
-// Leaves above the small-leaf size go to a list of their own (order irrelevant).
+// Leaves above the small-leaf size go to a list of their own (order
+// irrelevant); with huge != nullptr, leaves of more than huge_min records go
+// straight to that list instead (st->n_ovf), for the second count's larger
+// table: such leaves are the dense clusters that overflow the first table
+// (on 40,000,000 reads at k = 31 the overflowed leaves average 147,000
+// records, the others 4,600), and the first count would read part of them
+// before giving up.
 __global__ void k_classify_leaves(const Leaf* __restrict__ leaves, DevState* __restrict__ st,
-                                  uint64_t small_max, uint32_t* __restrict__ large) {
+                                  uint64_t small_max, uint32_t* __restrict__ large,
+                                  uint64_t huge_min, uint32_t* __restrict__ huge) {
   const unsigned long long n = st->n_leaves;
   const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
   for (unsigned long long i0 = (unsigned long long)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
     const unsigned long long i = i0 + threadIdx.x;
     const Leaf lf = i < n ? leaves[i] : Leaf{0, 0, 0, 0, 0, 0};
-    const bool big = lf.end - lf.begin > small_max;
+    const uint64_t len = lf.end - lf.begin;
+    const bool to_huge = huge && len > huge_min;
+    const bool big = !to_huge && len > small_max;
     const unsigned long long m = __ballot(big);
-    if (!m) continue;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)m) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(&st->n_large, (unsigned long long)__popcll(m));
-    base = __shfl(base, leader);
-    if (big) large[base + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)i;
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(&st->n_large, (unsigned long long)__popcll(m));
+      base = __shfl(base, leader);
+      if (big) large[base + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)i;
+    }
+    const unsigned long long mh = __ballot(to_huge);
+    if (mh) {
+      const int leader = __ffsll((long long)mh) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(&st->n_ovf, (unsigned long long)__popcll(mh));
+      base = __shfl(base, leader);
+      if (to_huge) huge[base + __popcll(mh & ((1ull << lane) - 1))] = (uint32_t)i;
+    }
   }
 }
 
@@ -2494,14 +2512,18 @@ uint64_t small_leaf_max(int words) {
 
 hipError_t launch_leaf_small(int words, int keybits, void* bufA, void* bufB, uint32_t* tmp_cnt,
                              const Leaf* leaves, DevState* st, uint64_t max_leaves,
-                             uint32_t* d_out, uint32_t* large_list, hipStream_t s, int mode,
-                             bool refine, bool merged) {
+                             uint32_t* d_out, uint32_t* large_list, uint32_t* ovf_list,
+                             int slots_log2, hipStream_t s, int mode, bool refine, bool merged) {
   const bool wide = words == 2;
   const uint64_t small_max = mode == 1 ? 0 : small_leaf_max(words);
+  // leaves of more than 8 first tables of records go straight to the second
+  // count (where it runs: launch_leaf_second)
+  const bool second = words == 1 && mode != 1 && slots_log2 < kRescueSlotsLog2 && ovf_list;
+  const uint64_t huge_min = 8ull << slots_log2;
   // n_large and n_ovf
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &st->n_large, (uint64_t)2, 0ull);
   hipLaunchKernelGGL(k_classify_leaves, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s,
-                     leaves, st, small_max, large_list);
+                     leaves, st, small_max, large_list, huge_min, second ? ovf_list : nullptr);
   if (mode == 1 || words == 4) {  // every non-empty leaf is in the list
     hipLaunchKernelGGL(k_empty_leaves, dim3(grid_for(max_leaves, 256, 2048)), dim3(256), 0, s,
                        leaves, st, d_out);

@@ -619,7 +619,8 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
     upload_sync(&dst_state->n_leaves, &nlu, 8, st);
     hipchk(kc::launch_leaf_small(q.words, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
-                                 (uint32_t*)c.alarge.p, st, q.o.mode, true, q.merged),
+                                 (uint32_t*)c.alarge.p, (uint32_t*)c.aovfl.p, q.slots_log2, st,
+                                 q.o.mode, true, q.merged),
            "leaf count launch");
     hipchk(kc::launch_leaf_large(q.words, q.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                  (kc::Leaf*)c.aleaves.p, dst_state, na, (uint32_t*)c.adcnt.p,
@@ -855,7 +856,8 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
   tm.mark(ST_SPLIT);
   hipchk(kc::launch_leaf_small(p.words, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
                                (kc::Leaf*)c.leaves.p, dstate, p.max_leaves, (uint32_t*)c.dcnt.p,
-                               (uint32_t*)c.large.p, st, p.mode, false, p.merge_cshift != 0),
+                               (uint32_t*)c.large.p, (uint32_t*)c.ovfl.p, p.slots_log2, st,
+                               p.mode, false, p.merge_cshift != 0),
          "leaf count launch");
   tm.mark(ST_LEAF_SMALL);
   hipchk(kc::launch_leaf_large(p.words, p.keybits, c.bufA.p, c.bufB.p, (uint32_t*)c.tmpcnt.p,
