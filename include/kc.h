@@ -15,7 +15,7 @@
  *     sorted by key ascending (the result of Algorithm 1),
  *     from count 1 up (Section VI counts from 1 to the maximum).
  * The P owner partitions stand in for the paper's P processing elements
- * (OwnerPE, Algorithms 2-4); the result does not depend on P.
+ * and their owner function (Algorithms 2-4); the result does not depend on P.
  *
  * Conventions
  *   - All array arguments of kc_count / kc_count_ex are DEVICE pointers
