@@ -69,6 +69,7 @@ constexpr uint32_t kNoSet = 0xFFFFFFFFu;
 constexpr int kMaxShardBits = 10;  // first-level shards (owner buckets are unions of them)
 constexpr int kSplitMaxBits = 10;  // sub-bins per split step: up to 1024
 constexpr int kWinStarts = 8;      // window starts per thread in the window kernels
+constexpr int kXcds = 8;           // XCDs of the chip: classes of owner-scatter tiles
 constexpr uint32_t kLeafOverflow = 0xFFFFFFFFu;
 
 int max_leaf_slots_log2(int words);
@@ -94,11 +95,14 @@ hipError_t launch_valid_mask(int words, const uint64_t* inv, const uint64_t* end
 // Window kernels over the bytes [byte_begin, byte_end) of the packed stream,
 // with the valid-start mask of launch_valid_mask for the same range and k.
 // keybits = 2k (plain) or 2k + set id bits (batch: batch != nullptr).
+// hist: (1 + kXcds) << shard_bits entries, zeroed: per-shard totals, then
+// per class of the owner scatter's tiles (tile index mod kXcds; the scatter's
+// shape follows from words and starts_per_thread).
 hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t* valid,
                               uint64_t byte_begin, uint64_t byte_end, int k,
                               int keybits, int shard_bits, const BatchSets* batch,
                               unsigned long long* hist, unsigned long long* wcount,
-                              hipStream_t s);
+                              int starts_per_thread, hipStream_t s);
 
 // starts_per_thread: 8, or 16 for one-word keys (16,384-record LDS tiles).
 hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* valid,

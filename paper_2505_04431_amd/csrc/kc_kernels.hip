@@ -569,12 +569,17 @@ __device__ __forceinline__ uint32_t rev5(uint32_t x) {
   return ((x & 0x3u) << 8) | ((x & 0xCu) << 4) | (x & 0x30u) | ((x >> 4) & 0xCu) | (x >> 8);
 }
 
-// Threads t in [t_begin, t_end) each take window starts [t*S, t*S + S).
+// Shard histogram over the owner scatter's tiles: tile j holds the window
+// starts [w_begin + j*tile_starts, w_begin + (j+1)*tile_starts) ∩ [.., w_end),
+// taken S per thread. Totals go to hist[0, nb); the counts of the tiles of
+// class c = j mod kXcds to hist[(1 + c)*nb, ..) (gridDim.x is a multiple of
+// kXcds, so all of a workgroup's tiles are of class blockIdx.x mod kXcds).
 template <typename K, typename Kc, int S, int TB, bool BATCH>
 __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__ packed,
                                                     const uint64_t* __restrict__ valid,
-                                                    uint64_t t_begin, uint64_t t_end, int k,
-                                                    int keybits, int shard_bits, BatchSets bs,
+                                                    uint64_t w_begin, uint64_t w_end,
+                                                    uint64_t tile_starts, int k, int keybits,
+                                                    int shard_bits, BatchSets bs,
                                                     unsigned long long* __restrict__ hist,
                                                     unsigned long long* __restrict__ wcount) {
   __shared__ uint32_t sh[1 << kMaxShardBits];
@@ -582,46 +587,53 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
   for (int i = threadIdx.x; i < nb; i += TB) sh[i] = 0;
   __syncthreads();
   uint32_t w = 0;
-  for (uint64_t t = t_begin + (uint64_t)blockIdx.x * TB + threadIdx.x; t < t_end;
-       t += (uint64_t)gridDim.x * TB) {
-    const uint64_t g = t * S;
-    uint32_t vm = valid_starts<S>(valid, g);
-    if (!vm) continue;
-    if constexpr (!BATCH && std::is_same<Kc, uint64_t>::value && S <= 8) {
-      if (k >= 5) {
-        // only the shard is needed: the top bits of min(fwd, rc) are the
-        // smaller of the top bits of fwd and of rc (if those are equal, so
-        // are both keys' top bits). The top 10 bits of fwd are its first 5
-        // bases, those of rc the complements of its last 5 bases, last first.
-        const uint64_t w0 = g >> 5;
-        const uint64_t p0 = packed[w0], p1 = packed[w0 + 1];
-        const int s0 = (int)(g & 31);
-        const uint32_t head = bits24(p0, p1, 2 * s0);            // bases g .. g+11
-        const uint32_t tail = bits24(p0, p1, 2 * (s0 + k - 5));  // bases g+k-5 .. g+k+6
+  const uint64_t n_tiles = (w_end - w_begin + tile_starts - 1) / tile_starts;
+  for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const uint64_t g_end = min(w_end, w_begin + (tile + 1) * tile_starts);
+    for (uint64_t g = w_begin + tile * tile_starts + (uint64_t)threadIdx.x * S; g < g_end;
+         g += (uint64_t)TB * S) {
+      uint32_t vm = valid_starts<S>(valid, g);
+      if (!vm) continue;
+      if constexpr (!BATCH && std::is_same<Kc, uint64_t>::value && S <= 8) {
+        if (k >= 5) {
+          // only the shard is needed: the top bits of min(fwd, rc) are the
+          // smaller of the top bits of fwd and of rc (if those are equal, so
+          // are both keys' top bits). The top 10 bits of fwd are its first 5
+          // bases, those of rc the complements of its last 5 bases, last first.
+          const uint64_t w0 = g >> 5;
+          const uint64_t p0 = packed[w0], p1 = packed[w0 + 1];
+          const int s0 = (int)(g & 31);
+          const uint32_t head = bits24(p0, p1, 2 * s0);            // bases g .. g+11
+          const uint32_t tail = bits24(p0, p1, 2 * (s0 + k - 5));  // bases g+k-5 .. g+k+6
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
-          if (!(vm & (1u << i))) continue;
-          const uint32_t f = rev5((head >> (2 * i)) & 0x3FFu);   // first base most significant
-          const uint32_t r = ((tail >> (2 * i)) & 0x3FFu) ^ 0x3FFu;
-          atomicAdd(&sh[min(f, r) >> (10 - shard_bits)], 1u);
+          for (int i = 0; i < S; ++i) {
+            if (!(vm & (1u << i))) continue;
+            const uint32_t f = rev5((head >> (2 * i)) & 0x3FFu);   // first base most significant
+            const uint32_t r = ((tail >> (2 * i)) & 0x3FFu) ^ 0x3FFu;
+            atomicAdd(&sh[min(f, r) >> (10 - shard_bits)], 1u);
+          }
+          w += __builtin_popcount(vm);
+          continue;
         }
-        w += __builtin_popcount(vm);
-        continue;
       }
-    }
-    K keys[S];
-    vm = window_keys<K, Kc, S, BATCH>(packed, g, k, vm, bs, keys);
+      K keys[S];
+      vm = window_keys<K, Kc, S, BATCH>(packed, g, k, vm, bs, keys);
 #pragma unroll
-    for (int i = 0; i < S; ++i)
-      if (vm & (1u << i)) atomicAdd(&sh[shard_of(keys[i], keybits, shard_bits)], 1u);
-    w += __builtin_popcount(vm);
+      for (int i = 0; i < S; ++i)
+        if (vm & (1u << i)) atomicAdd(&sh[shard_of(keys[i], keybits, shard_bits)], 1u);
+      w += __builtin_popcount(vm);
+    }
   }
   // per-wave sum of valid windows, one global atomic per wave
   for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
   if ((threadIdx.x & 63) == 0 && w) atomicAdd(wcount, (unsigned long long)w);
   __syncthreads();
+  unsigned long long* const hc = hist + (uint64_t)(1 + blockIdx.x % kXcds) * nb;
   for (int i = threadIdx.x; i < nb; i += TB)
-    if (sh[i]) atomicAdd(&hist[i], (unsigned long long)sh[i]);
+    if (sh[i]) {
+      atomicAdd(&hist[i], (unsigned long long)sh[i]);
+      atomicAdd(&hc[i], (unsigned long long)sh[i]);
+    }
 }
 
 // Owner-major scatter of window records into shard slices (cursor[i] starts at
@@ -643,6 +655,12 @@ __device__ __forceinline__ void window_scatter_body(const uint64_t* __restrict__
   const int nb = 1 << shard_bits;
   const uint64_t n_tiles = (t_end - t_begin + TB - 1) / TB;
   for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    // tiles of class tile mod kXcds take their runs from their own part of
+    // each shard slice (cursor[class * nb + shard], sized by k_window_hist):
+    // the concurrent tiles of one XCD (workgroups are dealt to the XCDs in
+    // turn) then write adjacent runs, whose shared 64-byte segments meet in
+    // that XCD's L2 instead of going to memory in halves
+    unsigned long long* const cls_cursor = cursor + (tile % kXcds) * (uint64_t)nb;
     for (int i = threadIdx.x; i < nb; i += TB) loff[i] = 0;
     __syncthreads();
     const uint64_t t = t_begin + tile * TB + threadIdx.x;
@@ -660,7 +678,7 @@ __device__ __forceinline__ void window_scatter_body(const uint64_t* __restrict__
     const uint32_t total = block_exscan_inplace<TB>(loff, nb, wsum);
     for (int i = threadIdx.x; i < nb; i += TB) {
       const uint32_t cnt = (i + 1 < nb ? loff[i + 1] : total) - loff[i];
-      if (cnt) gbase[i] = atomicAdd(&cursor[i], (unsigned long long)cnt);
+      if (cnt) gbase[i] = atomicAdd(&cls_cursor[i], (unsigned long long)cnt);
     }
 #pragma unroll
     for (int i = 0; i < S; ++i)
@@ -736,7 +754,12 @@ __global__ void __launch_bounds__(kPlanTB) k_plan_shards(
   const unsigned long long b0 = block_exscan<kPlanTB, unsigned long long>(ho, wsum, &total);
   if (t < nb) {
     sbegin[co] = b0;
-    cursor[co] = b0;
+    // each class's part of the slice: after the earlier classes' records
+    unsigned long long c = b0;
+    for (int x = 0; x < kXcds; ++x) {
+      cursor[(uint64_t)x * nb + co] = c;
+      c += hist[(uint64_t)(1 + x) * nb + co];
+    }
   }
   // split decision for shard t (key order)
   const unsigned long long h = t < nb ? hist[t] : 0ull;
@@ -2260,6 +2283,7 @@ __global__ void __launch_bounds__(256) k_check(const uint64_t* __restrict__ keys
 }
 
 constexpr int kHistTB = 256;
+constexpr unsigned kHistGrid = 2048;  // a multiple of kXcds
 constexpr int kScatterTB64 = 1024;
 constexpr int kScatterTB128 = 512;
 constexpr int kSplitTB64 = 1024;
@@ -2348,31 +2372,41 @@ hipError_t launch_valid_mask(int words, const uint64_t* inv, const uint64_t* end
   return hipGetLastError();
 }
 
+#define KC_HIST_LAUNCH(K, KC, BATCH)                                                            \
+  hipLaunchKernelGGL((k_window_hist<K, KC, kWinStarts, kHistTB, BATCH>), dim3(grid),            \
+                     dim3(kHistTB), 0, s, packed, valid, w_begin, w_end, tile_starts, k, keybits, \
+                     shard_bits, bs, hist, wcount)
+
 hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t* valid,
                               uint64_t byte_begin, uint64_t byte_end, int k,
                               int keybits, int shard_bits, const BatchSets* batch,
                               unsigned long long* hist, unsigned long long* wcount,
-                              hipStream_t s) {
-  const uint64_t t_begin = byte_begin / kWinStarts;
-  const uint64_t t_end = (byte_end + kWinStarts - 1) / kWinStarts;
-  const unsigned grid = grid_for(t_end - t_begin, kHistTB, 2048);
+                              int starts_per_thread, hipStream_t s) {
+  // the owner scatter's tiles (see launch_window_scatter)
+  const int S = words == 1 && starts_per_thread == 16 ? 16 : kWinStarts;
+  const int TBs = words == 4 ? kScatterTB256 : words == 2 ? kScatterTB128 : kScatterTB64;
+  const uint64_t w_begin = byte_begin / S * S;
+  const uint64_t w_end = (byte_end + S - 1) / S * S;
+  const uint64_t tile_starts = (uint64_t)TBs * S;
+  const uint64_t n_tiles = (w_end - w_begin + tile_starts - 1) / tile_starts;
+  // a multiple of kXcds workgroups (every workgroup's tiles share a class)
+  const unsigned grid = (unsigned)std::min<uint64_t>((n_tiles + kXcds - 1) / kXcds * kXcds,
+                                                     kHistGrid);
+  if (grid == 0) return hipSuccess;
   const BatchSets bs = batch ? *batch : BatchSets{nullptr, nullptr, 0};
-#define ARG0 hist
-#define ARG1 wcount
   const bool wide = words == 2;
   if (batch) {
     if (words == 4) return hipErrorInvalidValue;
-    if (wide) KC_WINDOW_LAUNCH(k_window_hist, u128, uint64_t, kHistTB, true, grid);
-    else KC_WINDOW_LAUNCH(k_window_hist, uint64_t, uint64_t, kHistTB, true, grid);
+    if (wide) KC_HIST_LAUNCH(u128, uint64_t, true);
+    else KC_HIST_LAUNCH(uint64_t, uint64_t, true);
   } else {
-    if (words == 4) KC_WINDOW_LAUNCH(k_window_hist, u256, u256, kHistTB, false, grid);
-    else if (wide) KC_WINDOW_LAUNCH(k_window_hist, u128, u128, kHistTB, false, grid);
-    else KC_WINDOW_LAUNCH(k_window_hist, uint64_t, uint64_t, kHistTB, false, grid);
+    if (words == 4) KC_HIST_LAUNCH(u256, u256, false);
+    else if (wide) KC_HIST_LAUNCH(u128, u128, false);
+    else KC_HIST_LAUNCH(uint64_t, uint64_t, false);
   }
-#undef ARG0
-#undef ARG1
   return hipGetLastError();
 }
+#undef KC_HIST_LAUNCH
 
 hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* valid,
                                  uint64_t byte_begin, uint64_t byte_end,

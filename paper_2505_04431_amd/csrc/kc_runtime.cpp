@@ -768,9 +768,9 @@ void pipeline_needs(const Pipe& p, F&& f) {
   f(&Ctx::bufA, std::max<uint64_t>(p.rec_bound, 1) * ksz, "record buffer A");
   f(&Ctx::bufB, std::max<uint64_t>(p.rec_bound, 1) * ksz, "record buffer B");
   f(&Ctx::tmpcnt, std::max<uint64_t>(p.rec_bound, 1) * 4, "pair counts");
-  f(&Ctx::hist, nb * 8, "shard histogram");
+  f(&Ctx::hist, (1 + kc::kXcds) * nb * 8, "shard histogram");  // totals, then per tile class
   f(&Ctx::sbegin, nb * 8, "shard begins");
-  f(&Ctx::cursor, nb * 8, "shard cursors");
+  f(&Ctx::cursor, kc::kXcds * nb * 8, "shard cursors");          // per tile class
   f(&Ctx::bins, nb * sizeof(kc::SplitBin), "split bins");
   f(&Ctx::items, p.max_items * sizeof(kc::SplitItem), "split items");
   f(&Ctx::itemoff, (nb + 1) * 8, "split item offsets");
@@ -813,13 +813,15 @@ struct PipeOut {
 
 void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, const PipeOut& out,
                       hipStream_t st) {
-  hipchk(kc::launch_fill_u64((unsigned long long*)c.hist.p, 1ull << p.sb, 0, st), "fill launch");
+  hipchk(kc::launch_fill_u64((unsigned long long*)c.hist.p, (1ull + kc::kXcds) << p.sb, 0, st),
+         "fill launch");
   hipchk(kc::launch_valid_mask(p.words, (uint64_t*)c.inv.p, (uint64_t*)c.endm.p, p.byte_begin,
                                p.byte_end, p.k, (uint64_t*)c.valid.p, st),
          "valid mask launch");
   hipchk(kc::launch_window_hist(p.words, (uint64_t*)c.packed.p, (uint64_t*)c.valid.p,
                                 p.byte_begin, p.byte_end, p.k, p.keybits,
-                                p.sb, p.batch, (unsigned long long*)c.hist.p, &dstate->W, st),
+                                p.sb, p.batch, (unsigned long long*)c.hist.p, &dstate->W,
+                                p.scatter_s, st),
          "window histogram launch");
   tm.mark(ST_HIST);
   hipchk(kc::launch_plan_shards((unsigned long long*)c.hist.p, p.order, p.sb, p.keybits, p.T, p.H,
