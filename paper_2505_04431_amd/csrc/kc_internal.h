@@ -115,38 +115,45 @@ hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64
 // owner-major; sbegin[] receives each shard's record range start, cursor[] a
 // copy for the scatter; bins[] the split of each shard; items[] the tiles of
 // the split shards (item_off[] holds nb+1 prefix offsets of them); subhist[]
-// (max_leaves entries) is prepared: zeros for split shards, the shard size for
-// unsplit ones; st->n_items and st->n_leaves are set.
+// (ncls * max_leaves entries: one part per item class of the split) is
+// prepared: zeros, but the shard size at the leaf of each unsplit shard in
+// the first part; st->n_items and st->n_leaves are set.
 hipError_t launch_plan_shards(const unsigned long long* hist, const int* order, int shard_bits,
                               int keybits, uint64_t leaf_target, uint64_t leaf_attempt,
                               int tile, unsigned long long* sbegin, unsigned long long* cursor,
                               SplitBin* bins, SplitItem* items, unsigned long long* item_off,
                               unsigned long long* subhist, uint64_t max_leaves,
-                              uint64_t max_items, DevState* st, hipStream_t s);
+                              uint64_t max_items, int ncls, DevState* st, hipStream_t s);
 
 // Device planning of the leaves (one block): leaf table in key order and the
 // sub-bin cursors of the split shards.
 // merge_cshift != 0: the split scatter pre-aggregates (the leaves of split
 // shards get cshift = merge_cshift and their shard).
+// Item classes: item w of the split is of class w mod ncls; the sub-bin
+// counts of class x are at subhist[x * cls_stride + leaf], and the split
+// scatter's cursors of class x at cursor[x * cls_stride + leaf] (each class
+// writes its own part of every sub-bin, the classes in order).
 hipError_t launch_plan_leaves(const unsigned long long* hist, const unsigned long long* sbegin,
                               const SplitBin* bins, int shard_bits,
                               const unsigned long long* subhist, Leaf* leaves,
-                              unsigned long long* cursor, int merge_cshift, hipStream_t s);
+                              unsigned long long* cursor, int merge_cshift, int ncls,
+                              uint64_t cls_stride, hipStream_t s);
 
 // Split kernels loop over st->n_items items (persistent grid of at most max_items blocks).
 hipError_t launch_split_hist(int words, const void* src, const SplitItem* items,
                              const DevState* st, uint64_t max_items, const SplitBin* bins,
-                             unsigned long long* subhist, hipStream_t s);
+                             unsigned long long* subhist, int ncls, uint64_t cls_stride,
+                             hipStream_t s);
 
 // merge_cshift != 0 (one-word keys, 16 records per thread): equal keys next
 // to each other in a tile's LDS staging (same sub-bin) leave as one record
 // carrying its count minus one in bits [merge_cshift, 64); the cursors then
 // advance by the records written, and launch_leaf_ends records where each
-// split leaf's records end.
+// split leaf's records end (ncls must then be 1).
 hipError_t launch_split_scatter(int words, const void* src, void* dst, const SplitItem* items,
                                 const DevState* st, uint64_t max_items, const SplitBin* bins,
                                 unsigned long long* cursor, int records_per_thread,
-                                int merge_cshift, hipStream_t s);
+                                int merge_cshift, int ncls, uint64_t cls_stride, hipStream_t s);
 hipError_t launch_leaf_ends(Leaf* leaves, const unsigned long long* cursor, const DevState* st,
                             uint64_t max_leaves, hipStream_t s);
 

@@ -812,7 +812,7 @@ __global__ void __launch_bounds__(kPlanTB) k_plan_leaves(
     const unsigned long long* __restrict__ hist, const unsigned long long* __restrict__ sbegin,
     const SplitBin* __restrict__ bins, int shard_bits,
     const unsigned long long* __restrict__ subhist, Leaf* __restrict__ leaves,
-    unsigned long long* __restrict__ cursor, int merge_cshift) {
+    unsigned long long* __restrict__ cursor, int merge_cshift, int ncls, uint64_t cls_stride) {
   __shared__ unsigned long long wsum[kPlanTB / 64];
   const int c = blockIdx.x;
   const unsigned long long h = hist[c];
@@ -824,14 +824,21 @@ __global__ void __launch_bounds__(kPlanTB) k_plan_leaves(
   }
   const uint32_t nsub = 1u << b.nbits;  // <= kPlanTB
   const uint32_t j = threadIdx.x;
-  const unsigned long long n = j < nsub ? subhist[b.hist_off + j] : 0ull;
+  unsigned long long n = 0;
+  if (j < nsub)
+    for (int x = 0; x < ncls; ++x) n += subhist[x * cls_stride + b.hist_off + j];
   unsigned long long total;
   const unsigned long long off = block_exscan<kPlanTB, unsigned long long>(n, wsum, &total);
   if (j < nsub) {
     const unsigned long long run = sbegin[c] + off;
     leaves[b.hist_off + j] = Leaf{run, run + n, 1u, (uint32_t)(shard_bits + b.nbits),
                                   (uint32_t)merge_cshift, (uint32_t)c};
-    cursor[b.hist_off + j] = run;
+    // each item class's part of the sub-bin: after the earlier classes' records
+    unsigned long long at = run;
+    for (int x = 0; x < ncls; ++x) {
+      cursor[x * cls_stride + b.hist_off + j] = at;
+      at += subhist[x * cls_stride + b.hist_off + j];
+    }
   }
 }
 
@@ -1026,11 +1033,14 @@ __global__ void __launch_bounds__(TB) k_split_hist(const K* __restrict__ src,
                                                    const SplitItem* __restrict__ items,
                                                    const DevState* __restrict__ st,
                                                    const SplitBin* __restrict__ bins,
-                                                   unsigned long long* __restrict__ subhist) {
+                                                   unsigned long long* __restrict__ subhist,
+                                                   int ncls, uint64_t cls_stride) {
   __shared__ uint32_t h[1 << kSplitMaxBits];
   const unsigned long long n_items = st->n_items;
   for (unsigned long long w = blockIdx.x; w < n_items; w += gridDim.x) {
     const SplitItem it = items[w];
+    // counts of item class w mod ncls (the split scatter's cursor classes)
+    unsigned long long* const sh = subhist + (w % ncls) * cls_stride;
     const SplitBin bn = bins[it.bin];
     const int nsub = 1 << bn.nbits;
     for (int i = threadIdx.x; i < nsub; i += TB) h[i] = 0;
@@ -1052,7 +1062,7 @@ __global__ void __launch_bounds__(TB) k_split_hist(const K* __restrict__ src,
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nsub; i += TB)
-      if (h[i]) atomicAdd(&subhist[bn.hist_off + i], (unsigned long long)h[i]);
+      if (h[i]) atomicAdd(&sh[bn.hist_off + i], (unsigned long long)h[i]);
     __syncthreads();
   }
 }
@@ -1063,7 +1073,8 @@ __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
                                                       const SplitItem* __restrict__ items,
                                                       const DevState* __restrict__ st,
                                                       const SplitBin* __restrict__ bins,
-                                                      unsigned long long* __restrict__ cursor) {
+                                                      unsigned long long* __restrict__ cursor,
+                                                      int ncls, uint64_t cls_stride) {
   constexpr int NS = 1 << kSplitMaxBits;
   __shared__ K stage[TB * R];
   __shared__ uint32_t hist[NS];  // per sub-bin: records in the tile, then their run offsets
@@ -1083,6 +1094,11 @@ __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
   for (unsigned long long w = blockIdx.x; w < n_items; w += gridDim.x) {
     const SplitBin bn = bins[it.bin];
     const int nsub = 1 << bn.nbits;
+    // items of class w mod ncls take their runs from their own part of each
+    // sub-bin (as in the owner scatter: with ncls = kXcds and the workgroups
+    // of one class on one XCD, the partial segments of adjacent runs meet in
+    // that XCD's L2)
+    unsigned long long* const cls_cursor = cursor + (w % ncls) * cls_stride;
     for (int i = threadIdx.x; i < nsub; i += TB) hist[i] = 0;
     __syncthreads();
     uint32_t sub[R], rank[R];
@@ -1098,7 +1114,7 @@ __global__ void __launch_bounds__(TB) k_split_scatter(const K* __restrict__ src,
     const uint32_t total = block_exscan_inplace<TB>(hist, nsub, wsum);
     for (int i = threadIdx.x; i < nsub; i += TB) {
       const uint32_t cnt = (i + 1 < nsub ? loff[i + 1] : total) - loff[i];
-      if (cnt) gbase[i] = atomicAdd(&cursor[bn.hist_off + i], (unsigned long long)cnt);
+      if (cnt) gbase[i] = atomicAdd(&cls_cursor[bn.hist_off + i], (unsigned long long)cnt);
     }
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -2463,9 +2479,9 @@ hipError_t launch_plan_shards(const unsigned long long* hist, const int* order, 
                               int tile, unsigned long long* sbegin, unsigned long long* cursor,
                               SplitBin* bins, SplitItem* items, unsigned long long* item_off,
                               unsigned long long* subhist, uint64_t max_leaves,
-                              uint64_t max_items, DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(max_leaves, 256, 1024)), dim3(256), 0, s, subhist,
-                     max_leaves, 0ull);
+                              uint64_t max_items, int ncls, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(max_leaves * ncls, 256, 1024)), dim3(256), 0, s,
+                     subhist, max_leaves * ncls, 0ull);
   hipLaunchKernelGGL(k_plan_shards, dim3(1), dim3(kPlanTB), 0, s, hist, order, shard_bits,
                      keybits, leaf_target, leaf_attempt, tile, sbegin, cursor, bins, item_off,
                      subhist, st);
@@ -2477,9 +2493,10 @@ hipError_t launch_plan_shards(const unsigned long long* hist, const int* order, 
 hipError_t launch_plan_leaves(const unsigned long long* hist, const unsigned long long* sbegin,
                               const SplitBin* bins, int shard_bits,
                               const unsigned long long* subhist, Leaf* leaves,
-                              unsigned long long* cursor, int merge_cshift, hipStream_t s) {
+                              unsigned long long* cursor, int merge_cshift, int ncls,
+                              uint64_t cls_stride, hipStream_t s) {
   hipLaunchKernelGGL(k_plan_leaves, dim3(1u << shard_bits), dim3(kPlanTB), 0, s, hist, sbegin,
-                     bins, shard_bits, subhist, leaves, cursor, merge_cshift);
+                     bins, shard_bits, subhist, leaves, cursor, merge_cshift, ncls, cls_stride);
   return hipGetLastError();
 }
 
@@ -2492,27 +2509,29 @@ hipError_t launch_leaf_ends(Leaf* leaves, const unsigned long long* cursor, cons
 
 hipError_t launch_split_hist(int words, const void* src, const SplitItem* items,
                              const DevState* st, uint64_t max_items, const SplitBin* bins,
-                             unsigned long long* subhist, hipStream_t s) {
+                             unsigned long long* subhist, int ncls, uint64_t cls_stride,
+                             hipStream_t s) {
   const unsigned grid = persistent(max_items, 4096);
   if (words == 4)
     hipLaunchKernelGGL((k_split_hist<u256, 256>), dim3(grid), dim3(256), 0, s, (const u256*)src,
-                       items, st, bins, subhist);
+                       items, st, bins, subhist, ncls, cls_stride);
   else if (words == 2)
     hipLaunchKernelGGL((k_split_hist<u128, 256>), dim3(grid), dim3(256), 0, s, (const u128*)src,
-                       items, st, bins, subhist);
+                       items, st, bins, subhist, ncls, cls_stride);
   else
     hipLaunchKernelGGL((k_split_hist<uint64_t, 256>), dim3(grid), dim3(256), 0, s,
-                       (const uint64_t*)src, items, st, bins, subhist);
+                       (const uint64_t*)src, items, st, bins, subhist, ncls, cls_stride);
   return hipGetLastError();
 }
 
 hipError_t launch_split_scatter(int words, const void* src, void* dst, const SplitItem* items,
                                 const DevState* st, uint64_t max_items, const SplitBin* bins,
                                 unsigned long long* cursor, int records_per_thread,
-                                int merge_cshift, hipStream_t s) {
+                                int merge_cshift, int ncls, uint64_t cls_stride, hipStream_t s) {
   const unsigned grid = persistent(max_items, 2048);
   if (merge_cshift) {
-    if (words != 1 || records_per_thread != 16) return hipErrorInvalidValue;
+    // one cursor per leaf: its final value is the leaf's end
+    if (words != 1 || records_per_thread != 16 || ncls != 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_split_scatter_merge<kSplitTB64, 16>), dim3(grid), dim3(kSplitTB64), 0,
                        s, (const uint64_t*)src, (uint64_t*)dst, items, st, bins, cursor,
                        merge_cshift);
@@ -2521,21 +2540,22 @@ hipError_t launch_split_scatter(int words, const void* src, void* dst, const Spl
   if (words == 1 && records_per_thread == 16) {
     // 16,384-record tiles: 128 KiB of LDS staging, one workgroup per CU
     hipLaunchKernelGGL((k_split_scatter<uint64_t, kSplitTB64, 16>), dim3(grid), dim3(kSplitTB64),
-                       0, s, (const uint64_t*)src, (uint64_t*)dst, items, st, bins, cursor);
+                       0, s, (const uint64_t*)src, (uint64_t*)dst, items, st, bins, cursor,
+                       ncls, cls_stride);
     return hipGetLastError();
   }
   if (words == 4)
     hipLaunchKernelGGL((k_split_scatter<u256, kSplitTB256, kSplitR>), dim3(grid),
                        dim3(kSplitTB256), 0, s, (const u256*)src, (u256*)dst, items, st, bins,
-                       cursor);
+                       cursor, ncls, cls_stride);
   else if (words == 2)
     hipLaunchKernelGGL((k_split_scatter<u128, kSplitTB128, kSplitR>), dim3(grid),
                        dim3(kSplitTB128), 0, s, (const u128*)src, (u128*)dst, items, st, bins,
-                       cursor);
+                       cursor, ncls, cls_stride);
   else
     hipLaunchKernelGGL((k_split_scatter<uint64_t, kSplitTB64, kSplitR>), dim3(grid),
                        dim3(kSplitTB64), 0, s, (const uint64_t*)src, (uint64_t*)dst, items, st,
-                       bins, cursor);
+                       bins, cursor, ncls, cls_stride);
   return hipGetLastError();
 }
 

@@ -571,7 +571,7 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
       hipchk(kc::launch_fill_u64((unsigned long long*)c.subhist.p, hoff, 0, st), "fill launch");
       hipchk(kc::launch_split_hist(q.words, bufs[src], (kc::SplitItem*)c.items.p, dst_state,
                                    it_src.size(), (kc::SplitBin*)c.bins.p,
-                                   (unsigned long long*)c.subhist.p, st),
+                                   (unsigned long long*)c.subhist.p, 1, 0, st),
              "split histogram launch");
       uint64_t* hsub = (uint64_t*)host_stage(c, hoff * 8 + 64);
       hipchk(hipMemcpyAsync(hsub, c.subhist.p, hoff * 8, hipMemcpyDeviceToHost, st),
@@ -600,7 +600,7 @@ void refine_overflowed(Ctx& c, Call& q, kc_stats& S, Timer& tm, uint64_t nl0,
       hipchk(kc::launch_split_scatter(q.words, bufs[src], bufs[1 - src],
                                       (kc::SplitItem*)c.items.p, dst_state, it_src.size(),
                                       (kc::SplitBin*)c.bins.p, (unsigned long long*)c.cursor2.p,
-                                      q.split_r, 0, st),
+                                      q.split_r, 0, 1, 0, st),
              "split scatter launch");
     }
     tm.mark(ST_REFINE);
@@ -774,8 +774,8 @@ void pipeline_needs(const Pipe& p, F&& f) {
   f(&Ctx::bins, nb * sizeof(kc::SplitBin), "split bins");
   f(&Ctx::items, p.max_items * sizeof(kc::SplitItem), "split items");
   f(&Ctx::itemoff, (nb + 1) * 8, "split item offsets");
-  f(&Ctx::subhist, p.max_leaves * 8, "sub-bin histogram");
-  f(&Ctx::cursor2, p.max_leaves * 8, "sub-bin cursors");
+  f(&Ctx::subhist, kc::kXcds * p.max_leaves * 8, "sub-bin histogram");  // per item class
+  f(&Ctx::cursor2, kc::kXcds * p.max_leaves * 8, "sub-bin cursors");
   f(&Ctx::leaves, p.max_leaves * sizeof(kc::Leaf), "leaf table");
   f(&Ctx::dcnt, p.max_leaves * 4, "leaf counts");
   f(&Ctx::outoff, p.max_leaves * 8, "output offsets");
@@ -813,6 +813,8 @@ struct PipeOut {
 
 void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, const PipeOut& out,
                       hipStream_t st) {
+  // item classes of the split scatter (one when a leaf's end is its cursor's last value)
+  const int ncls = p.merge_cshift ? 1 : kc::kXcds;
   hipchk(kc::launch_fill_u64((unsigned long long*)c.hist.p, (1ull + kc::kXcds) << p.sb, 0, st),
          "fill launch");
   hipchk(kc::launch_valid_mask(p.words, (uint64_t*)c.inv.p, (uint64_t*)c.endm.p, p.byte_begin,
@@ -829,7 +831,7 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
                                 (unsigned long long*)c.cursor.p, (kc::SplitBin*)c.bins.p,
                                 (kc::SplitItem*)c.items.p, (unsigned long long*)c.itemoff.p,
                                 (unsigned long long*)c.subhist.p, p.max_leaves, p.max_items,
-                                dstate, st),
+                                ncls, dstate, st),
          "plan_shards launch");
   hipchk(kc::launch_window_scatter(p.words, (uint64_t*)c.packed.p, (uint64_t*)c.valid.p,
                                    p.byte_begin, p.byte_end, p.k, p.keybits,
@@ -838,18 +840,19 @@ void enqueue_pipeline(Ctx& c, const Pipe& p, kc::DevState* dstate, Timer& tm, co
          "owner scatter launch");
   tm.mark(ST_SCATTER);
   hipchk(kc::launch_split_hist(p.words, c.bufA.p, (kc::SplitItem*)c.items.p, dstate, p.max_items,
-                               (kc::SplitBin*)c.bins.p, (unsigned long long*)c.subhist.p, st),
+                               (kc::SplitBin*)c.bins.p, (unsigned long long*)c.subhist.p, ncls,
+                               p.max_leaves, st),
          "split histogram launch");
   tm.mark(ST_SPLIT_HIST);
   hipchk(kc::launch_plan_leaves((unsigned long long*)c.hist.p, (unsigned long long*)c.sbegin.p,
                                 (kc::SplitBin*)c.bins.p, p.sb, (unsigned long long*)c.subhist.p,
                                 (kc::Leaf*)c.leaves.p, (unsigned long long*)c.cursor2.p,
-                                p.merge_cshift, st),
+                                p.merge_cshift, ncls, p.max_leaves, st),
          "plan_leaves launch");
   hipchk(kc::launch_split_scatter(p.words, c.bufA.p, c.bufB.p, (kc::SplitItem*)c.items.p, dstate,
                                   p.max_items, (kc::SplitBin*)c.bins.p,
                                   (unsigned long long*)c.cursor2.p, p.split_r, p.merge_cshift,
-                                  st),
+                                  ncls, p.max_leaves, st),
          "split scatter launch");
   if (p.merge_cshift)
     hipchk(kc::launch_leaf_ends((kc::Leaf*)c.leaves.p, (unsigned long long*)c.cursor2.p, dstate,
