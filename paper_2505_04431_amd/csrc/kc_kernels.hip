@@ -563,12 +563,6 @@ __device__ __forceinline__ uint32_t bits24(uint64_t p0, uint64_t p1, int q) {
   return (uint32_t)lo & 0xFFFFFFu;
 }
 
-// Five 2-bit bases in stream order (first base in the low bits) as a 10-bit
-// value with the first base most significant.
-__device__ __forceinline__ uint32_t rev5(uint32_t x) {
-  return ((x & 0x3u) << 8) | ((x & 0xCu) << 4) | (x & 0x30u) | ((x >> 4) & 0xCu) | (x >> 8);
-}
-
 // Shard histogram over the owner scatter's tiles: tile j holds the window
 // starts [w_begin + j*tile_starts, w_begin + (j+1)*tile_starts) ∩ [.., w_end),
 // taken S per thread. Totals go to hist[0, nb); the counts of the tiles of
@@ -605,10 +599,15 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
           const int s0 = (int)(g & 31);
           const uint32_t head = bits24(p0, p1, 2 * s0);            // bases g .. g+11
           const uint32_t tail = bits24(p0, p1, 2 * (s0 + k - 5));  // bases g+k-5 .. g+k+6
+          // the 12 head bases in reverse order (each base's 2-bit code kept):
+          // reverse all bits, then swap the two bits of every base
+          const uint32_t hb = __builtin_bitreverse32(head) >> 8;
+          const uint32_t hr = ((hb >> 1) & 0x555555u) | ((hb & 0x555555u) << 1);
 #pragma unroll
           for (int i = 0; i < S; ++i) {
             if (!(vm & (1u << i))) continue;
-            const uint32_t f = rev5((head >> (2 * i)) & 0x3FFu);   // first base most significant
+            // bases g+i .. g+i+4, the first most significant
+            const uint32_t f = (hr >> (2 * (7 - i))) & 0x3FFu;
             const uint32_t r = ((tail >> (2 * i)) & 0x3FFu) ^ 0x3FFu;
             atomicAdd(&sh[min(f, r) >> (10 - shard_bits)], 1u);
           }
