@@ -250,13 +250,13 @@ def batched_leg(n_sets: int, budget_gib: float, tune: bool) -> dict:
             base += r.size
         return reads, np.concatenate(offs)
 
-    tuned = {}
-    tune_info = None
-    plan = kc.BatchPlan(n_reads, set_bytes, ks, P=1, hbm_budget=budget)
-    if tune:
-        # candidates timed on the first wave (its own graph per candidate)
+    def tune_group(lo, hi):
+        """Options timed on the first wave of the sets [lo, hi) (one k)."""
+        plan = kc.BatchPlan(n_reads[lo:hi], set_bytes[lo:hi], ks[lo:hi], P=1, hbm_budget=budget)
         w0 = plan.waves[0]
-        r0, o0 = gen_wave(w0)
+        plan.close()
+        a, b = lo + w0["first_set"], lo + w0["first_set"] + w0["n_sets"]
+        r0, o0 = gen_wave({"first_set": a, "n_sets": b - a})
         rt = torch.from_numpy(r0).to(dev)
         ot = torch.from_numpy(o0.view(np.int64)).to(dev)
         cap = max(1, r0.size // 2)
@@ -270,75 +270,94 @@ def batched_leg(n_sets: int, budget_gib: float, tune: bool) -> dict:
                 if "plan" in cur:
                     cur.pop("plan").close()
                 cur["key"] = key
-                cur["plan"] = kc.BatchPlan(n_reads[:w0["n_sets"]], set_bytes[:w0["n_sets"]],
-                                           ks[:w0["n_sets"]], P=1, opts=kc.options(**o))
+                cur["plan"] = kc.BatchPlan(n_reads[a:b], set_bytes[a:b], ks[a:b], P=1,
+                                           opts=kc.options(**o))
             cur["plan"].run_into(rt, ot, keys, cnts, cap)
             torch.cuda.synchronize()
         cands = [{}, {"split_tile": 8}, {"scatter_tile": 16}, {"leaf_target": 3072},
                  {"leaf_target": 8192}, {"table_slots_log2": 11}]
-        tune_info = tuner.tune(tuner.class_key("batch", ks[:w0["n_sets"]], r0.size), run,
-                               candidates=cands, reps=2, use_cache=False)
-        tuned = tune_info["options"]
+        info = tuner.tune(tuner.class_key("batch", ks[a:b], r0.size), run, candidates=cands,
+                          reps=2, use_cache=False)
         if "plan" in cur:
             cur.pop("plan").close()
         del rt, ot, keys, cnts
-        if tuned:
-            plan.close()
-            plan = kc.BatchPlan(n_reads, set_bytes, ks, P=1, hbm_budget=budget,
-                                opts=kc.options(**tuned))
-    waves = plan.waves
+        return info
+
+    # one plan per k (the sets are in k order), tuned on its own first wave:
+    # the best leaf size differs between one-word keys and the two-word keys
+    # of k = 31 classes
+    groups = []
+    lo = 0
+    while lo < len(ks):
+        hi = lo
+        while hi < len(ks) and ks[hi] == ks[lo]:
+            hi += 1
+        groups.append((lo, hi))
+        lo = hi
     tot = dict(windows=0, bytes=0, pairs=0, t_first=0.0, t_batched=0.0, t_plain=0.0, t_gen=0.0)
     stream = torch.cuda.current_stream(dev).cuda_stream
     t_leg = time.time()
-    gen_pool = ThreadPoolExecutor(max_workers=1)
-    nxt = gen_pool.submit(gen_wave, waves[0]) if waves else None
-    for wi, w in enumerate(waves):
-        t0 = time.time()
-        reads, offs = nxt.result()
-        tot["t_gen"] += time.time() - t0
-        if wi + 1 < len(waves):
-            nxt = gen_pool.submit(gen_wave, waves[wi + 1])  # overlaps this wave's counting
-        rt = torch.from_numpy(reads).to(dev)
-        ot = torch.from_numpy(offs.view(np.int64)).to(dev)
-        cap = max(1, reads.size // 2)
-        keys = torch.empty(cap, dtype=torch.int64, device=dev)
-        cnts = torch.empty(cap, dtype=torch.int32, device=dev)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        n, _ = plan.run_wave_into(wi, rt, ot, keys, cnts, cap, stream)  # records the graph
-        torch.cuda.synchronize()
-        tot["t_first"] += time.perf_counter() - t
-        t = time.perf_counter()
-        n, set_off = plan.run_wave_into(wi, rt, ot, keys, cnts, cap, stream)
-        torch.cuda.synchronize()
-        tot["t_batched"] += time.perf_counter() - t
-        windows = plan.stats()["valid_windows"]
-        # plain: one call per set on the same resident inputs
-        r0 = 0
-        bounds = []
-        for s in range(w["first_set"], w["first_set"] + w["n_sets"]):
-            bounds.append((r0, r0 + n_reads[s], ks[s]))
-            r0 += n_reads[s]
-        t = time.perf_counter()
-        for a, b, k in bounds:
-            kc.count_into(rt, ot[a:b + 1], k, 1, keys, cnts, cap, None, stream)
-        torch.cuda.synchronize()
-        tot["t_plain"] += time.perf_counter() - t
-        tot["windows"] += windows
-        tot["bytes"] += reads.size
-        tot["pairs"] += n
-        print("bench: batched wave %d/%d: %d sets, %.2f GB, %.1f ms batched, %.1f ms plain"
-              % (wi + 1, len(waves), w["n_sets"], reads.size / 1e9, tot["t_batched"] * 1e3,
-                 tot["t_plain"] * 1e3), file=sys.stderr, flush=True)
-        del rt, ot, keys, cnts, reads, offs
-    gen_pool.shutdown()
+    tuned_by_k, tuning_by_k = {}, {}
+    n_waves, max_wave_bytes = 0, 0
+    for lo, hi in groups:
+        info = tune_group(lo, hi) if tune else None
+        tuned = info["options"] if info else {}
+        tuned_by_k[str(ks[lo])] = tuned
+        tuning_by_k[str(ks[lo])] = info["timings"] if info else None
+        plan = kc.BatchPlan(n_reads[lo:hi], set_bytes[lo:hi], ks[lo:hi], P=1,
+                            hbm_budget=budget, opts=kc.options(**tuned))
+        waves = [dict(w, first_set=w["first_set"] + lo) for w in plan.waves]
+        n_waves += len(waves)
+        max_wave_bytes = max([max_wave_bytes] + [w["device_bytes"] for w in waves])
+        gen_pool = ThreadPoolExecutor(max_workers=1)
+        nxt = gen_pool.submit(gen_wave, waves[0]) if waves else None
+        for wi, w in enumerate(waves):
+            t0 = time.time()
+            reads, offs = nxt.result()
+            tot["t_gen"] += time.time() - t0
+            if wi + 1 < len(waves):
+                nxt = gen_pool.submit(gen_wave, waves[wi + 1])  # overlaps this wave's counting
+            rt = torch.from_numpy(reads).to(dev)
+            ot = torch.from_numpy(offs.view(np.int64)).to(dev)
+            cap = max(1, reads.size // 2)
+            keys = torch.empty(cap, dtype=torch.int64, device=dev)
+            cnts = torch.empty(cap, dtype=torch.int32, device=dev)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            n, _ = plan.run_wave_into(wi, rt, ot, keys, cnts, cap, stream)  # records the graph
+            torch.cuda.synchronize()
+            tot["t_first"] += time.perf_counter() - t
+            t = time.perf_counter()
+            n, set_off = plan.run_wave_into(wi, rt, ot, keys, cnts, cap, stream)
+            torch.cuda.synchronize()
+            tot["t_batched"] += time.perf_counter() - t
+            windows = plan.stats()["valid_windows"]
+            # plain: one call per set on the same resident inputs
+            r0 = 0
+            bounds = []
+            for s in range(w["first_set"], w["first_set"] + w["n_sets"]):
+                bounds.append((r0, r0 + n_reads[s], ks[s]))
+                r0 += n_reads[s]
+            t = time.perf_counter()
+            for a, b, k in bounds:
+                kc.count_into(rt, ot[a:b + 1], k, 1, keys, cnts, cap, None, stream)
+            torch.cuda.synchronize()
+            tot["t_plain"] += time.perf_counter() - t
+            tot["windows"] += windows
+            tot["bytes"] += reads.size
+            tot["pairs"] += n
+            print("bench: batched k=%d wave %d/%d: %d sets, %.2f GB, %.1f ms batched, %.1f ms plain"
+                  % (ks[lo], wi + 1, len(waves), w["n_sets"], reads.size / 1e9,
+                     tot["t_batched"] * 1e3, tot["t_plain"] * 1e3), file=sys.stderr, flush=True)
+            del rt, ot, keys, cnts, reads, offs
+        gen_pool.shutdown()
+        plan.close()
     pool.shutdown()
-    plan.close()
     torch.cuda.empty_cache()
     return {
         "workload": "c4_batched_4096_sets", "sets": len(ids), "of_sets": len(spec),
-        "waves": len(waves), "hbm_budget_gib": budget_gib,
-        "max_wave_device_bytes": max(w["device_bytes"] for w in waves),
+        "waves": n_waves, "hbm_budget_gib": budget_gib,
+        "max_wave_device_bytes": max_wave_bytes,
         "bytes": tot["bytes"], "valid_windows": tot["windows"], "pairs": tot["pairs"],
         "value": round(tot["windows"] / tot["t_batched"], 1), "unit": "k-mers/s",
         "value_with_graph_recording": round(tot["windows"] / tot["t_first"], 1),
@@ -348,12 +367,12 @@ def batched_leg(n_sets: int, budget_gib: float, tune: bool) -> dict:
         "ms_first_runs": round(tot["t_first"] * 1e3, 3),
         "host_wait_for_generation_s": round(tot["t_gen"], 1),
         "leg_s": round(time.time() - t_leg, 1),
-        "tuned_options": tuned,
-        "tuning": tune_info["timings"] if tune_info else None,
-        "note": "every set of the recipe, in (k, size) order; waves planned by kc_batch_plan under "
-                "the budget; each wave's inputs generated on the host while the previous wave "
-                "counts; value: graph replays; plain: one kc_count per set on the same resident "
-                "inputs",
+        "tuned_options": tuned_by_k,
+        "tuning": tuning_by_k,
+        "note": "every set of the recipe, in (k, size) order; one plan per k, its options tuned "
+                "on its first wave; waves planned by kc_batch_plan under the budget; each wave's "
+                "inputs generated on the host while the previous wave counts; value: graph "
+                "replays; plain: one kc_count per set on the same resident inputs",
     }
 
 

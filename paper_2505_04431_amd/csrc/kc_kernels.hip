@@ -2169,11 +2169,14 @@ __global__ void __launch_bounds__(256) k_concat_batch(
 
 // start[s] = index of the first pair of set s (within a class output sorted
 // by set); sets without pairs get the index of the next pair. start has
-// n_local + 1 entries; start[n_local] = number of pairs.
+// n_local + 1 entries; start[n_local] = number of pairs. A class whose leaf
+// overflowed has no output (its concat returned at once, so the set ids hold
+// whatever the buffer held before): all its bounds are 0, and the host counts
+// the wave's sets one by one.
 __global__ void k_set_bounds(const uint32_t* __restrict__ set, const DevState* __restrict__ st,
                              uint32_t n_local, unsigned long long* __restrict__ start) {
   const unsigned long long n = st->D;
-  if (n == 0) {
+  if (n == 0 || st->overflow) {
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= n_local; t += gridDim.x * blockDim.x)
       start[t] = 0;
     return;
