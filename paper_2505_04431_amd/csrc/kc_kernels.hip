@@ -1317,10 +1317,11 @@ __device__ __forceinline__ uint32_t leaf_slots(uint64_t n, uint32_t cmax_rt) {
 // to dst/tmp_cnt at [begin, begin + d) in key order. Keys of one group share a
 // long prefix when sequencing errors sit near the k-mer's end (the erroneous
 // copies of one k-mer), so groups are not always tiny; a group larger than
-// kRankMax switches the leaf to a bitonic sort. Returns d.
+// kRankMax switches the leaf to a bitonic sort. Cn >> GSHIFT groups: aux holds
+// 2 * Cn >> GSHIFT counters. Returns d.
 constexpr uint32_t kRankMax = 256;
 
-template <typename K, typename C, int TB, int PER>
+template <typename K, typename C, int TB, int PER, int GSHIFT>
 __device__ __forceinline__ uint32_t leaf_sort_write(K* tk, C* tc, uint32_t* aux, uint32_t* wsum,
                                                     uint32_t* s_max, uint32_t Cn, int keybits,
                                                     int prefix_bits, K* __restrict__ dst,
@@ -1338,7 +1339,7 @@ __device__ __forceinline__ uint32_t leaf_sort_write(K* tk, C* tc, uint32_t* aux,
       rc[j] = tc[s];
     }
   }
-  int nbk_bits = 31 - __builtin_clz(Cn) - 1;  // Cn/2 groups
+  int nbk_bits = 31 - __builtin_clz(Cn) - GSHIFT;
   if (nbk_bits > keybits - prefix_bits) nbk_bits = keybits - prefix_bits;
   const uint32_t nbk = 1u << nbk_bits;
   const int shift = keybits - prefix_bits - nbk_bits;
@@ -1401,6 +1402,16 @@ __device__ __forceinline__ uint32_t leaf_sort_write(K* tk, C* tc, uint32_t* aux,
 __device__ bool occ32(uint32_t c) { return c != 0; }
 __device__ bool occ64(unsigned long long c) { return c != 0; }
 
+// One-word leaf tables: the epilogue's counting sort uses Cn/8 groups (8 KiB
+// of group counters for 4,096 slots instead of 32 KiB with Cn/2), so that
+// three 512-thread workgroups, 24 waves, share a CU (53 KB of LDS each, and
+// registers capped for 6 waves per SIMD: 79 VGPRs, no spills): 27.1 -> 25.7
+// ms for the large leaves of 40,000,000 reads at k = 31, 23.8 -> 21.9 ms at
+// k = 21, against two workgroups per CU.
+constexpr int kLeafGroupShift = 3;
+constexpr int kLeafOccTB = 512;
+constexpr int kLeafOccWaves = 6;
+
 // 64-bit keys: EMPTY (all ones) is never a canonical key for k <= 32, so a
 // slot is claimed by a 64-bit CAS of the key word itself; the count is then
 // added with an atomic add. FULL_FIRST: the first table is the full one (the
@@ -1415,7 +1426,9 @@ __device__ bool occ64(unsigned long long c) { return c != 0; }
 // table overflows are also appended there (count in st->n_ovf) for a second
 // launch with a larger table.
 template <int TB, int CMAX, int R, bool FULL_FIRST, bool MERGED>
-__global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA, uint64_t* bufB,
+__global__ void __launch_bounds__(TB)
+__attribute__((amdgpu_waves_per_eu(TB == kLeafOccTB ? kLeafOccWaves : 1)))
+k_leaf_count64(int keybits, uint64_t* bufA, uint64_t* bufB,
                                                      uint32_t* __restrict__ tmp_cnt,
                                                      const Leaf* __restrict__ leaves,
                                                      DevState* __restrict__ st,
@@ -1428,7 +1441,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
                                                      uint64_t small_max) {
   __shared__ unsigned long long tk[CMAX];
   __shared__ uint32_t tc[CMAX];
-  __shared__ uint32_t aux[CMAX];
+  __shared__ uint32_t aux[(2 * CMAX) >> kLeafGroupShift];
   __shared__ uint32_t wsum[TB / 64];
   __shared__ uint32_t s_nd, s_max, s_cov;
   __shared__ unsigned long long s_sum, s_windows;
@@ -1565,7 +1578,7 @@ __global__ void __launch_bounds__(TB) k_leaf_count64(int keybits, uint64_t* bufA
       __syncthreads();
       if (threadIdx.x == 0 && s_sum != windows) s_cov = 1;
     }
-    const uint32_t d = leaf_sort_write<unsigned long long, uint32_t, TB, CMAX / TB>(
+    const uint32_t d = leaf_sort_write<unsigned long long, uint32_t, TB, CMAX / TB, kLeafGroupShift>(
         tk, tc, aux, wsum, &s_max, Cn, keybits, (int)lf.bits, (unsigned long long*)dst, tmp_cnt,
         lf.begin, occ32);
     if (threadIdx.x == 0) {
@@ -1764,7 +1777,7 @@ __global__ void __launch_bounds__(TB) k_leaf_countw(int keybits, K* bufA, K* buf
       for (uint32_t i = threadIdx.x; i < Cn; i += TB)
         if ((unsigned long long)tc[i] > 0xFFFFFFFFull) s_cov = 1;
     }
-    const uint32_t d = leaf_sort_write<K, C, TB, CMAX / TB>(
+    const uint32_t d = leaf_sort_write<K, C, TB, CMAX / TB, 1>(
         tk, tc, aux, wsum, &s_max, Cn, keybits, (int)lf.bits, dst, tmp_cnt, lf.begin,
         HI ? (bool (*)(C))occ32 : (bool (*)(C))occ64);
     if (threadIdx.x == 0) {
