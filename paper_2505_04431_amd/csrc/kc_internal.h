@@ -105,6 +105,8 @@ hipError_t launch_window_hist(int words, const uint64_t* packed, const uint64_t*
                               int starts_per_thread, hipStream_t s);
 
 // starts_per_thread: 8, or 16 for one-word keys (16,384-record LDS tiles).
+// cursor[]: the class cursors of launch_plan_shards; a tile of class x takes
+// its runs from cursor[x << shard_bits + shard].
 hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64_t* valid,
                                  uint64_t byte_begin, uint64_t byte_end,
                                  int k, int keybits, int shard_bits, const BatchSets* batch,
@@ -112,8 +114,9 @@ hipError_t launch_window_scatter(int words, const uint64_t* packed, const uint64
                                  hipStream_t s);
 
 // Device planning of the first split level. order[] lists shards
-// owner-major; sbegin[] receives each shard's record range start, cursor[] a
-// copy for the scatter; bins[] the split of each shard; items[] the tiles of
+// owner-major; sbegin[] receives each shard's record range start, cursor[]
+// (kXcds << shard_bits entries) where each tile class's part of each shard
+// slice starts (from the class counts of hist[]); bins[] the split of each shard; items[] the tiles of
 // the split shards (item_off[] holds nb+1 prefix offsets of them); subhist[]
 // (ncls * max_leaves entries: one part per item class of the split) is
 // prepared: zeros, but the shard size at the leaf of each unsplit shard in
