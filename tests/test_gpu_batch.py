@@ -152,6 +152,34 @@ def test_batch_k32_single_set_class_and_forced_overflow():
     plan.close()
 
 
+def test_batch_tuner_candidates_against_oracle():
+    """Every option set the tuners try, on sets of k = 21 (one-word class keys)
+    and k = 31 (two-word class keys, whose tables hold 2,048 slots: a leaf
+    target of 8,192 records makes their leaves overflow, so the per-set
+    fallback runs after the wave's graph), each against the oracle."""
+    from paper_2505_04431_amd import tuner
+    reads, offsets, sr, sb, ks, per_set = make_batch(8, 24, [21, 31], min_g=3000, max_g=60000,
+                                                     cov=10, read_len=150)
+    rt, ot = to_device(reads, offsets)
+    want = [oracle.count(r, o, k) for r, o, k in per_set]
+    cands = list(tuner.DEFAULT_CANDIDATES) + [{"split_tile": 8}, {"scatter_tile": 16,
+                                                                  "leaf_target": 8192}]
+    for opts in cands:
+        print("batch: options %s" % opts, flush=True)
+        plan = kc.BatchPlan(sr, sb, ks, P=1, opts=kc.options(**opts))
+        for _ in range(2):  # record, then replay
+            keys, cnts, set_off = plan.run(rt, ot)
+            keys = keys.cpu().numpy().view(np.uint64)
+            cnts = cnts.cpu().numpy().view(np.uint32)
+            assert set_off[-1] == keys.size
+            for s, (r, o, k) in enumerate(per_set):
+                a, b = int(set_off[s]), int(set_off[s + 1])
+                assert_same((keys[a:b], cnts[a:b]), want[s],
+                            "options %s, set %d (k=%d)" % (opts, s, k))
+        print("batch:   overflowed waves %d" % plan.stats()["n_overflow"], flush=True)
+        plan.close()
+
+
 def test_batch_memory_waves_from_a_budget():
     """A device budget cuts the sets into several waves; running all waves at
     once and each wave from its own inputs both give the oracle's counts."""
