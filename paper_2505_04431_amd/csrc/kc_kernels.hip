@@ -635,10 +635,11 @@ __global__ void __launch_bounds__(TB) k_window_hist(const uint64_t* __restrict__
     }
 }
 
-// Owner-major scatter of window records into shard slices (cursor[i] starts at
-// shard i's slice begin). One tile = TB*S window starts: the tile's records
-// are ranked per shard in LDS, each shard's run reserves its place with one
-// global atomic, and the runs leave LDS as coalesced writes.
+// Owner-major scatter of window records into shard slices (cursor[x*nb + i]
+// starts where tile class x's part of shard i's slice begins). One tile =
+// TB*S window starts: the tile's records are ranked per shard in LDS, each
+// shard's run reserves its place in its class's part with one global atomic,
+// and the runs leave LDS as coalesced writes.
 template <typename K, typename Kc, int S, int TB, bool BATCH>
 __device__ __forceinline__ void window_scatter_body(const uint64_t* __restrict__ packed,
                                                     const uint64_t* __restrict__ valid,
